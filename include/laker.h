@@ -1,0 +1,183 @@
+/*
+ * laker.h -- C ABI of the MI355X (gfx950) LAKER solve path.
+ *
+ * LAKER (Tao & Tan, "Accelerating Regularized Attention Kernel Regression for
+ * Spectrum Cartography") solves the regularised attention-kernel regression
+ *     (lambda I + G) alpha = y,   G_ij = exp(s <e_i, e_j>)          (eq. sc-final, eq. sc-exp-kernel)
+ * by preconditioned conjugate gradients (Alg. 1) with the preconditioner
+ * P = Sigma_star^{-1/2} fitted by shrinkage-regularised CCCP maximum likelihood
+ * on normalised random directions u_k = (lambda I + G) z_k       (Sec. IV-B..D),
+ * and reconstructs the field r_hat(x) = sum_i G(x, x_i) alpha_i  (eq. sc-radio-map-reconstruction).
+ * The paper's kernel has s = 1; s = 1/sqrt(d) is the same kernel on embeddings
+ * scaled by s^{1/2}.
+ *
+ * Conventions for every entry point:
+ *  - Pointers documented as "device" point to HIP device memory owned by the
+ *    caller; the library never allocates or frees device memory.  Scratch space
+ *    is passed in as a caller-owned workspace whose size comes from the
+ *    matching *_workspace_bytes query.  Pointers documented as "host" are
+ *    ordinary host memory.
+ *  - Matrices are row-major and densely packed: E is n x d (row i = e_i), the
+ *    random directions Z are n x n_r (column k = z_k).
+ *  - y, alpha and r_hat are float64 at the boundary in every precision mode.
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream).  The
+ *    solver and fitter read convergence flags back, so they return only after
+ *    their work on `stream` has completed; stats structs are filled on return.
+ *  - Errors are returned, never thrown; arguments are validated before any
+ *    launch and an invalid call leaves outputs untouched (LAKER_EINVAL /
+ *    LAKER_ENOMEM).  A HIP runtime failure returns LAKER_EHIP; numerical
+ *    breakdown (p^T A p <= 0, a non-positive pivot, NaN) returns
+ *    LAKER_EBREAKDOWN; hitting max_iter returns LAKER_ENOCONV with alpha holding
+ *    the last iterate.
+ *  - Reductions use a fixed order: repeated calls on the same inputs give
+ *    bitwise-identical results.
+ */
+#ifndef LAKER_H
+#define LAKER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LAKER_OK = 0,
+  LAKER_EINVAL = -1,      /* invalid argument (sizes, null pointers, lambda <= 0, ...) */
+  LAKER_ENOMEM = -2,      /* workspace or preconditioner buffer too small             */
+  LAKER_EHIP = -3,        /* HIP runtime error                                         */
+  LAKER_EBREAKDOWN = -4,  /* p^T A p <= 0, non-positive pivot, or a NaN/Inf             */
+  LAKER_ENOCONV = -5      /* max_iter reached before the tolerance                      */
+} laker_status;
+
+/* Arithmetic of the kernel products.
+ *  LAKER_F64:   float64 scores, exp and accumulation; float64 PCG vectors.
+ *  LAKER_F32:   float32 scores (MFMA), exp2 in float32, float32 PCG vectors.
+ *  LAKER_BF16:  bfloat16 embeddings on MFMA with float32 accumulation, exp2 in
+ *               float32, float32 PCG vectors.
+ *  LAKER_F32 and LAKER_BF16 solves can run inside float64 iterative refinement
+ *  (laker_pcg_opts.refine), which keeps the outer residual y - A alpha, the
+ *  update of alpha and the stopping test in float64. */
+typedef enum { LAKER_F64 = 0, LAKER_F32 = 1, LAKER_BF16 = 2 } laker_precision;
+
+typedef enum {
+  LAKER_PRECOND_NONE = 0,    /* P = I (plain CG)                                         */
+  LAKER_PRECOND_JACOBI = 1,  /* P = diag(lambda I + G)^{-1} (Sec. V-A baseline)          */
+  LAKER_PRECOND_CCCP = 2,    /* P = Sigma_star^{-1/2} from laker_fit_precond (eq. preconditioner-Sigmma) */
+  LAKER_PRECOND_LEARNED = 3  /* P = S_theta^{-1} from laker_learned_precond              */
+} laker_precond_kind;
+
+/* The regression problem (Alg. 1 inputs).  Embedding construction is the
+ * caller's: the paper leaves the position-to-embedding map unspecified. */
+typedef struct {
+  int64_t n;          /* number of measurement sites, >= 1                     */
+  int32_t d;          /* embedding dimension, 1 <= d <= 128                    */
+  int32_t reserved;
+  const double* E;    /* device, n x d row-major embeddings e_i                */
+  double lambda;      /* regularisation weight, > 0                            */
+  double scale;       /* s in G_ij = exp(s <e_i,e_j>), > 0 (paper: 1)          */
+} laker_problem;
+
+/* Options of the preconditioner fit (Alg. 1, "Attention Kernel Regression Learning"). */
+typedef struct {
+  int32_t n_r;        /* number of random directions N_r, 1 <= n_r <= min(n, 1024) */
+  int32_t max_iter;   /* CCCP iteration cap (> 0)                                   */
+  double gamma;       /* nuclear-norm weight gamma >= 0 (eq. prob:kernel-mle)       */
+  double rho;         /* shrinkage rho in [0, 1] (eq. kernel_shrinkage_cccp_Sigma)   */
+  double eps;         /* safeguard eps > 0 (eq. kernel_shrinkage_cccp_F)             */
+  double tol;         /* stop when ||Sigma_{t+1}-Sigma_t||_F/||Sigma_t||_F <= tol   */
+  int32_t precision;  /* laker_precision of the products u_k = (lambda I + G) z_k    */
+  int32_t reserved;
+} laker_cccp_opts;
+
+/* A fitted preconditioner: a header the host keeps plus a caller-owned device
+ * buffer of laker_precond_bytes(n, n_r) bytes that the fit writes. */
+typedef struct {
+  int32_t kind;       /* laker_precond_kind                                    */
+  int32_t n_r;        /* rank of the low-rank part (CCCP: N_r; learned: 64)    */
+  int64_t n;
+  void* data;         /* device buffer                                          */
+  size_t bytes;       /* its size in bytes                                     */
+} laker_precond;
+
+typedef struct {
+  double tol;         /* stop when ||r|| / ||y|| <= tol (recursive r, Alg. 1)  */
+  int32_t max_iter;   /* PCG iteration cap (total over refinement steps)       */
+  int32_t precision;  /* laker_precision of the inner products A p             */
+  int32_t refine;     /* 1: float64 iterative refinement around an F32/BF16 PCG */
+  int32_t ir_max;     /* refinement step cap (<= 64)                            */
+  double inner_tol;   /* inner PCG tolerance per refinement step               */
+  int32_t warm_start; /* 1: alpha holds the starting iterate alpha^0            */
+  int32_t check_every;/* host polls the convergence flag every this many steps  */
+} laker_pcg_opts;
+
+typedef struct {
+  int32_t iters;        /* PCG iterations (products with A in the loop)         */
+  int32_t ir_steps;     /* refinement steps taken (0 without refinement)         */
+  int32_t cccp_iters;   /* CCCP iterations (fit only)                            */
+  int32_t status;       /* laker_status of the call                              */
+  double relres;        /* final recursive relative residual                     */
+  double relres_true;   /* ||y - (lambda I + G) alpha|| / ||y|| in float64        */
+  double ir_relres[64]; /* float64 true residual after each refinement step      */
+} laker_stats;
+
+/* ---- sizes ---------------------------------------------------------------- */
+
+/* Bytes of the device buffer of a preconditioner of rank n_r on n sites. */
+size_t laker_precond_bytes(int64_t n, int32_t n_r);
+/* Workspace bytes of laker_fit_precond. */
+size_t laker_fit_workspace_bytes(int64_t n, int32_t d, int32_t n_r);
+/* Workspace bytes of laker_pcg_solve / laker_kernel_matvec / laker_predict
+ * (m query points; pass m = 0 for the solver). */
+size_t laker_solve_workspace_bytes(int64_t n, int32_t d, int64_t m);
+
+/* ---- entry points ---------------------------------------------------------- */
+
+/* w = (lambda I + G) p, the product the whole method is built on (Alg. 1 step
+ * size and residual update; Sec. IV-D remark: G is never formed).
+ * p, w: device float64 vectors of length n.  precision: laker_precision. */
+laker_status laker_kernel_matvec(const laker_problem* prob, const double* p, double* w,
+                                 int32_t precision, void* workspace, size_t workspace_bytes,
+                                 void* stream);
+
+/* Fit P = Sigma_star^{-1/2} (Alg. 1, preconditioner learning):
+ * u_k = (lambda I + G) z_k, u_bar_k = u_k/||u_k|| (eq. random_directions);
+ * shrinkage-CCCP Sigma_{t+1} = n Sigma_tilde / tr(Sigma_tilde) with
+ * Sigma_tilde = (1-rho) F_gamma(Sigma_t) + rho I from Sigma_0 = I
+ * (eqs. kernel_shrinkage_cccp_F/Sigma/normalization), carried exactly in
+ * low-rank form Sigma = b I + a U_bar diag(w) U_bar^T; then P = Sigma^{-1/2}.
+ * Z: device, n x n_r row-major float64 standard normal draws (column k = z_k);
+ * the draws are inputs so that results are reproducible.
+ * out: kind/n/n_r are set by the call; out->data must hold
+ * laker_precond_bytes(n, n_r) bytes.  stats->cccp_iters is filled. */
+laker_status laker_fit_precond(const laker_problem* prob, const double* Z, const laker_cccp_opts* opts,
+                               laker_precond* out, void* workspace, size_t workspace_bytes,
+                               laker_stats* stats, void* stream);
+
+/* Jacobi preconditioner P_J = diag(lambda I + G)^{-1} (Sec. V-A numerical-layer
+ * baseline); out->data must hold laker_precond_bytes(n, 0) bytes. */
+laker_status laker_jacobi_precond(const laker_problem* prob, laker_precond* out, void* stream);
+
+/* Solve (lambda I + G) alpha = y by PCG (Alg. 1, Sec. IV-E).
+ * precond: NULL or kind LAKER_PRECOND_NONE for plain CG.
+ * y: device float64 (n); alpha: device float64 (n), read as alpha^0 when
+ * opts->warm_start, written with the solution.  stats is filled on return. */
+laker_status laker_pcg_solve(const laker_problem* prob, const laker_precond* precond, const double* y,
+                             double* alpha, const laker_pcg_opts* opts, void* workspace,
+                             size_t workspace_bytes, laker_stats* stats, void* stream);
+
+/* r_hat_j = sum_i exp(s <eq_j, e_i>) alpha_i for m query embeddings
+ * (eq. sc-radio-map-reconstruction).  Eq: device, m x d row-major float64;
+ * alpha: device (n); rhat: device (m). */
+laker_status laker_predict(const laker_problem* prob, const double* alpha, int64_t m, const double* Eq,
+                           double* rhat, int32_t precision, void* workspace, size_t workspace_bytes,
+                           void* stream);
+
+/* Human-readable name of a status code (static string). */
+const char* laker_status_str(int32_t status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LAKER_H */

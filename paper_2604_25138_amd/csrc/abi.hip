@@ -1,0 +1,259 @@
+// Entry points of the C ABI declared in laker.h: argument validation,
+// workspace carving and orchestration of the device kernels.
+#include <math.h>
+
+#include "fit.hpp"
+
+using namespace lk;
+
+namespace {
+
+bool finite_pos(double x) { return isfinite(x) && x > 0.0; }
+
+laker_status check_problem(const laker_problem* p) {
+  if (p == nullptr || p->E == nullptr) return LAKER_EINVAL;
+  if (p->n < 1 || p->d < 1 || p->d > kMaxD) return LAKER_EINVAL;
+  if (!finite_pos(p->lambda) || !finite_pos(p->scale)) return LAKER_EINVAL;
+  return LAKER_OK;
+}
+
+Problem to_problem(const laker_problem* p) {
+  Problem q;
+  q.n = p->n;
+  q.d = p->d;
+  q.dp = pad_dim(p->d);
+  q.lambda = p->lambda;
+  q.scale = p->scale;
+  q.E = p->E;
+  return q;
+}
+
+bool valid_precision(int32_t prec) { return prec == LAKER_F64 || prec == LAKER_F32; }
+
+}  // namespace
+
+namespace lk {
+
+PrecondLayout precond_layout(void* base, int64_t n, int nr) {
+  WsCarver c(base);
+  PrecondLayout L;
+  L.hdr = c.take<double>(32);
+  L.B64 = c.take<double>((size_t)n * nr);
+  L.Bt64 = c.take<double>((size_t)n * nr);
+  L.B32 = c.take<float>((size_t)n * nr);
+  L.Bt32 = c.take<float>((size_t)n * nr);
+  L.dinv64 = c.take<double>(n);
+  L.dinv32 = c.take<float>(n);
+  L.total = c.bytes();
+  return L;
+}
+
+}  // namespace lk
+
+extern "C" {
+
+const char* laker_status_str(int32_t s) {
+  switch (s) {
+    case LAKER_OK: return "ok";
+    case LAKER_EINVAL: return "invalid argument";
+    case LAKER_ENOMEM: return "workspace or buffer too small";
+    case LAKER_EHIP: return "HIP runtime error";
+    case LAKER_EBREAKDOWN: return "numerical breakdown";
+    case LAKER_ENOCONV: return "iteration cap reached before the tolerance";
+    default: return "unknown status";
+  }
+}
+
+size_t laker_precond_bytes(int64_t n, int32_t n_r) {
+  if (n < 1 || n_r < 0) return 0;
+  return precond_layout(nullptr, n, n_r).total;
+}
+
+size_t laker_fit_workspace_bytes(int64_t n, int32_t d, int32_t n_r) {
+  if (n < 1 || d < 1 || d > kMaxD || n_r < 1) return 0;
+  return plan_fit_ws(nullptr, n, d, n_r).total;
+}
+
+size_t laker_solve_workspace_bytes(int64_t n, int32_t d, int64_t m) {
+  if (n < 1 || d < 1 || d > kMaxD || m < 0) return 0;
+  return plan_solve_ws(nullptr, n, d, m).total;
+}
+
+laker_status laker_kernel_matvec(const laker_problem* prob, const double* p, double* w, int32_t precision,
+                                 void* workspace, size_t workspace_bytes, void* stream) {
+  laker_status e = check_problem(prob);
+  if (e != LAKER_OK) return e;
+  if (p == nullptr || w == nullptr || workspace == nullptr || !valid_precision(precision)) return LAKER_EINVAL;
+  SolveWs W = plan_solve_ws(workspace, prob->n, prob->d, 0);
+  if (workspace_bytes < W.total) return LAKER_ENOMEM;
+  Problem pb = to_problem(prob);
+  hipStream_t st = (hipStream_t)stream;
+  KmvPlan pl = kmv_plan(pb.n, pb.n, precision);
+  if (precision == LAKER_F64) {
+    LK_TRY(prep_embed(pb.E, pb.n, pb.d, pb.dp, pb.scale, LAKER_F64, W.e64, st));
+    LK_TRY(kmv_partials(LAKER_F64, pb.dp, W.e64, pb.n, W.e64, pb.n, p, W.part, pl, nullptr, st));
+    LK_TRY(kmv_finish(LAKER_F64, pb.n, pb.lambda, p, W.part, pl.nsplit, w, true, st));
+  } else {
+    LK_TRY(prep_embed(pb.E, pb.n, pb.d, pb.dp, pb.scale, precision, W.e32, st));
+    LK_TRY(convert_vec(p, LAKER_F64, W.vtmp, LAKER_F32, pb.n, st));
+    LK_TRY(kmv_partials(precision, pb.dp, W.e32, pb.n, W.e32, pb.n, W.vtmp, W.part, pl, nullptr, st));
+    LK_TRY(kmv_finish(precision, pb.n, pb.lambda, W.vtmp, W.part, pl.nsplit, w, true, st));
+  }
+  return LAKER_OK;
+}
+
+laker_status laker_fit_precond(const laker_problem* prob, const double* Z, const laker_cccp_opts* opts,
+                               laker_precond* out, void* workspace, size_t workspace_bytes, laker_stats* stats,
+                               void* stream) {
+  laker_status e = check_problem(prob);
+  if (e != LAKER_OK) return e;
+  if (Z == nullptr || opts == nullptr || out == nullptr || out->data == nullptr || workspace == nullptr)
+    return LAKER_EINVAL;
+  const int nr = opts->n_r;
+  if (nr < 1 || nr > kMaxNr || nr > prob->n) return LAKER_EINVAL;
+  if (!(opts->gamma >= 0.0) || !isfinite(opts->gamma)) return LAKER_EINVAL;
+  if (!(opts->rho >= 0.0 && opts->rho <= 1.0)) return LAKER_EINVAL;
+  if (!finite_pos(opts->eps) || !(opts->tol >= 0.0) || opts->max_iter < 1) return LAKER_EINVAL;
+  if (opts->precision != LAKER_F64) return LAKER_EINVAL;
+  FitWs W = plan_fit_ws(workspace, prob->n, prob->d, nr);
+  if (workspace_bytes < W.total) return LAKER_ENOMEM;
+  PrecondLayout L = precond_layout(out->data, prob->n, nr);
+  if (out->bytes < L.total) return LAKER_ENOMEM;
+  Problem pb = to_problem(prob);
+  out->kind = LAKER_PRECOND_CCCP;
+  out->n = prob->n;
+  out->n_r = nr;
+  laker_stats local{};
+  laker_stats* sp = stats != nullptr ? stats : &local;
+  sp->cccp_iters = 0;
+  laker_status r = fit_cccp(pb, Z, *opts, W, L, sp, (hipStream_t)stream);
+  sp->status = r;
+  return r;
+}
+
+laker_status laker_jacobi_precond(const laker_problem* prob, laker_precond* out, void* stream) {
+  laker_status e = check_problem(prob);
+  if (e != LAKER_OK) return e;
+  if (out == nullptr || out->data == nullptr) return LAKER_EINVAL;
+  PrecondLayout L = precond_layout(out->data, prob->n, 0);
+  if (out->bytes < L.total) return LAKER_ENOMEM;
+  out->kind = LAKER_PRECOND_JACOBI;
+  out->n = prob->n;
+  out->n_r = 0;
+  return fit_jacobi(to_problem(prob), L, (hipStream_t)stream);
+}
+
+laker_status laker_pcg_solve(const laker_problem* prob, const laker_precond* precond, const double* y, double* alpha,
+                             const laker_pcg_opts* opts, void* workspace, size_t workspace_bytes, laker_stats* stats,
+                             void* stream) {
+  laker_status e = check_problem(prob);
+  if (e != LAKER_OK) return e;
+  if (y == nullptr || alpha == nullptr || opts == nullptr || workspace == nullptr) return LAKER_EINVAL;
+  if (!valid_precision(opts->precision)) return LAKER_EINVAL;
+  if (!(opts->tol >= 0.0) || opts->max_iter < 1) return LAKER_EINVAL;
+  if (opts->refine && (opts->ir_max < 1 || opts->ir_max > 64 || !(opts->inner_tol > 0.0))) return LAKER_EINVAL;
+  PrecondView view{};
+  view.kind = LAKER_PRECOND_NONE;
+  if (precond != nullptr && precond->kind != LAKER_PRECOND_NONE) {
+    if (precond->data == nullptr || precond->n != prob->n) return LAKER_EINVAL;
+    PrecondLayout L = precond_layout(precond->data, prob->n, precond->n_r);
+    if (precond->bytes < L.total) return LAKER_ENOMEM;
+    const bool f64 = opts->precision == LAKER_F64;
+    view.kind = precond->kind;
+    view.nr = precond->n_r;
+    view.c0p = L.hdr;
+    if (precond->kind == LAKER_PRECOND_JACOBI) {
+      view.dinv = f64 ? (const void*)L.dinv64 : (const void*)L.dinv32;
+    } else if (precond->kind == LAKER_PRECOND_CCCP || precond->kind == LAKER_PRECOND_LEARNED) {
+      if (precond->n_r < 1 || precond->n_r > kMaxNr) return LAKER_EINVAL;
+      view.B = f64 ? (const void*)L.B64 : (const void*)L.B32;
+      view.Bt = f64 ? (const void*)L.Bt64 : (const void*)L.Bt32;
+    } else {
+      return LAKER_EINVAL;
+    }
+  }
+  SolveWs W = plan_solve_ws(workspace, prob->n, prob->d, 0);
+  if (workspace_bytes < W.total) return LAKER_ENOMEM;
+  Problem pb = to_problem(prob);
+  hipStream_t st = (hipStream_t)stream;
+  laker_stats local{};
+  laker_stats* sp = stats != nullptr ? stats : &local;
+  sp->iters = 0;
+  sp->ir_steps = 0;
+  sp->relres = 0.0;
+  sp->relres_true = 0.0;
+  const int check = opts->check_every > 0 ? opts->check_every : 16;
+  LK_TRY(hipMemsetAsync(W.S, 0, sizeof(PcgScalars), st));
+  LK_TRY(hipMemsetAsync(W.cnt, 0, 16 * sizeof(unsigned), st));
+  LK_TRY(prep_embed(pb.E, pb.n, pb.d, pb.dp, pb.scale, LAKER_F64, W.e64, st));
+  if (opts->precision != LAKER_F64)
+    LK_TRY(prep_embed(pb.E, pb.n, pb.d, pb.dp, pb.scale, opts->precision, W.e32, st));
+  laker_status r;
+  if (!opts->refine) {
+    r = pcg_run(pb, W, view, y, alpha, opts->warm_start != 0, opts->tol, opts->max_iter, check, opts->precision, sp,
+                st);
+    if (r == LAKER_OK || r == LAKER_ENOCONV) {
+      double rt = 0.0;
+      laker_status r2 = true_residual(pb, W, y, alpha, nullptr, &rt, true, st);
+      if (r2 != LAKER_OK) return r2;
+      sp->relres_true = rt;
+    }
+  } else {
+    if (!opts->warm_start) LK_TRY(hipMemsetAsync(alpha, 0, sizeof(double) * pb.n, st));
+    r = LAKER_ENOCONV;
+    int used = 0;
+    for (int s = 0; s <= opts->ir_max; ++s) {
+      double rel = 0.0;
+      laker_status r2 = true_residual(pb, W, y, alpha, W.rout, &rel, s > 0 || opts->warm_start, st);
+      if (r2 != LAKER_OK) return r2;
+      if (s < 64) sp->ir_relres[s] = rel;
+      sp->relres_true = rel;
+      sp->relres = rel;
+      sp->ir_steps = s;
+      if (rel <= opts->tol) {
+        r = LAKER_OK;
+        break;
+      }
+      if (s == opts->ir_max || used >= opts->max_iter) break;
+      laker_stats inner{};
+      laker_status ri = pcg_run(pb, W, view, W.rout, W.dalpha, false, opts->inner_tol, opts->max_iter - used, check,
+                                opts->precision, &inner, st);
+      used += inner.iters;
+      sp->iters = used;
+      if (ri == LAKER_EBREAKDOWN || ri == LAKER_EHIP || ri == LAKER_EINVAL) return ri;
+      r2 = axpy_inplace(alpha, W.dalpha, pb.n, st);
+      if (r2 != LAKER_OK) return r2;
+    }
+  }
+  LK_TRY(hipStreamSynchronize(st));
+  sp->status = r;
+  return r;
+}
+
+laker_status laker_predict(const laker_problem* prob, const double* alpha, int64_t m, const double* Eq, double* rhat,
+                           int32_t precision, void* workspace, size_t workspace_bytes, void* stream) {
+  laker_status e = check_problem(prob);
+  if (e != LAKER_OK) return e;
+  if (alpha == nullptr || Eq == nullptr || rhat == nullptr || workspace == nullptr || m < 1) return LAKER_EINVAL;
+  if (!valid_precision(precision)) return LAKER_EINVAL;
+  SolveWs W = plan_solve_ws(workspace, prob->n, prob->d, m);
+  if (workspace_bytes < W.total) return LAKER_ENOMEM;
+  Problem pb = to_problem(prob);
+  hipStream_t st = (hipStream_t)stream;
+  KmvPlan pl = kmv_plan(m, pb.n, precision);
+  if (precision == LAKER_F64) {
+    LK_TRY(prep_embed(pb.E, pb.n, pb.d, pb.dp, pb.scale, LAKER_F64, W.e64, st));
+    LK_TRY(prep_embed(Eq, m, pb.d, pb.dp, pb.scale, LAKER_F64, W.q64, st));
+    LK_TRY(kmv_partials(LAKER_F64, pb.dp, W.q64, m, W.e64, pb.n, alpha, W.part, pl, nullptr, st));
+    LK_TRY(kmv_finish(LAKER_F64, m, 0.0, nullptr, W.part, pl.nsplit, rhat, true, st));
+  } else {
+    LK_TRY(prep_embed(pb.E, pb.n, pb.d, pb.dp, pb.scale, precision, W.e32, st));
+    LK_TRY(prep_embed(Eq, m, pb.d, pb.dp, pb.scale, precision, W.q32, st));
+    LK_TRY(convert_vec(alpha, LAKER_F64, W.vtmp, LAKER_F32, pb.n, st));
+    LK_TRY(kmv_partials(precision, pb.dp, W.q32, m, W.e32, pb.n, W.vtmp, W.part, pl, nullptr, st));
+    LK_TRY(kmv_finish(precision, m, 0.0, nullptr, W.part, pl.nsplit, rhat, true, st));
+  }
+  return LAKER_OK;
+}
+
+}  // extern "C"

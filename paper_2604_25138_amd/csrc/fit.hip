@@ -1,0 +1,521 @@
+// Preconditioner fit of Alg. 1 ("Attention Kernel Regression Learning"):
+//   u_k = (lambda I + G) z_k,  u_bar_k = u_k / ||u_k||          (eq. random_directions)
+//   shrinkage-CCCP from Sigma_0 = I                             (eqs. kernel_shrinkage_cccp_F/Sigma/normalization)
+//   P = Sigma_star^{-1/2}                                        (eq. preconditioner-Sigmma)
+//
+// Sigma_t is carried exactly in low-rank form b I + a U_bar diag(w) U_bar^T:
+// one step computes q_k = u_k^T Sigma^{-1} u_k = (M^{-1} C)_kk / (a w_k) with
+// C = U_bar^T U_bar and M = (b/a) diag(1/w) + C (Woodbury), then
+// w_k = 1/(q_k + eps), tau = tr(Sigma_tilde)/n, a = (1-rho) c n / (N_r tau),
+// b = ((1-rho) c gamma + rho) / tau, c = 1/(1 + gamma/n).
+// With B = sqrt(a) U_bar diag(sqrt(w)) and R = b I + B^T B, the inverse square
+// root is P = b^{-1/2} I + B Gs B^T, Gs = -b^{-1/2} R^{-1/2} (sqrt(b) I + R^{1/2})^{-1};
+// R^{+-1/2} come from the scaled Denman-Beavers iteration, which needs only SPD
+// inverses.  The solver applies P as c0 r + Bt (B^T r) with Bt = B Gs.
+#include "fit.hpp"
+
+#include "dense.hpp"
+
+namespace lk {
+
+namespace {
+
+constexpr int kT = 256;
+
+// part[s][i][k] = sum_{j in split s} exp(<q_i, q_j>) Z[j][k]   (float64)
+template <int DP>
+__global__ __launch_bounds__(256) void mrhs_f64_kernel(const double* __restrict__ Eh, int64_t n,
+                                                       const double* __restrict__ Z, int nr,
+                                                       double* __restrict__ part, int64_t cps) {
+  constexpr int BM = 64, BN = 32, NC = 64;
+  __shared__ double Ei[BM][DP + 1];
+  __shared__ double Ej[BN][DP + 1];
+  __shared__ double X[BM][BN + 1];
+  __shared__ double Zs[BN][NC + 1];
+  const int tid = threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.x * BM;
+  const int c0 = blockIdx.y * NC;
+  const int64_t j0 = (int64_t)blockIdx.z * cps;
+  const int64_t j1 = j0 + cps < n ? j0 + cps : n;
+  for (int idx = tid; idx < BM * DP; idx += 256) {
+    int ii = idx / DP, c = idx % DP;
+    Ei[ii][c] = (i0 + ii < n) ? Eh[(i0 + ii) * DP + c] : 0.0;
+  }
+  const int ty = tid >> 4, tx = tid & 15;
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+  for (int64_t jt = j0; jt < j1; jt += BN) {
+    __syncthreads();
+    for (int idx = tid; idx < BN * DP; idx += 256) {
+      int jj = idx / DP, c = idx % DP;
+      Ej[jj][c] = (jt + jj < j1) ? Eh[(jt + jj) * DP + c] : 0.0;
+    }
+    for (int idx = tid; idx < BN * NC; idx += 256) {
+      int jj = idx / NC, c = idx % NC;
+      Zs[jj][c] = (jt + jj < j1 && c0 + c < nr) ? Z[(jt + jj) * nr + c0 + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < (BM * BN) / 256; ++q) {
+      int e = tid + 256 * q;
+      int ii = e / BN, jj = e % BN;
+      double s = 0.0;
+#pragma unroll
+      for (int c = 0; c < DP; ++c) s = fma(Ei[ii][c], Ej[jj][c], s);
+      X[ii][jj] = (jt + jj < j1) ? exp(s) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int jj = 0; jj < BN; ++jj) {
+      double xv[4], zv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) xv[a] = X[ty * 4 + a][jj];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) zv[b] = Zs[jj][tx * 4 + b];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = fma(xv[a], zv[b], acc[a][b]);
+    }
+  }
+  double* out = part + (int64_t)blockIdx.z * n * nr;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    int64_t i = i0 + ty * 4 + a;
+    if (i >= n) continue;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      int k = c0 + tx * 4 + b;
+      if (k < nr) out[i * nr + k] = acc[a][b];
+    }
+  }
+}
+
+// U = lambda Z + sum_s part[s]
+__global__ void mrhs_finish_kernel(const double* __restrict__ part, int nsplit, const double* __restrict__ Z,
+                                   double lam, int64_t total, double* __restrict__ U) {
+  for (int64_t idx = (int64_t)blockIdx.x * kT + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * kT) {
+    double s = 0.0;
+    for (int k = 0; k < nsplit; ++k) s += part[(int64_t)k * total + idx];
+    U[idx] = fma(lam, Z[idx], s);
+  }
+}
+
+// Column sums of squares of the n x nr matrix U (row chunks, ordered finish),
+// then norms.
+__global__ __launch_bounds__(256) void colsq_kernel(const double* __restrict__ U, int64_t n, int nr, int64_t rpb,
+                                                    double* __restrict__ cpart, double* __restrict__ norms,
+                                                    unsigned* cnt) {
+  const int64_t i0 = (int64_t)blockIdx.x * rpb;
+  const int64_t i1 = i0 + rpb < n ? i0 + rpb : n;
+  for (int k = threadIdx.x; k < nr; k += kT) {
+    double s = 0.0;
+    for (int64_t i = i0; i < i1; ++i) {
+      double u = U[i * nr + k];
+      s = fma(u, u, s);
+    }
+    cpart[(int64_t)blockIdx.x * nr + k] = s;
+  }
+  if (last_block_arrived(cnt)) {
+    for (int k = threadIdx.x; k < nr; k += kT) {
+      double s = 0.0;
+      for (unsigned b = 0; b < gridDim.x; ++b) s += __builtin_nontemporal_load(cpart + (int64_t)b * nr + k);
+      norms[k] = sqrt(s);
+    }
+    if (threadIdx.x == 0) *cnt = 0;
+  }
+}
+
+__global__ void colscale_kernel(double* __restrict__ U, int64_t n, int nr, const double* __restrict__ norms) {
+  const int64_t total = n * nr;
+  for (int64_t idx = (int64_t)blockIdx.x * kT + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * kT) {
+    int k = (int)(idx % nr);
+    U[idx] = U[idx] / norms[k];
+  }
+}
+
+// M = (b/a) diag(1/w) + C
+__global__ void cccp_build_m_kernel(const double* __restrict__ C, const double* __restrict__ w,
+                                    const CccpState* __restrict__ S, double* __restrict__ M, int nr) {
+  if (S->done) return;
+  const double ba = S->b / S->a;
+  const int64_t total = (int64_t)nr * nr;
+  for (int64_t idx = (int64_t)blockIdx.x * kT + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * kT) {
+    int64_t i = idx / nr, j = idx - i * nr;
+    M[idx] = C[idx] + (i == j ? ba / w[i] : 0.0);
+  }
+}
+
+// q_k = (M^{-1} C)_kk / (a w_k), or q_k = C_kk while Sigma = I; one wave per k.
+__global__ __launch_bounds__(256) void cccp_q_kernel(const double* __restrict__ Minv, const double* __restrict__ C,
+                                                     const double* __restrict__ w, const CccpState* __restrict__ S,
+                                                     double* __restrict__ q, int nr, int first) {
+  if (S->done) return;
+  const int lane = threadIdx.x & 63;
+  const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (k >= nr) return;
+  if (first) {
+    if (lane == 0) q[k] = C[(int64_t)k * nr + k];
+    return;
+  }
+  double s = 0.0;
+  const double* mr = Minv + (int64_t)k * nr;
+  const double* cr = C + (int64_t)k * nr;   // C symmetric: column k = row k
+  for (int j = lane; j < nr; j += 64) s = fma(mr[j], cr[j], s);
+  s = wave_sum(s);
+  if (lane == 0) q[k] = s / (S->a * w[k]);
+}
+
+// w <- 1/(q + eps); tau, a, b; exact Frobenius change of Sigma; stopping test.
+// One block of 1024 threads, fixed-order sums.
+__global__ __launch_bounds__(1024) void cccp_update_kernel(const double* __restrict__ C, const double* __restrict__ q,
+                                                           double* __restrict__ w, double* __restrict__ wnew,
+                                                           CccpState* S, int nr, double n, double gamma, double rho,
+                                                           double eps, double tol, int max_iter) {
+  if (S->done) return;
+  __shared__ double sh[16];
+  const int tid = threadIdx.x;
+  const double a0 = S->a, b0 = S->b;
+  double swc = 0.0;
+  for (int k = tid; k < nr; k += 1024) {
+    double wn = 1.0 / (q[k] + eps);
+    wnew[k] = wn;
+    swc += wn * C[(int64_t)k * nr + k];
+  }
+  swc = block_sum(swc, sh);
+  const double c = 1.0 / (1.0 + gamma / n);
+  const double tau = (1.0 - rho) * c * (swc / nr + gamma) + rho;
+  const double a1 = (1.0 - rho) * c * n / (nr * tau);
+  const double b1 = ((1.0 - rho) * c * gamma + rho) / tau;
+  __syncthreads();
+  // D = a1 wnew - a0 w ; F = a0 w
+  double t_dc = 0.0, t_fc = 0.0, t_dd = 0.0, t_ff = 0.0;
+  for (int64_t idx = tid; idx < (int64_t)nr * nr; idx += 1024) {
+    int64_t k = idx / nr, l = idx - k * nr;
+    double ckl = C[idx];
+    double dk = a1 * wnew[k] - a0 * w[k], dl = a1 * wnew[l] - a0 * w[l];
+    double fk = a0 * w[k], fl = a0 * w[l];
+    double c2 = ckl * ckl;
+    t_dd = fma(dk * dl, c2, t_dd);
+    t_ff = fma(fk * fl, c2, t_ff);
+    if (k == l) {
+      t_dc += dk * ckl;
+      t_fc += fk * ckl;
+    }
+  }
+  t_dd = block_sum(t_dd, sh);
+  t_ff = block_sum(t_ff, sh);
+  t_dc = block_sum(t_dc, sh);
+  t_fc = block_sum(t_fc, sh);
+  __syncthreads();
+  const double db = b1 - b0;
+  const double num = n * db * db + 2.0 * db * t_dc + t_dd;
+  const double den = n * b0 * b0 + 2.0 * b0 * t_fc + t_ff;
+  const double change = sqrt(fmax(num, 0.0) / den);
+  for (int k = tid; k < nr; k += 1024) w[k] = wnew[k];
+  if (tid == 0) {
+    S->a = a1;
+    S->b = b1;
+    S->tau = tau;
+    S->change = change;
+    int it = S->iters + 1;
+    S->iters = it;
+    if (!isfinite(change) || !(tau > 0.0)) S->done = 2;
+    else if (change <= tol) S->done = 1;
+    else if (it >= max_iter) S->done = 3;
+  }
+}
+
+__global__ void cccp_init_kernel(CccpState* S, double* w, int nr) {
+  for (int k = threadIdx.x; k < nr; k += blockDim.x) w[k] = 0.0;
+  if (threadIdx.x == 0) {
+    S->a = 0.0;
+    S->b = 1.0;
+    S->tau = 1.0;
+    S->change = 0.0;
+    S->iters = 0;
+    S->done = 0;
+    S->gjflag = 0;
+    S->db_iters = 0;
+    S->db_change = 0.0;
+  }
+}
+
+// B = sqrt(a) U_bar diag(sqrt(w))  (n x nr)
+__global__ void make_b_kernel(const double* __restrict__ Ub, const double* __restrict__ w,
+                              const CccpState* __restrict__ S, double* __restrict__ B, int64_t n, int nr) {
+  const double sa = sqrt(S->a);
+  const int64_t total = n * nr;
+  for (int64_t idx = (int64_t)blockIdx.x * kT + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * kT) {
+    int k = (int)(idx % nr);
+    B[idx] = sa * Ub[idx] * sqrt(w[k]);
+  }
+}
+
+// Y = b I + a diag(sqrt w) C diag(sqrt w) (= b I + B^T B),  Zm = I
+__global__ void db_init_kernel(const double* __restrict__ C, const double* __restrict__ w,
+                               const CccpState* __restrict__ S, double* __restrict__ Y, double* __restrict__ Zm,
+                               int nr) {
+  const int64_t total = (int64_t)nr * nr;
+  const double a = S->a, b = S->b;
+  for (int64_t idx = (int64_t)blockIdx.x * kT + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * kT) {
+    int64_t i = idx / nr, j = idx - i * nr;
+    Y[idx] = a * sqrt(w[i] * w[j]) * C[idx] + (i == j ? b : 0.0);
+    Zm[idx] = (i == j) ? 1.0 : 0.0;
+  }
+}
+
+// Scaled Denman-Beavers step: mu = (det Y det Z)^{-1/(2 N)},
+// Y <- (mu Y + Z^{-1}/mu)/2, Z <- (mu Z + Y^{-1}/mu)/2; relative change of Y.
+__global__ __launch_bounds__(256) void db_step_kernel(double* __restrict__ Y, double* __restrict__ Zm,
+                                                      const double* __restrict__ Yi, const double* __restrict__ Zi,
+                                                      CccpState* S, int nr, double* __restrict__ bpart) {
+  __shared__ double sh[16];
+  const double mu = exp(-(S->ld_y + S->ld_z) / (2.0 * nr));
+  const double imu = 1.0 / mu;
+  const int64_t total = (int64_t)nr * nr;
+  double dsum = 0.0, ysum = 0.0;
+  for (int64_t idx = (int64_t)blockIdx.x * kT + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * kT) {
+    double y0 = Y[idx];
+    double y1 = 0.5 * (mu * y0 + imu * Zi[idx]);
+    double z1 = 0.5 * (mu * Zm[idx] + imu * Yi[idx]);
+    Y[idx] = y1;
+    Zm[idx] = z1;
+    dsum += (y1 - y0) * (y1 - y0);
+    ysum += y1 * y1;
+  }
+  dsum = block_sum(dsum, sh);
+  ysum = block_sum(ysum, sh);
+  if (threadIdx.x == 0) {
+    bpart[blockIdx.x] = dsum;
+    bpart[kMaxBlocks + blockIdx.x] = ysum;
+  }
+  if (last_block_arrived(&S->cnt[0])) {
+    double d = ordered_sum(bpart, gridDim.x, sh);
+    double yv = ordered_sum(bpart + kMaxBlocks, gridDim.x, sh);
+    if (threadIdx.x == 0) {
+      S->db_change = sqrt(d / yv);
+      S->db_iters += 1;
+      S->cnt[0] = 0;
+    }
+  }
+}
+
+// W = sqrt(b) I + Y
+__global__ void add_sqrtb_diag_kernel(const double* __restrict__ Y, const CccpState* __restrict__ S,
+                                      double* __restrict__ W, int nr) {
+  const int64_t total = (int64_t)nr * nr;
+  const double sb = sqrt(S->b);
+  for (int64_t idx = (int64_t)blockIdx.x * kT + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * kT) {
+    int64_t i = idx / nr, j = idx - i * nr;
+    W[idx] = Y[idx] + (i == j ? sb : 0.0);
+  }
+}
+
+__global__ void write_header_kernel(const CccpState* __restrict__ S, double* __restrict__ hdr) {
+  if (threadIdx.x == 0) {
+    hdr[0] = 1.0 / sqrt(S->b);
+    hdr[1] = S->a;
+    hdr[2] = S->b;
+    hdr[3] = (double)S->iters;
+    hdr[4] = S->change;
+    hdr[5] = (double)S->db_iters;
+    hdr[6] = S->db_change;
+  }
+}
+
+// Jacobi: dinv_i = 1 / (lambda + exp(s <e_i, e_i>)).
+__global__ void jacobi_kernel(const double* __restrict__ E, int64_t n, int d, double s, double lam,
+                              double* __restrict__ d64, float* __restrict__ d32) {
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
+    double acc = 0.0;
+    for (int c = 0; c < d; ++c) acc = fma(E[i * d + c], E[i * d + c], acc);
+    double v = 1.0 / (lam + exp(s * acc));
+    d64[i] = v;
+    d32[i] = (float)v;
+  }
+}
+
+__global__ void to_f32_kernel(const double* __restrict__ src, float* __restrict__ dst, int64_t total) {
+  for (int64_t idx = (int64_t)blockIdx.x * kT + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * kT)
+    dst[idx] = (float)src[idx];
+}
+
+inline int ew_grid(int64_t total) {
+  int64_t g = (total + kT - 1) / kT;
+  if (g > 8192) g = 8192;
+  return (int)(g < 1 ? 1 : g);
+}
+
+inline int64_t mrhs_partial_cap(int64_t n, int nr) {
+  int64_t a = 4 * n * (int64_t)nr;
+  int64_t b = 16 * (int64_t)nr * nr;
+  int64_t c = (int64_t)1 << 22;
+  int64_t m = a > b ? a : b;
+  return m > c ? m : c;
+}
+
+hipError_t launch_mrhs(int dp, const double* Eh, int64_t n, const double* Z, int nr, double* part, int nsplit,
+                       int64_t cps, hipStream_t st) {
+  dim3 grid((unsigned)((n + 63) / 64), (unsigned)((nr + 63) / 64), (unsigned)nsplit);
+  switch (dp) {
+    case 16: mrhs_f64_kernel<16><<<grid, 256, 0, st>>>(Eh, n, Z, nr, part, cps); break;
+    case 32: mrhs_f64_kernel<32><<<grid, 256, 0, st>>>(Eh, n, Z, nr, part, cps); break;
+    case 64: mrhs_f64_kernel<64><<<grid, 256, 0, st>>>(Eh, n, Z, nr, part, cps); break;
+    case 128: mrhs_f64_kernel<128><<<grid, 256, 0, st>>>(Eh, n, Z, nr, part, cps); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+FitWs plan_fit_ws(void* base, int64_t n, int d, int nr) {
+  WsCarver c(base);
+  FitWs w;
+  const int dp = pad_dim(d);
+  w.e64 = c.take<double>((size_t)n * dp);
+  w.part_cap = mrhs_partial_cap(n, nr);
+  w.part = c.take<double>((size_t)w.part_cap);
+  w.U = c.take<double>((size_t)n * nr);
+  w.cpart = c.take<double>((size_t)256 * nr);
+  w.norms = c.take<double>(nr);
+  w.C = c.take<double>((size_t)nr * nr);
+  w.M = c.take<double>((size_t)nr * nr);
+  w.Y = c.take<double>((size_t)nr * nr);
+  w.Zm = c.take<double>((size_t)nr * nr);
+  w.Yi = c.take<double>((size_t)nr * nr);
+  w.Zi = c.take<double>((size_t)nr * nr);
+  w.Gs = c.take<double>((size_t)nr * nr);
+  w.side = c.take<double>(gj_side_elems(nr));
+  w.q = c.take<double>(nr);
+  w.w = c.take<double>(nr);
+  w.wnew = c.take<double>(nr);
+  w.S = c.take<CccpState>(1);
+  w.bpart = c.take<double>(2 * kMaxBlocks);
+  w.cnt = c.take<unsigned>(16);
+  w.total = c.bytes();
+  return w;
+}
+
+laker_status fit_cccp(const Problem& pb, const double* Z, const laker_cccp_opts& o, const FitWs& ws,
+                      const PrecondLayout& L, laker_stats* stats, hipStream_t st) {
+  const int64_t n = pb.n;
+  const int nr = o.n_r;
+  // 1. prepared embeddings (sqrt(s) e, float64)
+  LK_TRY(prep_embed(pb.E, n, pb.d, pb.dp, pb.scale, LAKER_F64, ws.e64, st));
+  // 2. U = (lambda I + G) Z
+  {
+    const int64_t rowtiles = (n + 63) / 64, coltiles = (nr + 63) / 64;
+    int64_t ns = (1024 + rowtiles * coltiles - 1) / (rowtiles * coltiles);
+    int64_t jt = (n + 31) / 32;
+    if (ns > jt) ns = jt;
+    if (ns > 64) ns = 64;
+    while (ns > 1 && ns * n * nr > ws.part_cap) --ns;
+    if (ns < 1) ns = 1;
+    int64_t cps = (((n + ns - 1) / ns) + 31) / 32 * 32;
+    ns = (n + cps - 1) / cps;
+    LK_TRY(launch_mrhs(pb.dp, ws.e64, n, Z, nr, ws.part, (int)ns, cps, st));
+    mrhs_finish_kernel<<<ew_grid(n * nr), kT, 0, st>>>(ws.part, (int)ns, Z, pb.lambda, n * nr, ws.U);
+    LK_CHECK_LAUNCH();
+  }
+  // 3. U_bar = U / ||U||  (column-wise)
+  {
+    int64_t rpb = (n + 255) / 256;
+    if (rpb < 16) rpb = 16;
+    int gb = (int)((n + rpb - 1) / rpb);
+    LK_TRY(hipMemsetAsync(ws.cnt, 0, 16 * sizeof(unsigned), st));
+    colsq_kernel<<<gb, kT, 0, st>>>(ws.U, n, nr, rpb, ws.cpart, ws.norms, ws.cnt);
+    LK_CHECK_LAUNCH();
+    colscale_kernel<<<ew_grid(n * nr), kT, 0, st>>>(ws.U, n, nr, ws.norms);
+    LK_CHECK_LAUNCH();
+  }
+  // 4. C = U_bar^T U_bar
+  {
+    int ns = gemm_pick_split(nr, nr, n, ws.part_cap);
+    LK_TRY(gemm_f64(nr, nr, n, ws.U, 1, nr, ws.U, nr, 1, ws.C, nr, 1.0, nullptr, 0.0, ws.part, ns, st));
+  }
+  // 5. CCCP iterations
+  cccp_init_kernel<<<1, 256, 0, st>>>(ws.S, ws.w, nr);
+  LK_CHECK_LAUNCH();
+  LK_TRY(hipMemsetAsync(ws.S->cnt, 0, sizeof(ws.S->cnt), st));
+  CccpState hs;
+  const int qgrid = (nr + 3) / 4;
+  for (int t = 0; t < o.max_iter; ++t) {
+    if (t > 0) {
+      cccp_build_m_kernel<<<ew_grid((int64_t)nr * nr), kT, 0, st>>>(ws.C, ws.w, ws.S, ws.M, nr);
+      LK_CHECK_LAUNCH();
+      LK_TRY(spd_inverse_inplace(ws.M, nr, ws.side, &ws.S->ld_y, &ws.S->gjflag, st));
+    }
+    cccp_q_kernel<<<qgrid, 256, 0, st>>>(ws.M, ws.C, ws.w, ws.S, ws.q, nr, t == 0 ? 1 : 0);
+    LK_CHECK_LAUNCH();
+    cccp_update_kernel<<<1, 1024, 0, st>>>(ws.C, ws.q, ws.w, ws.wnew, ws.S, nr, (double)n, o.gamma, o.rho, o.eps,
+                                           o.tol, o.max_iter);
+    LK_CHECK_LAUNCH();
+    LK_TRY(hipMemcpyAsync(&hs, ws.S, sizeof(hs), hipMemcpyDeviceToHost, st));
+    LK_TRY(hipStreamSynchronize(st));
+    if (hs.gjflag) return LAKER_EBREAKDOWN;
+    if (hs.done) break;
+  }
+  if (hs.done == 2) return LAKER_EBREAKDOWN;
+  if (stats) stats->cccp_iters = hs.iters;
+  // 6. B and R = b I + B^T B; Denman-Beavers for R^{1/2} (Y) and R^{-1/2} (Zm)
+  make_b_kernel<<<ew_grid(n * nr), kT, 0, st>>>(ws.U, ws.w, ws.S, L.B64, n, nr);
+  LK_CHECK_LAUNCH();
+  db_init_kernel<<<ew_grid((int64_t)nr * nr), kT, 0, st>>>(ws.C, ws.w, ws.S, ws.Y, ws.Zm, nr);
+  LK_CHECK_LAUNCH();
+  const size_t mb = (size_t)nr * nr * sizeof(double);
+  double prev_change = 1e300;
+  for (int it = 0; it < 80; ++it) {
+    LK_TRY(hipMemcpyAsync(ws.Yi, ws.Y, mb, hipMemcpyDeviceToDevice, st));
+    LK_TRY(hipMemcpyAsync(ws.Zi, ws.Zm, mb, hipMemcpyDeviceToDevice, st));
+    LK_TRY(spd_inverse_inplace(ws.Yi, nr, ws.side, &ws.S->ld_y, &ws.S->gjflag, st));
+    LK_TRY(spd_inverse_inplace(ws.Zi, nr, ws.side, &ws.S->ld_z, &ws.S->gjflag, st));
+    int gb = (int)(((int64_t)nr * nr + kT * 4 - 1) / (kT * 4));
+    if (gb > kMaxBlocks) gb = kMaxBlocks;
+    db_step_kernel<<<gb, kT, 0, st>>>(ws.Y, ws.Zm, ws.Yi, ws.Zi, ws.S, nr, ws.bpart);
+    LK_CHECK_LAUNCH();
+    LK_TRY(hipMemcpyAsync(&hs, ws.S, sizeof(hs), hipMemcpyDeviceToHost, st));
+    LK_TRY(hipStreamSynchronize(st));
+    if (hs.gjflag) return LAKER_EBREAKDOWN;
+    if (!(hs.db_change == hs.db_change)) return LAKER_EBREAKDOWN;
+    // quadratic convergence to rounding level, or stagnation there
+    if (hs.db_change <= 1e-13) break;
+    if (hs.db_change <= 1e-9 && hs.db_change >= 0.5 * prev_change) break;
+    prev_change = hs.db_change;
+  }
+  // 7. Gs = -b^{-1/2} Zm (sqrt(b) I + Y)^{-1}
+  add_sqrtb_diag_kernel<<<ew_grid((int64_t)nr * nr), kT, 0, st>>>(ws.Y, ws.S, ws.M, nr);
+  LK_CHECK_LAUNCH();
+  LK_TRY(spd_inverse_inplace(ws.M, nr, ws.side, &ws.S->ld_y, &ws.S->gjflag, st));
+  write_header_kernel<<<1, 64, 0, st>>>(ws.S, L.hdr);
+  LK_CHECK_LAUNCH();
+  {
+    int ns = gemm_pick_split(nr, nr, nr, ws.part_cap);
+    LK_TRY(gemm_f64(nr, nr, nr, ws.Zm, nr, 1, ws.M, nr, 1, ws.Gs, nr, -1.0, L.hdr, 0.0, ws.part, ns, st));
+  }
+  // 8. Bt = B Gs; float32 copies
+  {
+    int ns = gemm_pick_split(n, nr, nr, ws.part_cap);
+    LK_TRY(gemm_f64(n, nr, nr, L.B64, nr, 1, ws.Gs, nr, 1, L.Bt64, nr, 1.0, nullptr, 0.0, ws.part, ns, st));
+  }
+  to_f32_kernel<<<ew_grid(n * nr), kT, 0, st>>>(L.B64, L.B32, n * nr);
+  LK_CHECK_LAUNCH();
+  to_f32_kernel<<<ew_grid(n * nr), kT, 0, st>>>(L.Bt64, L.Bt32, n * nr);
+  LK_CHECK_LAUNCH();
+  LK_TRY(hipMemcpyAsync(&hs, ws.S, sizeof(hs), hipMemcpyDeviceToHost, st));
+  LK_TRY(hipStreamSynchronize(st));
+  if (hs.gjflag) return LAKER_EBREAKDOWN;
+  return LAKER_OK;   // a CCCP iterate stopped at max_iter still gives an SPD preconditioner
+}
+
+laker_status fit_jacobi(const Problem& pb, const PrecondLayout& L, hipStream_t st) {
+  jacobi_kernel<<<ew_grid(pb.n), kT, 0, st>>>(pb.E, pb.n, pb.d, pb.scale, pb.lambda, L.dinv64, L.dinv32);
+  LK_CHECK_LAUNCH();
+  return LAKER_OK;
+}
+
+}  // namespace lk

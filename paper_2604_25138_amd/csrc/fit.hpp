@@ -1,0 +1,45 @@
+// Internal interface of the preconditioner fit (fit.hip).
+#pragma once
+
+#include "pcg.hpp"
+
+namespace lk {
+
+struct CccpState {
+  double a, b, tau, change;   // Sigma = b I + a U_bar diag(w) U_bar^T; last relative change
+  double ld_y, ld_z;          // log det of the matrices inverted by the Denman-Beavers step
+  double db_change;           // relative change of the Denman-Beavers iterate
+  int iters, done, gjflag, db_iters;
+  unsigned cnt[4];
+};
+
+struct FitWs {
+  double* e64;
+  double* part;
+  int64_t part_cap;
+  double* U;
+  double* cpart;
+  double* norms;
+  double* C;
+  double* M;
+  double* Y;
+  double* Zm;
+  double* Yi;
+  double* Zi;
+  double* Gs;
+  double* side;
+  double* q;
+  double* w;
+  double* wnew;
+  CccpState* S;
+  double* bpart;
+  unsigned* cnt;
+  size_t total;
+};
+FitWs plan_fit_ws(void* base, int64_t n, int d, int nr);
+
+laker_status fit_cccp(const Problem& pb, const double* Z, const laker_cccp_opts& o, const FitWs& ws,
+                      const PrecondLayout& L, laker_stats* stats, hipStream_t st);
+laker_status fit_jacobi(const Problem& pb, const PrecondLayout& L, hipStream_t st);
+
+}  // namespace lk

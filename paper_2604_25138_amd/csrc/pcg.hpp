@@ -1,0 +1,80 @@
+// Internal interfaces of the solver, the fit and the entry points.
+#pragma once
+
+#include "internal.hpp"
+
+namespace lk {
+
+struct Problem {
+  int64_t n;
+  int d;
+  int dp;
+  double lambda;
+  double scale;
+  const double* E;
+};
+
+// Carved solve workspace.  Vectors are sized for float64 and reused as float32.
+struct SolveWs {
+  double* e64;
+  float* e32;
+  uint16_t* e16;
+  double* q64;
+  float* q32;
+  uint16_t* q16;
+  double* part;     // column-split partials, up to 64 x max(n, m)
+  double* r;
+  double* p;
+  double* ap;
+  double* theta;
+  double* vtmp;
+  double* w64;
+  double* rout;
+  double* dalpha;
+  PcgScalars* S;
+  double* bpart;
+  double* tpart;
+  double* t;
+  double* misc;
+  unsigned* cnt;
+  size_t total;
+};
+SolveWs plan_solve_ws(void* base, int64_t n, int d, int64_t m);
+
+// Preconditioner as the solver sees it, in one vector precision.
+//   CCCP / learned:  theta = c0 r + Bt (B^T r)   (B, Bt: n x nr row-major)
+//   Jacobi:          theta = dinv .* r
+struct PrecondView {
+  int kind;
+  int nr;
+  const double* c0p;   // device pointer to c0
+  const void* B;
+  const void* Bt;
+  const void* dinv;
+};
+
+// Layout of the preconditioner buffer (all offsets 256-byte aligned):
+//   header (32 doubles: [0] = b^{-1/2}, [1] = a, [2] = b, [3] = CCCP iterations, ...),
+//   B64, Bt64 (n x nr float64), B32, Bt32 (n x nr float32), dinv64 (n), dinv32 (n).
+struct PrecondLayout {
+  double* hdr;
+  double* B64;
+  double* Bt64;
+  float* B32;
+  float* Bt32;
+  double* dinv64;
+  float* dinv32;
+  size_t total;
+};
+PrecondLayout precond_layout(void* base, int64_t n, int nr);
+
+laker_status pcg_run(const Problem& pb, const SolveWs& ws, const PrecondView& P, const double* rhs, double* alpha,
+                     bool warm, double tol, int max_iter, int check_every, int prec, laker_stats* stats,
+                     hipStream_t st);
+laker_status true_residual(const Problem& pb, const SolveWs& ws, const double* y, const double* alpha,
+                           double* r_out, double* relres, bool have_alpha, hipStream_t st);
+laker_status axpy_inplace(double* x, const double* d, int64_t n, hipStream_t st);
+laker_status apply_lowrank_once(const PrecondView& P, const double* r, double* theta, int64_t n,
+                                const SolveWs& ws, hipStream_t st);
+
+}  // namespace lk

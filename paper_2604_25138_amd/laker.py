@@ -1,0 +1,275 @@
+"""Python binding of the LAKER C ABI (include/laker.h).
+
+Argument marshalling only: every step of the method runs in the HIP library
+``liblaker.so``.  torch provides device memory and the current stream.  The
+library must be built (``python -m paper_2604_25138_amd.build_lib``); there is
+no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "liblaker.so")
+
+LAKER_OK, LAKER_EINVAL, LAKER_ENOMEM, LAKER_EHIP, LAKER_EBREAKDOWN, LAKER_ENOCONV = 0, -1, -2, -3, -4, -5
+F64, F32, BF16 = 0, 1, 2
+PRECOND_NONE, PRECOND_JACOBI, PRECOND_CCCP, PRECOND_LEARNED = 0, 1, 2, 3
+_PREC = {"f64": F64, "f32": F32, "bf16": BF16, F64: F64, F32: F32, BF16: BF16}
+
+# every symbol declared in include/laker.h
+EXPORTS = (
+    "laker_precond_bytes", "laker_fit_workspace_bytes", "laker_solve_workspace_bytes",
+    "laker_kernel_matvec", "laker_fit_precond", "laker_jacobi_precond", "laker_pcg_solve",
+    "laker_predict", "laker_status_str",
+)
+
+
+class laker_problem(C.Structure):
+    _fields_ = [("n", C.c_int64), ("d", C.c_int32), ("reserved", C.c_int32), ("E", C.c_void_p),
+                ("lambda_", C.c_double), ("scale", C.c_double)]
+
+
+class laker_cccp_opts(C.Structure):
+    _fields_ = [("n_r", C.c_int32), ("max_iter", C.c_int32), ("gamma", C.c_double), ("rho", C.c_double),
+                ("eps", C.c_double), ("tol", C.c_double), ("precision", C.c_int32), ("reserved", C.c_int32)]
+
+
+class laker_precond(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n_r", C.c_int32), ("n", C.c_int64), ("data", C.c_void_p),
+                ("bytes", C.c_size_t)]
+
+
+class laker_pcg_opts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("precision", C.c_int32), ("refine", C.c_int32),
+                ("ir_max", C.c_int32), ("inner_tol", C.c_double), ("warm_start", C.c_int32),
+                ("check_every", C.c_int32)]
+
+
+class laker_stats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("ir_steps", C.c_int32), ("cccp_iters", C.c_int32), ("status", C.c_int32),
+                ("relres", C.c_double), ("relres_true", C.c_double), ("ir_relres", C.c_double * 64)]
+
+
+class LakerError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {status_str(status)} ({status})")
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load liblaker.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2604_25138_amd.build_lib`")
+    lib = C.CDLL(path)
+    vp, sz, i32, i64 = C.c_void_p, C.c_size_t, C.c_int32, C.c_int64
+    P = C.POINTER
+    lib.laker_precond_bytes.argtypes = [i64, i32]
+    lib.laker_precond_bytes.restype = sz
+    lib.laker_fit_workspace_bytes.argtypes = [i64, i32, i32]
+    lib.laker_fit_workspace_bytes.restype = sz
+    lib.laker_solve_workspace_bytes.argtypes = [i64, i32, i64]
+    lib.laker_solve_workspace_bytes.restype = sz
+    lib.laker_kernel_matvec.argtypes = [P(laker_problem), vp, vp, i32, vp, sz, vp]
+    lib.laker_kernel_matvec.restype = i32
+    lib.laker_fit_precond.argtypes = [P(laker_problem), vp, P(laker_cccp_opts), P(laker_precond), vp, sz,
+                                      P(laker_stats), vp]
+    lib.laker_fit_precond.restype = i32
+    lib.laker_jacobi_precond.argtypes = [P(laker_problem), P(laker_precond), vp]
+    lib.laker_jacobi_precond.restype = i32
+    lib.laker_pcg_solve.argtypes = [P(laker_problem), P(laker_precond), vp, vp, P(laker_pcg_opts), vp, sz,
+                                    P(laker_stats), vp]
+    lib.laker_pcg_solve.restype = i32
+    lib.laker_predict.argtypes = [P(laker_problem), vp, i64, vp, vp, i32, vp, sz, vp]
+    lib.laker_predict.restype = i32
+    lib.laker_status_str.argtypes = [i32]
+    lib.laker_status_str.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def status_str(s: int) -> str:
+    return load().laker_status_str(int(s)).decode()
+
+
+def _check(s: int, where: str, allow=(LAKER_OK,)):
+    if s not in allow:
+        raise LakerError(s, where)
+    return s
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None):
+    return C.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _dev_f64(x, device) -> torch.Tensor:
+    t = torch.as_tensor(x, dtype=torch.float64)
+    return t.to(device).contiguous()
+
+
+_ws: dict = {}
+
+
+def _workspace(name: str, nbytes: int, device) -> torch.Tensor:
+    """Grow-only cached workspace per (device, name)."""
+    key = (str(device), name)
+    t = _ws.get(key)
+    if t is None or t.numel() < nbytes:
+        t = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        _ws[key] = t
+    return t
+
+
+@dataclass
+class Problem:
+    """(lambda I + G) alpha = y with G_ij = exp(scale <e_i, e_j>); E on the device."""
+    E: torch.Tensor
+    lam: float
+    scale: float
+    c: laker_problem = field(init=False)
+
+    def __post_init__(self):
+        on_gpu = isinstance(self.E, torch.Tensor) and self.E.is_cuda
+        self.E = _dev_f64(self.E, self.E.device if on_gpu else torch.device("cuda"))
+        n, d = self.E.shape
+        self.c = laker_problem(n, d, 0, self.E.data_ptr(), float(self.lam), float(self.scale))
+
+    @property
+    def n(self):
+        return self.E.shape[0]
+
+    @property
+    def d(self):
+        return self.E.shape[1]
+
+    @property
+    def device(self):
+        return self.E.device
+
+
+@dataclass
+class Precond:
+    kind: int
+    n: int
+    n_r: int
+    data: torch.Tensor | None
+    c: laker_precond
+    stats: laker_stats | None = None
+
+    @property
+    def header(self) -> torch.Tensor:
+        """Scalars written by the fit: [b^{-1/2}, a, b, cccp_iters, change, db_iters, db_change]."""
+        return self.data[:256].view(torch.float64)[:7].cpu()
+
+
+def none_precond(n: int) -> Precond:
+    return Precond(PRECOND_NONE, n, 0, None, laker_precond(PRECOND_NONE, 0, n, None, 0))
+
+
+def kernel_matvec(prob: Problem, p: torch.Tensor, precision="f64") -> torch.Tensor:
+    lib = load()
+    p = _dev_f64(p, prob.device)
+    w = torch.empty_like(p)
+    nb = lib.laker_solve_workspace_bytes(prob.n, prob.d, 0)
+    ws = _workspace("solve", nb, prob.device)
+    s = lib.laker_kernel_matvec(C.byref(prob.c), _ptr(p), _ptr(w), _PREC[precision], _ptr(ws), ws.numel(), _stream())
+    _check(s, "laker_kernel_matvec")
+    return w
+
+
+def fit_precond(prob: Problem, Z: torch.Tensor, n_r: int | None = None, gamma: float = 0.1, rho: float = 0.0,
+                eps: float = 1e-10, tol: float = 1e-8, max_iter: int = 300, precision="f64") -> Precond:
+    lib = load()
+    Z = _dev_f64(Z, prob.device)
+    nr = Z.shape[1] if n_r is None else n_r
+    pbytes = lib.laker_precond_bytes(prob.n, nr)
+    data = torch.empty(pbytes, dtype=torch.uint8, device=prob.device)
+    pc = laker_precond(PRECOND_CCCP, nr, prob.n, data.data_ptr(), pbytes)
+    opts = laker_cccp_opts(nr, max_iter, gamma, rho, eps, tol, _PREC[precision], 0)
+    nb = lib.laker_fit_workspace_bytes(prob.n, prob.d, nr)
+    ws = _workspace("fit", nb, prob.device)
+    st = laker_stats()
+    s = lib.laker_fit_precond(C.byref(prob.c), _ptr(Z), C.byref(opts), C.byref(pc), _ptr(ws), ws.numel(),
+                              C.byref(st), _stream())
+    _check(s, "laker_fit_precond")
+    return Precond(pc.kind, prob.n, nr, data, pc, st)
+
+
+def jacobi_precond(prob: Problem) -> Precond:
+    lib = load()
+    pbytes = lib.laker_precond_bytes(prob.n, 0)
+    data = torch.empty(pbytes, dtype=torch.uint8, device=prob.device)
+    pc = laker_precond(PRECOND_JACOBI, 0, prob.n, data.data_ptr(), pbytes)
+    _check(lib.laker_jacobi_precond(C.byref(prob.c), C.byref(pc), _stream()), "laker_jacobi_precond")
+    return Precond(pc.kind, prob.n, 0, data, pc)
+
+
+def pcg_solve(prob: Problem, y, precond: Precond | None = None, tol: float = 1e-10, max_iter: int = 10000,
+              precision="f64", refine: bool = False, inner_tol: float = 1e-2, ir_max: int = 64,
+              alpha0: torch.Tensor | None = None, check_every: int = 16, allow_noconv: bool = False):
+    """Returns (alpha, stats)."""
+    lib = load()
+    y = _dev_f64(y, prob.device)
+    if alpha0 is not None:
+        alpha = _dev_f64(alpha0, prob.device).clone()
+    else:
+        alpha = torch.empty_like(y)
+    opts = laker_pcg_opts(tol, max_iter, _PREC[precision], 1 if refine else 0, ir_max, inner_tol,
+                          1 if alpha0 is not None else 0, check_every)
+    nb = lib.laker_solve_workspace_bytes(prob.n, prob.d, 0)
+    ws = _workspace("solve", nb, prob.device)
+    st = laker_stats()
+    pc = None if precond is None else C.byref(precond.c)
+    s = lib.laker_pcg_solve(C.byref(prob.c), pc, _ptr(y), _ptr(alpha), C.byref(opts), _ptr(ws), ws.numel(),
+                            C.byref(st), _stream())
+    _check(s, "laker_pcg_solve", (LAKER_OK, LAKER_ENOCONV) if allow_noconv else (LAKER_OK,))
+    return alpha, st
+
+
+def predict(prob: Problem, alpha: torch.Tensor, Eq, precision="f64") -> torch.Tensor:
+    lib = load()
+    Eq = _dev_f64(Eq, prob.device)
+    alpha = _dev_f64(alpha, prob.device)
+    m = Eq.shape[0]
+    rhat = torch.empty(m, dtype=torch.float64, device=prob.device)
+    nb = lib.laker_solve_workspace_bytes(prob.n, prob.d, m)
+    ws = _workspace("predict", nb, prob.device)
+    s = lib.laker_predict(C.byref(prob.c), _ptr(alpha), m, _ptr(Eq), _ptr(rhat), _PREC[precision], _ptr(ws),
+                          ws.numel(), _stream())
+    _check(s, "laker_predict")
+    return rhat
+
+
+def precond_parts(pc: Precond) -> dict:
+    """Device views of a fitted preconditioner buffer (layout of the library:
+    256-byte aligned header of 32 doubles, then B, Bt in float64, B, Bt in
+    float32, then the Jacobi diagonals)."""
+    def al(x):
+        return (x + 255) & ~255
+    n, nr = pc.n, pc.n_r
+    off = 0
+    out = {}
+    for name, count, dt, es in (("hdr", 32, torch.float64, 8), ("B64", n * nr, torch.float64, 8),
+                                ("Bt64", n * nr, torch.float64, 8), ("B32", n * nr, torch.float32, 4),
+                                ("Bt32", n * nr, torch.float32, 4), ("dinv64", n, torch.float64, 8),
+                                ("dinv32", n, torch.float32, 4)):
+        off = al(off)
+        out[name] = pc.data[off:off + count * es].view(dt)
+        off += count * es
+    out["B64"] = out["B64"].view(n, nr)
+    out["Bt64"] = out["Bt64"].view(n, nr)
+    return out

@@ -1,0 +1,75 @@
+"""Host-side checks of the C ABI: the built library loads without a GPU and
+exports every entry point that include/laker.h declares; size queries and
+argument validation need no device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "laker.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(laker_[a-z0-9_]+)\s*\(", src)))
+
+
+def _lib():
+    from paper_2604_25138_amd import laker
+    if not os.path.exists(laker.LIB_PATH):
+        pytest.skip("liblaker.so not built")
+    return laker, laker.load()
+
+
+def test_header_declarations_match_binding():
+    from paper_2604_25138_amd import laker
+    assert _declared() == sorted(laker.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    laker, lib = _lib()
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_size_queries_and_status_strings():
+    laker, lib = _lib()
+    assert lib.laker_precond_bytes(16384, 512) >= 16384 * 512 * 24
+    assert lib.laker_precond_bytes(0, 4) == 0
+    assert lib.laker_fit_workspace_bytes(512, 16, 91) > 0
+    assert lib.laker_fit_workspace_bytes(512, 200, 91) == 0        # d above the supported maximum
+    assert lib.laker_solve_workspace_bytes(1000, 10, 2025) > lib.laker_solve_workspace_bytes(1000, 10, 0)
+    assert laker.status_str(0) == "ok"
+    assert "invalid" in laker.status_str(-1)
+
+
+def test_invalid_arguments_rejected_before_any_launch():
+    """Validation happens on the host; null or inconsistent arguments return
+    LAKER_EINVAL without touching the device."""
+    laker, lib = _lib()
+    prob = laker.laker_problem(16, 4, 0, None, 1e-2, 0.5)          # E = NULL
+    opts = laker.laker_pcg_opts(1e-8, 10, 0, 0, 1, 1e-2, 0, 16)
+    st = laker.laker_stats()
+    r = lib.laker_pcg_solve(C.byref(prob), None, C.c_void_p(8), C.c_void_p(8), C.byref(opts), C.c_void_p(8),
+                            1 << 30, C.byref(st), None)
+    assert r == laker.LAKER_EINVAL
+    prob = laker.laker_problem(16, 4, 0, 8, -1.0, 0.5)              # lambda <= 0
+    r = lib.laker_kernel_matvec(C.byref(prob), C.c_void_p(8), C.c_void_p(8), 0, C.c_void_p(8), 1 << 30, None)
+    assert r == laker.LAKER_EINVAL
+    prob = laker.laker_problem(16, 4, 0, 8, 1e-2, 0.5)
+    co = laker.laker_cccp_opts(32, 10, 0.1, 0.0, 1e-10, 1e-8, 0, 0)   # n_r > n
+    pc = laker.laker_precond(2, 32, 16, 8, 1 << 30)
+    r = lib.laker_fit_precond(C.byref(prob), C.c_void_p(8), C.byref(co), C.byref(pc), C.c_void_p(8), 1 << 30,
+                              C.byref(st), None)
+    assert r == laker.LAKER_EINVAL
+    co = laker.laker_cccp_opts(8, 10, 0.1, 1.5, 1e-10, 1e-8, 0, 0)    # rho outside [0, 1]
+    r = lib.laker_fit_precond(C.byref(prob), C.c_void_p(8), C.byref(co), C.byref(pc), C.c_void_p(8), 1 << 30,
+                              C.byref(st), None)
+    assert r == laker.LAKER_EINVAL
+    opts = laker.laker_pcg_opts(1e-8, 10, 0, 0, 1, 1e-2, 0, 16)
+    r = lib.laker_pcg_solve(C.byref(prob), None, C.c_void_p(8), C.c_void_p(8), C.byref(opts), C.c_void_p(8),
+                            16, C.byref(st), None)                  # workspace too small
+    assert r == laker.LAKER_ENOMEM

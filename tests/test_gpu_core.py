@@ -1,0 +1,208 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Sizes span several tiles and a ragged tail; the BASELINE-size checks use
+sampled rows the oracle computes one by one.  Tolerances:
+  * float64 products: 1e-13 relative to sum_j |G_ij p_j| + lam |p_i| (FP64
+    rounding of d-term dot products, exp and n-term sums);
+  * float32 products: 2e-5 relative to the same magnitude (float32 inputs
+    rounded once, d-term float32 dot products, exp2 within 2 ulp, and n-term
+    float32 sums split into <= 1024-term chains);
+  * float64 solves: alpha within 1e-10 (relative) of the Cholesky solution when
+    PCG is run to 1e-12.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import laker_oracle as O
+from synth import make_directions, make_problem
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def L():
+    from paper_2604_25138_amd import laker
+    laker.load()
+    return laker
+
+
+def _gp(pr):
+    return L().Problem(torch.tensor(pr.E, device=DEV), pr.lam, pr.scale)
+
+
+def _mag(E, s, lam, p):
+    G = O.kernel_matrix(E, s)
+    return np.abs(G) @ np.abs(p) + lam * np.abs(p)
+
+
+@pytest.mark.parametrize("n,d", [(1, 4), (3, 2), (64, 16), (777, 10), (2048 + 37, 64), (1500, 128)])
+def test_matvec_f64_parity(n, d):
+    pr = make_problem(n, d, 1e-3, seed=n)
+    p = np.random.default_rng(n).normal(size=n)
+    w = L().kernel_matvec(_gp(pr), torch.tensor(p, device=DEV), "f64").cpu().numpy()
+    ref = O.matvec(pr.E, pr.scale, pr.lam, p)
+    err = np.abs(w - ref) / _mag(pr.E, pr.scale, pr.lam, p)
+    assert err.max() <= 1e-13, (n, d, err.max())
+
+
+@pytest.mark.parametrize("n,d", [(3, 2), (777, 10), (2048 + 37, 64)])
+def test_matvec_f32_parity(n, d):
+    pr = make_problem(n, d, 1e-3, seed=n)
+    p = np.random.default_rng(n).normal(size=n)
+    w = L().kernel_matvec(_gp(pr), torch.tensor(p, device=DEV), "f32").cpu().numpy()
+    ref = O.matvec(pr.E, pr.scale, pr.lam, p)
+    err = np.abs(w - ref) / _mag(pr.E, pr.scale, pr.lam, p)
+    assert err.max() <= 2e-5, (n, d, err.max())
+
+
+def test_matvec_zero_embeddings_exact():
+    """E = 0: G = 1 1^T in every precision, w = lam p + (sum p) 1."""
+    n = 1000
+    E = np.zeros((n, 8))
+    p = np.random.default_rng(0).normal(size=n)
+    prob = L().Problem(torch.tensor(E, device=DEV), 0.25, 1.0)
+    for prec, tol in (("f64", 1e-13), ("f32", 1e-5)):
+        w = L().kernel_matvec(prob, torch.tensor(p, device=DEV), prec).cpu().numpy()
+        ref = 0.25 * p + p.sum()
+        assert np.abs(w - ref).max() <= tol * (np.abs(p).sum() + 1), prec
+
+
+def test_matvec_full_size_sampled_rows():
+    """n = 16384, d = 64 (the at-scale configuration): sampled rows against
+    the oracle's one-row evaluation."""
+    pr = make_problem(16384, 64, 1e-4, n_tx=4, seed=0)
+    p = np.random.default_rng(1).normal(size=pr.n)
+    rows = np.random.default_rng(2).choice(pr.n, 64, replace=False)
+    rows = np.r_[rows, [0, pr.n - 1]]
+    ref = O.matvec_rows(pr.E, pr.scale, pr.lam, p, rows)
+    mag = np.array([np.exp(pr.scale * (pr.E @ pr.E[i])) @ np.abs(p) + pr.lam * abs(p[i]) for i in rows])
+    for prec, tol in (("f64", 1e-13), ("f32", 2e-5)):
+        w = L().kernel_matvec(_gp(pr), torch.tensor(p, device=DEV), prec).cpu().numpy()
+        assert (np.abs(w[rows] - ref) / mag).max() <= tol, prec
+
+
+def test_predict_parity_and_example1():
+    pr = make_problem(900, 16, 1e-3, seed=3)
+    alpha = np.random.default_rng(3).normal(size=pr.n)
+    rh = L().predict(_gp(pr), torch.tensor(alpha, device=DEV), pr.Eq, "f64").cpu().numpy()
+    ref = O.predict(pr.Eq, pr.E, pr.scale, alpha)
+    mag = np.abs(O.kernel_matrix(pr.E, pr.scale, Eq=pr.Eq)) @ np.abs(alpha)
+    assert (np.abs(rh - ref) / mag).max() <= 1e-13
+    rh32 = L().predict(_gp(pr), torch.tensor(alpha, device=DEV), pr.Eq, "f32").cpu().numpy()
+    assert (np.abs(rh32 - ref) / mag).max() <= 2e-5
+
+
+def test_example1_solve_and_predict():
+    import json, os
+    ex = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "example1.json")))
+    E, y = np.array(ex["E"]), np.array(ex["y"])
+    prob = L().Problem(torch.tensor(E, device=DEV), ex["lambda"], 1.0)
+    alpha, st = L().pcg_solve(prob, y, None, tol=1e-13, max_iter=50)
+    ref = O.solve_direct(O.system_matrix(E, 1.0, ex["lambda"]), y)
+    assert np.linalg.norm(alpha.cpu().numpy() - ref) <= 1e-12 * np.linalg.norm(ref)
+    r = L().predict(prob, alpha, np.array([ex["e_query"]]))
+    assert abs(r.item() - ex["r_hat_query"]) <= 0.05
+
+
+@pytest.mark.parametrize("kind", ["none", "jacobi"])
+def test_pcg_f64_small_config(kind):
+    """n = 512, d = 16, lam = 1e-3, s = 1/4: alpha within 1e-10 of Cholesky."""
+    pr = make_problem(512, 16, 1e-3, seed=0)
+    prob = _gp(pr)
+    pc = None if kind == "none" else L().jacobi_precond(prob)
+    alpha, st = L().pcg_solve(prob, pr.y, pc, tol=1e-12, max_iter=5000, precision="f64")
+    ref = O.solve_direct(O.system_matrix(pr.E, pr.scale, pr.lam), pr.y)
+    err = np.linalg.norm(alpha.cpu().numpy() - ref) / np.linalg.norm(ref)
+    assert err <= 1e-10, err
+    assert st.relres <= 1e-12 and st.relres_true <= 1e-11
+    # iteration count of the oracle's PCG on the same system (same arithmetic up to rounding)
+    A = O.system_matrix(pr.E, pr.scale, pr.lam)
+    Pj = (lambda v: v) if kind == "none" else (lambda v: v / O.jacobi_diag(pr.E, pr.scale, pr.lam))
+    _, it_o, _ = O.pcg(lambda v: A @ v, Pj, pr.y, 1e-12, 5000)
+    assert abs(st.iters - it_o) <= max(3, it_o // 20)
+
+
+def test_pcg_closed_forms():
+    """E = 0: 2 iterations, Sherman-Morrison alpha; one-hot clusters: 3 iterations."""
+    n, lam = 300, 0.5
+    y = np.random.default_rng(0).normal(-80, 10, n)
+    prob = L().Problem(torch.zeros((n, 4), dtype=torch.float64, device=DEV), lam, 0.25)
+    alpha, st = L().pcg_solve(prob, y, None, tol=1e-12, max_iter=100)
+    closed = y / lam - (y.sum() / (lam * (lam + n))) * np.ones(n)
+    assert st.iters <= 2
+    assert np.linalg.norm(alpha.cpu().numpy() - closed) <= 1e-11 * np.linalg.norm(closed)
+    Q, cval = 5, 1.1
+    E = np.zeros((n, Q))
+    E[np.arange(n), np.arange(n) % Q] = cval
+    prob = L().Problem(torch.tensor(E, device=DEV), 0.2, 1.0)
+    alpha, st = L().pcg_solve(prob, y, None, tol=1e-12, max_iter=100)
+    assert st.iters <= 3
+
+
+def test_cccp_fit_matches_oracle():
+    """Same directions Z: the fitted (a, b), the CCCP iteration count and the
+    operator P = Sigma^{-1/2} agree with the oracle's low-rank CCCP."""
+    pr = make_problem(700, 16, 1e-3, seed=7)
+    nr = 64
+    Z = make_directions(pr.n, nr, 7)
+    prob = _gp(pr)
+    pc = L().fit_precond(prob, torch.tensor(Z, device=DEV), gamma=0.1, rho=0.02, eps=1e-10, tol=1e-10,
+                         max_iter=300)
+    _, Ub = O.random_directions(pr.E, pr.scale, pr.lam, Z)
+    a, b, w, it = O.cccp_lowrank(Ub, 0.1, 0.02, 1e-10, 1e-10, 300)
+    hdr = pc.header.numpy()
+    assert abs(hdr[1] - a) <= 1e-9 * a and abs(hdr[2] - b) <= 1e-9 * b
+    assert abs(pc.stats.cccp_iters - it) <= 1
+    P = O.LowRankPrecond(Ub, a, b, w)
+    parts = L().precond_parts(pc)
+    v = np.random.default_rng(1).normal(size=pr.n)
+    vt = torch.tensor(v, device=DEV)
+    Pv = (parts["hdr"][0] * vt + parts["Bt64"] @ (parts["B64"].T @ vt)).cpu().numpy()
+    ref = P.apply(v)
+    assert np.linalg.norm(Pv - ref) <= 1e-8 * np.linalg.norm(ref)
+    # trace normalisation of Sigma_star: tr = n b + a sum_k w_k ||u_k||^2
+    assert abs(pr.n * hdr[2] + hdr[1] * np.sum(w * np.sum(Ub * Ub, axis=0)) - pr.n) <= 1e-8 * pr.n
+
+
+def test_laker_pcg_f64_matches_direct():
+    """Full method at n = 512: CCCP fit + PCG to 1e-12, alpha within 1e-10."""
+    pr = make_problem(512, 16, 1e-3, seed=0)
+    Z = make_directions(pr.n, 91, 0)
+    prob = _gp(pr)
+    pc = L().fit_precond(prob, torch.tensor(Z, device=DEV), gamma=0.1, rho=0.0)
+    alpha, st = L().pcg_solve(prob, pr.y, pc, tol=1e-12, max_iter=5000)
+    ref = O.solve_direct(O.system_matrix(pr.E, pr.scale, pr.lam), pr.y)
+    assert np.linalg.norm(alpha.cpu().numpy() - ref) / np.linalg.norm(ref) <= 1e-10
+    # oracle PCG with the oracle preconditioner on the same Z
+    Po, _ = O.fit_precond(pr.E, pr.scale, pr.lam, Z, gamma=0.1, rho=0.0)
+    A = O.system_matrix(pr.E, pr.scale, pr.lam)
+    _, it_o, _ = O.pcg(lambda v: A @ v, Po.apply, pr.y, 1e-12, 5000)
+    assert abs(st.iters - it_o) <= max(3, it_o // 20)
+
+
+def test_f32_refinement_reaches_f64_accuracy():
+    pr = make_problem(1000, 16, 1e-3, seed=5)
+    prob = _gp(pr)
+    alpha, st = L().pcg_solve(prob, pr.y, None, tol=1e-11, max_iter=20000, precision="f32", refine=True,
+                              inner_tol=1e-3, ir_max=40)
+    ref = O.solve_direct(O.system_matrix(pr.E, pr.scale, pr.lam), pr.y)
+    assert st.relres_true <= 1e-11
+    assert np.linalg.norm(alpha.cpu().numpy() - ref) / np.linalg.norm(ref) <= 1e-8
+    hist = [st.ir_relres[i] for i in range(st.ir_steps + 1)]
+    assert hist[-1] <= 1e-11 and all(b < a for a, b in zip(hist, hist[1:]))
+
+
+def test_solves_are_deterministic():
+    pr = make_problem(600, 16, 1e-3, seed=9)
+    prob = _gp(pr)
+    a1, s1 = L().pcg_solve(prob, pr.y, None, tol=1e-10, max_iter=5000)
+    a2, s2 = L().pcg_solve(prob, pr.y, None, tol=1e-10, max_iter=5000)
+    assert torch.equal(a1, a2) and s1.iters == s2.iters
+
+
+def test_iteration_cap_returns_enoconv():
+    pr = make_problem(512, 16, 1e-3, seed=0)
+    alpha, st = L().pcg_solve(_gp(pr), pr.y, None, tol=1e-12, max_iter=5, allow_noconv=True)
+    assert st.iters == 5 and st.status == L().LAKER_ENOCONV
