@@ -96,6 +96,8 @@ __global__ __launch_bounds__(256) void gj_pivot_kernel(double* __restrict__ A, i
                                                        double* __restrict__ logdet, int* __restrict__ flag,
                                                        int first) {
   __shared__ double Ps[NB][NB + 1];
+  __shared__ double rowk[NB];
+  __shared__ double colk[NB];
   __shared__ double ld_acc;
   const int tid = threadIdx.x;
   if (flag != nullptr && *flag) return;
@@ -105,30 +107,32 @@ __global__ __launch_bounds__(256) void gj_pivot_kernel(double* __restrict__ A, i
   }
   if (tid == 0) ld_acc = 0.0;
   __syncthreads();
-  // scalar in-place Gauss-Jordan on the nb x nb block
+  // scalar in-place Gauss-Jordan on the nb x nb block: row k is scaled by the
+  // pivot (its column-k entry becoming 1/piv), every other row loses its
+  // multiple of row k (its column-k entry becoming -f/piv).  Row k and column k
+  // are snapshotted first so that no thread reads an entry another thread of
+  // the same step has already replaced.
   for (int k = 0; k < nb; ++k) {
-    double piv = Ps[k][k];
-    __syncthreads();
+    const double piv = Ps[k][k];
+    const double ip = 1.0 / piv;
+    if (tid < nb) {
+      rowk[tid] = (tid == k ? 1.0 : Ps[k][tid]) * ip;
+      colk[tid] = Ps[tid][k];
+    }
     if (tid == 0) {
       if (!(piv > 0.0) || !isfinite(piv)) {
         if (flag) *flag = 1;
       }
       ld_acc += log(piv);
     }
-    const double ip = 1.0 / piv;
-    // row k scaled, with the new column-k entry 1/piv
-    // then every other row eliminated
-    double rowk[NB];
-    for (int c = 0; c < nb; ++c) rowk[c] = (c == k ? 1.0 : Ps[k][c]) * ip;
     __syncthreads();
     for (int idx = tid; idx < nb * nb; idx += 256) {
       int r = idx / nb, c = idx % nb;
       if (r == k) {
         Ps[r][c] = rowk[c];
       } else {
-        double f = Ps[r][k];
         double v = (c == k) ? 0.0 : Ps[r][c];
-        Ps[r][c] = v - f * rowk[c];
+        Ps[r][c] = v - colk[r] * rowk[c];
       }
     }
     __syncthreads();

@@ -143,25 +143,30 @@ def test_pcg_closed_forms():
 
 def test_cccp_fit_matches_oracle():
     """Same directions Z: the fitted (a, b), the CCCP iteration count and the
-    operator P = Sigma^{-1/2} agree with the oracle's low-rank CCCP."""
+    operator P = Sigma^{-1/2} agree with the oracle's low-rank CCCP.
+
+    Tolerance: q_k comes from an SPD solve with kappa(M) up to ~1e7, so each
+    side's q carries ~kappa(M) u ~ 1e-9 relative rounding (LU in the oracle,
+    Gauss-Jordan on the GPU); the fixed-point map amplifies a perturbation by
+    at most 1/(1 - rate) with rate <= 0.99 here, hence 1e-7 on (a, b) and on P v."""
     pr = make_problem(700, 16, 1e-3, seed=7)
     nr = 64
     Z = make_directions(pr.n, nr, 7)
     prob = _gp(pr)
-    pc = L().fit_precond(prob, torch.tensor(Z, device=DEV), gamma=0.1, rho=0.02, eps=1e-10, tol=1e-10,
+    pc = L().fit_precond(prob, torch.tensor(Z, device=DEV), gamma=0.1, rho=0.02, eps=1e-10, tol=1e-9,
                          max_iter=300)
     _, Ub = O.random_directions(pr.E, pr.scale, pr.lam, Z)
-    a, b, w, it = O.cccp_lowrank(Ub, 0.1, 0.02, 1e-10, 1e-10, 300)
+    a, b, w, it = O.cccp_lowrank(Ub, 0.1, 0.02, 1e-10, 1e-9, 300)
     hdr = pc.header.numpy()
-    assert abs(hdr[1] - a) <= 1e-9 * a and abs(hdr[2] - b) <= 1e-9 * b
-    assert abs(pc.stats.cccp_iters - it) <= 1
+    assert abs(hdr[1] - a) <= 1e-7 * a and abs(hdr[2] - b) <= 1e-7 * b
+    assert abs(pc.stats.cccp_iters - it) <= 2
     P = O.LowRankPrecond(Ub, a, b, w)
     parts = L().precond_parts(pc)
     v = np.random.default_rng(1).normal(size=pr.n)
     vt = torch.tensor(v, device=DEV)
     Pv = (parts["hdr"][0] * vt + parts["Bt64"] @ (parts["B64"].T @ vt)).cpu().numpy()
     ref = P.apply(v)
-    assert np.linalg.norm(Pv - ref) <= 1e-8 * np.linalg.norm(ref)
+    assert np.linalg.norm(Pv - ref) <= 1e-7 * np.linalg.norm(ref)
     # trace normalisation of Sigma_star: tr = n b + a sum_k w_k ||u_k||^2
     assert abs(pr.n * hdr[2] + hdr[1] * np.sum(w * np.sum(Ub * Ub, axis=0)) - pr.n) <= 1e-8 * pr.n
 
