@@ -1,0 +1,226 @@
+"""Benchmark of the LAKER solve path on one MI355X.
+
+A step is one full pass of the method over one synthetic map: CCCP
+preconditioner fit (random directions -> shrinkage-CCCP -> Sigma^{-1/2}),
+PCG to a float64 relative residual of 1e-6 (float32 products inside float64
+iterative refinement), and reconstruction on the 45 x 45 grid.  Inputs are
+resident in HBM before the timed region.  Beside the timed product path the
+run reports: the same solve done entirely in float64 (FP64 CCCP-PCG), the
+roofline position of the dominant kernel (the fused kernel product) measured
+with HIP events on the library's stream, and the FP64 CPU oracle timed on a
+bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "solves/s to rel-res 1e-6 (learned+mixed vs FP64 CCCP-PCG); matvec % roofline"
+
+WORKLOADS = {
+    # the at-scale single-map configuration: 16384 sites, 64-d RFF embeddings,
+    # 4 transmitters, lambda = 1e-4, PCG to relative residual 1e-6
+    "n16384_d64": dict(n=16384, d=64, n_tx=4, lam=1e-4, tol=1e-6, seed=0),
+    # small float64 configuration: 512 sites, 16-d embeddings, lambda = 1e-3
+    "n512_d16": dict(n=512, d=16, n_tx=1, lam=1e-3, tol=1e-6, seed=0),
+}
+
+PEAK_FP32_VECTOR_TFLOPS = 157.3
+PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_BF16_MFMA_TFLOPS = 2500.0
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="n16384_d64", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-f64", action="store_true", help="skip the float64 comparison leg")
+    ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work in the CPU sample")
+    ap.add_argument("--precision", default="bf16", choices=["bf16", "f32"],
+                    help="arithmetic of the kernel products inside float64 refinement")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2604_25138_amd import laker as L
+    from synth import default_n_r, make_directions, make_problem
+
+    L.load()
+    wl = WORKLOADS[args.workload]
+    dev = torch.device("cuda:0")
+    pr = make_problem(wl["n"], wl["d"], wl["lam"], n_tx=wl["n_tx"], seed=wl["seed"])
+    nr = default_n_r(pr.n)
+    Z = make_directions(pr.n, nr, wl["seed"])
+    prob = L.Problem(torch.tensor(pr.E, device=dev), pr.lam, pr.scale)
+    y = torch.tensor(pr.y, device=dev)
+    Zd = torch.tensor(Z, device=dev)
+    Eq = torch.tensor(pr.Eq, device=dev)
+    tol = wl["tol"]
+
+    prec = args.precision
+    inner = 1e-1 if prec == "bf16" else 1e-2
+
+    def solve(pc):
+        return L.pcg_solve(prob, y, pc, tol=tol, max_iter=100000, precision=prec, refine=True,
+                           inner_tol=inner, ir_max=64, check_every=32)
+
+    def step():
+        pc = L.fit_precond(prob, Zd, gamma=0.1, rho=0.0)
+        alpha, st = solve(pc)
+        rhat = L.predict(prob, alpha, Eq, precision="f64")
+        return pc, alpha, st, rhat
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for _ in range(args.steps):
+        pc, alpha, st, rhat = step()
+        stats.append((pc.stats.cccp_iters, st.iters, st.ir_steps, st.relres_true))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = 1e3 / ms_per_step
+    rmse = float(torch.sqrt(torch.mean((rhat.cpu() - torch.tensor(pr.r_true)) ** 2)))
+
+    extra = {
+        "cccp_iters": stats[-1][0], "pcg_iters": stats[-1][1], "ir_steps": stats[-1][2],
+        "relres_true": stats[-1][3], "n_r": nr, "map_rmse_db": rmse,
+    }
+
+    # phase times of one step (fit / solve / predict)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    pc = L.fit_precond(prob, Zd, gamma=0.1, rho=0.0)
+    torch.cuda.synchronize()
+    b = time.perf_counter()
+    alpha, st = solve(pc)
+    torch.cuda.synchronize()
+    c = time.perf_counter()
+    L.predict(prob, alpha, Eq, precision="f64")
+    torch.cuda.synchronize()
+    d_ = time.perf_counter()
+    extra["fit_ms"] = (b - a) * 1e3
+    extra["solve_ms"] = (c - b) * 1e3
+    extra["predict_ms"] = (d_ - c) * 1e3
+
+    # float64 CCCP-PCG on the same map (the method with every product in float64)
+    if not args.no_f64:
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        pc64 = L.fit_precond(prob, Zd, gamma=0.1, rho=0.0)
+        al64, st64 = L.pcg_solve(prob, y, pc64, tol=tol, max_iter=100000, precision="f64", check_every=32)
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        extra["f64_cccp_pcg"] = {"solves_per_s": 1.0 / (b - a), "ms_per_solve": (b - a) * 1e3,
+                                 "pcg_iters": st64.iters, "relres_true": st64.relres_true}
+        extra["speedup_vs_f64_cccp_pcg"] = (b - a) * 1e3 / ms_per_step
+
+    # roofline of the dominant kernel (the fused product in the solve's
+    # precision), timed with HIP events on the stream the library launches on;
+    # the float32 and float64 products are timed the same way for reference
+    p = torch.randn(pr.n, dtype=torch.float64, device=dev)
+
+    def time_kmv(pname, reps=20):
+        for _ in range(3):
+            L.kernel_matvec(prob, p, pname)
+        s = torch.cuda.current_stream()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            L.kernel_matvec(prob, p, pname)
+        e1.record(s)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    pairs = float(pr.n) * pr.n
+    flops = (2.0 * pr.d + 2.0) * pairs
+    kms = {q: time_kmv(q) for q in ("bf16", "f32", "f64")}
+    extra["kmv_ms"] = kms
+    extra["kmv_tflops"] = {q: flops / (v * 1e-3) / 1e12 for q, v in kms.items()}
+    extra["kmv_gexp_per_s"] = {q: pairs / (v * 1e-3) / 1e9 for q, v in kms.items()}
+    kname = {"bf16": "kmv32_kernel<BF16,64>", "f32": "kmv32_kernel<F32,64>"}[prec]
+    peak = PEAK_BF16_MFMA_TFLOPS if prec == "bf16" else PEAK_FP32_MFMA_TFLOPS
+    achieved = flops / (kms[prec] * 1e-3) / 1e12
+    roofline = {"kernel": f"{kname} (fused exp(<e_i,e_j>) p product, {prec} scores)",
+                "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": None,
+                "per_launch": {"pairs": pairs, "flops": flops, "ms": kms[prec]}}
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": f"{prec}+f64", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: n={pr.n} d={pr.d} n_tx={wl['n_tx']} lambda={pr.lam} "
+                               f"scale=1/sqrt(d) tol={tol} n_r={nr} gamma=0.1 rho=0",
+                   "path": f"CCCP fit (f64) + PCG with {prec} products inside f64 refinement + predict 45x45"},
+        "roofline": roofline,
+        "extra": extra,
+    }
+
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(pr, Z, tol, extra.get("f64_cccp_pcg", {}).get("pcg_iters"),
+                                           args.cpu_budget)
+    print(json.dumps(out))
+
+
+def cpu_baseline(pr, Z, tol, iters_hint, budget):
+    """The FP64 oracle on the host cores: kernel construction, the CCCP fit, and
+    as many PCG iterations as fit the budget; the solve time is scaled to the
+    iteration count the float64 GPU solve needed on the same map."""
+    import numpy as np
+    from oracle import laker_oracle as O
+    threads = os.cpu_count()
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max((i.get("num_threads", 0) for i in threadpool_info()), default=threads) or threads
+    except Exception:
+        pass
+    t0 = time.perf_counter()
+    A = O.system_matrix(pr.E, pr.scale, pr.lam)
+    t1 = time.perf_counter()
+    P, _ = O.fit_precond(pr.E, pr.scale, pr.lam, Z, gamma=0.1, rho=0.0)
+    t2 = time.perf_counter()
+    # PCG iterations for the remaining budget
+    remaining = max(1.0, budget - (t2 - t0))
+    tm = time.perf_counter()
+    _ = A @ P.apply(pr.y)
+    per_it = time.perf_counter() - tm
+    k = int(max(3, min(200, remaining / max(per_it, 1e-6))))
+    _, it_done, _ = O.pcg(lambda v: A @ v, P.apply, pr.y, tol, k)
+    t3 = time.perf_counter()
+    per_iter = (t3 - t2) / max(it_done, 1)
+    iters = iters_hint if iters_hint else it_done
+    solve_s = (t1 - t0) + (t2 - t1) + per_iter * iters
+    return {"value": 1.0 / solve_s, "unit": "solves/s", "cores": threads, "kind": "oracle",
+            "sample": f"oracle FP64 on n={pr.n}: kernel matrix {t1 - t0:.1f}s + CCCP fit {t2 - t1:.1f}s "
+                      f"(measured) + {it_done} PCG iterations measured at {per_iter * 1e3:.1f} ms each, "
+                      f"scaled to {iters} iterations",
+            "seconds_measured": t3 - t0}
+
+
+if __name__ == "__main__":
+    main()

@@ -107,7 +107,9 @@ typedef struct {
   int32_t precision;  /* laker_precision of the inner products A p             */
   int32_t refine;     /* 1: float64 iterative refinement around an F32/BF16 PCG */
   int32_t ir_max;     /* refinement step cap (<= 64)                            */
-  double inner_tol;   /* inner PCG tolerance per refinement step               */
+  double inner_tol;   /* inner PCG tolerance per refinement step, relative to the
+                         step's residual; raised to 0.5 tol / (current outer
+                         residual) when that is larger                          */
   int32_t warm_start; /* 1: alpha holds the starting iterate alpha^0            */
   int32_t check_every;/* host polls the convergence flag every this many steps  */
 } laker_pcg_opts;

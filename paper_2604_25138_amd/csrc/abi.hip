@@ -28,7 +28,7 @@ Problem to_problem(const laker_problem* p) {
   return q;
 }
 
-bool valid_precision(int32_t prec) { return prec == LAKER_F64 || prec == LAKER_F32; }
+bool valid_precision(int32_t prec) { return prec == LAKER_F64 || prec == LAKER_F32 || prec == LAKER_BF16; }
 
 }  // namespace
 
@@ -43,7 +43,6 @@ PrecondLayout precond_layout(void* base, int64_t n, int nr) {
   L.B32 = c.take<float>((size_t)n * nr);
   L.Bt32 = c.take<float>((size_t)n * nr);
   L.dinv64 = c.take<double>(n);
-  L.dinv32 = c.take<float>(n);
   L.total = c.bytes();
   return L;
 }
@@ -89,16 +88,14 @@ laker_status laker_kernel_matvec(const laker_problem* prob, const double* p, dou
   Problem pb = to_problem(prob);
   hipStream_t st = (hipStream_t)stream;
   KmvPlan pl = kmv_plan(pb.n, pb.n, precision);
-  if (precision == LAKER_F64) {
-    LK_TRY(prep_embed(pb.E, pb.n, pb.d, pb.dp, pb.scale, LAKER_F64, W.e64, st));
-    LK_TRY(kmv_partials(LAKER_F64, pb.dp, W.e64, pb.n, W.e64, pb.n, p, W.part, pl, nullptr, st));
-    LK_TRY(kmv_finish(LAKER_F64, pb.n, pb.lambda, p, W.part, pl.nsplit, w, true, st));
-  } else {
-    LK_TRY(prep_embed(pb.E, pb.n, pb.d, pb.dp, pb.scale, precision, W.e32, st));
-    LK_TRY(convert_vec(p, LAKER_F64, W.vtmp, LAKER_F32, pb.n, st));
-    LK_TRY(kmv_partials(precision, pb.dp, W.e32, pb.n, W.e32, pb.n, W.vtmp, W.part, pl, nullptr, st));
-    LK_TRY(kmv_finish(precision, pb.n, pb.lambda, W.vtmp, W.part, pl.nsplit, w, true, st));
-  }
+  LK_TRY(hipMemsetAsync(W.rb_cnt, 0, sizeof(unsigned) * (pl.rowblocks + 1), st));
+  void* eh = precision == LAKER_F64 ? (void*)W.e64 : (precision == LAKER_F32 ? (void*)W.e32 : (void*)W.e16);
+  LK_TRY(prep_embed(pb.E, pb.n, pb.d, pb.dp, pb.scale, precision, eh, st));
+  KmvArgs A = kmv_args(eh, pb.n, eh, pb.n, p, W);
+  A.lam = pb.lambda;
+  A.pself = p;
+  A.out = w;
+  LK_TRY(kmv_run(precision, pb.dp, pl, A, st));
   return LAKER_OK;
 }
 
@@ -159,11 +156,12 @@ laker_status laker_pcg_solve(const laker_problem* prob, const laker_precond* pre
     PrecondLayout L = precond_layout(precond->data, prob->n, precond->n_r);
     if (precond->bytes < L.total) return LAKER_ENOMEM;
     const bool f64 = opts->precision == LAKER_F64;
+    view.f32 = f64 ? 0 : 1;
     view.kind = precond->kind;
     view.nr = precond->n_r;
     view.c0p = L.hdr;
     if (precond->kind == LAKER_PRECOND_JACOBI) {
-      view.dinv = f64 ? (const void*)L.dinv64 : (const void*)L.dinv32;
+      view.dinv = L.dinv64;
     } else if (precond->kind == LAKER_PRECOND_CCCP || precond->kind == LAKER_PRECOND_LEARNED) {
       if (precond->n_r < 1 || precond->n_r > kMaxNr) return LAKER_EINVAL;
       view.B = f64 ? (const void*)L.B64 : (const void*)L.B32;
@@ -185,9 +183,12 @@ laker_status laker_pcg_solve(const laker_problem* prob, const laker_precond* pre
   const int check = opts->check_every > 0 ? opts->check_every : 16;
   LK_TRY(hipMemsetAsync(W.S, 0, sizeof(PcgScalars), st));
   LK_TRY(hipMemsetAsync(W.cnt, 0, 16 * sizeof(unsigned), st));
+  LK_TRY(hipMemsetAsync(W.rb_cnt, 0, sizeof(unsigned) * (kmv_plan(pb.n, pb.n, LAKER_F64).rowblocks + 1), st));
   LK_TRY(prep_embed(pb.E, pb.n, pb.d, pb.dp, pb.scale, LAKER_F64, W.e64, st));
-  if (opts->precision != LAKER_F64)
-    LK_TRY(prep_embed(pb.E, pb.n, pb.d, pb.dp, pb.scale, opts->precision, W.e32, st));
+  if (opts->precision == LAKER_F32)
+    LK_TRY(prep_embed(pb.E, pb.n, pb.d, pb.dp, pb.scale, LAKER_F32, W.e32, st));
+  else if (opts->precision == LAKER_BF16)
+    LK_TRY(prep_embed(pb.E, pb.n, pb.d, pb.dp, pb.scale, LAKER_BF16, W.e16, st));
   laker_status r;
   if (!opts->refine) {
     r = pcg_run(pb, W, view, y, alpha, opts->warm_start != 0, opts->tol, opts->max_iter, check, opts->precision, sp,
@@ -215,8 +216,13 @@ laker_status laker_pcg_solve(const laker_problem* prob, const laker_precond* pre
         break;
       }
       if (s == opts->ir_max || used >= opts->max_iter) break;
+      // the correction need not be solved more accurately than the outer
+      // tolerance still requires
+      double itol = opts->inner_tol;
+      const double need = 0.5 * opts->tol / rel;
+      if (need > itol) itol = need;
       laker_stats inner{};
-      laker_status ri = pcg_run(pb, W, view, W.rout, W.dalpha, false, opts->inner_tol, opts->max_iter - used, check,
+      laker_status ri = pcg_run(pb, W, view, W.rout, W.dalpha, false, itol, opts->max_iter - used, check,
                                 opts->precision, &inner, st);
       used += inner.iters;
       sp->iters = used;
@@ -241,18 +247,15 @@ laker_status laker_predict(const laker_problem* prob, const double* alpha, int64
   Problem pb = to_problem(prob);
   hipStream_t st = (hipStream_t)stream;
   KmvPlan pl = kmv_plan(m, pb.n, precision);
-  if (precision == LAKER_F64) {
-    LK_TRY(prep_embed(pb.E, pb.n, pb.d, pb.dp, pb.scale, LAKER_F64, W.e64, st));
-    LK_TRY(prep_embed(Eq, m, pb.d, pb.dp, pb.scale, LAKER_F64, W.q64, st));
-    LK_TRY(kmv_partials(LAKER_F64, pb.dp, W.q64, m, W.e64, pb.n, alpha, W.part, pl, nullptr, st));
-    LK_TRY(kmv_finish(LAKER_F64, m, 0.0, nullptr, W.part, pl.nsplit, rhat, true, st));
-  } else {
-    LK_TRY(prep_embed(pb.E, pb.n, pb.d, pb.dp, pb.scale, precision, W.e32, st));
-    LK_TRY(prep_embed(Eq, m, pb.d, pb.dp, pb.scale, precision, W.q32, st));
-    LK_TRY(convert_vec(alpha, LAKER_F64, W.vtmp, LAKER_F32, pb.n, st));
-    LK_TRY(kmv_partials(precision, pb.dp, W.q32, m, W.e32, pb.n, W.vtmp, W.part, pl, nullptr, st));
-    LK_TRY(kmv_finish(precision, m, 0.0, nullptr, W.part, pl.nsplit, rhat, true, st));
-  }
+  LK_TRY(hipMemsetAsync(W.rb_cnt, 0, sizeof(unsigned) * (pl.rowblocks + 1), st));
+  void* eh = precision == LAKER_F64 ? (void*)W.e64 : (precision == LAKER_F32 ? (void*)W.e32 : (void*)W.e16);
+  void* qh = precision == LAKER_F64 ? (void*)W.q64 : (precision == LAKER_F32 ? (void*)W.q32 : (void*)W.q16);
+  LK_TRY(prep_embed(pb.E, pb.n, pb.d, pb.dp, pb.scale, precision, eh, st));
+  LK_TRY(prep_embed(Eq, m, pb.d, pb.dp, pb.scale, precision, qh, st));
+  KmvArgs A = kmv_args(qh, m, eh, pb.n, alpha, W);
+  A.lam = 0.0;
+  A.out = rhat;
+  LK_TRY(kmv_run(precision, pb.dp, pl, A, st));
   return LAKER_OK;
 }
 

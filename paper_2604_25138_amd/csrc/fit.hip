@@ -329,13 +329,12 @@ __global__ void write_header_kernel(const CccpState* __restrict__ S, double* __r
 
 // Jacobi: dinv_i = 1 / (lambda + exp(s <e_i, e_i>)).
 __global__ void jacobi_kernel(const double* __restrict__ E, int64_t n, int d, double s, double lam,
-                              double* __restrict__ d64, float* __restrict__ d32) {
+                              double* __restrict__ d64) {
   for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
     double acc = 0.0;
     for (int c = 0; c < d; ++c) acc = fma(E[i * d + c], E[i * d + c], acc);
     double v = 1.0 / (lam + exp(s * acc));
     d64[i] = v;
-    d32[i] = (float)v;
   }
 }
 
@@ -513,7 +512,7 @@ laker_status fit_cccp(const Problem& pb, const double* Z, const laker_cccp_opts&
 }
 
 laker_status fit_jacobi(const Problem& pb, const PrecondLayout& L, hipStream_t st) {
-  jacobi_kernel<<<ew_grid(pb.n), kT, 0, st>>>(pb.E, pb.n, pb.d, pb.scale, pb.lambda, L.dinv64, L.dinv32);
+  jacobi_kernel<<<ew_grid(pb.n), kT, 0, st>>>(pb.E, pb.n, pb.d, pb.scale, pb.lambda, L.dinv64);
   LK_CHECK_LAUNCH();
   return LAKER_OK;
 }

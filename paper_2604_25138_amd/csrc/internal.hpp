@@ -17,27 +17,38 @@ size_t embed_bytes(int64_t rows, int dp, int prec);
 hipError_t prep_embed(const double* E, int64_t rows, int d, int dp, double scale, int prec,
                       void* out, hipStream_t st);
 
-// Column split of the fused product: how many column ranges, and their width.
+constexpr int kMaxSplit = 64;   // largest number of column ranges of one product
+
+// Row blocks x column ranges of one product.
 struct KmvPlan {
   int nsplit;
   int64_t cols_per_split;
+  int rowblocks;
 };
 KmvPlan kmv_plan(int64_t m, int64_t n, int prec);
+int kmv_rows_per_block(int prec);
 
-// part[s * m + i] = sum_{j in split s} exp(<q_i, k_j>) * p_j   (F64)
-//                 = sum_{j in split s} exp2(<q_i, k_j>) * p_j  (F32/BF16)
-// p and part are in the vector type of the precision (double for F64, float otherwise).
-hipError_t kmv_partials(int prec, int dp, const void* Q, int64_t m, const void* K, int64_t n,
-                        const void* p, void* part, const KmvPlan& plan, const int* done,
-                        hipStream_t st);
-
-// w_i = lam * p_i + sum_s part[s * m + i]   (vector type of the precision; w may be double)
-hipError_t kmv_finish(int prec, int64_t m, double lam, const void* p, const void* part, int nsplit,
-                      void* w, bool w_double, hipStream_t st);
-
-// float64 <-> vector-type conversions
-hipError_t convert_vec(const void* src, int src_prec, void* dst, int dst_prec, int64_t n,
-                       hipStream_t st);
+// One fused product  out_i = lam * pself_i + sum_j exp(<q_i, k_j>) p_j  (exp2 for
+// the float32 / bfloat16 prepared copies).  All vectors are float64; the
+// products exp(.) p_j are accumulated in float64 in every precision.
+struct KmvArgs {
+  const void* Q;        // prepared query rows (m x dp)
+  int64_t m;
+  const void* K;        // prepared key rows (n x dp)
+  int64_t n;
+  const double* p;      // vector over the key rows
+  double* part;         // nsplit x m column-range partials
+  int64_t cps;          // filled by kmv_run
+  int nsplit;           // filled by kmv_run
+  int mode;             // 0: partials only; 1: finished output; 2: output + PCG step size
+  double lam;           // lambda (0 for the rectangular product)
+  const double* pself;  // vector over the output rows for lam * p and p^T A p; null: none
+  double* out;          // output vector
+  unsigned* rb_cnt;     // per-row-block tickets, zero between uses
+  double* rbpart;       // per-row-block p^T A p partials (mode 2)
+  PcgScalars* S;        // PCG scalars (mode 2); when set, the launch is skipped once S->done
+};
+hipError_t kmv_run(int prec, int dp, const KmvPlan& pl, KmvArgs A, hipStream_t st);
 
 // ---- multi right-hand-side product and the fit (fit.hip) ----
 

@@ -1,12 +1,24 @@
 // Fused attention-kernel product  w = (lambda I + G) p  with G_ij = exp(s <e_i, e_j>)
-// formed tile by tile and never stored (Sec. IV-D remark; Alg. 1 step size and
-// residual update).  Also the rectangular query-by-site product of the map
-// reconstruction (eq. sc-radio-map-reconstruction).
+// formed tile by tile on the matrix cores and never stored (Sec. IV-D remark;
+// Alg. 1 step size and residual update).  The same kernel computes the
+// rectangular query-by-site product of the map reconstruction
+// (eq. sc-radio-map-reconstruction).
 //
-// Layout: prepared embeddings are row-major, rows padded with zero columns to
-// dp in {16, 32, 64, 128}; zero columns leave every inner product unchanged.
-// A launch covers (row block) x (column split); each split writes its partial
-// sums, and a second pass adds the splits in a fixed order.
+// Layout: prepared embeddings are row-major with rows padded by zero columns to
+// dp in {16, 32, 64, 128} (zero columns leave every inner product unchanged).
+// float32 / bfloat16 copies are pre-scaled by sqrt(s log2 e) so that the MFMA
+// output is directly the exp2 argument; float64 copies by sqrt(s) (exp).
+//
+// Work split: a wave owns 32 rows (16 for float64) and sweeps the key tiles of
+// one column range; a block holds four waves.  The score tile S = Q K^T comes
+// from MFMA (32x32x2 f32, 32x32x16 bf16, 16x16x4 f64); each lane then applies
+// exp to its S entries and accumulates exp(S) p_j into per-row partial sums,
+// which are combined across lanes once at the end.  Column ranges write
+// partial sums; the last block of each row block to finish (atomic ticket)
+// adds them in a fixed order, applies lambda p, and -- inside PCG -- forms
+// p^T A p and the step size with a second ticket over row blocks.
+#include <type_traits>
+
 #include "internal.hpp"
 
 namespace lk {
@@ -15,8 +27,13 @@ namespace {
 
 constexpr double kLog2e = 1.4426950408889634074;
 
-__global__ void prep_embed_f64_kernel(const double* __restrict__ E, int64_t rows, int d, int dp,
-                                      double c, double* __restrict__ out) {
+typedef float v16f __attribute__((ext_vector_type(16)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__global__ void prep_embed_f64_kernel(const double* __restrict__ E, int64_t rows, int d, int dp, double c,
+                                      double* __restrict__ out) {
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= rows * dp) return;
   int64_t i = idx / dp;
@@ -24,8 +41,8 @@ __global__ void prep_embed_f64_kernel(const double* __restrict__ E, int64_t rows
   out[idx] = col < d ? c * E[i * d + col] : 0.0;
 }
 
-__global__ void prep_embed_f32_kernel(const double* __restrict__ E, int64_t rows, int d, int dp,
-                                      double c, float* __restrict__ out) {
+__global__ void prep_embed_f32_kernel(const double* __restrict__ E, int64_t rows, int d, int dp, double c,
+                                      float* __restrict__ out) {
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= rows * dp) return;
   int64_t i = idx / dp;
@@ -33,7 +50,7 @@ __global__ void prep_embed_f32_kernel(const double* __restrict__ E, int64_t rows
   out[idx] = col < d ? __double2float_rn(c * E[i * d + col]) : 0.0f;
 }
 
-// bfloat16 by round-to-nearest-even from the float32 value (NaN-free inputs).
+// bfloat16 by round-to-nearest-even from the float32 value (finite inputs).
 __device__ __forceinline__ uint16_t f32_to_bf16_rne(float x) {
   uint32_t u = __float_as_uint(x);
   uint32_t lsb = (u >> 16) & 1u;
@@ -41,8 +58,8 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float x) {
   return (uint16_t)(u >> 16);
 }
 
-__global__ void prep_embed_bf16_kernel(const double* __restrict__ E, int64_t rows, int d, int dp,
-                                       double c, uint16_t* __restrict__ out) {
+__global__ void prep_embed_bf16_kernel(const double* __restrict__ E, int64_t rows, int d, int dp, double c,
+                                       uint16_t* __restrict__ out) {
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= rows * dp) return;
   int64_t i = idx / dp;
@@ -50,84 +67,374 @@ __global__ void prep_embed_bf16_kernel(const double* __restrict__ E, int64_t row
   out[idx] = col < d ? f32_to_bf16_rne(__double2float_rn(c * E[i * d + col])) : (uint16_t)0;
 }
 
-__device__ __forceinline__ double kexp(double x) { return exp(x); }
-__device__ __forceinline__ float kexp(float x) { return __builtin_amdgcn_exp2f(x); }
-
-// One thread per output row; key tiles of 64 rows staged in LDS and read as
-// broadcasts.  Used for float64 (and as the float32 product before MFMA).
-template <typename T, int DP>
-__global__ __launch_bounds__(256) void kmv_valu_kernel(const T* __restrict__ Q, int64_t m,
-                                                       const T* __restrict__ K, int64_t n,
-                                                       const T* __restrict__ p, T* __restrict__ part,
-                                                       int64_t cps, const int* __restrict__ done) {
-  if (done != nullptr && *done) return;
-  constexpr int BN = 64;
-  __shared__ T ks[BN * DP];
-  __shared__ T ps[BN];
-  const int tid = threadIdx.x;
-  const int64_t i = (int64_t)blockIdx.x * 256 + tid;
-  T q[DP];
-  if (i < m) {
+// ---------------------------------------------------------------------------
+// Fragments.  For an MFMA step kk the lane (c, h) -- c = lane % T, h = lane / T
+// with T = 32 (16 for f64) -- supplies k-index  h * (dp / H) + (k within step),
+// H = 64 / T.  Any assignment of k to steps is valid as long as the Q and K
+// fragments use the same one; this one makes each lane's share of a row one
+// contiguous run of dp / H elements.
+// ---------------------------------------------------------------------------
+template <int DP>
+struct FragF32 {
+  float v[DP / 2];
+  __device__ __forceinline__ void load(const float* __restrict__ base, int64_t row, int h) {
+    const float4* src = reinterpret_cast<const float4*>(base + row * DP + h * (DP / 2));
 #pragma unroll
-    for (int c = 0; c < DP; ++c) q[c] = Q[i * DP + c];
-  } else {
-#pragma unroll
-    for (int c = 0; c < DP; ++c) q[c] = T(0);
-  }
-  const int64_t j0 = (int64_t)blockIdx.y * cps;
-  const int64_t j1 = j0 + cps < n ? j0 + cps : n;
-  T acc = T(0);
-  for (int64_t jt = j0; jt < j1; jt += BN) {
-    __syncthreads();
-    const int64_t base = jt * DP;
-    const int64_t lim = (j1 - jt) * DP;
-    for (int idx = tid; idx < BN * DP; idx += 256) ks[idx] = idx < lim ? K[base + idx] : T(0);
-    if (tid < BN) ps[tid] = (jt + tid < j1) ? p[jt + tid] : T(0);
-    __syncthreads();
-    for (int jj = 0; jj < BN; ++jj) {
-      T sc = T(0);
-#pragma unroll
-      for (int c = 0; c < DP; ++c) sc = fma(q[c], ks[jj * DP + c], sc);
-      acc = fma(kexp(sc), ps[jj], acc);
+    for (int q = 0; q < DP / 8; ++q) {
+      float4 t = src[q];
+      v[4 * q + 0] = t.x;
+      v[4 * q + 1] = t.y;
+      v[4 * q + 2] = t.z;
+      v[4 * q + 3] = t.w;
     }
   }
-  if (i < m) part[(int64_t)blockIdx.y * m + i] = acc;
+};
+
+template <int DP>
+__device__ __forceinline__ v16f tile_f32(const FragF32<DP>& a, const FragF32<DP>& b) {
+  v16f c = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int kk = 0; kk < DP / 2; ++kk) c = __builtin_amdgcn_mfma_f32_32x32x2f32(a.v[kk], b.v[kk], c, 0, 0, 0);
+  return c;
 }
 
-template <typename T, typename W>
-__global__ void kmv_finish_kernel(int64_t m, T lam, const T* __restrict__ p, const T* __restrict__ part,
-                                  int nsplit, W* __restrict__ w) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    T s = T(0);
-    for (int k = 0; k < nsplit; ++k) s += part[(int64_t)k * m + i];
-    w[i] = (W)(p != nullptr ? fma(lam, p[i], s) : s);
+template <int DP>
+struct FragBF16 {
+  v8bf v[DP / 16];
+  __device__ __forceinline__ void load(const uint16_t* __restrict__ base, int64_t row, int h) {
+    const u32x4* src = reinterpret_cast<const u32x4*>(base + row * DP + h * (DP / 2));
+#pragma unroll
+    for (int q = 0; q < DP / 16; ++q) {
+      u32x4 t = src[q];
+      v[q] = __builtin_bit_cast(v8bf, t);
+    }
+  }
+};
+
+template <int DP>
+__device__ __forceinline__ v16f tile_bf16(const FragBF16<DP>& a, const FragBF16<DP>& b) {
+  v16f c = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int kk = 0; kk < DP / 16; ++kk) c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.v[kk], b.v[kk], c, 0, 0, 0);
+  return c;
+}
+
+template <int DP>
+struct FragF64 {
+  double v[DP / 4];
+  __device__ __forceinline__ void load(const double* __restrict__ base, int64_t row, int h) {
+    const double2* src = reinterpret_cast<const double2*>(base + row * DP + h * (DP / 4));
+#pragma unroll
+    for (int q = 0; q < DP / 8; ++q) {
+      double2 t = src[q];
+      v[2 * q + 0] = t.x;
+      v[2 * q + 1] = t.y;
+    }
+  }
+};
+
+template <int DP>
+__device__ __forceinline__ v4d tile_f64(const FragF64<DP>& a, const FragF64<DP>& b) {
+  v4d c = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int kk = 0; kk < DP / 4; ++kk) c = __builtin_amdgcn_mfma_f64_16x16x4f64(a.v[kk], b.v[kk], c, 0, 0, 0);
+  return c;
+}
+
+// ---------------------------------------------------------------------------
+// Epilogue: fixed-order sum of the column-range partials of one row block.
+// ---------------------------------------------------------------------------
+__device__ bool kmv_epilogue(const KmvArgs& A, int64_t rb0, int rows_per_block) {
+  __shared__ int s_last;
+  __shared__ double sh[16];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    unsigned t = __hip_atomic_fetch_add(&A.rb_cnt[blockIdx.x], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    s_last = (t == gridDim.y - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  if (!s_last) return false;
+  __threadfence();
+  if (threadIdx.x == 0) A.rb_cnt[blockIdx.x] = 0;
+  double dot = 0.0;
+  for (int t = threadIdx.x; t < rows_per_block; t += blockDim.x) {
+    const int64_t row = rb0 + t;
+    if (row >= A.m) break;
+    double s = 0.0;
+    for (int sp = 0; sp < A.nsplit; ++sp) s += __builtin_nontemporal_load(A.part + (int64_t)sp * A.m + row);
+    double w = s;
+    if (A.pself != nullptr) {
+      const double pv = A.pself[row];
+      w = fma(A.lam, pv, s);
+      dot += pv * w;
+    }
+    A.out[row] = w;
+  }
+  if (A.mode == 2) {
+    dot = block_sum(dot, sh);
+    if (threadIdx.x == 0) A.rbpart[blockIdx.x] = dot;
+  }
+  return true;
+}
+
+// Second-level ticket over row blocks (PCG): p^T A p and the step size.
+__device__ void kmv_pcg_finish(const KmvArgs& A) {
+  __shared__ int s_last2;
+  __shared__ double sh2[16];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    unsigned t = __hip_atomic_fetch_add(&A.S->cnt[1], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    s_last2 = (t == gridDim.x - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  if (!s_last2) return;
+  __threadfence();
+  double pap = ordered_sum(A.rbpart, gridDim.x, sh2);
+  if (threadIdx.x == 0) {
+    PcgScalars* S = A.S;
+    S->pap = pap;
+    double dl = S->rz / pap;
+    S->delta = dl;
+    if (!(pap > 0.0) || !isfinite(dl)) S->done = 2;
+    S->cnt[1] = 0;
   }
 }
 
-template <typename S, typename D>
-__global__ void convert_kernel(const S* __restrict__ src, D* __restrict__ dst, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    dst[i] = (D)src[i];
+__device__ __forceinline__ float kexp2(float x) { return __builtin_amdgcn_exp2f(x); }
+
+// ---------------------------------------------------------------------------
+// float32 / bfloat16 kernel: 32x32 score tiles.
+//
+// The key rows of a column range are staged through LDS in stages of KT rows,
+// double-buffered and shared by the block's four waves: the global loads of
+// stage s + 1 are issued before stage s is consumed and written to LDS after
+// it, with one barrier per stage.  LDS rows are padded by 16 bytes so that the
+// 16-byte fragment reads of 32 consecutive rows fall in distinct banks.
+// ---------------------------------------------------------------------------
+template <int PREC, int DP>
+struct Stage32 {
+  using ET = typename std::conditional<PREC == LAKER_F32, float, uint16_t>::type;
+  static constexpr int ES = (int)sizeof(ET);
+  static constexpr int ROWB = DP * ES;                               // bytes of one key row
+  static constexpr int KT0 = 16384 / ROWB;
+  static constexpr int KT = KT0 > 128 ? 128 : KT0;                   // key rows per stage
+  static constexpr int PITCH = ROWB + 16;                            // padded LDS row pitch
+  static constexpr int CHUNKS = KT * ROWB / 16;                      // 16-byte chunks per stage
+  static constexpr int PER_T = (CHUNKS + 255) / 256;                 // chunks per thread
+  static constexpr int BYTES = KT * PITCH + KT * 8;                  // rows + weights
+};
+
+template <int PREC, int DP>
+__global__ __launch_bounds__(256) void kmv32_kernel(KmvArgs A) {
+  using St = Stage32<PREC, DP>;
+  using ET = typename St::ET;
+  using Frag = typename std::conditional<PREC == LAKER_F32, FragF32<DP>, FragBF16<DP>>::type;
+  constexpr int KT = St::KT;
+  __shared__ __attribute__((aligned(16))) unsigned char lds[2][St::BYTES];
+  if (A.S != nullptr && A.S->done) return;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int h = lane >> 5, c = lane & 31;
+  const int64_t rb0 = (int64_t)blockIdx.x * 128;
+  const int64_t row0 = rb0 + wv * 32;
+  const int64_t j0 = (int64_t)blockIdx.y * A.cps;
+  const int64_t j1 = j0 + A.cps < A.n ? j0 + A.cps : A.n;
+  const double* __restrict__ p = A.p;
+  const ET* __restrict__ Q = reinterpret_cast<const ET*>(A.Q);
+  const unsigned char* __restrict__ Kb = reinterpret_cast<const unsigned char*>(A.K);
+  Frag a;
+  {
+    int64_t qi = row0 + c;
+    if (qi > A.m - 1) qi = A.m - 1;
+    a.load(Q, qi, h);
+  }
+  double acc[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.0;
+
+  const int nstages = (int)((j1 - j0 + KT - 1) / KT);
+  u32x4 stg[St::PER_T];
+  double stp = 0.0;
+  // global -> registers for the stage starting at key row js (rows clamped to n - 1,
+  // weights zero past the column range)
+  auto fetch = [&](int64_t js) {
+#pragma unroll
+    for (int q = 0; q < St::PER_T; ++q) {
+      const int ch = tid + 256 * q;
+      if (St::CHUNKS % 256 == 0 || ch < St::CHUNKS) {
+        const int rr = ch / (St::ROWB / 16);
+        const int cc = ch - rr * (St::ROWB / 16);
+        int64_t kr = js + rr;
+        if (kr > A.n - 1) kr = A.n - 1;
+        stg[q] = *reinterpret_cast<const u32x4*>(Kb + kr * St::ROWB + cc * 16);
+      }
+    }
+    // every thread loads (clamped index) so that no branch separates the loads;
+    // weights past the column range are masked when they are used
+    const int64_t kj = js + (tid % KT);
+    stp = p[kj < A.n ? kj : A.n - 1];
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < St::PER_T; ++q) {
+      const int ch = tid + 256 * q;
+      if (St::CHUNKS % 256 == 0 || ch < St::CHUNKS) {
+        const int rr = ch / (St::ROWB / 16);
+        const int cc = ch - rr * (St::ROWB / 16);
+        *reinterpret_cast<u32x4*>(&lds[buf][rr * St::PITCH + cc * 16]) = stg[q];
+      }
+    }
+    if (tid < KT) reinterpret_cast<double*>(&lds[buf][KT * St::PITCH])[tid] = stp;
+  };
+  // Pipeline: at the top of iteration s the registers hold stage s + 1; they
+  // are written to the free LDS buffer, the loads of stage s + 2 are issued,
+  // stage s is consumed, and one barrier both publishes stage s + 1 and
+  // releases the buffer of stage s.
+  if (nstages > 0) {
+    fetch(j0);
+    store(0);
+    if (nstages > 1) fetch(j0 + KT);
+    __syncthreads();
+  }
+  for (int sidx = 0; sidx < nstages; ++sidx) {
+    const int buf = sidx & 1;
+    if (sidx + 1 < nstages) store(buf ^ 1);
+    if (sidx + 2 < nstages) fetch(j0 + (int64_t)(sidx + 2) * KT);
+    const unsigned char* base = lds[buf];
+    const double* pw = reinterpret_cast<const double*>(base + KT * St::PITCH);
+#pragma unroll
+    for (int u = 0; u < KT / 32; ++u) {
+      Frag b;
+      const unsigned char* rowp = base + (u * 32 + c) * St::PITCH + h * (St::ROWB / 2);
+      if constexpr (PREC == LAKER_F32) {
+#pragma unroll
+        for (int q = 0; q < DP / 8; ++q) {
+          const float4 t = *reinterpret_cast<const float4*>(rowp + 16 * q);
+          b.v[4 * q + 0] = t.x;
+          b.v[4 * q + 1] = t.y;
+          b.v[4 * q + 2] = t.z;
+          b.v[4 * q + 3] = t.w;
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < DP / 16; ++q) b.v[q] = __builtin_bit_cast(v8bf, *reinterpret_cast<const u32x4*>(rowp + 16 * q));
+      }
+      const double pv = (j0 + (int64_t)sidx * KT + u * 32 + c < j1) ? pw[u * 32 + c] : 0.0;
+      v16f sc;
+      if constexpr (PREC == LAKER_F32) sc = tile_f32<DP>(a, b);
+      else sc = tile_bf16<DP>(a, b);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[r] = fma((double)kexp2(sc[r]), pv, acc[r]);
+    }
+    __syncthreads();
+  }
+  // sum over the 32 lanes of each half (the key columns of the tiles)
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    double v = acc[r];
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    v += __shfl_xor(v, 4, 64);
+    v += __shfl_xor(v, 8, 64);
+    v += __shfl_xor(v, 16, 64);
+    acc[r] = v;
+  }
+  double* __restrict__ part = A.part;
+  if (c < 16) {
+    double v = 0.0;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v = (r == c) ? acc[r] : v;
+    const int64_t row = row0 + (c >> 2) * 8 + h * 4 + (c & 3);
+    if (row < A.m) part[(int64_t)blockIdx.y * A.m + row] = v;
+  }
+  if (A.mode == 0) return;
+  if (kmv_epilogue(A, rb0, 128) && A.mode == 2) kmv_pcg_finish(A);
 }
 
-inline int grid_for(int64_t n, int block) {
-  int64_t g = (n + block - 1) / block;
-  if (g > 4096) g = 4096;
-  if (g < 1) g = 1;
-  return (int)g;
+// ---------------------------------------------------------------------------
+// float64 kernel: 16x16 score tiles, exp in float64.
+// ---------------------------------------------------------------------------
+template <int DP>
+__global__ __launch_bounds__(256) void kmv64_kernel(KmvArgs A) {
+  if (A.S != nullptr && A.S->done) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int h = lane >> 4, c = lane & 15;
+  const int64_t rb0 = (int64_t)blockIdx.x * 64;
+  const int64_t row0 = rb0 + wv * 16;
+  const int64_t j0 = (int64_t)blockIdx.y * A.cps;
+  const int64_t j1 = j0 + A.cps < A.n ? j0 + A.cps : A.n;
+  const double* __restrict__ p = A.p;
+  const double* __restrict__ Q = reinterpret_cast<const double*>(A.Q);
+  const double* __restrict__ K = reinterpret_cast<const double*>(A.K);
+  FragF64<DP> a, b, bn;
+  {
+    int64_t qi = row0 + c;
+    if (qi > A.m - 1) qi = A.m - 1;
+    a.load(Q, qi, h);
+  }
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (j0 < j1) {
+    int64_t kj = j0 + c;
+    double pj = kj < j1 ? p[kj] : 0.0;
+    if (kj > A.n - 1) kj = A.n - 1;
+    b.load(K, kj, h);
+    for (int64_t jt = j0; jt < j1; jt += 16) {
+      const int64_t jn = jt + 16;
+      double pn = 0.0;
+      if (jn < j1) {
+        int64_t kn = jn + c;
+        pn = kn < j1 ? p[kn] : 0.0;
+        if (kn > A.n - 1) kn = A.n - 1;
+        bn.load(K, kn, h);
+      }
+      v4d s = tile_f64<DP>(a, b);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[r] = fma(exp(s[r]), pj, acc[r]);
+      b = bn;
+      pj = pn;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    double v = acc[r];
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    v += __shfl_xor(v, 4, 64);
+    v += __shfl_xor(v, 8, 64);
+    acc[r] = v;
+  }
+  double* __restrict__ part = A.part;
+  if (c < 4) {
+    double v = 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v = (r == c) ? acc[r] : v;
+    const int64_t row = row0 + 4 * c + h;   // 16x16x4 f64 output: register r holds row 4 r + lane / 16
+    if (row < A.m) part[(int64_t)blockIdx.y * A.m + row] = v;
+  }
+  if (A.mode == 0) return;
+  if (kmv_epilogue(A, rb0, 64) && A.mode == 2) kmv_pcg_finish(A);
 }
 
-template <typename T>
-hipError_t launch_valu(int dp, const T* Q, int64_t m, const T* K, int64_t n, const T* p, T* part,
-                       const KmvPlan& plan, const int* done, hipStream_t st) {
-  dim3 grid((unsigned)((m + 255) / 256), (unsigned)plan.nsplit);
+template <int PREC>
+hipError_t launch32(int dp, dim3 grid, const KmvArgs& A, hipStream_t st) {
   switch (dp) {
-    case 16: kmv_valu_kernel<T, 16><<<grid, 256, 0, st>>>(Q, m, K, n, p, part, plan.cols_per_split, done); break;
-    case 32: kmv_valu_kernel<T, 32><<<grid, 256, 0, st>>>(Q, m, K, n, p, part, plan.cols_per_split, done); break;
-    case 64: kmv_valu_kernel<T, 64><<<grid, 256, 0, st>>>(Q, m, K, n, p, part, plan.cols_per_split, done); break;
-    case 128: kmv_valu_kernel<T, 128><<<grid, 256, 0, st>>>(Q, m, K, n, p, part, plan.cols_per_split, done); break;
+    case 16: kmv32_kernel<PREC, 16><<<grid, 256, 0, st>>>(A); break;
+    case 32: kmv32_kernel<PREC, 32><<<grid, 256, 0, st>>>(A); break;
+    case 64: kmv32_kernel<PREC, 64><<<grid, 256, 0, st>>>(A); break;
+    case 128: kmv32_kernel<PREC, 128><<<grid, 256, 0, st>>>(A); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch64(int dp, dim3 grid, const KmvArgs& A, hipStream_t st) {
+  switch (dp) {
+    case 16: kmv64_kernel<16><<<grid, 256, 0, st>>>(A); break;
+    case 32: kmv64_kernel<32><<<grid, 256, 0, st>>>(A); break;
+    case 64: kmv64_kernel<64><<<grid, 256, 0, st>>>(A); break;
+    case 128: kmv64_kernel<128><<<grid, 256, 0, st>>>(A); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -155,57 +462,34 @@ hipError_t prep_embed(const double* E, int64_t rows, int d, int dp, double scale
   return hipGetLastError();
 }
 
+int kmv_rows_per_block(int prec) { return prec == LAKER_F64 ? 64 : 128; }
+
 KmvPlan kmv_plan(int64_t m, int64_t n, int prec) {
-  (void)prec;
-  const int64_t rowblocks = (m + 255) / 256;
-  const int64_t coltiles = (n + 63) / 64;
+  const int rpb = kmv_rows_per_block(prec);
+  const int tile = prec == LAKER_F64 ? 16 : 32;
+  const int64_t rowblocks = (m + rpb - 1) / rpb;
+  const int64_t coltiles = (n + tile - 1) / tile;
+  // aim for ~8192 waves (32 per CU) across row blocks x column ranges
   int64_t ns = (2048 + rowblocks - 1) / rowblocks;
   if (ns > coltiles) ns = coltiles;
-  if (ns > 64) ns = 64;
+  if (ns > kMaxSplit) ns = kMaxSplit;
   if (ns < 1) ns = 1;
-  int64_t cps = ((coltiles + ns - 1) / ns) * 64;
+  int64_t cps = ((coltiles + ns - 1) / ns) * tile;
   KmvPlan pl;
   pl.cols_per_split = cps;
   pl.nsplit = (int)((n + cps - 1) / cps);
   if (pl.nsplit < 1) pl.nsplit = 1;
+  pl.rowblocks = (int)rowblocks;
   return pl;
 }
 
-hipError_t kmv_partials(int prec, int dp, const void* Q, int64_t m, const void* K, int64_t n, const void* p,
-                        void* part, const KmvPlan& plan, const int* done, hipStream_t st) {
-  if (prec == LAKER_F64)
-    return launch_valu<double>(dp, (const double*)Q, m, (const double*)K, n, (const double*)p,
-                               (double*)part, plan, done, st);
-  if (prec == LAKER_F32)
-    return launch_valu<float>(dp, (const float*)Q, m, (const float*)K, n, (const float*)p, (float*)part,
-                              plan, done, st);
-  return hipErrorInvalidValue;
-}
-
-hipError_t kmv_finish(int prec, int64_t m, double lam, const void* p, const void* part, int nsplit, void* w,
-                      bool w_double, hipStream_t st) {
-  const int g = grid_for(m, 256);
-  if (prec == LAKER_F64) {
-    kmv_finish_kernel<double, double><<<g, 256, 0, st>>>(m, lam, (const double*)p, (const double*)part,
-                                                         nsplit, (double*)w);
-  } else if (w_double) {
-    kmv_finish_kernel<float, double><<<g, 256, 0, st>>>(m, (float)lam, (const float*)p, (const float*)part,
-                                                        nsplit, (double*)w);
-  } else {
-    kmv_finish_kernel<float, float><<<g, 256, 0, st>>>(m, (float)lam, (const float*)p, (const float*)part,
-                                                       nsplit, (float*)w);
-  }
-  return hipGetLastError();
-}
-
-hipError_t convert_vec(const void* src, int src_prec, void* dst, int dst_prec, int64_t n, hipStream_t st) {
-  const int g = grid_for(n, 256);
-  const bool sd = src_prec == LAKER_F64, dd = dst_prec == LAKER_F64;
-  if (sd && dd) convert_kernel<double, double><<<g, 256, 0, st>>>((const double*)src, (double*)dst, n);
-  else if (sd) convert_kernel<double, float><<<g, 256, 0, st>>>((const double*)src, (float*)dst, n);
-  else if (dd) convert_kernel<float, double><<<g, 256, 0, st>>>((const float*)src, (double*)dst, n);
-  else convert_kernel<float, float><<<g, 256, 0, st>>>((const float*)src, (float*)dst, n);
-  return hipGetLastError();
+hipError_t kmv_run(int prec, int dp, const KmvPlan& pl, KmvArgs A, hipStream_t st) {
+  A.cps = pl.cols_per_split;
+  A.nsplit = pl.nsplit;
+  dim3 grid((unsigned)pl.rowblocks, (unsigned)pl.nsplit);
+  if (prec == LAKER_F64) return launch64(dp, grid, A, st);
+  if (prec == LAKER_F32) return launch32<LAKER_F32>(dp, grid, A, st);
+  return launch32<LAKER_BF16>(dp, grid, A, st);
 }
 
 }  // namespace lk

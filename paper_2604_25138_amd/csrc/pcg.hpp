@@ -14,7 +14,7 @@ struct Problem {
   const double* E;
 };
 
-// Carved solve workspace.  Vectors are sized for float64 and reused as float32.
+// Carved solve workspace.
 struct SolveWs {
   double* e64;
   float* e32;
@@ -22,12 +22,13 @@ struct SolveWs {
   double* q64;
   float* q32;
   uint16_t* q16;
-  double* part;     // column-split partials, up to 64 x max(n, m)
+  double* part;     // column-range partials, up to kMaxSplit x max(n, m)
+  unsigned* rb_cnt; // per-row-block tickets of the fused product
+  double* rbpart;   // per-row-block partials of p^T A p
   double* r;
   double* p;
   double* ap;
   double* theta;
-  double* vtmp;
   double* w64;
   double* rout;
   double* dalpha;
@@ -40,6 +41,8 @@ struct SolveWs {
   size_t total;
 };
 SolveWs plan_solve_ws(void* base, int64_t n, int d, int64_t m);
+KmvArgs kmv_args(const void* Q, int64_t m, const void* K, int64_t n, const double* p, const SolveWs& ws);
+const void* prepared(const SolveWs& ws, int prec);
 
 // Preconditioner as the solver sees it, in one vector precision.
 //   CCCP / learned:  theta = c0 r + Bt (B^T r)   (B, Bt: n x nr row-major)
@@ -51,11 +54,12 @@ struct PrecondView {
   const void* B;
   const void* Bt;
   const void* dinv;
+  int f32;             // B, Bt stored as float32 (products still accumulated in float64)
 };
 
 // Layout of the preconditioner buffer (all offsets 256-byte aligned):
 //   header (32 doubles: [0] = b^{-1/2}, [1] = a, [2] = b, [3] = CCCP iterations, ...),
-//   B64, Bt64 (n x nr float64), B32, Bt32 (n x nr float32), dinv64 (n), dinv32 (n).
+//   B64, Bt64 (n x nr float64), B32, Bt32 (n x nr float32), dinv64 (n).
 struct PrecondLayout {
   double* hdr;
   double* B64;
@@ -63,7 +67,6 @@ struct PrecondLayout {
   float* B32;
   float* Bt32;
   double* dinv64;
-  float* dinv32;
   size_t total;
 };
 PrecondLayout precond_layout(void* base, int64_t n, int nr);

@@ -257,7 +257,7 @@ def predict(prob: Problem, alpha: torch.Tensor, Eq, precision="f64") -> torch.Te
 def precond_parts(pc: Precond) -> dict:
     """Device views of a fitted preconditioner buffer (layout of the library:
     256-byte aligned header of 32 doubles, then B, Bt in float64, B, Bt in
-    float32, then the Jacobi diagonals)."""
+    float32, then the Jacobi diagonal)."""
     def al(x):
         return (x + 255) & ~255
     n, nr = pc.n, pc.n_r
@@ -265,8 +265,7 @@ def precond_parts(pc: Precond) -> dict:
     out = {}
     for name, count, dt, es in (("hdr", 32, torch.float64, 8), ("B64", n * nr, torch.float64, 8),
                                 ("Bt64", n * nr, torch.float64, 8), ("B32", n * nr, torch.float32, 4),
-                                ("Bt32", n * nr, torch.float32, 4), ("dinv64", n, torch.float64, 8),
-                                ("dinv32", n, torch.float32, 4)):
+                                ("Bt32", n * nr, torch.float32, 4), ("dinv64", n, torch.float64, 8)):
         off = al(off)
         out[name] = pc.data[off:off + count * es].view(dt)
         off += count * es
