@@ -86,7 +86,7 @@ def main():
                            inner_tol=inner, ir_max=64, check_every=32)
 
     def step():
-        pc = L.fit_precond(prob, Zd, gamma=0.1, rho=0.0)
+        pc = L.fit_precond(prob, Zd, gamma=0.1, rho=0.0, precision=prec)
         alpha, st = solve(pc)
         rhat = L.predict(prob, alpha, Eq, precision="f64")
         return pc, alpha, st, rhat
@@ -113,7 +113,7 @@ def main():
     # phase times of one step (fit / solve / predict)
     torch.cuda.synchronize()
     a = time.perf_counter()
-    pc = L.fit_precond(prob, Zd, gamma=0.1, rho=0.0)
+    pc = L.fit_precond(prob, Zd, gamma=0.1, rho=0.0, precision=prec)
     torch.cuda.synchronize()
     b = time.perf_counter()
     alpha, st = solve(pc)
@@ -176,7 +176,8 @@ def main():
         "vs_baseline": None, "dtype": f"{prec}+f64", "data": "synthetic",
         "config": {"workload": f"{args.workload}: n={pr.n} d={pr.d} n_tx={wl['n_tx']} lambda={pr.lam} "
                                f"scale=1/sqrt(d) tol={tol} n_r={nr} gamma=0.1 rho=0",
-                   "path": f"CCCP fit (f64) + PCG with {prec} products inside f64 refinement + predict 45x45"},
+                   "path": f"CCCP fit ({prec} directions, f64 CCCP) + PCG with {prec} products inside f64 "
+                           f"refinement + predict 45x45"},
         "roofline": roofline,
         "extra": extra,
     }

@@ -38,10 +38,11 @@ PrecondLayout precond_layout(void* base, int64_t n, int nr) {
   WsCarver c(base);
   PrecondLayout L;
   L.hdr = c.take<double>(32);
-  L.B64 = c.take<double>((size_t)n * nr);
-  L.Bt64 = c.take<double>((size_t)n * nr);
-  L.B32 = c.take<float>((size_t)n * nr);
-  L.Bt32 = c.take<float>((size_t)n * nr);
+  const int nrp = pad_nr(nr);
+  L.B64 = c.take<double>((size_t)n * nrp);
+  L.Bt64 = c.take<double>((size_t)n * nrp);
+  L.B32 = c.take<float>((size_t)n * nrp);
+  L.Bt32 = c.take<float>((size_t)n * nrp);
   L.dinv64 = c.take<double>(n);
   L.total = c.bytes();
   return L;
@@ -88,7 +89,6 @@ laker_status laker_kernel_matvec(const laker_problem* prob, const double* p, dou
   Problem pb = to_problem(prob);
   hipStream_t st = (hipStream_t)stream;
   KmvPlan pl = kmv_plan(pb.n, pb.n, precision);
-  LK_TRY(hipMemsetAsync(W.rb_cnt, 0, sizeof(unsigned) * (pl.rowblocks + 1), st));
   void* eh = precision == LAKER_F64 ? (void*)W.e64 : (precision == LAKER_F32 ? (void*)W.e32 : (void*)W.e16);
   LK_TRY(prep_embed(pb.E, pb.n, pb.d, pb.dp, pb.scale, precision, eh, st));
   KmvArgs A = kmv_args(eh, pb.n, eh, pb.n, p, W);
@@ -111,7 +111,7 @@ laker_status laker_fit_precond(const laker_problem* prob, const double* Z, const
   if (!(opts->gamma >= 0.0) || !isfinite(opts->gamma)) return LAKER_EINVAL;
   if (!(opts->rho >= 0.0 && opts->rho <= 1.0)) return LAKER_EINVAL;
   if (!finite_pos(opts->eps) || !(opts->tol >= 0.0) || opts->max_iter < 1) return LAKER_EINVAL;
-  if (opts->precision != LAKER_F64) return LAKER_EINVAL;
+  if (!valid_precision(opts->precision)) return LAKER_EINVAL;
   FitWs W = plan_fit_ws(workspace, prob->n, prob->d, nr);
   if (workspace_bytes < W.total) return LAKER_ENOMEM;
   PrecondLayout L = precond_layout(out->data, prob->n, nr);
@@ -159,6 +159,7 @@ laker_status laker_pcg_solve(const laker_problem* prob, const laker_precond* pre
     view.f32 = f64 ? 0 : 1;
     view.kind = precond->kind;
     view.nr = precond->n_r;
+    view.nrp = pad_nr(precond->n_r);
     view.c0p = L.hdr;
     if (precond->kind == LAKER_PRECOND_JACOBI) {
       view.dinv = L.dinv64;
@@ -183,7 +184,6 @@ laker_status laker_pcg_solve(const laker_problem* prob, const laker_precond* pre
   const int check = opts->check_every > 0 ? opts->check_every : 16;
   LK_TRY(hipMemsetAsync(W.S, 0, sizeof(PcgScalars), st));
   LK_TRY(hipMemsetAsync(W.cnt, 0, 16 * sizeof(unsigned), st));
-  LK_TRY(hipMemsetAsync(W.rb_cnt, 0, sizeof(unsigned) * (kmv_plan(pb.n, pb.n, LAKER_F64).rowblocks + 1), st));
   LK_TRY(prep_embed(pb.E, pb.n, pb.d, pb.dp, pb.scale, LAKER_F64, W.e64, st));
   if (opts->precision == LAKER_F32)
     LK_TRY(prep_embed(pb.E, pb.n, pb.d, pb.dp, pb.scale, LAKER_F32, W.e32, st));
@@ -247,7 +247,6 @@ laker_status laker_predict(const laker_problem* prob, const double* alpha, int64
   Problem pb = to_problem(prob);
   hipStream_t st = (hipStream_t)stream;
   KmvPlan pl = kmv_plan(m, pb.n, precision);
-  LK_TRY(hipMemsetAsync(W.rb_cnt, 0, sizeof(unsigned) * (pl.rowblocks + 1), st));
   void* eh = precision == LAKER_F64 ? (void*)W.e64 : (precision == LAKER_F32 ? (void*)W.e32 : (void*)W.e16);
   void* qh = precision == LAKER_F64 ? (void*)W.q64 : (precision == LAKER_F32 ? (void*)W.q32 : (void*)W.q16);
   LK_TRY(prep_embed(pb.E, pb.n, pb.d, pb.dp, pb.scale, precision, eh, st));

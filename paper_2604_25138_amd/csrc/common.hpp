@@ -27,14 +27,13 @@ constexpr int kMaxD = 128;           // largest embedding dimension
 // at once when it is set, so the host can enqueue a chunk of iterations ahead
 // of its convergence check.
 struct PcgScalars {
-  double rz;        // r^T theta of the current iterate
+  double rzbuf[2];  // r^T theta of iteration k in slot k & 1 (read and written by different launches)
   double pap;       // p^T A p
   double delta;     // step size
   double beta;      // conjugation coefficient
   double rr;        // ||r||^2 (recursive residual)
   double yy;        // ||y||^2 of the right-hand side
   double tol2;      // tol^2 * ||y||^2
-  double c0;        // scalar part of the preconditioner (b^{-1/2} for low rank)
   int iters;
   int max_iter;
   int done;         // 0 running, 1 converged, 2 breakdown, 3 iteration cap

@@ -87,25 +87,31 @@ __global__ void gemm_reduce_kernel(int64_t M, int64_t N, const double* __restric
 
 constexpr int NB = 32;   // Gauss-Jordan pivot block
 
-// Pivot step of blocked Gauss-Jordan on block column kb:
+// Pivot step of blocked Gauss-Jordan on block column K = [k0, k0 + nb):
 //   Pinv = A_KK^{-1} (scalar GJ in LDS; log det accumulated),
 //   Rh[r][j] = (Pinv A_K,:)[r][j] for j outside K, Pinv[r][j - k0] inside K,
 //   Cp[i][r] = A[i][k0 + r] (old column panel).
-__global__ __launch_bounds__(256) void gj_pivot_kernel(double* __restrict__ A, int64_t N, int64_t lda, int64_t k0,
-                                                       int nb, double* __restrict__ Rh, double* __restrict__ Cp,
-                                                       double* __restrict__ logdet, int* __restrict__ flag,
-                                                       int first) {
+// Every block inverts the small pivot block itself (identically) and then
+// produces its own 64 columns of Rh and 64 rows of Cp; block 0 records log det.
+__global__ __launch_bounds__(256) void gj_pivot_kernel(const double* __restrict__ A, int64_t N, int64_t lda,
+                                                       int64_t k0, int nb, double* __restrict__ Rh,
+                                                       double* __restrict__ Cp, double* __restrict__ logdet,
+                                                       int* __restrict__ flag, int first) {
   __shared__ double Ps[NB][NB + 1];
   __shared__ double rowk[NB];
   __shared__ double colk[NB];
   __shared__ double ld_acc;
+  __shared__ int bad;
   const int tid = threadIdx.x;
   if (flag != nullptr && *flag) return;
   for (int idx = tid; idx < nb * nb; idx += 256) {
     int r = idx / nb, c = idx % nb;
     Ps[r][c] = A[(k0 + r) * lda + k0 + c];
   }
-  if (tid == 0) ld_acc = 0.0;
+  if (tid == 0) {
+    ld_acc = 0.0;
+    bad = 0;
+  }
   __syncthreads();
   // scalar in-place Gauss-Jordan on the nb x nb block: row k is scaled by the
   // pivot (its column-k entry becoming 1/piv), every other row loses its
@@ -120,9 +126,7 @@ __global__ __launch_bounds__(256) void gj_pivot_kernel(double* __restrict__ A, i
       colk[tid] = Ps[tid][k];
     }
     if (tid == 0) {
-      if (!(piv > 0.0) || !isfinite(piv)) {
-        if (flag) *flag = 1;
-      }
+      if (!(piv > 0.0) || !isfinite(piv)) bad = 1;
       ld_acc += log(piv);
     }
     __syncthreads();
@@ -137,24 +141,39 @@ __global__ __launch_bounds__(256) void gj_pivot_kernel(double* __restrict__ A, i
     }
     __syncthreads();
   }
-  if (tid == 0) logdet[0] = (first ? 0.0 : logdet[0]) + ld_acc;
-  // Rh = Pinv * A[K, :]  (outside K), Pinv (inside K)
-  for (int64_t idx = tid; idx < (int64_t)nb * N; idx += 256) {
-    int r = (int)(idx / N);
-    int64_t j = idx - (int64_t)r * N;
+  if (blockIdx.x == 0 && tid == 0) {
+    logdet[0] = (first ? 0.0 : logdet[0]) + ld_acc;
+    if (bad && flag != nullptr) *flag = 1;
+  }
+  // this block's 64 columns of Rh = Pinv * A[K, :] (outside K), Pinv (inside K);
+  // the nb x 64 slab of A[K, :] is staged in LDS first
+  __shared__ double As[NB][64 + 1];
+  const int64_t c0 = (int64_t)blockIdx.x * 64;
+  for (int idx = tid; idx < nb * 64; idx += 256) {
+    const int r = idx / 64;
+    const int64_t j = c0 + (idx % 64);
+    As[r][idx % 64] = j < N ? A[(k0 + r) * lda + j] : 0.0;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < nb * 64; idx += 256) {
+    const int r = idx / 64;
+    const int jl = idx % 64;
+    const int64_t j = c0 + jl;
+    if (j >= N) continue;
     double v;
     if (j >= k0 && j < k0 + nb) {
       v = Ps[r][j - k0];
     } else {
       v = 0.0;
-      for (int c = 0; c < nb; ++c) v = fma(Ps[r][c], A[(k0 + c) * lda + j], v);
+      for (int c = 0; c < nb; ++c) v = fma(Ps[r][c], As[c][jl], v);
     }
     Rh[(int64_t)r * N + j] = v;
   }
-  for (int64_t idx = tid; idx < N * (int64_t)nb; idx += 256) {
-    int64_t i = idx / nb;
-    int c = (int)(idx - i * nb);
-    Cp[i * NB + c] = A[i * lda + k0 + c];
+  // and its 64 rows of the old column panel
+  for (int idx = tid; idx < 64 * nb; idx += 256) {
+    const int64_t i = c0 + idx / nb;
+    const int c = idx % nb;
+    if (i < N) Cp[i * NB + c] = A[i * lda + k0 + c];
   }
 }
 
@@ -244,7 +263,8 @@ hipError_t spd_inverse_inplace(double* A, int64_t N, double* side, double* logde
   dim3 grid((unsigned)((N + TB - 1) / TB), (unsigned)((N + TB - 1) / TB));
   for (int64_t k0 = 0; k0 < N; k0 += NB) {
     int nb = (int)(N - k0 < NB ? N - k0 : NB);
-    gj_pivot_kernel<<<1, 256, 0, st>>>(A, N, N, k0, nb, Rh, Cp, logdet, flag, k0 == 0 ? 1 : 0);
+    gj_pivot_kernel<<<(unsigned)((N + 63) / 64), 256, 0, st>>>(A, N, N, k0, nb, Rh, Cp, logdet, flag,
+                                                               k0 == 0 ? 1 : 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     gj_update_kernel<<<grid, 256, 0, st>>>(A, N, N, k0, nb, Rh, Cp, flag);

@@ -15,6 +15,7 @@
 #include "fit.hpp"
 
 #include "dense.hpp"
+#include "mrhs.hpp"
 
 namespace lk {
 
@@ -244,14 +245,15 @@ __global__ void cccp_init_kernel(CccpState* S, double* w, int nr) {
   }
 }
 
-// B = sqrt(a) U_bar diag(sqrt(w))  (n x nr)
+// B = sqrt(a) U_bar diag(sqrt(w))  (n x nr, stored with row stride nrp, zero padding)
 __global__ void make_b_kernel(const double* __restrict__ Ub, const double* __restrict__ w,
-                              const CccpState* __restrict__ S, double* __restrict__ B, int64_t n, int nr) {
+                              const CccpState* __restrict__ S, double* __restrict__ B, int64_t n, int nr, int nrp) {
   const double sa = sqrt(S->a);
-  const int64_t total = n * nr;
+  const int64_t total = n * nrp;
   for (int64_t idx = (int64_t)blockIdx.x * kT + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * kT) {
-    int k = (int)(idx % nr);
-    B[idx] = sa * Ub[idx] * sqrt(w[k]);
+    const int64_t i = idx / nrp;
+    const int k = (int)(idx - i * nrp);
+    B[idx] = k < nr ? sa * Ub[i * nr + k] * sqrt(w[k]) : 0.0;
   }
 }
 
@@ -377,6 +379,8 @@ FitWs plan_fit_ws(void* base, int64_t n, int d, int nr) {
   FitWs w;
   const int dp = pad_dim(d);
   w.e64 = c.take<double>((size_t)n * dp);
+  w.elow = c.take<float>((size_t)n * dp);
+  w.zlow = c.take<unsigned char>(mrhs_z_bytes(n, nr));
   w.part_cap = mrhs_partial_cap(n, nr);
   w.part = c.take<double>((size_t)w.part_cap);
   w.U = c.take<double>((size_t)n * nr);
@@ -404,10 +408,9 @@ laker_status fit_cccp(const Problem& pb, const double* Z, const laker_cccp_opts&
                       const PrecondLayout& L, laker_stats* stats, hipStream_t st) {
   const int64_t n = pb.n;
   const int nr = o.n_r;
-  // 1. prepared embeddings (sqrt(s) e, float64)
-  LK_TRY(prep_embed(pb.E, n, pb.d, pb.dp, pb.scale, LAKER_F64, ws.e64, st));
-  // 2. U = (lambda I + G) Z
-  {
+  // 1-2. U = (lambda I + G) Z: float64 tiles, or float32 / bfloat16 MFMA tiles
+  if (o.precision == LAKER_F64) {
+    LK_TRY(prep_embed(pb.E, n, pb.d, pb.dp, pb.scale, LAKER_F64, ws.e64, st));
     const int64_t rowtiles = (n + 63) / 64, coltiles = (nr + 63) / 64;
     int64_t ns = (1024 + rowtiles * coltiles - 1) / (rowtiles * coltiles);
     int64_t jt = (n + 31) / 32;
@@ -420,6 +423,9 @@ laker_status fit_cccp(const Problem& pb, const double* Z, const laker_cccp_opts&
     LK_TRY(launch_mrhs(pb.dp, ws.e64, n, Z, nr, ws.part, (int)ns, cps, st));
     mrhs_finish_kernel<<<ew_grid(n * nr), kT, 0, st>>>(ws.part, (int)ns, Z, pb.lambda, n * nr, ws.U);
     LK_CHECK_LAUNCH();
+  } else {
+    LK_TRY(prep_embed(pb.E, n, pb.d, pb.dp, pb.scale, o.precision, ws.elow, st));
+    LK_TRY(mrhs_mfma(o.precision, pb.dp, ws.elow, n, Z, ws.zlow, nr, pb.lambda, ws.U, st));
   }
   // 3. U_bar = U / ||U||  (column-wise)
   {
@@ -462,7 +468,8 @@ laker_status fit_cccp(const Problem& pb, const double* Z, const laker_cccp_opts&
   if (hs.done == 2) return LAKER_EBREAKDOWN;
   if (stats) stats->cccp_iters = hs.iters;
   // 6. B and R = b I + B^T B; Denman-Beavers for R^{1/2} (Y) and R^{-1/2} (Zm)
-  make_b_kernel<<<ew_grid(n * nr), kT, 0, st>>>(ws.U, ws.w, ws.S, L.B64, n, nr);
+  const int nrp = pad_nr(nr);
+  make_b_kernel<<<ew_grid(n * nrp), kT, 0, st>>>(ws.U, ws.w, ws.S, L.B64, n, nr, nrp);
   LK_CHECK_LAUNCH();
   db_init_kernel<<<ew_grid((int64_t)nr * nr), kT, 0, st>>>(ws.C, ws.w, ws.S, ws.Y, ws.Zm, nr);
   LK_CHECK_LAUNCH();
@@ -499,11 +506,12 @@ laker_status fit_cccp(const Problem& pb, const double* Z, const laker_cccp_opts&
   // 8. Bt = B Gs; float32 copies
   {
     int ns = gemm_pick_split(n, nr, nr, ws.part_cap);
-    LK_TRY(gemm_f64(n, nr, nr, L.B64, nr, 1, ws.Gs, nr, 1, L.Bt64, nr, 1.0, nullptr, 0.0, ws.part, ns, st));
+    LK_TRY(hipMemsetAsync(L.Bt64, 0, sizeof(double) * n * nrp, st));
+    LK_TRY(gemm_f64(n, nr, nr, L.B64, nrp, 1, ws.Gs, nr, 1, L.Bt64, nrp, 1.0, nullptr, 0.0, ws.part, ns, st));
   }
-  to_f32_kernel<<<ew_grid(n * nr), kT, 0, st>>>(L.B64, L.B32, n * nr);
+  to_f32_kernel<<<ew_grid(n * nrp), kT, 0, st>>>(L.B64, L.B32, n * nrp);
   LK_CHECK_LAUNCH();
-  to_f32_kernel<<<ew_grid(n * nr), kT, 0, st>>>(L.Bt64, L.Bt32, n * nr);
+  to_f32_kernel<<<ew_grid(n * nrp), kT, 0, st>>>(L.Bt64, L.Bt32, n * nrp);
   LK_CHECK_LAUNCH();
   LK_TRY(hipMemcpyAsync(&hs, ws.S, sizeof(hs), hipMemcpyDeviceToHost, st));
   LK_TRY(hipStreamSynchronize(st));

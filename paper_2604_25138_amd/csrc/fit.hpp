@@ -15,6 +15,8 @@ struct CccpState {
 
 struct FitWs {
   double* e64;
+  float* elow;            // float32 / bfloat16 prepared embeddings
+  unsigned char* zlow;    // float32 / bfloat16 copy of Z
   double* part;
   int64_t part_cap;
   double* U;

@@ -40,13 +40,11 @@ struct KmvArgs {
   double* part;         // nsplit x m column-range partials
   int64_t cps;          // filled by kmv_run
   int nsplit;           // filled by kmv_run
-  int mode;             // 0: partials only; 1: finished output; 2: output + PCG step size
+  int mode;             // 0: partials only; 1: finished output
   double lam;           // lambda (0 for the rectangular product)
-  const double* pself;  // vector over the output rows for lam * p and p^T A p; null: none
-  double* out;          // output vector
-  unsigned* rb_cnt;     // per-row-block tickets, zero between uses
-  double* rbpart;       // per-row-block p^T A p partials (mode 2)
-  PcgScalars* S;        // PCG scalars (mode 2); when set, the launch is skipped once S->done
+  const double* pself;  // vector over the output rows for lam * pself; null: none
+  double* out;          // output vector (mode 1)
+  PcgScalars* S;        // when set, the launch is skipped once S->done
 };
 hipError_t kmv_run(int prec, int dp, const KmvPlan& pl, KmvArgs A, hipStream_t st);
 

@@ -14,9 +14,8 @@
 // from MFMA (32x32x2 f32, 32x32x16 bf16, 16x16x4 f64); each lane then applies
 // exp to its S entries and accumulates exp(S) p_j into per-row partial sums,
 // which are combined across lanes once at the end.  Column ranges write
-// partial sums; the last block of each row block to finish (atomic ticket)
-// adds them in a fixed order, applies lambda p, and -- inside PCG -- forms
-// p^T A p and the step size with a second ticket over row blocks.
+// partial sums; a following pass adds them in a fixed order and applies
+// lambda p (inside PCG that pass also forms the p^T A p partials).
 #include <type_traits>
 
 #include "internal.hpp"
@@ -142,63 +141,18 @@ __device__ __forceinline__ v4d tile_f64(const FragF64<DP>& a, const FragF64<DP>&
 }
 
 // ---------------------------------------------------------------------------
-// Epilogue: fixed-order sum of the column-range partials of one row block.
+// Finish: out_i = lam * pself_i + sum_s part[s][i], the column ranges added in a
+// fixed order.  A separate launch: completing a reduction inside the product
+// with per-block atomic tickets serializes ~40 ns of fence and atomic per
+// block, more than this pass costs.
 // ---------------------------------------------------------------------------
-__device__ bool kmv_epilogue(const KmvArgs& A, int64_t rb0, int rows_per_block) {
-  __shared__ int s_last;
-  __shared__ double sh[16];
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    unsigned t = __hip_atomic_fetch_add(&A.rb_cnt[blockIdx.x], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    s_last = (t == gridDim.y - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  if (!s_last) return false;
-  __threadfence();
-  if (threadIdx.x == 0) A.rb_cnt[blockIdx.x] = 0;
-  double dot = 0.0;
-  for (int t = threadIdx.x; t < rows_per_block; t += blockDim.x) {
-    const int64_t row = rb0 + t;
-    if (row >= A.m) break;
+__global__ __launch_bounds__(256) void kmv_finish_kernel(const double* __restrict__ part, int nsplit, int64_t m,
+                                                         double lam, const double* __restrict__ pself,
+                                                         double* __restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < m; i += (int64_t)gridDim.x * 256) {
     double s = 0.0;
-    for (int sp = 0; sp < A.nsplit; ++sp) s += __builtin_nontemporal_load(A.part + (int64_t)sp * A.m + row);
-    double w = s;
-    if (A.pself != nullptr) {
-      const double pv = A.pself[row];
-      w = fma(A.lam, pv, s);
-      dot += pv * w;
-    }
-    A.out[row] = w;
-  }
-  if (A.mode == 2) {
-    dot = block_sum(dot, sh);
-    if (threadIdx.x == 0) A.rbpart[blockIdx.x] = dot;
-  }
-  return true;
-}
-
-// Second-level ticket over row blocks (PCG): p^T A p and the step size.
-__device__ void kmv_pcg_finish(const KmvArgs& A) {
-  __shared__ int s_last2;
-  __shared__ double sh2[16];
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    unsigned t = __hip_atomic_fetch_add(&A.S->cnt[1], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    s_last2 = (t == gridDim.x - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  if (!s_last2) return;
-  __threadfence();
-  double pap = ordered_sum(A.rbpart, gridDim.x, sh2);
-  if (threadIdx.x == 0) {
-    PcgScalars* S = A.S;
-    S->pap = pap;
-    double dl = S->rz / pap;
-    S->delta = dl;
-    if (!(pap > 0.0) || !isfinite(dl)) S->done = 2;
-    S->cnt[1] = 0;
+    for (int sp = 0; sp < nsplit; ++sp) s += part[(int64_t)sp * m + i];
+    out[i] = pself != nullptr ? fma(lam, pself[i], s) : s;
   }
 }
 
@@ -349,8 +303,6 @@ __global__ __launch_bounds__(256) void kmv32_kernel(KmvArgs A) {
     const int64_t row = row0 + (c >> 2) * 8 + h * 4 + (c & 3);
     if (row < A.m) part[(int64_t)blockIdx.y * A.m + row] = v;
   }
-  if (A.mode == 0) return;
-  if (kmv_epilogue(A, rb0, 128) && A.mode == 2) kmv_pcg_finish(A);
 }
 
 // ---------------------------------------------------------------------------
@@ -413,8 +365,6 @@ __global__ __launch_bounds__(256) void kmv64_kernel(KmvArgs A) {
     const int64_t row = row0 + 4 * c + h;   // 16x16x4 f64 output: register r holds row 4 r + lane / 16
     if (row < A.m) part[(int64_t)blockIdx.y * A.m + row] = v;
   }
-  if (A.mode == 0) return;
-  if (kmv_epilogue(A, rb0, 64) && A.mode == 2) kmv_pcg_finish(A);
 }
 
 template <int PREC>
@@ -487,9 +437,15 @@ hipError_t kmv_run(int prec, int dp, const KmvPlan& pl, KmvArgs A, hipStream_t s
   A.cps = pl.cols_per_split;
   A.nsplit = pl.nsplit;
   dim3 grid((unsigned)pl.rowblocks, (unsigned)pl.nsplit);
-  if (prec == LAKER_F64) return launch64(dp, grid, A, st);
-  if (prec == LAKER_F32) return launch32<LAKER_F32>(dp, grid, A, st);
-  return launch32<LAKER_BF16>(dp, grid, A, st);
+  hipError_t e;
+  if (prec == LAKER_F64) e = launch64(dp, grid, A, st);
+  else if (prec == LAKER_F32) e = launch32<LAKER_F32>(dp, grid, A, st);
+  else e = launch32<LAKER_BF16>(dp, grid, A, st);
+  if (e != hipSuccess || A.mode == 0) return e;
+  int64_t g = (A.m + 255) / 256;
+  if (g > 4096) g = 4096;
+  kmv_finish_kernel<<<(unsigned)g, 256, 0, st>>>(A.part, A.nsplit, A.m, A.lam, A.pself, A.out);
+  return hipGetLastError();
 }
 
 }  // namespace lk

@@ -21,6 +21,13 @@ namespace {
 
 constexpr int kThreads = 256;
 
+// blocks of the low-rank apply: 16 rows per block pass, at most kMaxBlocks blocks
+inline int apply_blocks(int64_t n) {
+  int64_t g = (n + 15) / 16;
+  if (g > kMaxBlocks) g = kMaxBlocks;
+  return (int)(g < 1 ? 1 : g);
+}
+
 inline int red_blocks(int64_t n) {
   int64_t g = (n + kThreads - 1) / kThreads;
   if (g > kMaxBlocks) g = kMaxBlocks;
@@ -28,19 +35,15 @@ inline int red_blocks(int64_t n) {
   return (int)g;
 }
 
-// one wave per row, up to 1024 blocks of four waves
-inline int apply_blocks(int64_t n) {
-  int64_t g = (n + 3) / 4;
-  if (g > kMaxBlocks) g = kMaxBlocks;
-  return (int)(g < 1 ? 1 : g);
-}
+// Grid reductions: every kernel writes one float64 partial per block with a
+// plain store; the kernel that needs the total (launched after it, so the
+// partials are visible) adds them in a fixed order in each of its blocks, and
+// block 0 records the scalar.  No atomics or fences inside the loop.
 
-// r = y - w (or r = y when w is null); S->yy = ||y||^2, S->rr = ||r||^2;
-// resets the iteration state; p = 0.
+// r = y - w (or y when w is null); p = 0; partials of ||y||^2 and ||r||^2.
 __global__ __launch_bounds__(kThreads) void pcg_init_kernel(const double* __restrict__ y, const double* __restrict__ w,
                                                             double* __restrict__ r, double* __restrict__ p, int64_t n,
-                                                            double tol, int max_iter, PcgScalars* S,
-                                                            double* __restrict__ bpart) {
+                                                            double* __restrict__ yyp, double* __restrict__ rrp) {
   __shared__ double sh[16];
   double yy = 0.0, rr = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
@@ -54,39 +57,70 @@ __global__ __launch_bounds__(kThreads) void pcg_init_kernel(const double* __rest
   yy = block_sum(yy, sh);
   rr = block_sum(rr, sh);
   if (threadIdx.x == 0) {
-    bpart[blockIdx.x] = yy;
-    bpart[kMaxBlocks + blockIdx.x] = rr;
-  }
-  if (last_block_arrived(&S->cnt[0])) {
-    const double syy = ordered_sum(bpart, gridDim.x, sh);
-    const double srr = ordered_sum(bpart + kMaxBlocks, gridDim.x, sh);
-    if (threadIdx.x == 0) {
-      S->yy = syy;
-      S->rr = srr;
-      S->tol2 = tol * tol * syy;
-      S->iters = 0;
-      S->max_iter = max_iter;
-      S->rz = 1.0;     // so that the first preconditioner pass sets p = theta
-      S->beta = 0.0;
-      S->done = (srr <= tol * tol * syy) ? 1 : (syy == 0.0 ? 1 : 0);
-      S->cnt[0] = 0;
-    }
+    yyp[blockIdx.x] = yy;
+    rrp[blockIdx.x] = rr;
   }
 }
 
-// alpha += delta p; r -= delta Ap; ||r||^2; stopping test (Alg. 1: before the
-// preconditioner is applied).  For P = I and Jacobi the preconditioned
-// residual and r^T theta are formed here too and beta is set.
+// One block: ||y||^2, ||r^0||^2, the tolerance and the initial state.
+__global__ __launch_bounds__(kThreads) void pcg_start_kernel(PcgScalars* S, const double* __restrict__ yyp,
+                                                             const double* __restrict__ rrp, int g, double tol,
+                                                             int max_iter) {
+  __shared__ double sh[16];
+  const double yy = ordered_sum(yyp, g, sh);
+  const double rr = ordered_sum(rrp, g, sh);
+  if (threadIdx.x == 0) {
+    S->yy = yy;
+    S->rr = rr;
+    S->tol2 = tol * tol * yy;
+    S->iters = 0;
+    S->max_iter = max_iter;
+    S->beta = 0.0;
+    S->done = (yy == 0.0 || rr <= tol * tol * yy) ? 1 : 0;
+  }
+}
+
+// Ap = lambda p + sum of the column-range partials; partials of p^T A p.
+__global__ __launch_bounds__(kThreads) void pcg_ap_kernel(const double* __restrict__ p, const double* __restrict__ part,
+                                                          int nsplit, double* __restrict__ Ap, int64_t n, double lam,
+                                                          double* __restrict__ pap_p, const PcgScalars* S) {
+  if (S->done) return;
+  __shared__ double sh[16];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+    double s = 0.0;
+    for (int k = 0; k < nsplit; ++k) s += part[(int64_t)k * n + i];
+    const double pi = p[i];
+    const double a = fma(lam, pi, s);
+    Ap[i] = a;
+    acc += pi * a;
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) pap_p[blockIdx.x] = acc;
+}
+
+// delta = r^T theta / p^T A p; alpha += delta p; r -= delta Ap (Alg. 1);
+// partials of ||r||^2 and, for Jacobi, theta = r / diag and r^T theta.
 template <int KIND>
-__global__ __launch_bounds__(kThreads) void pcg_update_kernel(double* __restrict__ alpha, double* __restrict__ r,
+__global__ __launch_bounds__(kThreads) void pcg_update_kernel(int k, double* __restrict__ alpha, double* __restrict__ r,
                                                               const double* __restrict__ p,
                                                               const double* __restrict__ Ap,
                                                               const double* __restrict__ dinv,
                                                               double* __restrict__ theta, int64_t n, PcgScalars* S,
-                                                              double* __restrict__ bpart) {
+                                                              const double* __restrict__ pap_p, int gp,
+                                                              double* __restrict__ rrp, double* __restrict__ rzp) {
   if (S->done) return;
   __shared__ double sh[16];
-  const double dl = S->delta;
+  const double pap = ordered_sum(pap_p, gp, sh);
+  const double dl = S->rzbuf[k & 1] / pap;
+  if (!(pap > 0.0) || !isfinite(dl)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) S->done = 2;
+    return;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    S->pap = pap;
+    S->delta = dl;
+  }
   double rr = 0.0, rz = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
     alpha[i] = fma(dl, p[i], alpha[i]);
@@ -102,107 +136,210 @@ __global__ __launch_bounds__(kThreads) void pcg_update_kernel(double* __restrict
   rr = block_sum(rr, sh);
   if (KIND == LAKER_PRECOND_JACOBI) rz = block_sum(rz, sh);
   if (threadIdx.x == 0) {
-    bpart[blockIdx.x] = rr;
-    bpart[kMaxBlocks + blockIdx.x] = rz;
-  }
-  if (last_block_arrived(&S->cnt[2])) {
-    const double srr = ordered_sum(bpart, gridDim.x, sh);
-    const double srz = KIND == LAKER_PRECOND_JACOBI ? ordered_sum(bpart + kMaxBlocks, gridDim.x, sh) : srr;
-    if (threadIdx.x == 0) {
-      S->rr = srr;
-      const int it = S->iters + 1;
-      S->iters = it;
-      if (!isfinite(srr)) S->done = 2;
-      else if (srr <= S->tol2) S->done = 1;
-      else if (it >= S->max_iter) S->done = 3;
-      if (KIND == LAKER_PRECOND_NONE || KIND == LAKER_PRECOND_JACOBI) {
-        S->beta = srz / S->rz;
-        S->rz = srz;
-      }
-      S->cnt[2] = 0;
-    }
+    rrp[blockIdx.x] = rr;
+    rzp[blockIdx.x] = rz;
   }
 }
 
-// First half of the low-rank preconditioner: t = B^T r.  Block b sums rows
-// [32 b, 32 b + 32): each wave takes every fourth row, each lane the columns
-// k = lane + 64 c; the four waves are combined in LDS and written as one
-// float64 partial row.  A second kernel adds the block partials in order.
-// MT is the storage type of B (float64, or float32 for the reduced-precision
-// solves); products are accumulated in float64.
-constexpr int kTRows = 32;
+// Stopping test of iteration k on the recursive residual (Alg. 1), evaluated
+// identically by every block; block 0 records it.  Returns true to continue.
+__device__ bool pcg_decide(int k, PcgScalars* S, const double* __restrict__ rrp, int g, double* sh) {
+  const double rr = ordered_sum(rrp, g, sh);
+  int d = 0;
+  if (!isfinite(rr)) d = 2;
+  else if (rr <= S->tol2) d = 1;
+  else if (k + 1 >= S->max_iter) d = 3;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    S->rr = rr;
+    S->iters = k + 1;
+    if (d) S->done = d;
+  }
+  return d == 0;
+}
+
+// p = theta + beta p with beta = r_new^T theta_new / r^T theta.  With
+// init set: p = theta and r^T theta is stored for iteration 0.  For P = I and
+// Jacobi this kernel also takes the stopping decision of iteration k.
+template <int KIND>
+__global__ __launch_bounds__(kThreads) void pcg_pupdate_kernel(int k, int init, const double* __restrict__ theta,
+                                                               double* __restrict__ p, int64_t n, PcgScalars* S,
+                                                               const double* __restrict__ rrp, int grr,
+                                                               const double* __restrict__ rzp, int grz) {
+  if (S->done) return;
+  __shared__ double sh[16];
+  if (!init && KIND != LAKER_PRECOND_CCCP && !pcg_decide(k, S, rrp, grr, sh)) return;
+  const double rz = ordered_sum(KIND == LAKER_PRECOND_NONE ? rrp : rzp, KIND == LAKER_PRECOND_NONE ? grr : grz, sh);
+  const int slot = init ? 0 : ((k + 1) & 1);
+  const double b = init ? 0.0 : rz / S->rzbuf[k & 1];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    S->rzbuf[slot] = rz;
+    S->beta = b;
+  }
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+    p[i] = fma(b, p[i], theta[i]);
+}
+
+// theta = r / diag (Jacobi) with r^T theta partials, for the start of the iteration.
+__global__ __launch_bounds__(kThreads) void jacobi_apply_kernel(const double* __restrict__ r,
+                                                                const double* __restrict__ dinv,
+                                                                double* __restrict__ theta, int64_t n,
+                                                                const PcgScalars* S, double* __restrict__ rzp) {
+  if (S->done) return;
+  __shared__ double sh[16];
+  double rz = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+    const double ri = r[i];
+    const double ti = ri * dinv[i];
+    theta[i] = ti;
+    rz += ri * ti;
+  }
+  rz = block_sum(rz, sh);
+  if (threadIdx.x == 0) rzp[blockIdx.x] = rz;
+}
+
+// Low-rank preconditioner  theta = c0 r + Bt (B^T r)  with B, Bt stored n x nrp
+// row-major (nrp = N_r rounded up to a multiple of 4, zero padding), as float64
+// or float32 (MT); products are accumulated in float64.
+//
+// t = B^T r, first half: block b owns rows [64 b, 64 b + 64).  A thread owns
+// four consecutive columns (one 16-byte load per row, 8 bytes for float64
+// pairs twice) and the block's threads are split into row groups when fewer
+// than 256 threads cover the columns; groups are combined in LDS in a fixed
+// order into one float64 partial row per block.
+constexpr int kTRows = 64;
 
 template <typename MT>
 __global__ __launch_bounds__(kThreads) void lr_t_partial_kernel(const MT* __restrict__ B, const double* __restrict__ r,
-                                                                int64_t n, int nr, double* __restrict__ tpart,
-                                                                const PcgScalars* S) {
+                                                                int64_t n, int nrp, double* __restrict__ tpart,
+                                                                PcgScalars* S, int k, const double* __restrict__ rrp,
+                                                                int grr) {
   if (S != nullptr && S->done) return;
-  constexpr int MAXC = kMaxNr / 64;
-  __shared__ double red[4][kMaxNr];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __shared__ double red[kMaxNr];
+  __shared__ double shd[16];
+  // inside the loop this pass takes the stopping decision of iteration k first
+  if (rrp != nullptr && !pcg_decide(k, S, rrp, grr, shd)) return;
+  const int tid = threadIdx.x;
+  const int cq = nrp / 4;                       // column quads
+  int tpr = 1;                                  // threads per row group (power of two >= cq)
+  while (tpr < cq) tpr <<= 1;
+  const int groups = kThreads / tpr;
+  const int g = tid / tpr, q = tid % tpr;
   const int64_t i0 = (int64_t)blockIdx.x * kTRows;
-  double acc[MAXC];
-#pragma unroll
-  for (int c = 0; c < MAXC; ++c) acc[c] = 0.0;
-  for (int rr = wv; rr < kTRows; rr += 4) {
-    const int64_t i = i0 + rr;
-    if (i >= n) break;
-    const double ri = r[i];
-    const MT* row = B + i * nr;
-#pragma unroll
-    for (int c = 0; c < MAXC; ++c) {
-      const int k = lane + 64 * c;
-      if (k < nr) acc[c] = fma((double)row[k], ri, acc[c]);
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  if (q < cq) {
+#pragma unroll 8
+    for (int rr = g; rr < kTRows; rr += groups) {
+      const int64_t i = i0 + rr;
+      if (i < n) {
+        const double ri = r[i];
+        const MT* row = B + i * nrp + 4 * q;
+        a0 = fma((double)row[0], ri, a0);
+        a1 = fma((double)row[1], ri, a1);
+        a2 = fma((double)row[2], ri, a2);
+        a3 = fma((double)row[3], ri, a3);
+      }
     }
   }
-#pragma unroll
-  for (int c = 0; c < MAXC; ++c) {
-    const int k = lane + 64 * c;
-    if (k < nr) red[wv][k] = acc[c];
+  // fixed-order combination of the row groups
+  for (int gg = 0; gg < groups; ++gg) {
+    if (g == gg && q < cq) {
+      if (gg == 0) {
+        red[4 * q + 0] = a0;
+        red[4 * q + 1] = a1;
+        red[4 * q + 2] = a2;
+        red[4 * q + 3] = a3;
+      } else {
+        red[4 * q + 0] += a0;
+        red[4 * q + 1] += a1;
+        red[4 * q + 2] += a2;
+        red[4 * q + 3] += a3;
+      }
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  for (int k = threadIdx.x; k < nr; k += kThreads)
-    tpart[(int64_t)blockIdx.x * nr + k] = (red[0][k] + red[1][k]) + (red[2][k] + red[3][k]);
+  for (int k = tid; k < nrp; k += kThreads) tpart[(int64_t)blockIdx.x * nrp + k] = red[k];
 }
 
-// t[k] = sum_b tpart[b][k] in a fixed order: block handles 64 columns, the four
-// waves take every fourth partial row, then combine in LDS.
-__global__ __launch_bounds__(kThreads) void lr_t_finish_kernel(const double* __restrict__ tpart, int nb, int nr,
+// t[k] = sum_b tpart[b][k] in a fixed order: a block owns 16 columns; its 16
+// row groups of 16 threads each sum every 16th partial row, then combine in LDS.
+__global__ __launch_bounds__(kThreads) void lr_t_finish_kernel(const double* __restrict__ tpart, int nb, int nrp,
                                                                double* __restrict__ t, const PcgScalars* S) {
   if (S != nullptr && S->done) return;
-  __shared__ double red[4][64];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int k = blockIdx.x * 64 + lane;
+  __shared__ double red[16][17];
+  const int g = threadIdx.x >> 4, cl = threadIdx.x & 15;
+  const int k = blockIdx.x * 16 + cl;
   double s = 0.0;
-  if (k < nr)
-    for (int b = wv; b < nb; b += 4) s += tpart[(int64_t)b * nr + k];
-  red[wv][lane] = s;
+  if (k < nrp)
+    for (int b = g; b < nb; b += 16) s += tpart[(int64_t)b * nrp + k];
+  red[g][cl] = s;
   __syncthreads();
-  if (wv == 0 && k < nr) t[k] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+  if (g == 0 && k < nrp) {
+    double v = 0.0;
+    for (int gg = 0; gg < 16; ++gg) v += red[gg][cl];
+    t[k] = v;
+  }
 }
 
-// Second half: theta = c0 r + Bt t, one wave per row; r^T theta and beta.
+// theta = c0 r + Bt t: 16 lanes per row (four rows per wave), 16-byte loads,
+// t in LDS; partials of r^T theta.
 template <typename MT>
 __global__ __launch_bounds__(kThreads) void lr_apply_kernel(const MT* __restrict__ Bt, const double* __restrict__ t,
                                                             const double* __restrict__ r, double* __restrict__ theta,
-                                                            int64_t n, int nr, const double* __restrict__ c0p,
-                                                            PcgScalars* S, double* __restrict__ bpart, int set_beta) {
+                                                            int64_t n, int nrp, const double* __restrict__ c0p,
+                                                            const PcgScalars* S, double* __restrict__ rzp) {
   if (S != nullptr && S->done) return;
+  constexpr int VEC = 16 / (int)sizeof(MT);
   __shared__ double sh[16];
   __shared__ double ts[kMaxNr];
   const double c0 = c0p[0];
-  for (int k = threadIdx.x; k < nr; k += kThreads) ts[k] = t[k];
+  for (int k = threadIdx.x; k < nrp; k += kThreads) ts[k] = t[k];
   __syncthreads();
-  const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-  const int64_t wstride = (int64_t)gridDim.x * (kThreads / 64);
+  const int sub = threadIdx.x & 15;
+  const int rl = threadIdx.x >> 4;                  // row slot within the block (16 per pass)
+  const int nvec = nrp / VEC;
   double rz = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * (kThreads / 64) + wv; i < n; i += wstride) {
+  for (int64_t i0 = (int64_t)blockIdx.x * 16; i0 < n; i0 += (int64_t)gridDim.x * 16) {
+    const int64_t i = i0 + rl;
     double acc = 0.0;
-    const MT* row = Bt + i * nr;
-    for (int k = lane; k < nr; k += 64) acc = fma((double)row[k], ts[k], acc);
-    acc = wave_sum(acc);
-    if (lane == 0) {
+    if (i < n) {
+      // all of the lane's loads are issued before the first use
+      constexpr int MAXV = kMaxNr / VEC / 16;
+      const MT* row = Bt + i * nrp;
+      if constexpr (VEC == 4) {
+        float4 x[MAXV];
+#pragma unroll
+        for (int j = 0; j < MAXV; ++j)
+          if (sub + 16 * j < nvec) x[j] = *reinterpret_cast<const float4*>(row + 4 * (sub + 16 * j));
+#pragma unroll
+        for (int j = 0; j < MAXV; ++j) {
+          if (sub + 16 * j < nvec) {
+            const int v = sub + 16 * j;
+            acc = fma((double)x[j].x, ts[4 * v + 0], acc);
+            acc = fma((double)x[j].y, ts[4 * v + 1], acc);
+            acc = fma((double)x[j].z, ts[4 * v + 2], acc);
+            acc = fma((double)x[j].w, ts[4 * v + 3], acc);
+          }
+        }
+      } else {
+        double2 x[MAXV];
+#pragma unroll
+        for (int j = 0; j < MAXV; ++j)
+          if (sub + 16 * j < nvec) x[j] = *reinterpret_cast<const double2*>(row + 2 * (sub + 16 * j));
+#pragma unroll
+        for (int j = 0; j < MAXV; ++j) {
+          if (sub + 16 * j < nvec) {
+            const int v = sub + 16 * j;
+            acc = fma(x[j].x, ts[2 * v + 0], acc);
+            acc = fma(x[j].y, ts[2 * v + 1], acc);
+          }
+        }
+      }
+    }
+    acc += __shfl_xor(acc, 1, 64);
+    acc += __shfl_xor(acc, 2, 64);
+    acc += __shfl_xor(acc, 4, 64);
+    acc += __shfl_xor(acc, 8, 64);
+    if (sub == 0 && i < n) {
       const double ri = r[i];
       const double th = fma(c0, ri, acc);
       theta[i] = th;
@@ -210,54 +347,7 @@ __global__ __launch_bounds__(kThreads) void lr_apply_kernel(const MT* __restrict
     }
   }
   rz = block_sum(rz, sh);
-  if (S == nullptr) return;
-  if (threadIdx.x == 0) bpart[blockIdx.x] = rz;
-  if (last_block_arrived(&S->cnt[3])) {
-    const double srz = ordered_sum(bpart, gridDim.x, sh);
-    if (threadIdx.x == 0) {
-      if (set_beta) {
-        S->beta = srz / S->rz;
-        S->rz = srz;
-      }
-      S->cnt[3] = 0;
-    }
-  }
-}
-
-// p = theta + beta p
-__global__ __launch_bounds__(kThreads) void pcg_pupdate_kernel(const double* __restrict__ theta, double* __restrict__ p,
-                                                               int64_t n, const PcgScalars* S) {
-  if (S->done) return;
-  const double b = S->beta;
-  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
-    p[i] = fma(b, p[i], theta[i]);
-}
-
-// Initial preconditioned residual when P = I or Jacobi: theta = P r, rz, beta.
-template <int KIND>
-__global__ __launch_bounds__(kThreads) void simple_precond_kernel(const double* __restrict__ r,
-                                                                  const double* __restrict__ dinv,
-                                                                  double* __restrict__ theta, int64_t n,
-                                                                  PcgScalars* S, double* __restrict__ bpart) {
-  if (S->done) return;
-  __shared__ double sh[16];
-  double rz = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
-    const double ri = r[i];
-    const double ti = KIND == LAKER_PRECOND_JACOBI ? ri * dinv[i] : ri;
-    theta[i] = ti;
-    rz += ri * ti;
-  }
-  rz = block_sum(rz, sh);
-  if (threadIdx.x == 0) bpart[blockIdx.x] = rz;
-  if (last_block_arrived(&S->cnt[4])) {
-    const double srz = ordered_sum(bpart, gridDim.x, sh);
-    if (threadIdx.x == 0) {
-      S->beta = srz / S->rz;
-      S->rz = srz;
-      S->cnt[4] = 0;
-    }
-  }
+  if (threadIdx.x == 0 && rzp != nullptr) rzp[blockIdx.x] = rz;
 }
 
 // ||y - w||^2 and ||y||^2 (float64), for the true residual; r = y - w if r is set.
@@ -295,24 +385,27 @@ __global__ void axpy_kernel(double* __restrict__ x, const double* __restrict__ d
     x[i] += d[i];
 }
 
+// theta = P r for the low-rank preconditioner; inside the loop (rrp set) the
+// first pass also takes the stopping decision of iteration k.
 template <typename MT>
-laker_status enqueue_lowrank(const PrecondView& P, const double* r, double* theta, int64_t n, PcgScalars* S,
-                             double* bpart, double* tpart, double* t, int set_beta, hipStream_t st) {
+laker_status enqueue_lowrank(const PrecondView& P, const double* r, double* theta, int64_t n, PcgScalars* S, int k,
+                             const double* rrp, int grr, double* rzp, double* tpart, double* t, hipStream_t st) {
   const int nb = (int)((n + kTRows - 1) / kTRows);
-  lr_t_partial_kernel<MT><<<nb, kThreads, 0, st>>>((const MT*)P.B, r, n, P.nr, tpart, S);
+  lr_t_partial_kernel<MT><<<nb, kThreads, 0, st>>>((const MT*)P.B, r, n, P.nrp, tpart, S, k, rrp, grr);
   LK_CHECK_LAUNCH();
-  lr_t_finish_kernel<<<(P.nr + 63) / 64, kThreads, 0, st>>>(tpart, nb, P.nr, t, S);
+  lr_t_finish_kernel<<<(P.nrp + 15) / 16, kThreads, 0, st>>>(tpart, nb, P.nrp, t, S);
   LK_CHECK_LAUNCH();
-  lr_apply_kernel<MT><<<apply_blocks(n), kThreads, 0, st>>>((const MT*)P.Bt, t, r, theta, n, P.nr, P.c0p, S, bpart,
-                                                            set_beta);
+  lr_apply_kernel<MT><<<(unsigned)apply_blocks(n), kThreads, 0, st>>>((const MT*)P.Bt, t, r, theta, n, P.nrp, P.c0p,
+                                                                      S, rzp);
   LK_CHECK_LAUNCH();
   return LAKER_OK;
 }
 
-laker_status enqueue_precond(const PrecondView& P, const double* r, double* theta, int64_t n, PcgScalars* S,
-                             const SolveWs& ws, hipStream_t st) {
-  if (P.f32) return enqueue_lowrank<float>(P, r, theta, n, S, ws.bpart, ws.tpart, ws.t, 1, st);
-  return enqueue_lowrank<double>(P, r, theta, n, S, ws.bpart, ws.tpart, ws.t, 1, st);
+laker_status enqueue_lowrank_any(const PrecondView& P, const double* r, double* theta, int64_t n, PcgScalars* S,
+                                 int k, const double* rrp, int grr, double* rzp, double* tpart, double* t,
+                                 hipStream_t st) {
+  if (P.f32) return enqueue_lowrank<float>(P, r, theta, n, S, k, rrp, grr, rzp, tpart, t, st);
+  return enqueue_lowrank<double>(P, r, theta, n, S, k, rrp, grr, rzp, tpart, t, st);
 }
 
 }  // namespace
@@ -330,8 +423,6 @@ SolveWs plan_solve_ws(void* base, int64_t n, int d, int64_t m) {
   w.q32 = c.take<float>((size_t)mq * dp);
   w.q16 = c.take<uint16_t>((size_t)mq * dp);
   w.part = c.take<double>((size_t)kMaxSplit * rows);
-  w.rb_cnt = c.take<unsigned>((size_t)(rows + 63) / 64 + 1);
-  w.rbpart = c.take<double>((size_t)(rows + 63) / 64 + 1);
   w.r = c.take<double>(n);
   w.p = c.take<double>(n);
   w.ap = c.take<double>(n);
@@ -341,6 +432,10 @@ SolveWs plan_solve_ws(void* base, int64_t n, int d, int64_t m) {
   w.dalpha = c.take<double>(n);
   w.S = c.take<PcgScalars>(1);
   w.bpart = c.take<double>(2 * kMaxBlocks);
+  w.yyp = c.take<double>(kMaxBlocks);
+  w.rrp = c.take<double>(kMaxBlocks);
+  w.rzp = c.take<double>(kMaxBlocks);
+  w.papp = c.take<double>(kMaxBlocks);
   w.tpart = c.take<double>((size_t)((n + kTRows - 1) / kTRows) * kMaxNr);
   w.t = c.take<double>(kMaxNr);
   w.misc = c.take<double>(16);
@@ -358,8 +453,6 @@ KmvArgs kmv_args(const void* Q, int64_t m, const void* K, int64_t n, const doubl
   A.p = p;
   A.part = ws.part;
   A.mode = 1;
-  A.rb_cnt = ws.rb_cnt;
-  A.rbpart = ws.rbpart;
   return A;
 }
 
@@ -394,6 +487,7 @@ laker_status pcg_run(const Problem& pb, const SolveWs& ws, const PrecondView& P,
                      hipStream_t st) {
   const int64_t n = pb.n;
   const int g = red_blocks(n);
+  const int ga = apply_blocks(n);
   double* r = ws.r;
   double* p = ws.p;
   double* Ap = ws.ap;
@@ -401,6 +495,8 @@ laker_status pcg_run(const Problem& pb, const SolveWs& ws, const PrecondView& P,
   PcgScalars* S = ws.S;
   const void* eh = prepared(ws, prec);
   const KmvPlan pl = kmv_plan(n, n, prec);
+  const bool lowrank = P.kind == LAKER_PRECOND_CCCP || P.kind == LAKER_PRECOND_LEARNED;
+  const double* dinv = (const double*)P.dinv;
 
   // r^0 = y - A alpha^0
   const double* wv = nullptr;
@@ -414,56 +510,58 @@ laker_status pcg_run(const Problem& pb, const SolveWs& ws, const PrecondView& P,
   } else {
     LK_TRY(hipMemsetAsync(alpha, 0, sizeof(double) * n, st));
   }
-  pcg_init_kernel<<<g, kThreads, 0, st>>>(rhs, wv, r, p, n, tol, max_iter, S, ws.bpart);
+  pcg_init_kernel<<<g, kThreads, 0, st>>>(rhs, wv, r, p, n, ws.yyp, ws.rrp);
   LK_CHECK_LAUNCH();
-  // theta^0 = P r^0, p^0 = theta^0
-  const double* dinv = (const double*)P.dinv;
+  pcg_start_kernel<<<1, kThreads, 0, st>>>(S, ws.yyp, ws.rrp, g, tol, max_iter);
+  LK_CHECK_LAUNCH();
+  // theta^0 = P r^0, p^0 = theta^0, r^T theta stored for iteration 0
   if (P.kind == LAKER_PRECOND_JACOBI) {
-    simple_precond_kernel<LAKER_PRECOND_JACOBI><<<g, kThreads, 0, st>>>(r, dinv, th, n, S, ws.bpart);
+    jacobi_apply_kernel<<<g, kThreads, 0, st>>>(r, dinv, th, n, S, ws.rzp);
     LK_CHECK_LAUNCH();
+    pcg_pupdate_kernel<LAKER_PRECOND_JACOBI><<<g, kThreads, 0, st>>>(0, 1, th, p, n, S, ws.rrp, g, ws.rzp, g);
   } else if (P.kind == LAKER_PRECOND_NONE) {
-    simple_precond_kernel<LAKER_PRECOND_NONE><<<g, kThreads, 0, st>>>(r, nullptr, th, n, S, ws.bpart);
-    LK_CHECK_LAUNCH();
+    pcg_pupdate_kernel<LAKER_PRECOND_NONE><<<g, kThreads, 0, st>>>(0, 1, r, p, n, S, ws.rrp, g, ws.rzp, g);
   } else {
-    laker_status e = enqueue_precond(P, r, th, n, S, ws, st);
+    laker_status e = enqueue_lowrank_any(P, r, th, n, S, 0, nullptr, 0, ws.rzp, ws.tpart, ws.t, st);
     if (e != LAKER_OK) return e;
+    pcg_pupdate_kernel<LAKER_PRECOND_CCCP><<<g, kThreads, 0, st>>>(0, 1, th, p, n, S, ws.rrp, g, ws.rzp, ga);
   }
-  pcg_pupdate_kernel<<<g, kThreads, 0, st>>>(th, p, n, S);
   LK_CHECK_LAUNCH();
 
-  // A p, p^T A p and the step size in one launch
   KmvArgs Ak = kmv_args(eh, n, eh, n, p, ws);
-  Ak.mode = 2;
-  Ak.lam = pb.lambda;
-  Ak.pself = p;
-  Ak.out = Ap;
+  Ak.mode = 0;
   Ak.S = S;
   PcgScalars hs;
-  int enq = 0;
+  int k = 0;
   for (;;) {
-    for (int k = 0; k < check_every; ++k) {
+    for (int c = 0; c < check_every; ++c, ++k) {
+      // A p (column-range partials), then Ap and p^T A p partials
       LK_TRY(kmv_run(prec, pb.dp, pl, Ak, st));
+      pcg_ap_kernel<<<g, kThreads, 0, st>>>(p, ws.part, pl.nsplit, Ap, n, pb.lambda, ws.papp, S);
+      LK_CHECK_LAUNCH();
       if (P.kind == LAKER_PRECOND_JACOBI) {
-        pcg_update_kernel<LAKER_PRECOND_JACOBI><<<g, kThreads, 0, st>>>(alpha, r, p, Ap, dinv, th, n, S, ws.bpart);
+        pcg_update_kernel<LAKER_PRECOND_JACOBI><<<g, kThreads, 0, st>>>(k, alpha, r, p, Ap, dinv, th, n, S, ws.papp,
+                                                                         g, ws.rrp, ws.rzp);
         LK_CHECK_LAUNCH();
-        pcg_pupdate_kernel<<<g, kThreads, 0, st>>>(th, p, n, S);
+        pcg_pupdate_kernel<LAKER_PRECOND_JACOBI><<<g, kThreads, 0, st>>>(k, 0, th, p, n, S, ws.rrp, g, ws.rzp, g);
       } else if (P.kind == LAKER_PRECOND_NONE) {
-        pcg_update_kernel<LAKER_PRECOND_NONE><<<g, kThreads, 0, st>>>(alpha, r, p, Ap, nullptr, th, n, S, ws.bpart);
+        pcg_update_kernel<LAKER_PRECOND_NONE><<<g, kThreads, 0, st>>>(k, alpha, r, p, Ap, nullptr, th, n, S, ws.papp,
+                                                                       g, ws.rrp, ws.rzp);
         LK_CHECK_LAUNCH();
-        pcg_pupdate_kernel<<<g, kThreads, 0, st>>>(r, p, n, S);
+        pcg_pupdate_kernel<LAKER_PRECOND_NONE><<<g, kThreads, 0, st>>>(k, 0, r, p, n, S, ws.rrp, g, ws.rzp, g);
       } else {
-        pcg_update_kernel<LAKER_PRECOND_CCCP><<<g, kThreads, 0, st>>>(alpha, r, p, Ap, nullptr, th, n, S, ws.bpart);
+        pcg_update_kernel<LAKER_PRECOND_CCCP><<<g, kThreads, 0, st>>>(k, alpha, r, p, Ap, nullptr, th, n, S, ws.papp,
+                                                                       g, ws.rrp, ws.rzp);
         LK_CHECK_LAUNCH();
-        laker_status e = enqueue_precond(P, r, th, n, S, ws, st);
+        laker_status e = enqueue_lowrank_any(P, r, th, n, S, k, ws.rrp, g, ws.rzp, ws.tpart, ws.t, st);
         if (e != LAKER_OK) return e;
-        pcg_pupdate_kernel<<<g, kThreads, 0, st>>>(th, p, n, S);
+        pcg_pupdate_kernel<LAKER_PRECOND_CCCP><<<g, kThreads, 0, st>>>(k, 0, th, p, n, S, ws.rrp, g, ws.rzp, ga);
       }
       LK_CHECK_LAUNCH();
     }
-    enq += check_every;
     LK_TRY(hipMemcpyAsync(&hs, S, sizeof(hs), hipMemcpyDeviceToHost, st));
     LK_TRY(hipStreamSynchronize(st));
-    if (hs.done || enq >= max_iter + check_every) break;
+    if (hs.done || k >= max_iter + check_every) break;
   }
   if (stats) {
     stats->iters += hs.iters;
@@ -482,8 +580,7 @@ laker_status axpy_inplace(double* x, const double* d, int64_t n, hipStream_t st)
 
 laker_status apply_lowrank_once(const PrecondView& P, const double* r, double* theta, int64_t n, const SolveWs& ws,
                                 hipStream_t st) {
-  if (P.f32) return enqueue_lowrank<float>(P, r, theta, n, nullptr, ws.bpart, ws.tpart, ws.t, 0, st);
-  return enqueue_lowrank<double>(P, r, theta, n, nullptr, ws.bpart, ws.tpart, ws.t, 0, st);
+  return enqueue_lowrank_any(P, r, theta, n, nullptr, 0, nullptr, 0, nullptr, ws.tpart, ws.t, st);
 }
 
 }  // namespace lk

@@ -23,8 +23,6 @@ struct SolveWs {
   float* q32;
   uint16_t* q16;
   double* part;     // column-range partials, up to kMaxSplit x max(n, m)
-  unsigned* rb_cnt; // per-row-block tickets of the fused product
-  double* rbpart;   // per-row-block partials of p^T A p
   double* r;
   double* p;
   double* ap;
@@ -34,6 +32,10 @@ struct SolveWs {
   double* dalpha;
   PcgScalars* S;
   double* bpart;
+  double* yyp;      // per-block partials of ||y||^2, ||r||^2, r^T theta, p^T A p
+  double* rrp;
+  double* rzp;
+  double* papp;
   double* tpart;
   double* t;
   double* misc;
@@ -50,6 +52,7 @@ const void* prepared(const SolveWs& ws, int prec);
 struct PrecondView {
   int kind;
   int nr;
+  int nrp;             // row stride of B, Bt: nr rounded up to a multiple of 4
   const double* c0p;   // device pointer to c0
   const void* B;
   const void* Bt;
@@ -59,7 +62,8 @@ struct PrecondView {
 
 // Layout of the preconditioner buffer (all offsets 256-byte aligned):
 //   header (32 doubles: [0] = b^{-1/2}, [1] = a, [2] = b, [3] = CCCP iterations, ...),
-//   B64, Bt64 (n x nr float64), B32, Bt32 (n x nr float32), dinv64 (n).
+//   B64, Bt64 (n x nrp float64), B32, Bt32 (n x nrp float32), dinv64 (n), with
+//   nrp = nr rounded up to a multiple of 4 and zero padding columns.
 struct PrecondLayout {
   double* hdr;
   double* B64;
@@ -70,6 +74,7 @@ struct PrecondLayout {
   size_t total;
 };
 PrecondLayout precond_layout(void* base, int64_t n, int nr);
+inline int pad_nr(int nr) { return (nr + 3) & ~3; }
 
 laker_status pcg_run(const Problem& pb, const SolveWs& ws, const PrecondView& P, const double* rhs, double* alpha,
                      bool warm, double tol, int max_iter, int check_every, int prec, laker_stats* stats,

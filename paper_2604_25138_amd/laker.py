@@ -261,14 +261,15 @@ def precond_parts(pc: Precond) -> dict:
     def al(x):
         return (x + 255) & ~255
     n, nr = pc.n, pc.n_r
+    nrp = (nr + 3) & ~3          # row stride: N_r rounded up to a multiple of 4
     off = 0
     out = {}
-    for name, count, dt, es in (("hdr", 32, torch.float64, 8), ("B64", n * nr, torch.float64, 8),
-                                ("Bt64", n * nr, torch.float64, 8), ("B32", n * nr, torch.float32, 4),
-                                ("Bt32", n * nr, torch.float32, 4), ("dinv64", n, torch.float64, 8)):
+    for name, count, dt, es in (("hdr", 32, torch.float64, 8), ("B64", n * nrp, torch.float64, 8),
+                                ("Bt64", n * nrp, torch.float64, 8), ("B32", n * nrp, torch.float32, 4),
+                                ("Bt32", n * nrp, torch.float32, 4), ("dinv64", n, torch.float64, 8)):
         off = al(off)
         out[name] = pc.data[off:off + count * es].view(dt)
         off += count * es
-    out["B64"] = out["B64"].view(n, nr)
-    out["Bt64"] = out["Bt64"].view(n, nr)
+    for name in ("B64", "Bt64", "B32", "Bt32"):
+        out[name] = out[name].view(n, nrp)[:, :nr]
     return out

@@ -208,6 +208,34 @@ def test_cccp_fit_matches_oracle():
     assert abs(pr.n * hdr[2] + hdr[1] * np.sum(w * np.sum(Ub * Ub, axis=0)) - pr.n) <= 1e-8 * pr.n
 
 
+@pytest.mark.parametrize("prec,tol_ab,tol_p", [("f32", 1e-4, 1e-3), ("bf16", 3e-2, 1e-1)])
+def test_cccp_fit_reduced_precision_directions(prec, tol_ab, tol_p):
+    """Directions u_k = (lam I + G) z_k formed on the matrix cores in float32 /
+    bfloat16: the fit lands near the oracle's (same Z).  The directions carry
+    relative errors ~1e-6 (f32) / ~4e-3 (bf16); the CCCP fixed point moves by
+    that times its sensitivity (up to ~10 here), hence the tolerances on (a, b)
+    and on P v.  PCG with the resulting P still reaches the float64 solution."""
+    pr = make_problem(700, 16, 1e-3, seed=7)
+    nr = 64
+    Z = make_directions(pr.n, nr, 7)
+    prob = _gp(pr)
+    pc = L().fit_precond(prob, torch.tensor(Z, device=DEV), gamma=0.1, rho=0.02, eps=1e-10, tol=1e-9,
+                         max_iter=300, precision=prec)
+    _, Ub = O.random_directions(pr.E, pr.scale, pr.lam, Z)
+    a, b, w, it = O.cccp_lowrank(Ub, 0.1, 0.02, 1e-10, 1e-9, 300)
+    hdr = pc.header.numpy()
+    assert abs(hdr[1] - a) <= tol_ab * a and abs(hdr[2] - b) <= tol_ab * b, (hdr[1], a, hdr[2], b)
+    parts = L().precond_parts(pc)
+    v = np.random.default_rng(1).normal(size=pr.n)
+    vt = torch.tensor(v, device=DEV)
+    Pv = (parts["hdr"][0] * vt + parts["Bt64"] @ (parts["B64"].T @ vt)).cpu().numpy()
+    ref = O.LowRankPrecond(Ub, a, b, w).apply(v)
+    assert np.linalg.norm(Pv - ref) <= tol_p * np.linalg.norm(ref)
+    alpha, st = L().pcg_solve(prob, pr.y, pc, tol=1e-12, max_iter=5000)
+    sol = O.solve_direct(O.system_matrix(pr.E, pr.scale, pr.lam), pr.y)
+    assert np.linalg.norm(alpha.cpu().numpy() - sol) / np.linalg.norm(sol) <= 1e-10
+
+
 def test_laker_pcg_f64_matches_direct():
     """Full method at n = 512: CCCP fit + PCG to 1e-12, alpha within 1e-10."""
     pr = make_problem(512, 16, 1e-3, seed=0)
