@@ -112,6 +112,10 @@ typedef struct {
                          residual) when that is larger                          */
   int32_t warm_start; /* 1: alpha holds the starting iterate alpha^0            */
   int32_t check_every;/* host polls the convergence flag every this many steps  */
+  int32_t graph;      /* 1: each chunk of check_every iterations is captured once
+                         into a HIP graph and replayed (same results)          */
+  int32_t profile;    /* 1: time every kernel product of the loop with HIP events
+                         on `stream` (eager launches; fills stats->kmv_ms)      */
 } laker_pcg_opts;
 
 typedef struct {
@@ -122,6 +126,12 @@ typedef struct {
   double relres;        /* final recursive relative residual                     */
   double relres_true;   /* ||y - (lambda I + G) alpha|| / ||y|| in float64        */
   double ir_relres[64]; /* float64 true residual after each refinement step      */
+  double kmv_ms;        /* profile: mean duration of the loop's kernel products of
+                           iterations that ran                                   */
+  int32_t kmv_count;    /* profile: number of those products                      */
+  int32_t kmv_launches; /* profile: product launches, including the ones enqueued
+                           after convergence, which return at entry              */
+  double kmv_launch_ms; /* profile: mean duration over all kmv_launches          */
 } laker_stats;
 
 /* ---- sizes ---------------------------------------------------------------- */

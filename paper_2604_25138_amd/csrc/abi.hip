@@ -181,6 +181,10 @@ laker_status laker_pcg_solve(const laker_problem* prob, const laker_precond* pre
   sp->ir_steps = 0;
   sp->relres = 0.0;
   sp->relres_true = 0.0;
+  sp->kmv_ms = 0.0;
+  sp->kmv_count = 0;
+  sp->kmv_launches = 0;
+  sp->kmv_launch_ms = 0.0;
   const int check = opts->check_every > 0 ? opts->check_every : 16;
   LK_TRY(hipMemsetAsync(W.S, 0, sizeof(PcgScalars), st));
   LK_TRY(hipMemsetAsync(W.cnt, 0, 16 * sizeof(unsigned), st));
@@ -191,8 +195,8 @@ laker_status laker_pcg_solve(const laker_problem* prob, const laker_precond* pre
     LK_TRY(prep_embed(pb.E, pb.n, pb.d, pb.dp, pb.scale, LAKER_BF16, W.e16, st));
   laker_status r;
   if (!opts->refine) {
-    r = pcg_run(pb, W, view, y, alpha, opts->warm_start != 0, opts->tol, opts->max_iter, check, opts->precision, sp,
-                st);
+    r = pcg_run(pb, W, view, y, alpha, opts->warm_start != 0, opts->tol, opts->max_iter, check, opts->precision,
+                opts->graph != 0, opts->profile != 0, sp, st);
     if (r == LAKER_OK || r == LAKER_ENOCONV) {
       double rt = 0.0;
       laker_status r2 = true_residual(pb, W, y, alpha, nullptr, &rt, true, st);
@@ -223,9 +227,19 @@ laker_status laker_pcg_solve(const laker_problem* prob, const laker_precond* pre
       if (need > itol) itol = need;
       laker_stats inner{};
       laker_status ri = pcg_run(pb, W, view, W.rout, W.dalpha, false, itol, opts->max_iter - used, check,
-                                opts->precision, &inner, st);
+                                opts->precision, opts->graph != 0, opts->profile != 0, &inner, st);
       used += inner.iters;
       sp->iters = used;
+      if (inner.kmv_count > 0) {
+        const double prev = sp->kmv_ms * sp->kmv_count;
+        sp->kmv_count += inner.kmv_count;
+        sp->kmv_ms = (prev + inner.kmv_ms * inner.kmv_count) / sp->kmv_count;
+      }
+      if (inner.kmv_launches > 0) {
+        const double prev = sp->kmv_launch_ms * sp->kmv_launches;
+        sp->kmv_launches += inner.kmv_launches;
+        sp->kmv_launch_ms = (prev + inner.kmv_launch_ms * inner.kmv_launches) / sp->kmv_launches;
+      }
       if (ri == LAKER_EBREAKDOWN || ri == LAKER_EHIP || ri == LAKER_EINVAL) return ri;
       r2 = axpy_inplace(alpha, W.dalpha, pb.n, st);
       if (r2 != LAKER_OK) return r2;

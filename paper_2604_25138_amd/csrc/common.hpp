@@ -37,7 +37,7 @@ struct PcgScalars {
   int iters;
   int max_iter;
   int done;         // 0 running, 1 converged, 2 breakdown, 3 iteration cap
-  int pad;
+  int kcur;         // iterations started: the product launch of iteration k sets it to k + 1
   unsigned cnt[8];  // arrival counters of the grid reductions (kept at zero between uses)
 };
 

@@ -97,53 +97,47 @@ __global__ __launch_bounds__(256) void gj_pivot_kernel(const double* __restrict_
                                                        int64_t k0, int nb, double* __restrict__ Rh,
                                                        double* __restrict__ Cp, double* __restrict__ logdet,
                                                        int* __restrict__ flag, int first) {
-  __shared__ double Ps[NB][NB + 1];
-  __shared__ double rowk[NB];
-  __shared__ double colk[NB];
-  __shared__ double ld_acc;
-  __shared__ int bad;
+  __shared__ double Ps[2][NB][NB + 1];
+  __shared__ double pivs[NB];
+  __shared__ double lsum;
   const int tid = threadIdx.x;
   if (flag != nullptr && *flag) return;
   for (int idx = tid; idx < nb * nb; idx += 256) {
     int r = idx / nb, c = idx % nb;
-    Ps[r][c] = A[(k0 + r) * lda + k0 + c];
-  }
-  if (tid == 0) {
-    ld_acc = 0.0;
-    bad = 0;
+    Ps[0][r][c] = A[(k0 + r) * lda + k0 + c];
   }
   __syncthreads();
-  // scalar in-place Gauss-Jordan on the nb x nb block: row k is scaled by the
-  // pivot (its column-k entry becoming 1/piv), every other row loses its
-  // multiple of row k (its column-k entry becoming -f/piv).  Row k and column k
-  // are snapshotted first so that no thread reads an entry another thread of
-  // the same step has already replaced.
+  // scalar in-place Gauss-Jordan on the nb x nb block, one barrier per step:
+  // step k reads buffer k & 1 and writes the other.  Row k is scaled by the
+  // pivot (its column-k entry becoming 1/piv); every other row loses its
+  // multiple of row k (its column-k entry becoming -f/piv).
   for (int k = 0; k < nb; ++k) {
-    const double piv = Ps[k][k];
+    const int cur = k & 1;
+    const double piv = Ps[cur][k][k];
     const double ip = 1.0 / piv;
-    if (tid < nb) {
-      rowk[tid] = (tid == k ? 1.0 : Ps[k][tid]) * ip;
-      colk[tid] = Ps[tid][k];
-    }
-    if (tid == 0) {
-      if (!(piv > 0.0) || !isfinite(piv)) bad = 1;
-      ld_acc += log(piv);
-    }
-    __syncthreads();
+    if (tid == 0) pivs[k] = piv;
     for (int idx = tid; idx < nb * nb; idx += 256) {
-      int r = idx / nb, c = idx % nb;
-      if (r == k) {
-        Ps[r][c] = rowk[c];
-      } else {
-        double v = (c == k) ? 0.0 : Ps[r][c];
-        Ps[r][c] = v - colk[r] * rowk[c];
-      }
+      const int r = idx / nb, c = idx % nb;
+      const double rk = (c == k ? 1.0 : Ps[cur][k][c]) * ip;
+      double v;
+      if (r == k) v = rk;
+      else v = (c == k ? 0.0 : Ps[cur][r][c]) - Ps[cur][r][k] * rk;
+      Ps[cur ^ 1][r][c] = v;
     }
     __syncthreads();
   }
-  if (blockIdx.x == 0 && tid == 0) {
-    logdet[0] = (first ? 0.0 : logdet[0]) + ld_acc;
-    if (bad && flag != nullptr) *flag = 1;
+  const int fin = nb & 1;   // buffer holding the inverse
+  // log det = sum of the logs of the pivots (one per thread, summed in order)
+  if (blockIdx.x == 0) {
+    if (tid < nb) pivs[tid] = (pivs[tid] > 0.0 && isfinite(pivs[tid])) ? log(pivs[tid]) : NAN;
+    __syncthreads();
+    if (tid == 0) {
+      double s = 0.0;
+      for (int k = 0; k < nb; ++k) s += pivs[k];
+      lsum = s;
+      logdet[0] = (first ? 0.0 : logdet[0]) + s;
+      if (!isfinite(s) && flag != nullptr) *flag = 1;
+    }
   }
   // this block's 64 columns of Rh = Pinv * A[K, :] (outside K), Pinv (inside K);
   // the nb x 64 slab of A[K, :] is staged in LDS first
@@ -162,10 +156,10 @@ __global__ __launch_bounds__(256) void gj_pivot_kernel(const double* __restrict_
     if (j >= N) continue;
     double v;
     if (j >= k0 && j < k0 + nb) {
-      v = Ps[r][j - k0];
+      v = Ps[fin][r][j - k0];
     } else {
       v = 0.0;
-      for (int c = 0; c < nb; ++c) v = fma(Ps[r][c], As[c][jl], v);
+      for (int c = 0; c < nb; ++c) v = fma(Ps[fin][r][c], As[c][jl], v);
     }
     Rh[(int64_t)r * N + j] = v;
   }

@@ -45,6 +45,7 @@ struct KmvArgs {
   const double* pself;  // vector over the output rows for lam * pself; null: none
   double* out;          // output vector (mode 1)
   PcgScalars* S;        // when set, the launch is skipped once S->done
+  int pcg_step;         // 1: this product starts a PCG iteration (advances S->kcur)
 };
 hipError_t kmv_run(int prec, int dp, const KmvPlan& pl, KmvArgs A, hipStream_t st);
 

@@ -172,8 +172,11 @@ struct Stage32 {
   using ET = typename std::conditional<PREC == LAKER_F32, float, uint16_t>::type;
   static constexpr int ES = (int)sizeof(ET);
   static constexpr int ROWB = DP * ES;                               // bytes of one key row
-  static constexpr int KT0 = 16384 / ROWB;
-  static constexpr int KT = KT0 > 128 ? 128 : KT0;                   // key rows per stage
+#ifndef LAKER_KMV_STAGE_BYTES
+#define LAKER_KMV_STAGE_BYTES 16384
+#endif
+  static constexpr int KT0 = LAKER_KMV_STAGE_BYTES / ROWB;
+  static constexpr int KT = KT0 > 128 ? 128 : (KT0 < 32 ? 32 : KT0);  // key rows per stage
   static constexpr int PITCH = ROWB + 16;                            // padded LDS row pitch
   static constexpr int CHUNKS = KT * ROWB / 16;                      // 16-byte chunks per stage
   static constexpr int PER_T = (CHUNKS + 255) / 256;                 // chunks per thread
@@ -188,6 +191,7 @@ __global__ __launch_bounds__(256) void kmv32_kernel(KmvArgs A) {
   constexpr int KT = St::KT;
   __shared__ __attribute__((aligned(16))) unsigned char lds[2][St::BYTES];
   if (A.S != nullptr && A.S->done) return;
+  if (A.pcg_step && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) A.S->kcur += 1;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const int h = lane >> 5, c = lane & 31;
@@ -311,6 +315,7 @@ __global__ __launch_bounds__(256) void kmv32_kernel(KmvArgs A) {
 template <int DP>
 __global__ __launch_bounds__(256) void kmv64_kernel(KmvArgs A) {
   if (A.S != nullptr && A.S->done) return;
+  if (A.pcg_step && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) A.S->kcur += 1;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int h = lane >> 4, c = lane & 15;
   const int64_t rb0 = (int64_t)blockIdx.x * 64;

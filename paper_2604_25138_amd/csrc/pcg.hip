@@ -13,6 +13,9 @@
 // products or float32 recurrences roughly double the iteration count, because
 // their rounding noise is of the order of lambda |p| in the directions CG
 // resolves last.
+#include <mutex>
+#include <vector>
+
 #include "pcg.hpp"
 
 namespace lk {
@@ -20,6 +23,20 @@ namespace lk {
 namespace {
 
 constexpr int kThreads = 256;
+
+// A non-blocking stream per device on which PCG chunks are captured into graphs
+// (capture needs a stream other than the null stream; the graphs are launched on
+// the caller's stream).
+hipStream_t capture_stream() {
+  static hipStream_t streams[64] = {};
+  static std::mutex mu;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> lock(mu);
+  if (streams[dev] == nullptr && hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess)
+    streams[dev] = nullptr;
+  return streams[dev];
+}
 
 // blocks of the low-rank apply: 16 rows per block pass, at most kMaxBlocks blocks
 inline int apply_blocks(int64_t n) {
@@ -76,6 +93,7 @@ __global__ __launch_bounds__(kThreads) void pcg_start_kernel(PcgScalars* S, cons
     S->iters = 0;
     S->max_iter = max_iter;
     S->beta = 0.0;
+    S->kcur = 0;
     S->done = (yy == 0.0 || rr <= tol * tol * yy) ? 1 : 0;
   }
 }
@@ -102,7 +120,7 @@ __global__ __launch_bounds__(kThreads) void pcg_ap_kernel(const double* __restri
 // delta = r^T theta / p^T A p; alpha += delta p; r -= delta Ap (Alg. 1);
 // partials of ||r||^2 and, for Jacobi, theta = r / diag and r^T theta.
 template <int KIND>
-__global__ __launch_bounds__(kThreads) void pcg_update_kernel(int k, double* __restrict__ alpha, double* __restrict__ r,
+__global__ __launch_bounds__(kThreads) void pcg_update_kernel(double* __restrict__ alpha, double* __restrict__ r,
                                                               const double* __restrict__ p,
                                                               const double* __restrict__ Ap,
                                                               const double* __restrict__ dinv,
@@ -111,6 +129,7 @@ __global__ __launch_bounds__(kThreads) void pcg_update_kernel(int k, double* __r
                                                               double* __restrict__ rrp, double* __restrict__ rzp) {
   if (S->done) return;
   __shared__ double sh[16];
+  const int k = S->kcur - 1;
   const double pap = ordered_sum(pap_p, gp, sh);
   const double dl = S->rzbuf[k & 1] / pap;
   if (!(pap > 0.0) || !isfinite(dl)) {
@@ -161,12 +180,13 @@ __device__ bool pcg_decide(int k, PcgScalars* S, const double* __restrict__ rrp,
 // init set: p = theta and r^T theta is stored for iteration 0.  For P = I and
 // Jacobi this kernel also takes the stopping decision of iteration k.
 template <int KIND>
-__global__ __launch_bounds__(kThreads) void pcg_pupdate_kernel(int k, int init, const double* __restrict__ theta,
+__global__ __launch_bounds__(kThreads) void pcg_pupdate_kernel(int init, const double* __restrict__ theta,
                                                                double* __restrict__ p, int64_t n, PcgScalars* S,
                                                                const double* __restrict__ rrp, int grr,
                                                                const double* __restrict__ rzp, int grz) {
   if (S->done) return;
   __shared__ double sh[16];
+  const int k = S->kcur - 1;
   if (!init && KIND != LAKER_PRECOND_CCCP && !pcg_decide(k, S, rrp, grr, sh)) return;
   const double rz = ordered_sum(KIND == LAKER_PRECOND_NONE ? rrp : rzp, KIND == LAKER_PRECOND_NONE ? grr : grz, sh);
   const int slot = init ? 0 : ((k + 1) & 1);
@@ -211,13 +231,9 @@ constexpr int kTRows = 64;
 template <typename MT>
 __global__ __launch_bounds__(kThreads) void lr_t_partial_kernel(const MT* __restrict__ B, const double* __restrict__ r,
                                                                 int64_t n, int nrp, double* __restrict__ tpart,
-                                                                PcgScalars* S, int k, const double* __restrict__ rrp,
-                                                                int grr) {
+                                                                const PcgScalars* S) {
   if (S != nullptr && S->done) return;
   __shared__ double red[kMaxNr];
-  __shared__ double shd[16];
-  // inside the loop this pass takes the stopping decision of iteration k first
-  if (rrp != nullptr && !pcg_decide(k, S, rrp, grr, shd)) return;
   const int tid = threadIdx.x;
   const int cq = nrp / 4;                       // column quads
   int tpr = 1;                                  // threads per row group (power of two >= cq)
@@ -260,23 +276,109 @@ __global__ __launch_bounds__(kThreads) void lr_t_partial_kernel(const MT* __rest
   for (int k = tid; k < nrp; k += kThreads) tpart[(int64_t)blockIdx.x * nrp + k] = red[k];
 }
 
+// PCG update fused with the first half of the low-rank preconditioner: block
+// b owns rows [64 b, 64 b + 64): delta from the p^T A p partials, alpha += delta p,
+// r -= delta Ap, the ||r||^2 partial, and t_b = B[rows]^T r[rows] from the
+// fresh r kept in LDS.  The stopping decision is taken by the next pass.
+template <typename MT>
+__global__ __launch_bounds__(kThreads) void pcg_update_t_kernel(double* __restrict__ alpha,
+                                                                double* __restrict__ r, const double* __restrict__ p,
+                                                                const double* __restrict__ Ap,
+                                                                const MT* __restrict__ B, int nrp, int64_t n,
+                                                                PcgScalars* S, const double* __restrict__ pap_p,
+                                                                int gp, double* __restrict__ rrp,
+                                                                double* __restrict__ tpart) {
+  if (S->done) return;
+  __shared__ double sh[16];
+  __shared__ double rs[kTRows];
+  __shared__ double red[kMaxNr];
+  const int tid = threadIdx.x;
+  const int k = S->kcur - 1;
+  const double pap = ordered_sum(pap_p, gp, sh);
+  const double dl = S->rzbuf[k & 1] / pap;
+  if (!(pap > 0.0) || !isfinite(dl)) {
+    if (blockIdx.x == 0 && tid == 0) S->done = 2;
+    return;
+  }
+  if (blockIdx.x == 0 && tid == 0) {
+    S->pap = pap;
+    S->delta = dl;
+  }
+  const int64_t i0 = (int64_t)blockIdx.x * kTRows;
+  double rr = 0.0;
+  if (tid < kTRows) {
+    const int64_t i = i0 + tid;
+    double ri = 0.0;
+    if (i < n) {
+      alpha[i] = fma(dl, p[i], alpha[i]);
+      ri = fma(-dl, Ap[i], r[i]);
+      r[i] = ri;
+    }
+    rs[tid] = ri;
+    rr = ri * ri;
+  }
+  rr = block_sum(rr, sh);     // contains the barrier that publishes rs
+  if (tid == 0) rrp[blockIdx.x] = rr;
+  const int cq = nrp / 4;
+  int tpr = 1;
+  while (tpr < cq) tpr <<= 1;
+  const int groups = kThreads / tpr;
+  const int g = tid / tpr, q = tid % tpr;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  if (q < cq) {
+#pragma unroll 8
+    for (int rr2 = g; rr2 < kTRows; rr2 += groups) {
+      const int64_t i = i0 + rr2;
+      if (i < n) {
+        const double ri = rs[rr2];
+        const MT* row = B + i * nrp + 4 * q;
+        a0 = fma((double)row[0], ri, a0);
+        a1 = fma((double)row[1], ri, a1);
+        a2 = fma((double)row[2], ri, a2);
+        a3 = fma((double)row[3], ri, a3);
+      }
+    }
+  }
+  for (int gg = 0; gg < groups; ++gg) {
+    if (g == gg && q < cq) {
+      if (gg == 0) {
+        red[4 * q + 0] = a0;
+        red[4 * q + 1] = a1;
+        red[4 * q + 2] = a2;
+        red[4 * q + 3] = a3;
+      } else {
+        red[4 * q + 0] += a0;
+        red[4 * q + 1] += a1;
+        red[4 * q + 2] += a2;
+        red[4 * q + 3] += a3;
+      }
+    }
+    __syncthreads();
+  }
+  for (int c = tid; c < nrp; c += kThreads) tpart[(int64_t)blockIdx.x * nrp + c] = red[c];
+}
+
 // t[k] = sum_b tpart[b][k] in a fixed order: a block owns 16 columns; its 16
 // row groups of 16 threads each sum every 16th partial row, then combine in LDS.
 __global__ __launch_bounds__(kThreads) void lr_t_finish_kernel(const double* __restrict__ tpart, int nb, int nrp,
-                                                               double* __restrict__ t, const PcgScalars* S) {
+                                                               double* __restrict__ t, PcgScalars* S,
+                                                               const double* __restrict__ rrp, int grr) {
   if (S != nullptr && S->done) return;
   __shared__ double red[16][17];
+  __shared__ double shd[16];
+  // inside the loop this pass takes the stopping decision of the current iteration first
+  if (rrp != nullptr && !pcg_decide(S->kcur - 1, S, rrp, grr, shd)) return;
   const int g = threadIdx.x >> 4, cl = threadIdx.x & 15;
-  const int k = blockIdx.x * 16 + cl;
+  const int col = blockIdx.x * 16 + cl;
   double s = 0.0;
-  if (k < nrp)
-    for (int b = g; b < nb; b += 16) s += tpart[(int64_t)b * nrp + k];
+  if (col < nrp)
+    for (int b = g; b < nb; b += 16) s += tpart[(int64_t)b * nrp + col];
   red[g][cl] = s;
   __syncthreads();
-  if (g == 0 && k < nrp) {
+  if (g == 0 && col < nrp) {
     double v = 0.0;
     for (int gg = 0; gg < 16; ++gg) v += red[gg][cl];
-    t[k] = v;
+    t[col] = v;
   }
 }
 
@@ -385,15 +487,20 @@ __global__ void axpy_kernel(double* __restrict__ x, const double* __restrict__ d
     x[i] += d[i];
 }
 
-// theta = P r for the low-rank preconditioner; inside the loop (rrp set) the
-// first pass also takes the stopping decision of iteration k.
+// theta = P r for the low-rank preconditioner (three passes); with rrp set the
+// middle pass first takes the stopping decision of iteration k, and the first
+// pass is skipped when `skip_partial` says the fused update already wrote the
+// t partials.
 template <typename MT>
-laker_status enqueue_lowrank(const PrecondView& P, const double* r, double* theta, int64_t n, PcgScalars* S, int k,
-                             const double* rrp, int grr, double* rzp, double* tpart, double* t, hipStream_t st) {
+laker_status enqueue_lowrank(const PrecondView& P, const double* r, double* theta, int64_t n, PcgScalars* S,
+                             const double* rrp, int grr, double* rzp, double* tpart, double* t, bool skip_partial,
+                             hipStream_t st) {
   const int nb = (int)((n + kTRows - 1) / kTRows);
-  lr_t_partial_kernel<MT><<<nb, kThreads, 0, st>>>((const MT*)P.B, r, n, P.nrp, tpart, S, k, rrp, grr);
-  LK_CHECK_LAUNCH();
-  lr_t_finish_kernel<<<(P.nrp + 15) / 16, kThreads, 0, st>>>(tpart, nb, P.nrp, t, S);
+  if (!skip_partial) {
+    lr_t_partial_kernel<MT><<<nb, kThreads, 0, st>>>((const MT*)P.B, r, n, P.nrp, tpart, S);
+    LK_CHECK_LAUNCH();
+  }
+  lr_t_finish_kernel<<<(P.nrp + 15) / 16, kThreads, 0, st>>>(tpart, nb, P.nrp, t, S, rrp, grr);
   LK_CHECK_LAUNCH();
   lr_apply_kernel<MT><<<(unsigned)apply_blocks(n), kThreads, 0, st>>>((const MT*)P.Bt, t, r, theta, n, P.nrp, P.c0p,
                                                                       S, rzp);
@@ -402,10 +509,10 @@ laker_status enqueue_lowrank(const PrecondView& P, const double* r, double* thet
 }
 
 laker_status enqueue_lowrank_any(const PrecondView& P, const double* r, double* theta, int64_t n, PcgScalars* S,
-                                 int k, const double* rrp, int grr, double* rzp, double* tpart, double* t,
-                                 hipStream_t st) {
-  if (P.f32) return enqueue_lowrank<float>(P, r, theta, n, S, k, rrp, grr, rzp, tpart, t, st);
-  return enqueue_lowrank<double>(P, r, theta, n, S, k, rrp, grr, rzp, tpart, t, st);
+                                 const double* rrp, int grr, double* rzp, double* tpart, double* t,
+                                 bool skip_partial, hipStream_t st) {
+  if (P.f32) return enqueue_lowrank<float>(P, r, theta, n, S, rrp, grr, rzp, tpart, t, skip_partial, st);
+  return enqueue_lowrank<double>(P, r, theta, n, S, rrp, grr, rzp, tpart, t, skip_partial, st);
 }
 
 }  // namespace
@@ -433,7 +540,9 @@ SolveWs plan_solve_ws(void* base, int64_t n, int d, int64_t m) {
   w.S = c.take<PcgScalars>(1);
   w.bpart = c.take<double>(2 * kMaxBlocks);
   w.yyp = c.take<double>(kMaxBlocks);
-  w.rrp = c.take<double>(kMaxBlocks);
+  // partials of ||r||^2 come from up to max(kMaxBlocks, n / kTRows) blocks
+  const int64_t nrrp = (n + kTRows - 1) / kTRows > kMaxBlocks ? (n + kTRows - 1) / kTRows : kMaxBlocks;
+  w.rrp = c.take<double>((size_t)nrrp);
   w.rzp = c.take<double>(kMaxBlocks);
   w.papp = c.take<double>(kMaxBlocks);
   w.tpart = c.take<double>((size_t)((n + kTRows - 1) / kTRows) * kMaxNr);
@@ -483,8 +592,8 @@ laker_status true_residual(const Problem& pb, const SolveWs& ws, const double* y
 }
 
 laker_status pcg_run(const Problem& pb, const SolveWs& ws, const PrecondView& P, const double* rhs, double* alpha,
-                     bool warm, double tol, int max_iter, int check_every, int prec, laker_stats* stats,
-                     hipStream_t st) {
+                     bool warm, double tol, int max_iter, int check_every, int prec, bool use_graph, bool profile,
+                     laker_stats* stats, hipStream_t st) {
   const int64_t n = pb.n;
   const int g = red_blocks(n);
   const int ga = apply_blocks(n);
@@ -518,51 +627,143 @@ laker_status pcg_run(const Problem& pb, const SolveWs& ws, const PrecondView& P,
   if (P.kind == LAKER_PRECOND_JACOBI) {
     jacobi_apply_kernel<<<g, kThreads, 0, st>>>(r, dinv, th, n, S, ws.rzp);
     LK_CHECK_LAUNCH();
-    pcg_pupdate_kernel<LAKER_PRECOND_JACOBI><<<g, kThreads, 0, st>>>(0, 1, th, p, n, S, ws.rrp, g, ws.rzp, g);
+    pcg_pupdate_kernel<LAKER_PRECOND_JACOBI><<<g, kThreads, 0, st>>>(1, th, p, n, S, ws.rrp, g, ws.rzp, g);
   } else if (P.kind == LAKER_PRECOND_NONE) {
-    pcg_pupdate_kernel<LAKER_PRECOND_NONE><<<g, kThreads, 0, st>>>(0, 1, r, p, n, S, ws.rrp, g, ws.rzp, g);
+    pcg_pupdate_kernel<LAKER_PRECOND_NONE><<<g, kThreads, 0, st>>>(1, r, p, n, S, ws.rrp, g, ws.rzp, g);
   } else {
-    laker_status e = enqueue_lowrank_any(P, r, th, n, S, 0, nullptr, 0, ws.rzp, ws.tpart, ws.t, st);
+    laker_status e = enqueue_lowrank_any(P, r, th, n, S, nullptr, 0, ws.rzp, ws.tpart, ws.t, false, st);
     if (e != LAKER_OK) return e;
-    pcg_pupdate_kernel<LAKER_PRECOND_CCCP><<<g, kThreads, 0, st>>>(0, 1, th, p, n, S, ws.rrp, g, ws.rzp, ga);
+    pcg_pupdate_kernel<LAKER_PRECOND_CCCP><<<g, kThreads, 0, st>>>(1, th, p, n, S, ws.rrp, g, ws.rzp, ga);
   }
   LK_CHECK_LAUNCH();
 
   KmvArgs Ak = kmv_args(eh, n, eh, n, p, ws);
   Ak.mode = 0;
   Ak.S = S;
+  Ak.pcg_step = 1;
+  const int nbt = (int)((n + kTRows - 1) / kTRows);
+  // one PCG iteration; every argument is fixed, the iteration index lives on the device
+  // profiling: a pair of events around each kernel product (eager launches only)
+  std::vector<hipEvent_t> pev;
+  const bool prof = profile && !use_graph;
+  auto enqueue_iteration = [&](hipStream_t s2) -> laker_status {
+    if (prof) {
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      LK_TRY(hipEventCreate(&e0));
+      LK_TRY(hipEventCreate(&e1));
+      pev.push_back(e0);
+      pev.push_back(e1);
+      LK_TRY(hipEventRecord(e0, s2));
+      LK_TRY(kmv_run(prec, pb.dp, pl, Ak, s2));
+      LK_TRY(hipEventRecord(e1, s2));
+    } else {
+      LK_TRY(kmv_run(prec, pb.dp, pl, Ak, s2));
+    }
+    pcg_ap_kernel<<<g, kThreads, 0, s2>>>(p, ws.part, pl.nsplit, Ap, n, pb.lambda, ws.papp, S);
+    LK_CHECK_LAUNCH();
+    if (P.kind == LAKER_PRECOND_JACOBI) {
+      pcg_update_kernel<LAKER_PRECOND_JACOBI><<<g, kThreads, 0, s2>>>(alpha, r, p, Ap, dinv, th, n, S, ws.papp, g,
+                                                                      ws.rrp, ws.rzp);
+      LK_CHECK_LAUNCH();
+      pcg_pupdate_kernel<LAKER_PRECOND_JACOBI><<<g, kThreads, 0, s2>>>(0, th, p, n, S, ws.rrp, g, ws.rzp, g);
+    } else if (P.kind == LAKER_PRECOND_NONE) {
+      pcg_update_kernel<LAKER_PRECOND_NONE><<<g, kThreads, 0, s2>>>(alpha, r, p, Ap, nullptr, th, n, S, ws.papp, g,
+                                                                    ws.rrp, ws.rzp);
+      LK_CHECK_LAUNCH();
+      pcg_pupdate_kernel<LAKER_PRECOND_NONE><<<g, kThreads, 0, s2>>>(0, r, p, n, S, ws.rrp, g, ws.rzp, g);
+    } else {
+      if (P.f32)
+        pcg_update_t_kernel<float><<<nbt, kThreads, 0, s2>>>(alpha, r, p, Ap, (const float*)P.B, P.nrp, n, S,
+                                                             ws.papp, g, ws.rrp, ws.tpart);
+      else
+        pcg_update_t_kernel<double><<<nbt, kThreads, 0, s2>>>(alpha, r, p, Ap, (const double*)P.B, P.nrp, n, S,
+                                                              ws.papp, g, ws.rrp, ws.tpart);
+      LK_CHECK_LAUNCH();
+      laker_status e = enqueue_lowrank_any(P, r, th, n, S, ws.rrp, nbt, ws.rzp, ws.tpart, ws.t, true, s2);
+      if (e != LAKER_OK) return e;
+      pcg_pupdate_kernel<LAKER_PRECOND_CCCP><<<g, kThreads, 0, s2>>>(0, th, p, n, S, ws.rrp, g, ws.rzp, ga);
+    }
+    LK_CHECK_LAUNCH();
+    return LAKER_OK;
+  };
+
+  // The chunk of `check_every` iterations is captured once into a HIP graph
+  // (on a capture stream of the library) and replayed on `st`: the launches
+  // of a chunk then leave the host together.  Without graphs the kernels are
+  // enqueued one by one.
+  hipGraphExec_t gexec = nullptr;
+  if (use_graph) {
+    hipStream_t cs = capture_stream();
+    hipGraph_t graph = nullptr;
+    bool ok = cs != nullptr && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+      laker_status e = LAKER_OK;
+      for (int c = 0; c < check_every && e == LAKER_OK; ++c) e = enqueue_iteration(cs);
+      ok = hipStreamEndCapture(cs, &graph) == hipSuccess && e == LAKER_OK;
+      if (ok) ok = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0) == hipSuccess;
+      if (graph != nullptr) (void)hipGraphDestroy(graph);
+    }
+    if (!ok) {
+      (void)hipGetLastError();
+      if (gexec != nullptr) (void)hipGraphExecDestroy(gexec);
+      return LAKER_EHIP;
+    }
+  }
   PcgScalars hs;
   int k = 0;
+  laker_status loop_status = LAKER_OK;
   for (;;) {
-    for (int c = 0; c < check_every; ++c, ++k) {
-      // A p (column-range partials), then Ap and p^T A p partials
-      LK_TRY(kmv_run(prec, pb.dp, pl, Ak, st));
-      pcg_ap_kernel<<<g, kThreads, 0, st>>>(p, ws.part, pl.nsplit, Ap, n, pb.lambda, ws.papp, S);
-      LK_CHECK_LAUNCH();
-      if (P.kind == LAKER_PRECOND_JACOBI) {
-        pcg_update_kernel<LAKER_PRECOND_JACOBI><<<g, kThreads, 0, st>>>(k, alpha, r, p, Ap, dinv, th, n, S, ws.papp,
-                                                                         g, ws.rrp, ws.rzp);
-        LK_CHECK_LAUNCH();
-        pcg_pupdate_kernel<LAKER_PRECOND_JACOBI><<<g, kThreads, 0, st>>>(k, 0, th, p, n, S, ws.rrp, g, ws.rzp, g);
-      } else if (P.kind == LAKER_PRECOND_NONE) {
-        pcg_update_kernel<LAKER_PRECOND_NONE><<<g, kThreads, 0, st>>>(k, alpha, r, p, Ap, nullptr, th, n, S, ws.papp,
-                                                                       g, ws.rrp, ws.rzp);
-        LK_CHECK_LAUNCH();
-        pcg_pupdate_kernel<LAKER_PRECOND_NONE><<<g, kThreads, 0, st>>>(k, 0, r, p, n, S, ws.rrp, g, ws.rzp, g);
-      } else {
-        pcg_update_kernel<LAKER_PRECOND_CCCP><<<g, kThreads, 0, st>>>(k, alpha, r, p, Ap, nullptr, th, n, S, ws.papp,
-                                                                       g, ws.rrp, ws.rzp);
-        LK_CHECK_LAUNCH();
-        laker_status e = enqueue_lowrank_any(P, r, th, n, S, k, ws.rrp, g, ws.rzp, ws.tpart, ws.t, st);
-        if (e != LAKER_OK) return e;
-        pcg_pupdate_kernel<LAKER_PRECOND_CCCP><<<g, kThreads, 0, st>>>(k, 0, th, p, n, S, ws.rrp, g, ws.rzp, ga);
+    if (gexec != nullptr) {
+      if (hipGraphLaunch(gexec, st) != hipSuccess) {
+        loop_status = LAKER_EHIP;
+        break;
       }
-      LK_CHECK_LAUNCH();
+    } else {
+      for (int c = 0; c < check_every; ++c) {
+        loop_status = enqueue_iteration(st);
+        if (loop_status != LAKER_OK) break;
+      }
+      if (loop_status != LAKER_OK) break;
     }
-    LK_TRY(hipMemcpyAsync(&hs, S, sizeof(hs), hipMemcpyDeviceToHost, st));
-    LK_TRY(hipStreamSynchronize(st));
+    k += check_every;
+    if (hipMemcpyAsync(&hs, S, sizeof(hs), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      loop_status = LAKER_EHIP;
+      break;
+    }
     if (hs.done || k >= max_iter + check_every) break;
   }
+  if (gexec != nullptr) (void)hipGraphExecDestroy(gexec);
+  if (prof) {
+    // products of iterations that ran, and all launches (the ones enqueued after
+    // convergence return at entry)
+    double tot = 0.0, tot_all = 0.0;
+    int cnt = 0, cnt_all = 0;
+    for (size_t q = 0; q + 1 < pev.size(); q += 2) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, pev[q], pev[q + 1]) != hipSuccess) continue;
+      tot_all += ms;
+      ++cnt_all;
+      if ((int)(q / 2) < hs.iters) {
+        tot += ms;
+        ++cnt;
+      }
+    }
+    for (hipEvent_t e : pev) (void)hipEventDestroy(e);
+    if (stats != nullptr) {
+      if (cnt > 0) {
+        const double prev = stats->kmv_ms * stats->kmv_count;
+        stats->kmv_count += cnt;
+        stats->kmv_ms = (prev + tot) / stats->kmv_count;
+      }
+      if (cnt_all > 0) {
+        const double prev = stats->kmv_launch_ms * stats->kmv_launches;
+        stats->kmv_launches += cnt_all;
+        stats->kmv_launch_ms = (prev + tot_all) / stats->kmv_launches;
+      }
+    }
+  }
+  if (loop_status != LAKER_OK) return loop_status;
   if (stats) {
     stats->iters += hs.iters;
     stats->relres = hs.yy > 0 ? sqrt(hs.rr / hs.yy) : 0.0;
@@ -580,7 +781,7 @@ laker_status axpy_inplace(double* x, const double* d, int64_t n, hipStream_t st)
 
 laker_status apply_lowrank_once(const PrecondView& P, const double* r, double* theta, int64_t n, const SolveWs& ws,
                                 hipStream_t st) {
-  return enqueue_lowrank_any(P, r, theta, n, nullptr, 0, nullptr, 0, nullptr, ws.tpart, ws.t, st);
+  return enqueue_lowrank_any(P, r, theta, n, nullptr, nullptr, 0, nullptr, ws.tpart, ws.t, false, st);
 }
 
 }  // namespace lk

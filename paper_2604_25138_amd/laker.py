@@ -47,12 +47,14 @@ class laker_precond(C.Structure):
 class laker_pcg_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("precision", C.c_int32), ("refine", C.c_int32),
                 ("ir_max", C.c_int32), ("inner_tol", C.c_double), ("warm_start", C.c_int32),
-                ("check_every", C.c_int32)]
+                ("check_every", C.c_int32), ("graph", C.c_int32), ("profile", C.c_int32)]
 
 
 class laker_stats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("ir_steps", C.c_int32), ("cccp_iters", C.c_int32), ("status", C.c_int32),
-                ("relres", C.c_double), ("relres_true", C.c_double), ("ir_relres", C.c_double * 64)]
+                ("relres", C.c_double), ("relres_true", C.c_double), ("ir_relres", C.c_double * 64),
+                ("kmv_ms", C.c_double), ("kmv_count", C.c_int32), ("kmv_launches", C.c_int32),
+                ("kmv_launch_ms", C.c_double)]
 
 
 class LakerError(RuntimeError):
@@ -220,7 +222,8 @@ def jacobi_precond(prob: Problem) -> Precond:
 
 def pcg_solve(prob: Problem, y, precond: Precond | None = None, tol: float = 1e-10, max_iter: int = 10000,
               precision="f64", refine: bool = False, inner_tol: float = 1e-2, ir_max: int = 64,
-              alpha0: torch.Tensor | None = None, check_every: int = 16, allow_noconv: bool = False):
+              alpha0: torch.Tensor | None = None, check_every: int = 16, allow_noconv: bool = False,
+              graph: bool = False, profile: bool = False):
     """Returns (alpha, stats)."""
     lib = load()
     y = _dev_f64(y, prob.device)
@@ -229,7 +232,7 @@ def pcg_solve(prob: Problem, y, precond: Precond | None = None, tol: float = 1e-
     else:
         alpha = torch.empty_like(y)
     opts = laker_pcg_opts(tol, max_iter, _PREC[precision], 1 if refine else 0, ir_max, inner_tol,
-                          1 if alpha0 is not None else 0, check_every)
+                          1 if alpha0 is not None else 0, check_every, 1 if graph else 0, 1 if profile else 0)
     nb = lib.laker_solve_workspace_bytes(prob.n, prob.d, 0)
     ws = _workspace("solve", nb, prob.device)
     st = laker_stats()

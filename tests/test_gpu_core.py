@@ -277,7 +277,50 @@ def test_solves_are_deterministic():
     assert torch.equal(a1, a2) and s1.iters == s2.iters
 
 
+@pytest.mark.parametrize("kind", ["none", "jacobi", "cccp"])
+def test_graph_replay_matches_eager(kind):
+    """Chunks of PCG iterations replayed from a captured HIP graph (many
+    replays, with host synchronisation and other eager work in between) give
+    bitwise the same iterate as the eagerly enqueued kernels."""
+    pr = make_problem(900, 16, 1e-3, seed=11)
+    prob = _gp(pr)
+    if kind == "none":
+        pc = None
+    elif kind == "jacobi":
+        pc = L().jacobi_precond(prob)
+    else:
+        pc = L().fit_precond(prob, torch.tensor(make_directions(pr.n, 48, 11), device=DEV))
+    a1, s1 = L().pcg_solve(prob, pr.y, pc, tol=1e-11, max_iter=5000, check_every=8, graph=True)
+    _ = L().kernel_matvec(prob, torch.ones(pr.n, dtype=torch.float64, device=DEV))   # eager work in between
+    a2, s2 = L().pcg_solve(prob, pr.y, pc, tol=1e-11, max_iter=5000, check_every=8, graph=False)
+    assert s1.iters == s2.iters and s1.iters > 16
+    assert torch.equal(a1, a2)
+    b1, t1 = L().pcg_solve(prob, pr.y, pc, tol=1e-11, max_iter=5000, precision="bf16", refine=True,
+                           inner_tol=1e-1, check_every=8, graph=True)
+    b2, t2 = L().pcg_solve(prob, pr.y, pc, tol=1e-11, max_iter=5000, precision="bf16", refine=True,
+                           inner_tol=1e-1, check_every=8, graph=False)
+    assert t1.iters == t2.iters and torch.equal(b1, b2)
+
+
 def test_iteration_cap_returns_enoconv():
     pr = make_problem(512, 16, 1e-3, seed=0)
     alpha, st = L().pcg_solve(_gp(pr), pr.y, None, tol=1e-12, max_iter=5, allow_noconv=True)
     assert st.iters == 5 and st.status == L().LAKER_ENOCONV
+
+
+def test_profiled_solve_matches_and_counts_products():
+    """Timing every product with events changes nothing in the result; one
+    timed product per iteration that ran, plus the launches that returned at
+    entry after convergence."""
+    pr = make_problem(900, 16, 1e-3, seed=12)
+    prob = _gp(pr)
+    pc = L().fit_precond(prob, torch.tensor(make_directions(pr.n, 48, 12), device=DEV))
+    a1, s1 = L().pcg_solve(prob, pr.y, pc, tol=1e-11, max_iter=5000, check_every=8, profile=True)
+    a2, s2 = L().pcg_solve(prob, pr.y, pc, tol=1e-11, max_iter=5000, check_every=8)
+    assert torch.equal(a1, a2) and s1.iters == s2.iters
+    assert s1.kmv_count == s1.iters and s1.kmv_ms > 0.0
+    assert s1.iters <= s1.kmv_launches < s1.iters + 8 and s1.kmv_launch_ms > 0.0
+    assert s2.kmv_count == 0
+    b1, t1 = L().pcg_solve(prob, pr.y, pc, tol=1e-11, max_iter=5000, precision="bf16", refine=True,
+                           inner_tol=1e-1, check_every=8, profile=True)
+    assert t1.kmv_count == t1.iters and t1.kmv_launches >= t1.iters
