@@ -86,132 +86,227 @@ __global__ void gemm_reduce_kernel(int64_t M, int64_t N, const double* __restric
 }
 
 constexpr int NB = 32;   // Gauss-Jordan pivot block
+constexpr int GT = 64;   // output tile of one block of the sweep
 
-// Pivot step of blocked Gauss-Jordan on block column K = [k0, k0 + nb):
-//   Pinv = A_KK^{-1} (scalar GJ in LDS; log det accumulated),
-//   Rh[r][j] = (Pinv A_K,:)[r][j] for j outside K, Pinv[r][j - k0] inside K,
-//   Cp[i][r] = A[i][k0 + r] (old column panel).
-// Every block inverts the small pivot block itself (identically) and then
-// produces its own 64 columns of Rh and 64 rows of Cp; block 0 records log det.
-__global__ __launch_bounds__(256) void gj_pivot_kernel(const double* __restrict__ A, int64_t N, int64_t lda,
-                                                       int64_t k0, int nb, double* __restrict__ Rh,
-                                                       double* __restrict__ Cp, double* __restrict__ logdet,
-                                                       int* __restrict__ flag, int first) {
-  __shared__ double Ps[2][NB][NB + 1];
-  __shared__ double pivs[NB];
-  __shared__ double lsum;
-  const int tid = threadIdx.x;
-  if (flag != nullptr && *flag) return;
-  for (int idx = tid; idx < nb * nb; idx += 256) {
-    int r = idx / nb, c = idx % nb;
-    Ps[0][r][c] = A[(k0 + r) * lda + k0 + c];
+// Arrival barrier over all blocks of a cooperative launch: every block adds one
+// to *bar once its writes are done, and waits until the counter reaches
+// `target`.  The wait is bounded (about 0.1 s); a block that gives up sets
+// *flag, so a stuck launch still drains.
+__device__ bool grid_barrier(unsigned* bar, unsigned target, int* flag) {
+  __shared__ int ok;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int good = 1;
+    unsigned spins = 0;
+    while ((int)(__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) < 0) {
+      __builtin_amdgcn_s_sleep(2);
+      if (++spins > (1u << 21)) {
+        good = 0;
+        break;
+      }
+    }
+    __threadfence();
+    if (!good) __hip_atomic_store(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    ok = good;
   }
   __syncthreads();
-  // scalar in-place Gauss-Jordan on the nb x nb block, one barrier per step:
-  // step k reads buffer k & 1 and writes the other.  Row k is scaled by the
-  // pivot (its column-k entry becoming 1/piv); every other row loses its
-  // multiple of row k (its column-k entry becoming -f/piv).
-  for (int k = 0; k < nb; ++k) {
-    const int cur = k & 1;
-    const double piv = Ps[cur][k][k];
-    const double ip = 1.0 / piv;
-    if (tid == 0) pivs[k] = piv;
-    for (int idx = tid; idx < nb * nb; idx += 256) {
-      const int r = idx / nb, c = idx % nb;
-      const double rk = (c == k ? 1.0 : Ps[cur][k][c]) * ip;
-      double v;
-      if (r == k) v = rk;
-      else v = (c == k ? 0.0 : Ps[cur][r][c]) - Ps[cur][r][k] * rk;
-      Ps[cur ^ 1][r][c] = v;
-    }
-    __syncthreads();
-  }
-  const int fin = nb & 1;   // buffer holding the inverse
-  // log det = sum of the logs of the pivots (one per thread, summed in order)
-  if (blockIdx.x == 0) {
-    if (tid < nb) pivs[tid] = (pivs[tid] > 0.0 && isfinite(pivs[tid])) ? log(pivs[tid]) : NAN;
-    __syncthreads();
-    if (tid == 0) {
-      double s = 0.0;
-      for (int k = 0; k < nb; ++k) s += pivs[k];
-      lsum = s;
-      logdet[0] = (first ? 0.0 : logdet[0]) + s;
-      if (!isfinite(s) && flag != nullptr) *flag = 1;
-    }
-  }
-  // this block's 64 columns of Rh = Pinv * A[K, :] (outside K), Pinv (inside K);
-  // the nb x 64 slab of A[K, :] is staged in LDS first
-  __shared__ double As[NB][64 + 1];
-  const int64_t c0 = (int64_t)blockIdx.x * 64;
-  for (int idx = tid; idx < nb * 64; idx += 256) {
-    const int r = idx / 64;
-    const int64_t j = c0 + (idx % 64);
-    As[r][idx % 64] = j < N ? A[(k0 + r) * lda + j] : 0.0;
-  }
-  __syncthreads();
-  for (int idx = tid; idx < nb * 64; idx += 256) {
-    const int r = idx / 64;
-    const int jl = idx % 64;
-    const int64_t j = c0 + jl;
-    if (j >= N) continue;
-    double v;
-    if (j >= k0 && j < k0 + nb) {
-      v = Ps[fin][r][j - k0];
-    } else {
-      v = 0.0;
-      for (int c = 0; c < nb; ++c) v = fma(Ps[fin][r][c], As[c][jl], v);
-    }
-    Rh[(int64_t)r * N + j] = v;
-  }
-  // and its 64 rows of the old column panel
-  for (int idx = tid; idx < 64 * nb; idx += 256) {
-    const int64_t i = c0 + idx / nb;
-    const int c = idx % nb;
-    if (i < N) Cp[i * NB + c] = A[i * lda + k0 + c];
-  }
+  return ok != 0;
 }
 
-// Update of all entries for pivot block K:
-//   rows in K:      A[i][j] = Rh[i - k0][j]
-//   rows outside K: A[i][j] = [j outside K] A[i][j] - sum_r Cp[i][r] Rh[r][j]
-__global__ __launch_bounds__(256) void gj_update_kernel(double* __restrict__ A, int64_t N, int64_t lda, int64_t k0,
-                                                        int nb, const double* __restrict__ Rh,
-                                                        const double* __restrict__ Cp, const int* __restrict__ flag) {
-  if (flag != nullptr && *flag) return;
-  __shared__ double Rs[NB][TB + 1];
-  __shared__ double Cs[TB][NB + 1];
+struct GjArgs {
+  double* A[2];       // matrices inverted in place (blockIdx.z selects one)
+  double* T[2];       // N x N partner buffer of each: the sweep alternates between the two
+  double* logdet[2];  // log det of each input
+  int* flag;          // set to 1 on a non-positive or non-finite pivot (or a stalled barrier)
+  unsigned* bar;      // arrival counter of the grid barrier
+  unsigned base;      // its value when the launch starts
+  int64_t N;
+};
+
+// Blocked Gauss-Jordan inverse of SPD matrices (no pivoting: every Schur
+// complement of an SPD matrix is SPD) in one cooperative launch.  Step k takes
+// the pivot block K = [k0, k0 + nb) of the current matrix S and writes the next
+// matrix D:
+//   P = S_KK^{-1};  x_j = P S_Kj for j outside K,  x_j = P e_(j - k0) inside K;
+//   D_ij = x_j[i - k0]                        for i in K,
+//   D_ij = [j outside K] S_ij - S_iK x_j      for i outside K,
+// which is the usual in-place sweep written with one update formula.  Every block
+// owns one 64 x 64 tile of D and computes P itself from the same data (so all
+// blocks take the same pivots and the same exits); one grid barrier per step
+// publishes the tiles.  log det is the sum of the logs of the scalar pivots.
+__global__ __launch_bounds__(256) void gj_sweep_kernel(GjArgs g) {
+  __shared__ double Ps[2][NB][NB + 1];
+  __shared__ double Sik[GT][NB + 1];
+  __shared__ double Skj[NB][GT + 1];
+  __shared__ double X[NB][GT + 1];
+  __shared__ double pivs[NB];
+  __shared__ double lds_ld;
+  __shared__ int bad;
   const int tid = threadIdx.x;
-  const int64_t i0 = (int64_t)blockIdx.y * TB, j0 = (int64_t)blockIdx.x * TB;
-  for (int idx = tid; idx < NB * TB; idx += 256) {
-    int r = idx / TB, c = idx % TB;
-    int64_t j = j0 + c;
-    Rs[r][c] = (r < nb && j < N) ? Rh[(int64_t)r * N + j] : 0.0;
-    int ii = idx / NB, rr = idx % NB;
-    int64_t i = i0 + ii;
-    Cs[ii][rr] = (rr < nb && i < N) ? Cp[i * NB + rr] : 0.0;
+  const int z = blockIdx.z;
+  const int64_t N = g.N;
+  const int64_t i0 = (int64_t)blockIdx.y * GT, j0 = (int64_t)blockIdx.x * GT;
+  const unsigned nblk = gridDim.x * gridDim.y * gridDim.z;
+  double* const bufs[2] = {g.A[z], g.T[z]};
+  if (__hip_atomic_load(g.flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+  if (tid == 0) {
+    lds_ld = 0.0;
+    bad = 0;
   }
-  __syncthreads();
   const int ty = tid >> 4, tx = tid & 15;
+  int step = 0;
+  for (int64_t k0 = 0; k0 < N; k0 += NB, ++step) {
+    const int nb = (int)(N - k0 < NB ? N - k0 : NB);
+    const double* __restrict__ S = bufs[step & 1];
+    double* __restrict__ D = bufs[(step & 1) ^ 1];
+    for (int idx = tid; idx < NB * NB; idx += 256) {
+      const int r = idx / NB, c = idx % NB;
+      Ps[0][r][c] = (r < nb && c < nb) ? S[(k0 + r) * N + k0 + c] : 0.0;
+    }
+    for (int idx = tid; idx < GT * NB; idx += 256) {
+      const int r = idx / NB, c = idx % NB;
+      const int64_t i = i0 + r;
+      Sik[r][c] = (i < N && c < nb) ? S[i * N + k0 + c] : 0.0;
+    }
+    for (int idx = tid; idx < NB * GT; idx += 256) {
+      const int r = idx / GT, c = idx % GT;
+      const int64_t j = j0 + c;
+      Skj[r][c] = (r < nb && j < N) ? S[(k0 + r) * N + j] : 0.0;
+    }
+    __syncthreads();
+    // Gauss-Jordan of the pivot block by the first wave, rows in registers:
+    // lane l holds row l / 2, columns 16 (l % 2) .. 16 (l % 2) + 15; pivot rows
+    // and multipliers travel by lane shuffles.  Rows and columns past nb are
+    // zero and stay zero.  The inverse lands in Ps[1].
+    if (tid < 64) {
+      const int r = tid >> 1, h = tid & 1;
+      double v[16];
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    int64_t i = i0 + ty * 4 + a;
-    if (i >= N) continue;
-    const bool in_k_row = (i >= k0 && i < k0 + nb);
+      for (int q = 0; q < 16; ++q) v[q] = Ps[0][r][16 * h + q];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      int64_t j = j0 + tx * 4 + b;
-      if (j >= N) continue;
-      double* aij = A + i * lda + j;
-      if (in_k_row) {
-        *aij = Rs[i - k0][tx * 4 + b];
-      } else {
-        double s = 0.0;
-        for (int r = 0; r < nb; ++r) s = fma(Cs[ty * 4 + a][r], Rs[r][tx * 4 + b], s);
-        const bool in_k_col = (j >= k0 && j < k0 + nb);
-        *aij = (in_k_col ? 0.0 : *aij) - s;
+      for (int k = 0; k < NB; ++k) {
+        if (k < nb) {
+          const int kq = k & 15, kh = k >> 4;
+          const double piv = __shfl(v[kq], 2 * k + kh, 64);
+          const double m = __shfl(v[kq], 2 * r + kh, 64);
+          const double ip = 1.0 / piv;
+          if (tid == 0) pivs[k] = piv;
+#pragma unroll
+          for (int q = 0; q < 16; ++q) {
+            const double rowk = __shfl(v[q], 2 * k + h, 64);
+            const int c = 16 * h + q;
+            const double rk = (c == k ? 1.0 : rowk) * ip;
+            v[q] = (r == k) ? rk : (c == k ? 0.0 : v[q]) - m * rk;
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 16; ++q) Ps[1][r][16 * h + q] = v[q];
+    }
+    __syncthreads();
+    // log det: the logs of the pivots, summed in order by one thread
+    if (tid < nb) {
+      const double pv = pivs[tid];
+      pivs[tid] = (pv > 0.0 && isfinite(pv)) ? log(pv) : NAN;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double sl = 0.0;
+      for (int k = 0; k < nb; ++k) sl += pivs[k];
+      if (isfinite(sl)) lds_ld += sl;
+      else bad = 1;
+    }
+    __syncthreads();
+    if (bad) {
+      if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0)
+        __hip_atomic_store(g.flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return;   // every block saw the same pivots and leaves at the same step
+    }
+    // X = P S_KJ (2 x 4 outputs per thread), then the columns inside K
+    {
+      const int r0 = (tid >> 4) * 2, cx = tid & 15;
+      double xa[2][4];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) xa[a][b] = 0.0;
+      for (int q = 0; q < nb; ++q) {
+        const double p0 = Ps[1][r0][q], p1 = Ps[1][r0 + 1][q];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const double sk = Skj[q][cx + 16 * b];
+          xa[0][b] = fma(p0, sk, xa[0][b]);
+          xa[1][b] = fma(p1, sk, xa[1][b]);
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int rr = r0 + a, c = cx + 16 * b;
+          const int64_t j = j0 + c;
+          double v = xa[a][b];
+          if (j >= k0 && j < k0 + nb) v = Ps[1][rr][j - k0];
+          X[rr][c] = (rr < nb && j < N) ? v : 0.0;
+        }
+    }
+    __syncthreads();
+    // the tile of D (4 x 4 outputs per thread)
+    {
+      double acc[4][4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+      for (int q = 0; q < nb; ++q) {
+        double sa[4], xb[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) sa[a] = Sik[ty + 16 * a][q];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) xb[b] = X[q][tx + 16 * b];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) acc[a][b] = fma(sa[a], xb[b], acc[a][b]);
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int il = ty + 16 * a;
+        const int64_t i = i0 + il;
+        if (i >= N) continue;
+        const bool in_k = (i >= k0 && i < k0 + nb);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int jl = tx + 16 * b;
+          const int64_t j = j0 + jl;
+          if (j >= N) continue;
+          const bool k_col = (j >= k0 && j < k0 + nb);
+          D[i * N + j] = in_k ? X[i - k0][jl] : (k_col ? 0.0 : S[i * N + j]) - acc[a][b];
+        }
+      }
+    }
+    if (k0 + NB < N) {
+      if (!grid_barrier(g.bar, g.base + (unsigned)(step + 1) * nblk, g.flag)) return;
+    }
+  }
+  // the result sits in the buffer written last; bring it home (each block
+  // copies the tile it wrote itself)
+  if (step & 1) {
+    const double* __restrict__ R = bufs[1];
+    double* __restrict__ A = bufs[0];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int64_t i = i0 + ty + 16 * a;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int64_t j = j0 + tx + 16 * b;
+        if (i < N && j < N) A[i * N + j] = R[i * N + j];
       }
     }
   }
+  if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) g.logdet[z][0] = lds_ld;
 }
 
 inline int ew_grid(int64_t n) {
@@ -249,23 +344,31 @@ hipError_t gemm_f64(int64_t M, int64_t N, int64_t K, const double* A, int64_t sa
   return hipGetLastError();
 }
 
-size_t gj_side_elems(int64_t N) { return (size_t)N * NB * 2; }
+size_t gj_side_elems(int64_t N) { return (size_t)N * N; }
 
-hipError_t spd_inverse_inplace(double* A, int64_t N, double* side, double* logdet, int* flag, hipStream_t st) {
-  double* Rh = side;
-  double* Cp = side + (size_t)N * NB;
-  dim3 grid((unsigned)((N + TB - 1) / TB), (unsigned)((N + TB - 1) / TB));
-  for (int64_t k0 = 0; k0 < N; k0 += NB) {
-    int nb = (int)(N - k0 < NB ? N - k0 : NB);
-    gj_pivot_kernel<<<(unsigned)((N + 63) / 64), 256, 0, st>>>(A, N, N, k0, nb, Rh, Cp, logdet, flag,
-                                                               k0 == 0 ? 1 : 0);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    gj_update_kernel<<<grid, 256, 0, st>>>(A, N, N, k0, nb, Rh, Cp, flag);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
+unsigned gj_barriers(int64_t N, int count) {
+  const unsigned t = (unsigned)((N + GT - 1) / GT);
+  const unsigned steps = (unsigned)((N + NB - 1) / NB);
+  return (steps > 0 ? steps - 1 : 0) * t * t * (unsigned)count;
+}
+
+hipError_t spd_inverse_sweep(int count, double* const* A, double* const* side, double* const* logdet, int64_t N,
+                             int* flag, unsigned* bar, unsigned base, hipStream_t st) {
+  if (count < 1 || count > 2) return hipErrorInvalidValue;
+  GjArgs g{};
+  for (int z = 0; z < count; ++z) {
+    g.A[z] = A[z];
+    g.T[z] = side[z];
+    g.logdet[z] = logdet[z];
   }
-  return hipSuccess;
+  g.flag = flag;
+  g.bar = bar;
+  g.base = base;
+  g.N = N;
+  const unsigned t = (unsigned)((N + GT - 1) / GT);
+  dim3 grid(t, t, (unsigned)count);
+  void* args[] = {&g};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(gj_sweep_kernel), grid, dim3(256), args, 0, st);
 }
 
 }  // namespace lk

@@ -17,12 +17,21 @@ hipError_t gemm_f64(int64_t M, int64_t N, int64_t K, const double* A, int64_t sa
                     int64_t sbk, int64_t sbj, double* C, int64_t ldc, double alpha, const double* alpha_dev,
                     double beta, double* partials, int nsplit, hipStream_t st);
 
-// Doubles of side storage spd_inverse_inplace needs for an N x N matrix.
+// Doubles of the partner buffer spd_inverse_sweep needs per N x N matrix.
 size_t gj_side_elems(int64_t N);
 
-// In-place inverse of an SPD N x N row-major matrix by blocked Gauss-Jordan;
-// logdet[0] receives log det A; flag[0] is set to 1 on a non-positive pivot
-// (and later launches of the same inverse do nothing).
-hipError_t spd_inverse_inplace(double* A, int64_t N, double* side, double* logdet, int* flag, hipStream_t st);
+// Grid-barrier arrivals one spd_inverse_sweep of `count` N x N matrices adds to
+// its counter.
+unsigned gj_barriers(int64_t N, int count);
+
+// In-place inverses of `count` (1 or 2) SPD N x N row-major matrices A[z] by a
+// blocked Gauss-Jordan sweep in one cooperative launch; side[z] is an N x N
+// partner buffer, logdet[z][0] receives log det A[z].  flag[0] is set to 1 on a
+// non-positive pivot (later sweeps then do nothing).  `bar` is the barrier
+// counter, whose value at launch must be `base`; the sweep adds
+// gj_barriers(N, count) to it.  The launch needs (ceil(N/64))^2 * count blocks
+// resident at once.
+hipError_t spd_inverse_sweep(int count, double* const* A, double* const* side, double* const* logdet, int64_t N,
+                             int* flag, unsigned* bar, unsigned base, hipStream_t st);
 
 }  // namespace lk

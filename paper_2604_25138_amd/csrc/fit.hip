@@ -14,6 +14,9 @@
 // inverses.  The solver applies P as c0 r + Bt (B^T r) with Bt = B Gs.
 #include "fit.hpp"
 
+#include <algorithm>
+#include <utility>
+
 #include "dense.hpp"
 #include "mrhs.hpp"
 
@@ -192,19 +195,23 @@ __global__ __launch_bounds__(1024) void cccp_update_kernel(const double* __restr
   const double a1 = (1.0 - rho) * c * n / (nr * tau);
   const double b1 = ((1.0 - rho) * c * gamma + rho) / tau;
   __syncthreads();
-  // D = a1 wnew - a0 w ; F = a0 w
+  // D = a1 wnew - a0 w ; F = a0 w.  Wave v takes rows v, v + 16, ...; its lanes
+  // the columns.
   double t_dc = 0.0, t_fc = 0.0, t_dd = 0.0, t_ff = 0.0;
-  for (int64_t idx = tid; idx < (int64_t)nr * nr; idx += 1024) {
-    int64_t k = idx / nr, l = idx - k * nr;
-    double ckl = C[idx];
-    double dk = a1 * wnew[k] - a0 * w[k], dl = a1 * wnew[l] - a0 * w[l];
-    double fk = a0 * w[k], fl = a0 * w[l];
-    double c2 = ckl * ckl;
-    t_dd = fma(dk * dl, c2, t_dd);
-    t_ff = fma(fk * fl, c2, t_ff);
-    if (k == l) {
-      t_dc += dk * ckl;
-      t_fc += fk * ckl;
+  const int lane = tid & 63, wv = tid >> 6;
+  for (int k = wv; k < nr; k += 16) {
+    const double dk = a1 * wnew[k] - a0 * w[k], fk = a0 * w[k];
+    const double* __restrict__ Ck = C + (int64_t)k * nr;
+    for (int l = lane; l < nr; l += 64) {
+      const double ckl = Ck[l];
+      const double dl = a1 * wnew[l] - a0 * w[l], fl = a0 * w[l];
+      const double c2 = ckl * ckl;
+      t_dd = fma(dk * dl, c2, t_dd);
+      t_ff = fma(fk * fl, c2, t_ff);
+      if (k == l) {
+        t_dc += dk * ckl;
+        t_fc += fk * ckl;
+      }
     }
   }
   t_dd = block_sum(t_dd, sh);
@@ -258,61 +265,72 @@ __global__ void make_b_kernel(const double* __restrict__ Ub, const double* __res
 }
 
 // Y = b I + a diag(sqrt w) C diag(sqrt w) (= b I + B^T B),  Zm = I
-__global__ void db_init_kernel(const double* __restrict__ C, const double* __restrict__ w,
-                               const CccpState* __restrict__ S, double* __restrict__ Y, double* __restrict__ Zm,
-                               int nr) {
-  const int64_t total = (int64_t)nr * nr;
+// R = b I + B^T B = b I + a diag(sqrt w) C diag(sqrt w) into Y, Zm = I, and
+// c = ||R||_F (>= the largest eigenvalue of R) into S->sq_c.
+__global__ __launch_bounds__(256) void sq_init_kernel(const double* __restrict__ C, const double* __restrict__ w,
+                                                      CccpState* S, double* __restrict__ Y, double* __restrict__ Zm,
+                                                      int nr, double* __restrict__ bpart) {
+  __shared__ double sh[16];
   const double a = S->a, b = S->b;
-  for (int64_t idx = (int64_t)blockIdx.x * kT + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * kT) {
-    int64_t i = idx / nr, j = idx - i * nr;
-    Y[idx] = a * sqrt(w[i] * w[j]) * C[idx] + (i == j ? b : 0.0);
+  double ss = 0.0;
+  const int total = nr * nr;
+  for (int idx = blockIdx.x * kT + threadIdx.x; idx < total; idx += gridDim.x * kT) {
+    const int i = idx / nr, j = idx - i * nr;
+    const double r = a * sqrt(w[i] * w[j]) * C[idx] + (i == j ? b : 0.0);
+    Y[idx] = r;
     Zm[idx] = (i == j) ? 1.0 : 0.0;
+    ss = fma(r, r, ss);
+  }
+  ss = block_sum(ss, sh);
+  if (threadIdx.x == 0) bpart[blockIdx.x] = ss;
+  if (last_block_arrived(&S->cnt[0])) {
+    const double t = ordered_sum(bpart, gridDim.x, sh);
+    if (threadIdx.x == 0) {
+      S->sq_c = sqrt(t);
+      S->db_iters = 0;
+      S->cnt[0] = 0;
+    }
   }
 }
 
-// Scaled Denman-Beavers step: mu = (det Y det Z)^{-1/(2 N)},
-// Y <- (mu Y + Z^{-1}/mu)/2, Z <- (mu Z + Y^{-1}/mu)/2; relative change of Y.
-__global__ __launch_bounds__(256) void db_step_kernel(double* __restrict__ Y, double* __restrict__ Zm,
-                                                      const double* __restrict__ Yi, const double* __restrict__ Zi,
-                                                      CccpState* S, int nr, double* __restrict__ bpart) {
+// X <- X / c (mode 0), X * sqrt(c) (mode 1), X / sqrt(c) (mode 2), c = S->sq_c
+__global__ void sq_scale_kernel(double* __restrict__ X, const CccpState* __restrict__ S, int mode, int total) {
+  const double c = S->sq_c;
+  const double f = mode == 0 ? 1.0 / c : (mode == 1 ? sqrt(c) : 1.0 / sqrt(c));
+  for (int idx = blockIdx.x * kT + threadIdx.x; idx < total; idx += gridDim.x * kT) X[idx] *= f;
+}
+
+// Coupled Newton-Schulz step, middle part: P = Z Y given, T = (3 I - P) / 2 in
+// place, and ||I - P||_F / sqrt(N) into S->db_change.
+__global__ __launch_bounds__(256) void sq_t_kernel(double* __restrict__ P, CccpState* S, int nr,
+                                                   double* __restrict__ bpart) {
   __shared__ double sh[16];
-  const double mu = exp(-(S->ld_y + S->ld_z) / (2.0 * nr));
-  const double imu = 1.0 / mu;
-  const int64_t total = (int64_t)nr * nr;
-  double dsum = 0.0, ysum = 0.0;
-  for (int64_t idx = (int64_t)blockIdx.x * kT + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * kT) {
-    double y0 = Y[idx];
-    double y1 = 0.5 * (mu * y0 + imu * Zi[idx]);
-    double z1 = 0.5 * (mu * Zm[idx] + imu * Yi[idx]);
-    Y[idx] = y1;
-    Zm[idx] = z1;
-    dsum += (y1 - y0) * (y1 - y0);
-    ysum += y1 * y1;
+  double ss = 0.0;
+  const int total = nr * nr;
+  for (int idx = blockIdx.x * kT + threadIdx.x; idx < total; idx += gridDim.x * kT) {
+    const int i = idx / nr, j = idx - i * nr;
+    const double e = (i == j ? 1.0 : 0.0) - P[idx];
+    ss = fma(e, e, ss);
+    P[idx] = (i == j ? 1.5 : 0.0) - 0.5 * P[idx];
   }
-  dsum = block_sum(dsum, sh);
-  ysum = block_sum(ysum, sh);
-  if (threadIdx.x == 0) {
-    bpart[blockIdx.x] = dsum;
-    bpart[kMaxBlocks + blockIdx.x] = ysum;
-  }
+  ss = block_sum(ss, sh);
+  if (threadIdx.x == 0) bpart[blockIdx.x] = ss;
   if (last_block_arrived(&S->cnt[0])) {
-    double d = ordered_sum(bpart, gridDim.x, sh);
-    double yv = ordered_sum(bpart + kMaxBlocks, gridDim.x, sh);
+    const double t = ordered_sum(bpart, gridDim.x, sh);
     if (threadIdx.x == 0) {
-      S->db_change = sqrt(d / yv);
+      S->db_change = sqrt(t / nr);
       S->db_iters += 1;
       S->cnt[0] = 0;
     }
   }
 }
 
-// W = sqrt(b) I + Y
 __global__ void add_sqrtb_diag_kernel(const double* __restrict__ Y, const CccpState* __restrict__ S,
                                       double* __restrict__ W, int nr) {
   const int64_t total = (int64_t)nr * nr;
   const double sb = sqrt(S->b);
   for (int64_t idx = (int64_t)blockIdx.x * kT + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * kT) {
-    int64_t i = idx / nr, j = idx - i * nr;
+    const int64_t i = idx / nr, j = idx - i * nr;
     W[idx] = Y[idx] + (i == j ? sb : 0.0);
   }
 }
@@ -393,7 +411,8 @@ FitWs plan_fit_ws(void* base, int64_t n, int d, int nr) {
   w.Yi = c.take<double>((size_t)nr * nr);
   w.Zi = c.take<double>((size_t)nr * nr);
   w.Gs = c.take<double>((size_t)nr * nr);
-  w.side = c.take<double>(gj_side_elems(nr));
+  w.side = c.take<double>(2 * gj_side_elems(nr));
+  w.gbar = c.take<unsigned>(64);
   w.q = c.take<double>(nr);
   w.w = c.take<double>(nr);
   w.wnew = c.take<double>(nr);
@@ -446,6 +465,18 @@ laker_status fit_cccp(const Problem& pb, const double* Z, const laker_cccp_opts&
   // 5. CCCP iterations
   cccp_init_kernel<<<1, 256, 0, st>>>(ws.S, ws.w, nr);
   LK_CHECK_LAUNCH();
+  // grid-barrier counter of the inverse sweeps: zero here, then advanced by a
+  // known amount per sweep
+  LK_TRY(hipMemsetAsync(ws.gbar, 0, sizeof(unsigned), st));
+  unsigned gbase = 0;
+  auto inverse = [&](int count, double* A0, double* A1, double* ld0, double* ld1) -> hipError_t {
+    double* As[2] = {A0, A1};
+    double* Ss[2] = {ws.side, ws.side + gj_side_elems(nr)};
+    double* Ls[2] = {ld0, ld1};
+    hipError_t e = spd_inverse_sweep(count, As, Ss, Ls, nr, &ws.S->gjflag, ws.gbar, gbase, st);
+    gbase += gj_barriers(nr, count);
+    return e;
+  };
   LK_TRY(hipMemsetAsync(ws.S->cnt, 0, sizeof(ws.S->cnt), st));
   CccpState hs;
   const int qgrid = (nr + 3) / 4;
@@ -453,7 +484,7 @@ laker_status fit_cccp(const Problem& pb, const double* Z, const laker_cccp_opts&
     if (t > 0) {
       cccp_build_m_kernel<<<ew_grid((int64_t)nr * nr), kT, 0, st>>>(ws.C, ws.w, ws.S, ws.M, nr);
       LK_CHECK_LAUNCH();
-      LK_TRY(spd_inverse_inplace(ws.M, nr, ws.side, &ws.S->ld_y, &ws.S->gjflag, st));
+      LK_TRY(inverse(1, ws.M, nullptr, &ws.S->ld_y, nullptr));
     }
     cccp_q_kernel<<<qgrid, 256, 0, st>>>(ws.M, ws.C, ws.w, ws.S, ws.q, nr, t == 0 ? 1 : 0);
     LK_CHECK_LAUNCH();
@@ -467,36 +498,56 @@ laker_status fit_cccp(const Problem& pb, const double* Z, const laker_cccp_opts&
   }
   if (hs.done == 2) return LAKER_EBREAKDOWN;
   if (stats) stats->cccp_iters = hs.iters;
-  // 6. B and R = b I + B^T B; Denman-Beavers for R^{1/2} (Y) and R^{-1/2} (Zm)
+  // 6. B and R = b I + B^T B; coupled Newton-Schulz iteration on R / c
+  //    (c = ||R||_F, so the spectrum lies in (0, 1]):
+  //      P = Z Y,  T = (3 I - P) / 2,  Y <- Y T,  Z <- T Z,
+  //    with Y -> (R/c)^{1/2} and Z -> (R/c)^{-1/2}; GEMMs only.
   const int nrp = pad_nr(nr);
   make_b_kernel<<<ew_grid(n * nrp), kT, 0, st>>>(ws.U, ws.w, ws.S, L.B64, n, nr, nrp);
   LK_CHECK_LAUNCH();
-  db_init_kernel<<<ew_grid((int64_t)nr * nr), kT, 0, st>>>(ws.C, ws.w, ws.S, ws.Y, ws.Zm, nr);
+  const int sq_grid = (int)std::min<int64_t>(kMaxBlocks, ((int64_t)nr * nr + kT * 4 - 1) / (kT * 4));
+  sq_init_kernel<<<sq_grid, kT, 0, st>>>(ws.C, ws.w, ws.S, ws.Y, ws.Zm, nr, ws.bpart);
   LK_CHECK_LAUNCH();
-  const size_t mb = (size_t)nr * nr * sizeof(double);
-  double prev_change = 1e300;
-  for (int it = 0; it < 80; ++it) {
-    LK_TRY(hipMemcpyAsync(ws.Yi, ws.Y, mb, hipMemcpyDeviceToDevice, st));
-    LK_TRY(hipMemcpyAsync(ws.Zi, ws.Zm, mb, hipMemcpyDeviceToDevice, st));
-    LK_TRY(spd_inverse_inplace(ws.Yi, nr, ws.side, &ws.S->ld_y, &ws.S->gjflag, st));
-    LK_TRY(spd_inverse_inplace(ws.Zi, nr, ws.side, &ws.S->ld_z, &ws.S->gjflag, st));
-    int gb = (int)(((int64_t)nr * nr + kT * 4 - 1) / (kT * 4));
-    if (gb > kMaxBlocks) gb = kMaxBlocks;
-    db_step_kernel<<<gb, kT, 0, st>>>(ws.Y, ws.Zm, ws.Yi, ws.Zi, ws.S, nr, ws.bpart);
+  sq_scale_kernel<<<ew_grid((int64_t)nr * nr), kT, 0, st>>>(ws.Y, ws.S, 0, nr * nr);
+  LK_CHECK_LAUNCH();
+  {
+    double* yc = ws.Y;
+    double* zc = ws.Zm;
+    double* y2 = ws.Zi;
+    double* z2 = ws.M;
+    double* pt = ws.Yi;
+    int nsq = gemm_pick_split(nr, nr, nr, ws.part_cap);
+    if (nsq > 4) nsq = 4;
+    double prev_change = 1e300;
+    for (int it = 0; it < 100; ++it) {
+      LK_TRY(gemm_f64(nr, nr, nr, zc, nr, 1, yc, nr, 1, pt, nr, 1.0, nullptr, 0.0, ws.part, nsq, st));
+      sq_t_kernel<<<sq_grid, kT, 0, st>>>(pt, ws.S, nr, ws.bpart);
+      LK_CHECK_LAUNCH();
+      LK_TRY(gemm_f64(nr, nr, nr, yc, nr, 1, pt, nr, 1, y2, nr, 1.0, nullptr, 0.0, ws.part, nsq, st));
+      LK_TRY(gemm_f64(nr, nr, nr, pt, nr, 1, zc, nr, 1, z2, nr, 1.0, nullptr, 0.0, ws.part, nsq, st));
+      std::swap(yc, y2);
+      std::swap(zc, z2);
+      LK_TRY(hipMemcpyAsync(&hs, ws.S, sizeof(hs), hipMemcpyDeviceToHost, st));
+      LK_TRY(hipStreamSynchronize(st));
+      if (!(hs.db_change == hs.db_change)) return LAKER_EBREAKDOWN;
+      // quadratic convergence to rounding level, or stagnation there
+      if (hs.db_change <= 1e-14) break;
+      if (hs.db_change <= 1e-10 && hs.db_change >= 0.5 * prev_change) break;
+      prev_change = hs.db_change;
+    }
+    // R^{1/2} = sqrt(c) Y into ws.Y, R^{-1/2} = Z / sqrt(c) into ws.Zm
+    const size_t mb = (size_t)nr * nr * sizeof(double);
+    if (yc != ws.Y) LK_TRY(hipMemcpyAsync(ws.Y, yc, mb, hipMemcpyDeviceToDevice, st));
+    if (zc != ws.Zm) LK_TRY(hipMemcpyAsync(ws.Zm, zc, mb, hipMemcpyDeviceToDevice, st));
+    sq_scale_kernel<<<ew_grid((int64_t)nr * nr), kT, 0, st>>>(ws.Y, ws.S, 1, nr * nr);
     LK_CHECK_LAUNCH();
-    LK_TRY(hipMemcpyAsync(&hs, ws.S, sizeof(hs), hipMemcpyDeviceToHost, st));
-    LK_TRY(hipStreamSynchronize(st));
-    if (hs.gjflag) return LAKER_EBREAKDOWN;
-    if (!(hs.db_change == hs.db_change)) return LAKER_EBREAKDOWN;
-    // quadratic convergence to rounding level, or stagnation there
-    if (hs.db_change <= 1e-13) break;
-    if (hs.db_change <= 1e-9 && hs.db_change >= 0.5 * prev_change) break;
-    prev_change = hs.db_change;
+    sq_scale_kernel<<<ew_grid((int64_t)nr * nr), kT, 0, st>>>(ws.Zm, ws.S, 2, nr * nr);
+    LK_CHECK_LAUNCH();
   }
   // 7. Gs = -b^{-1/2} Zm (sqrt(b) I + Y)^{-1}
   add_sqrtb_diag_kernel<<<ew_grid((int64_t)nr * nr), kT, 0, st>>>(ws.Y, ws.S, ws.M, nr);
   LK_CHECK_LAUNCH();
-  LK_TRY(spd_inverse_inplace(ws.M, nr, ws.side, &ws.S->ld_y, &ws.S->gjflag, st));
+  LK_TRY(inverse(1, ws.M, nullptr, &ws.S->ld_y, nullptr));
   write_header_kernel<<<1, 64, 0, st>>>(ws.S, L.hdr);
   LK_CHECK_LAUNCH();
   {

@@ -8,7 +8,8 @@ namespace lk {
 struct CccpState {
   double a, b, tau, change;   // Sigma = b I + a U_bar diag(w) U_bar^T; last relative change
   double ld_y, ld_z;          // log det of the matrices inverted by the Denman-Beavers step
-  double db_change;           // relative change of the Denman-Beavers iterate
+  double db_change;           // ||I - Z Y||_F / sqrt(N_r) of the square-root iteration
+  double sq_c;                // ||R||_F, the scale of the square-root iteration
   int iters, done, gjflag, db_iters;
   unsigned cnt[4];
 };
@@ -29,7 +30,8 @@ struct FitWs {
   double* Yi;
   double* Zi;
   double* Gs;
-  double* side;
+  double* side;           // 2 N_r x N_r partner buffers of the inverse sweeps
+  unsigned* gbar;         // grid-barrier counter of the inverse sweeps
   double* q;
   double* w;
   double* wnew;

@@ -712,26 +712,43 @@ laker_status pcg_run(const Problem& pb, const SolveWs& ws, const PrecondView& P,
   PcgScalars hs;
   int k = 0;
   laker_status loop_status = LAKER_OK;
+  // Eager chunks shrink near convergence: the next chunk is the number of
+  // iterations the residual decay of the last chunk predicts are still needed
+  // (plus one), so few launches are enqueued past the converged iteration.
+  int chunk = check_every;
+  double last_rr = -1.0;
+  int last_it = 0;
   for (;;) {
     if (gexec != nullptr) {
       if (hipGraphLaunch(gexec, st) != hipSuccess) {
         loop_status = LAKER_EHIP;
         break;
       }
+      k += check_every;
     } else {
-      for (int c = 0; c < check_every; ++c) {
+      for (int c = 0; c < chunk; ++c) {
         loop_status = enqueue_iteration(st);
         if (loop_status != LAKER_OK) break;
       }
       if (loop_status != LAKER_OK) break;
+      k += chunk;
     }
-    k += check_every;
     if (hipMemcpyAsync(&hs, S, sizeof(hs), hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess) {
       loop_status = LAKER_EHIP;
       break;
     }
     if (hs.done || k >= max_iter + check_every) break;
+    chunk = check_every;
+    if (last_rr > 0.0 && hs.rr > 0.0 && hs.rr < last_rr && hs.iters > last_it && hs.tol2 > 0.0) {
+      const double per_it = log(hs.rr / last_rr) / (double)(hs.iters - last_it);
+      const double need = log(hs.tol2 / hs.rr) / per_it;
+      if (need >= 0.0 && need < (double)check_every) chunk = (int)ceil(need) + 1;
+      if (chunk < 1) chunk = 1;
+      if (chunk > check_every) chunk = check_every;
+    }
+    last_rr = hs.rr;
+    last_it = hs.iters;
   }
   if (gexec != nullptr) (void)hipGraphExecDestroy(gexec);
   if (prof) {
