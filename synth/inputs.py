@@ -114,3 +114,24 @@ def make_batch_specs(count: int, n_lo: int, n_hi: int, lam_lo: float, lam_hi: fl
     lams = np.exp(rng.uniform(math.log(lam_lo), math.log(lam_hi), size=count))
     txs = rng.integers(tx_lo, tx_hi + 1, size=count)
     return [(int(a), float(b), int(c), seed * 100003 + i) for i, (a, b, c) in enumerate(zip(ns, lams, txs))]
+
+
+def make_probes(n: int, m: int, seed: int) -> np.ndarray:
+    """Gaussian probe vectors (n, m) for training the learned preconditioner."""
+    rng = np.random.default_rng(seed + 2_000_000)
+    return np.ascontiguousarray(rng.standard_normal(size=(n, m)))
+
+
+def make_mlp_init(in_dim: int, hidden: int, out_dim: int, seed: int, log_delta0: float = -7.0) -> dict:
+    """Initial weights of the 3-layer network (stored fan_in x fan_out), each
+    entry uniform in +-1/sqrt(fan_in); the last output's bias (the log of the
+    diagonal) starts at log_delta0."""
+    rng = np.random.default_rng(seed + 3_000_000)
+    dims = [(in_dim, hidden), (hidden, hidden), (hidden, out_dim)]
+    p = {}
+    for i, (a, b) in enumerate(dims, start=1):
+        bound = 1.0 / math.sqrt(a)
+        p[f"W{i}"] = rng.uniform(-bound, bound, size=(a, b))
+        p[f"b{i}"] = rng.uniform(-bound, bound, size=b)
+    p["b3"][out_dim - 1] = log_delta0
+    return p
