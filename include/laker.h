@@ -186,6 +186,71 @@ laker_status laker_predict(const laker_problem* prob, const double* alpha, int64
                            double* rhat, int32_t precision, void* workspace, size_t workspace_bytes,
                            void* stream);
 
+/* ---- learned rank-64-plus-diagonal preconditioner --------------------------
+ *
+ * Replaces the CCCP fit of Alg. 1 by a per-point network trained on CCCP fits.
+ * Network: x_i = [e_i, log lambda, log(n)/10, mean_j e_j, mean_j e_j^2]
+ * (3 d + 2 inputs) -> 256 -> 256 -> 65 with SiLU activations, bfloat16 MFMA
+ * products with float32 accumulation and float32 master weights.  Outputs
+ * o_i = (v_i in R^64, log delta_i) define S = diag(delta) + V V^T, a surrogate
+ * of Sigma_star^{1/2} (Sec. IV; SPD for any weights), and P = S^{-1} by the
+ * Woodbury identity.  Training minimises ||Z - S^{-1} U||_F^2 / (n m) over
+ * Gaussian probes Z with U = Sigma_star^{1/2} Z from laker_precond_sigma_half.
+ *
+ * Model buffer (device, caller-owned, laker_mlp_layout.bytes): three blocks of
+ * block_bytes -- weights theta, Adam first moments, Adam second moments -- each
+ * holding `count` floats with W1 (in x 256), b1, W2 (256 x 256), b2,
+ * W3 (256 x 65), b3 at the element offsets off[0..5] (weights fan_in x fan_out,
+ * row-major).  Callers write the initial weights and zero the moments. */
+typedef struct {
+  int32_t d;          /* embedding dimension                                   */
+  int32_t in_dim;     /* 3 d + 2                                               */
+  int64_t count;      /* floats in one block                                   */
+  int64_t off[6];     /* element offsets of W1 b1 W2 b2 W3 b3                   */
+  size_t block_bytes; /* bytes of one block (256-byte multiple)                 */
+  size_t bytes;       /* bytes of the model buffer                              */
+} laker_mlp_layout;
+
+typedef struct {
+  double lr, beta1, beta2, eps; /* Adam hyper-parameters                        */
+  int32_t step;       /* Adam step t >= 1 (bias correction)                     */
+  int32_t update;     /* 1: apply the Adam step; 0: gradient only               */
+} laker_train_opts;
+
+/* Layout of the model buffer for embeddings of dimension d (1..128). */
+laker_status laker_mlp_layout_query(int32_t d, laker_mlp_layout* out);
+/* Workspace bytes of the learned entry points for n points and m probes
+ * (m = 0 for inference). */
+size_t laker_learned_workspace_bytes(int64_t n, int32_t d, int32_t m);
+
+/* Network outputs o (n x 65 float32, device) for the problem's embeddings. */
+laker_status laker_learned_forward(const laker_problem* prob, const void* model, float* out, void* workspace,
+                                   size_t workspace_bytes, void* stream);
+
+/* One training step on one problem: loss ||Z - S^{-1} U||_F^2 / (n m) and its
+ * gradient; with opts->update the Adam step is applied to the model buffer.
+ * Z, U: device float64, n x m row-major.  grad_out: optional device float
+ * buffer of `count` floats (the gradient block); loss_out: optional host
+ * double (the call then synchronises `stream`). */
+laker_status laker_learned_train_step(const laker_problem* prob, void* model, int32_t m, const double* Z,
+                                      const double* U, const laker_train_opts* opts, float* grad_out,
+                                      double* loss_out, void* workspace, size_t workspace_bytes, void* stream);
+
+/* P = S^{-1} of the trained network into out->data (laker_precond_bytes(n, 64)
+ * bytes): kind LAKER_PRECOND_LEARNED, n_r = 64, P = D^{-1} + Bt B^T with
+ * B = D^{-1} V, Bt = -B (I + V^T D^{-1} V)^{-1}. */
+laker_status laker_learned_precond(const laker_problem* prob, const void* model, laker_precond* out,
+                                   void* workspace, size_t workspace_bytes, void* stream);
+
+/* Workspace bytes of laker_precond_sigma_half. */
+size_t laker_sigma_half_workspace_bytes(int64_t n, int32_t n_r, int32_t m);
+
+/* U = Sigma_star^{1/2} Z for a CCCP preconditioner P = Sigma_star^{-1/2}
+ * (eq. preconditioner-Sigmma), computed as Sigma_star (P Z) with
+ * Sigma_star = b I + B B^T.  Z, U: device float64 n x m row-major. */
+laker_status laker_precond_sigma_half(const laker_precond* precond, int32_t m, const double* Z, double* U,
+                                      void* workspace, size_t workspace_bytes, void* stream);
+
 /* Human-readable name of a status code (static string). */
 const char* laker_status_str(int32_t status);
 

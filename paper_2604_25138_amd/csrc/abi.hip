@@ -167,6 +167,7 @@ laker_status laker_pcg_solve(const laker_problem* prob, const laker_precond* pre
       if (precond->n_r < 1 || precond->n_r > kMaxNr) return LAKER_EINVAL;
       view.B = f64 ? (const void*)L.B64 : (const void*)L.B32;
       view.Bt = f64 ? (const void*)L.Bt64 : (const void*)L.Bt32;
+      if (precond->kind == LAKER_PRECOND_LEARNED) view.dinv = L.dinv64;
     } else {
       return LAKER_EINVAL;
     }
@@ -270,6 +271,131 @@ laker_status laker_predict(const laker_problem* prob, const double* alpha, int64
   A.out = rhat;
   LK_TRY(kmv_run(precision, pb.dp, pl, A, st));
   return LAKER_OK;
+}
+
+}  // extern "C"
+
+// ---- learned preconditioner -------------------------------------------------
+
+#include "learned.hpp"
+
+namespace {
+
+laker_status learned_flag(const LearnedWs& w, hipStream_t st) {
+  int f = 0;
+  LK_TRY(hipMemcpyAsync(&f, w.flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  LK_TRY(hipStreamSynchronize(st));
+  return f ? LAKER_EBREAKDOWN : LAKER_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+laker_status laker_mlp_layout_query(int32_t d, laker_mlp_layout* out) {
+  if (out == nullptr || d < 1 || d > kMaxD) return LAKER_EINVAL;
+  MlpLayout L = mlp_layout(d);
+  out->d = L.d;
+  out->in_dim = L.in_dim;
+  out->count = L.count;
+  for (int t = 0; t < 6; ++t) out->off[t] = L.off[t];
+  out->block_bytes = L.block_bytes;
+  out->bytes = L.bytes;
+  return LAKER_OK;
+}
+
+size_t laker_learned_workspace_bytes(int64_t n, int32_t d, int32_t m) {
+  if (n < 1 || d < 1 || d > kMaxD || m < 0) return 0;
+  return plan_learned_ws(nullptr, n, d, m).total;
+}
+
+laker_status laker_learned_forward(const laker_problem* prob, const void* model, float* out, void* workspace,
+                                   size_t workspace_bytes, void* stream) {
+  laker_status e = check_problem(prob);
+  if (e != LAKER_OK) return e;
+  if (model == nullptr || out == nullptr || workspace == nullptr) return LAKER_EINVAL;
+  LearnedWs W = plan_learned_ws(workspace, prob->n, prob->d, 0);
+  if (workspace_bytes < W.total) return LAKER_ENOMEM;
+  hipStream_t st = (hipStream_t)stream;
+  MlpLayout L = mlp_layout(prob->d);
+  e = learned_forward(to_problem(prob), L, (const float*)model, W, st);
+  if (e != LAKER_OK) return e;
+  LK_TRY(hipMemcpyAsync(out, W.O, sizeof(float) * prob->n * kOut, hipMemcpyDeviceToDevice, st));
+  return LAKER_OK;
+}
+
+laker_status laker_learned_train_step(const laker_problem* prob, void* model, int32_t m, const double* Z,
+                                      const double* U, const laker_train_opts* opts, float* grad_out,
+                                      double* loss_out, void* workspace, size_t workspace_bytes, void* stream) {
+  laker_status e = check_problem(prob);
+  if (e != LAKER_OK) return e;
+  if (model == nullptr || Z == nullptr || U == nullptr || opts == nullptr || workspace == nullptr || m < 1)
+    return LAKER_EINVAL;
+  if (opts->update && (opts->step < 1 || !finite_pos(opts->lr) || !(opts->beta1 >= 0.0 && opts->beta1 < 1.0) ||
+                       !(opts->beta2 >= 0.0 && opts->beta2 < 1.0) || !finite_pos(opts->eps)))
+    return LAKER_EINVAL;
+  LearnedWs W = plan_learned_ws(workspace, prob->n, prob->d, m);
+  if (workspace_bytes < W.total) return LAKER_ENOMEM;
+  hipStream_t st = (hipStream_t)stream;
+  MlpLayout L = mlp_layout(prob->d);
+  Problem pb = to_problem(prob);
+  float* theta = (float*)model;
+  e = learned_forward(pb, L, theta, W, st);
+  if (e != LAKER_OK) return e;
+  e = learned_loss_grad(pb, L, theta, Z, U, m, W, st);
+  if (e != LAKER_OK) return e;
+  if (grad_out != nullptr)
+    LK_TRY(hipMemcpyAsync(grad_out, W.grad, sizeof(float) * L.count, hipMemcpyDeviceToDevice, st));
+  if (opts->update) {
+    char* base = (char*)model;
+    LK_TRY(adam_update(theta, (float*)(base + L.block_bytes), (float*)(base + 2 * L.block_bytes), W.grad, L.count,
+                       opts->lr, opts->beta1, opts->beta2, opts->eps, opts->step, st));
+  }
+  if (loss_out != nullptr) {
+    LK_TRY(hipMemcpyAsync(loss_out, W.scal, sizeof(double), hipMemcpyDeviceToHost, st));
+    return learned_flag(W, st);
+  }
+  return LAKER_OK;
+}
+
+laker_status laker_learned_precond(const laker_problem* prob, const void* model, laker_precond* out,
+                                   void* workspace, size_t workspace_bytes, void* stream) {
+  laker_status e = check_problem(prob);
+  if (e != LAKER_OK) return e;
+  if (model == nullptr || out == nullptr || out->data == nullptr || workspace == nullptr) return LAKER_EINVAL;
+  if (prob->n < kRank) return LAKER_EINVAL;
+  LearnedWs W = plan_learned_ws(workspace, prob->n, prob->d, 0);
+  if (workspace_bytes < W.total) return LAKER_ENOMEM;
+  PrecondLayout P = precond_layout(out->data, prob->n, kRank);
+  if (out->bytes < P.total) return LAKER_ENOMEM;
+  hipStream_t st = (hipStream_t)stream;
+  MlpLayout L = mlp_layout(prob->d);
+  Problem pb = to_problem(prob);
+  e = learned_forward(pb, L, (const float*)model, W, st);
+  if (e != LAKER_OK) return e;
+  e = learned_build(pb, W, P, st);
+  if (e != LAKER_OK) return e;
+  out->kind = LAKER_PRECOND_LEARNED;
+  out->n = prob->n;
+  out->n_r = kRank;
+  return learned_flag(W, st);
+}
+
+size_t laker_sigma_half_workspace_bytes(int64_t n, int32_t n_r, int32_t m) {
+  if (n < 1 || n_r < 1 || n_r > kMaxNr || m < 1) return 0;
+  return plan_sigma_half_ws(nullptr, n, n_r, m).total;
+}
+
+laker_status laker_precond_sigma_half(const laker_precond* precond, int32_t m, const double* Z, double* U,
+                                      void* workspace, size_t workspace_bytes, void* stream) {
+  if (precond == nullptr || precond->data == nullptr || precond->kind != LAKER_PRECOND_CCCP) return LAKER_EINVAL;
+  if (Z == nullptr || U == nullptr || workspace == nullptr || m < 1 || precond->n < 1) return LAKER_EINVAL;
+  if (precond->n_r < 1 || precond->n_r > kMaxNr) return LAKER_EINVAL;
+  PrecondLayout P = precond_layout(precond->data, precond->n, precond->n_r);
+  if (precond->bytes < P.total) return LAKER_ENOMEM;
+  SigmaHalfWs W = plan_sigma_half_ws(workspace, precond->n, precond->n_r, m);
+  if (workspace_bytes < W.total) return LAKER_ENOMEM;
+  return sigma_half(P, precond->n, precond->n_r, m, Z, U, W, (hipStream_t)stream);
 }
 
 }  // extern "C"

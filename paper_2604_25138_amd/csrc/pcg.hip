@@ -382,13 +382,15 @@ __global__ __launch_bounds__(kThreads) void lr_t_finish_kernel(const double* __r
   }
 }
 
-// theta = c0 r + Bt t: 16 lanes per row (four rows per wave), 16-byte loads,
+// theta = c r + Bt t (c = c0, or dinv_i for a diagonal-plus-low-rank
+// preconditioner): 16 lanes per row (four rows per wave), 16-byte loads,
 // t in LDS; partials of r^T theta.
 template <typename MT>
 __global__ __launch_bounds__(kThreads) void lr_apply_kernel(const MT* __restrict__ Bt, const double* __restrict__ t,
                                                             const double* __restrict__ r, double* __restrict__ theta,
                                                             int64_t n, int nrp, const double* __restrict__ c0p,
-                                                            const PcgScalars* S, double* __restrict__ rzp) {
+                                                            const double* __restrict__ dinv, const PcgScalars* S,
+                                                            double* __restrict__ rzp) {
   if (S != nullptr && S->done) return;
   constexpr int VEC = 16 / (int)sizeof(MT);
   __shared__ double sh[16];
@@ -443,7 +445,7 @@ __global__ __launch_bounds__(kThreads) void lr_apply_kernel(const MT* __restrict
     acc += __shfl_xor(acc, 8, 64);
     if (sub == 0 && i < n) {
       const double ri = r[i];
-      const double th = fma(c0, ri, acc);
+      const double th = fma(dinv != nullptr ? dinv[i] : c0, ri, acc);
       theta[i] = th;
       rz += ri * th;
     }
@@ -503,7 +505,7 @@ laker_status enqueue_lowrank(const PrecondView& P, const double* r, double* thet
   lr_t_finish_kernel<<<(P.nrp + 15) / 16, kThreads, 0, st>>>(tpart, nb, P.nrp, t, S, rrp, grr);
   LK_CHECK_LAUNCH();
   lr_apply_kernel<MT><<<(unsigned)apply_blocks(n), kThreads, 0, st>>>((const MT*)P.Bt, t, r, theta, n, P.nrp, P.c0p,
-                                                                      S, rzp);
+                                                                      (const double*)P.dinv, S, rzp);
   LK_CHECK_LAUNCH();
   return LAKER_OK;
 }

@@ -25,8 +25,12 @@ _PREC = {"f64": F64, "f32": F32, "bf16": BF16, F64: F64, F32: F32, BF16: BF16}
 EXPORTS = (
     "laker_precond_bytes", "laker_fit_workspace_bytes", "laker_solve_workspace_bytes",
     "laker_kernel_matvec", "laker_fit_precond", "laker_jacobi_precond", "laker_pcg_solve",
-    "laker_predict", "laker_status_str",
+    "laker_predict", "laker_status_str", "laker_mlp_layout_query", "laker_learned_workspace_bytes",
+    "laker_learned_forward", "laker_learned_train_step", "laker_learned_precond",
+    "laker_sigma_half_workspace_bytes", "laker_precond_sigma_half",
 )
+MLP_KEYS = ("W1", "b1", "W2", "b2", "W3", "b3")
+MLP_HIDDEN, MLP_RANK = 256, 64
 
 
 class laker_problem(C.Structure):
@@ -55,6 +59,16 @@ class laker_stats(C.Structure):
                 ("relres", C.c_double), ("relres_true", C.c_double), ("ir_relres", C.c_double * 64),
                 ("kmv_ms", C.c_double), ("kmv_count", C.c_int32), ("kmv_launches", C.c_int32),
                 ("kmv_launch_ms", C.c_double)]
+
+
+class laker_mlp_layout(C.Structure):
+    _fields_ = [("d", C.c_int32), ("in_dim", C.c_int32), ("count", C.c_int64), ("off", C.c_int64 * 6),
+                ("block_bytes", C.c_size_t), ("bytes", C.c_size_t)]
+
+
+class laker_train_opts(C.Structure):
+    _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
+                ("step", C.c_int32), ("update", C.c_int32)]
 
 
 class LakerError(RuntimeError):
@@ -96,6 +110,21 @@ def load(path: str = LIB_PATH):
     lib.laker_predict.restype = i32
     lib.laker_status_str.argtypes = [i32]
     lib.laker_status_str.restype = C.c_char_p
+    lib.laker_mlp_layout_query.argtypes = [i32, P(laker_mlp_layout)]
+    lib.laker_mlp_layout_query.restype = i32
+    lib.laker_learned_workspace_bytes.argtypes = [i64, i32, i32]
+    lib.laker_learned_workspace_bytes.restype = sz
+    lib.laker_learned_forward.argtypes = [P(laker_problem), vp, vp, vp, sz, vp]
+    lib.laker_learned_forward.restype = i32
+    lib.laker_learned_train_step.argtypes = [P(laker_problem), vp, i32, vp, vp, P(laker_train_opts), vp,
+                                             P(C.c_double), vp, sz, vp]
+    lib.laker_learned_train_step.restype = i32
+    lib.laker_learned_precond.argtypes = [P(laker_problem), vp, P(laker_precond), vp, sz, vp]
+    lib.laker_learned_precond.restype = i32
+    lib.laker_sigma_half_workspace_bytes.argtypes = [i64, i32, i32]
+    lib.laker_sigma_half_workspace_bytes.restype = sz
+    lib.laker_precond_sigma_half.argtypes = [P(laker_precond), i32, vp, vp, vp, sz, vp]
+    lib.laker_precond_sigma_half.restype = i32
     _lib = lib
     return lib
 
@@ -276,3 +305,121 @@ def precond_parts(pc: Precond) -> dict:
     for name in ("B64", "Bt64", "B32", "Bt32"):
         out[name] = out[name].view(n, nrp)[:, :nr]
     return out
+
+
+# ---------------------------------------------------------------------------
+# learned rank-64-plus-diagonal preconditioner
+# ---------------------------------------------------------------------------
+
+def mlp_layout(d: int) -> laker_mlp_layout:
+    L = laker_mlp_layout()
+    _check(load().laker_mlp_layout_query(int(d), C.byref(L)), "laker_mlp_layout_query")
+    return L
+
+
+class MlpModel:
+    """Device buffer of the network: weights, Adam moments (library layout)."""
+
+    def __init__(self, d: int, device="cuda"):
+        self.d = int(d)
+        self.layout = mlp_layout(d)
+        self.buf = torch.zeros(self.layout.bytes, dtype=torch.uint8, device=device)
+        self.step = 0
+
+    @property
+    def device(self):
+        return self.buf.device
+
+    def _block(self, k: int) -> torch.Tensor:
+        L = self.layout
+        return self.buf[k * L.block_bytes:k * L.block_bytes + 4 * L.count].view(torch.float32)
+
+    def _shapes(self):
+        i, h, r = self.layout.in_dim, MLP_HIDDEN, MLP_RANK + 1
+        return {"W1": (i, h), "b1": (h,), "W2": (h, h), "b2": (h,), "W3": (h, r), "b3": (r,)}
+
+    def tensor_views(self, block: int = 0) -> dict:
+        th = self._block(block)
+        out = {}
+        for t, (k, shp) in enumerate(self._shapes().items()):
+            o = self.layout.off[t]
+            cnt = 1
+            for x in shp:
+                cnt *= x
+            out[k] = th[o:o + cnt].view(*shp)
+        return out
+
+    def set_params(self, params: dict) -> None:
+        """Write weights (numpy or torch, fan_in x fan_out) and zero the Adam moments."""
+        self.buf.zero_()
+        views = self.tensor_views(0)
+        for k in MLP_KEYS:
+            views[k].copy_(torch.as_tensor(params[k], dtype=torch.float32))
+        self.step = 0
+
+    def params(self) -> dict:
+        return {k: v.detach().cpu().double().numpy() for k, v in self.tensor_views(0).items()}
+
+    def grad_views(self, flat: torch.Tensor) -> dict:
+        out = {}
+        for t, (k, shp) in enumerate(self._shapes().items()):
+            o = self.layout.off[t]
+            cnt = 1
+            for x in shp:
+                cnt *= x
+            out[k] = flat[o:o + cnt].view(*shp)
+        return out
+
+
+def learned_forward(prob: Problem, model: MlpModel) -> torch.Tensor:
+    lib = load()
+    out = torch.empty(prob.n, MLP_RANK + 1, dtype=torch.float32, device=prob.device)
+    nb = lib.laker_learned_workspace_bytes(prob.n, prob.d, 0)
+    ws = _workspace("learned", nb, prob.device)
+    s = lib.laker_learned_forward(C.byref(prob.c), _ptr(model.buf), _ptr(out), _ptr(ws), ws.numel(), _stream())
+    _check(s, "laker_learned_forward")
+    return out
+
+
+def learned_train_step(prob: Problem, model: MlpModel, Z: torch.Tensor, U: torch.Tensor, lr: float = 1e-3,
+                       update: bool = True, want_grad: bool = False, want_loss: bool = True,
+                       beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+    """One Adam step on one problem; returns (loss or None, gradient dict or None)."""
+    lib = load()
+    m = Z.shape[1]
+    if update:
+        model.step += 1
+    opts = laker_train_opts(lr, beta1, beta2, eps, max(model.step, 1), 1 if update else 0)
+    g = torch.empty(model.layout.count, dtype=torch.float32, device=prob.device) if want_grad else None
+    loss = C.c_double(0.0)
+    nb = lib.laker_learned_workspace_bytes(prob.n, prob.d, m)
+    ws = _workspace("learned", nb, prob.device)
+    s = lib.laker_learned_train_step(C.byref(prob.c), _ptr(model.buf), m, _ptr(Z), _ptr(U), C.byref(opts), _ptr(g),
+                                     C.byref(loss) if want_loss else None, _ptr(ws), ws.numel(), _stream())
+    _check(s, "laker_learned_train_step")
+    return (loss.value if want_loss else None), (model.grad_views(g) if want_grad else None)
+
+
+def learned_precond(prob: Problem, model: MlpModel) -> Precond:
+    lib = load()
+    pbytes = lib.laker_precond_bytes(prob.n, MLP_RANK)
+    data = torch.empty(pbytes, dtype=torch.uint8, device=prob.device)
+    pc = laker_precond(PRECOND_LEARNED, MLP_RANK, prob.n, data.data_ptr(), pbytes)
+    nb = lib.laker_learned_workspace_bytes(prob.n, prob.d, 0)
+    ws = _workspace("learned", nb, prob.device)
+    s = lib.laker_learned_precond(C.byref(prob.c), _ptr(model.buf), C.byref(pc), _ptr(ws), ws.numel(), _stream())
+    _check(s, "laker_learned_precond")
+    return Precond(pc.kind, prob.n, MLP_RANK, data, pc)
+
+
+def sigma_half(pc: Precond, Z: torch.Tensor) -> torch.Tensor:
+    """U = Sigma_star^{1/2} Z for a fitted CCCP preconditioner."""
+    lib = load()
+    Z = _dev_f64(Z, pc.data.device)
+    m = Z.shape[1]
+    U = torch.empty_like(Z)
+    nb = lib.laker_sigma_half_workspace_bytes(pc.n, pc.n_r, m)
+    ws = _workspace("sigma_half", nb, pc.data.device)
+    s = lib.laker_precond_sigma_half(C.byref(pc.c), m, _ptr(Z), _ptr(U), _ptr(ws), ws.numel(), _stream())
+    _check(s, "laker_precond_sigma_half")
+    return U

@@ -1,0 +1,85 @@
+"""Training and use of the learned rank-64-plus-diagonal preconditioner.
+
+Orchestration only: every numerical step (the CCCP fits that provide the
+targets, Sigma_star^{1/2} Z, the network's forward and backward passes, the
+Adam update, the Woodbury preconditioner and the PCG solves) runs in the HIP
+library through the bindings of ``laker``.
+
+Targets: for each training problem the CCCP preconditioner P = Sigma_star^{-1/2}
+is fitted (Alg. 1, preconditioner learning) and U = Sigma_star^{1/2} Z is formed
+for Gaussian probes Z; the network learns S with S^{-1} U close to Z.
+At solve time the learned P = S^{-1} replaces the fit; when PCG stalls (the
+iteration budget runs out) the solve falls back to a CCCP fit, warm-started
+from the learned solve's iterate.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import laker as L
+
+
+@dataclass
+class Example:
+    prob: L.Problem
+    Z: torch.Tensor      # probes, n x m (device float64)
+    U: torch.Tensor      # Sigma_star^{1/2} Z
+
+
+def make_example(prob: L.Problem, directions, probes, gamma: float = 1e-3, precision: str = "bf16") -> Example:
+    """Fit CCCP on the problem and form its training pair (Z, Sigma_star^{1/2} Z)."""
+    pc = L.fit_precond(prob, directions, gamma=gamma, rho=0.0, precision=precision)
+    Z = L._dev_f64(probes, prob.device)
+    return Example(prob, Z, L.sigma_half(pc, Z))
+
+
+def train(model: L.MlpModel, examples: list, epochs: int, lr: float = 1e-3, seed: int = 0,
+          log_every: int = 0) -> list:
+    """Adam over the examples in a seeded random order each epoch; returns the
+    mean loss per epoch."""
+    rng = np.random.default_rng(seed)
+    hist = []
+    for ep in range(epochs):
+        order = rng.permutation(len(examples))
+        tot = 0.0
+        for i in order:
+            ex = examples[i]
+            loss, _ = L.learned_train_step(ex.prob, model, ex.Z, ex.U, lr=lr, update=True, want_loss=True)
+            tot += loss
+        hist.append(tot / len(examples))
+        if log_every and (ep % log_every == 0 or ep == epochs - 1):
+            print(f"epoch {ep}: mean loss {hist[-1]:.4e}", flush=True)
+    return hist
+
+
+@dataclass
+class LearnedSolve:
+    alpha: torch.Tensor
+    stats: L.laker_stats
+    fell_back: bool
+    learned_iters: int
+    precond_ms: float
+
+
+def solve_with_fallback(prob: L.Problem, y, model: L.MlpModel, fallback_directions, tol: float = 1e-6,
+                        budget: int = 4000, precision: str = "bf16", refine: bool = True, inner_tol: float = 0.1,
+                        gamma: float = 0.1, check_every: int = 32) -> LearnedSolve:
+    """PCG with the learned preconditioner; on a stall (budget exhausted) fit
+    CCCP and continue from the current iterate."""
+    t0 = time.perf_counter()
+    pc = L.learned_precond(prob, model)
+    torch.cuda.synchronize()
+    pms = (time.perf_counter() - t0) * 1e3
+    alpha, st = L.pcg_solve(prob, y, pc, tol=tol, max_iter=budget, precision=precision, refine=refine,
+                            inner_tol=inner_tol, ir_max=64, check_every=check_every, allow_noconv=True)
+    if st.status == L.LAKER_OK:
+        return LearnedSolve(alpha, st, False, st.iters, pms)
+    used = st.iters
+    pc2 = L.fit_precond(prob, fallback_directions, gamma=gamma, rho=0.0, precision=precision)
+    alpha, st2 = L.pcg_solve(prob, y, pc2, tol=tol, max_iter=100000, precision=precision, refine=refine,
+                             inner_tol=inner_tol, ir_max=64, alpha0=alpha, check_every=check_every)
+    return LearnedSolve(alpha, st2, True, used, pms)

@@ -1,0 +1,178 @@
+"""GPU parity of the learned preconditioner against its FP64 oracle, through the C ABI.
+
+Tolerances:
+  * network output and gradients: the library multiplies bfloat16-rounded
+    operands (8-bit significands, relative rounding 2^-9) with float32
+    accumulation; the oracle is exact float64.  Three stacked layers give a
+    norm-wise relative error of a few 2^-9; the bound used is 2e-2 per tensor
+    for outputs and gradients;
+  * Sigma^{1/2} Z, the Woodbury preconditioner and the solves are float64:
+    bounds scale with the conditioning as stated in each test.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import laker_oracle as O
+from oracle import learned_oracle as LO
+from synth import make_directions, make_mlp_init, make_probes, make_problem
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def L():
+    from paper_2604_25138_amd import laker
+    laker.load()
+    return laker
+
+
+def _gp(pr):
+    return L().Problem(torch.tensor(pr.E, device=DEV), pr.lam, pr.scale)
+
+
+def _model(d, seed, log_delta0=-1.0, scale=1.0):
+    p = make_mlp_init(LO.input_dim(d), LO.HIDDEN, LO.RANK + 1, seed, log_delta0=log_delta0)
+    for k in p:
+        p[k] = p[k] * scale
+    p["b3"][LO.RANK] = log_delta0
+    m = L().MlpModel(d, DEV)
+    m.set_params(p)
+    return m, m.params()     # the float32 weights the library holds, back in float64
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300))
+
+
+def test_sigma_half_matches_dense_root_of_fitted_sigma():
+    pr = make_problem(300, 8, 1e-3, seed=7)
+    prob = _gp(pr)
+    Z = make_directions(pr.n, 40, 7)
+    pc = L().fit_precond(prob, torch.tensor(Z, device=DEV), gamma=1e-3)
+    parts = L().precond_parts(pc)
+    B = parts["B64"].cpu().numpy()
+    b = float(parts["hdr"][2].cpu())
+    Sigma = b * np.eye(pr.n) + B @ B.T
+    ev, V = np.linalg.eigh(Sigma)
+    probes = make_probes(pr.n, 6, 7)
+    U = L().sigma_half(pc, torch.tensor(probes, device=DEV)).cpu().numpy()
+    ref = (V * np.sqrt(ev)) @ V.T @ probes
+    assert np.abs(U - ref).max() <= 1e-13 * (ev[-1] / ev[0]) * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("n,d", [(300, 8), (1000, 16), (77, 4)])
+def test_network_forward_matches_oracle(n, d):
+    pr = make_problem(n, d, 1e-3, seed=n)
+    model, params = _model(d, n)
+    O_gpu = L().learned_forward(_gp(pr), model).cpu().double().numpy()
+    X = LO.features(pr.E, pr.lam)
+    O_ref, _ = LO.mlp_forward(params, X)
+    assert O_gpu.shape == O_ref.shape
+    assert _rel(O_gpu, O_ref) <= 2e-2
+    # the float32 inputs the library builds are the oracle's features
+    assert np.isfinite(O_gpu).all()
+
+
+def test_gradient_matches_oracle():
+    n, d, m = 400, 8, 12
+    pr = make_problem(n, d, 1e-3, seed=21)
+    model, params = _model(d, 21)
+    Zd = make_directions(n, 48, 21)
+    P, _ = O.fit_precond(pr.E, pr.scale, pr.lam, Zd, gamma=1e-3)
+    probes = make_probes(n, m, 21)
+    U = LO.sigma_half_apply(P.b, P.B, P.apply, probes)
+    loss, g = L().learned_train_step(_gp(pr), model, torch.tensor(probes, device=DEV), torch.tensor(U, device=DEV),
+                                     update=False, want_grad=True)
+    X = LO.features(pr.E, pr.lam)
+    Lref, gref, _ = LO.loss_and_grad(params, X, probes, U)
+    assert abs(loss - Lref) <= 2e-2 * Lref
+    for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        assert _rel(g[k].cpu().double().numpy(), gref[k]) <= 2e-2, k
+
+
+def test_first_adam_step_closed_form():
+    n, d, m = 256, 8, 8
+    pr = make_problem(n, d, 1e-3, seed=22)
+    model, params = _model(d, 22)
+    probes = make_probes(n, m, 22)
+    U = probes * 2.0
+    lr = 1e-3
+    _, g = L().learned_train_step(_gp(pr), model, torch.tensor(probes, device=DEV), torch.tensor(U, device=DEV),
+                                  lr=lr, update=True, want_grad=True)
+    new = model.params()
+    for k in params:
+        gk = g[k].cpu().double().numpy()
+        expect = params[k] - lr * gk / (np.abs(gk) + 1e-8)
+        assert np.abs(new[k] - expect).max() <= 1e-6 * max(1.0, np.abs(params[k]).max()), k
+
+
+def test_learned_preconditioner_is_inverse_of_s():
+    n, d = 500, 8
+    pr = make_problem(n, d, 1e-3, seed=23)
+    prob = _gp(pr)
+    model, _ = _model(d, 23, log_delta0=-2.0, scale=0.5)
+    out = L().learned_forward(prob, model).cpu().double().numpy()
+    pc = L().learned_precond(prob, model)
+    parts = L().precond_parts(pc)
+    B = parts["B64"].cpu().numpy()
+    Bt = parts["Bt64"].cpu().numpy()
+    dinv = parts["dinv64"].cpu().numpy()
+    V, delta = out[:, :LO.RANK], np.exp(out[:, LO.RANK])
+    S = LO.learned_dense(V, delta)
+    Pd = np.diag(dinv) + Bt @ B.T
+    ev = np.linalg.eigvalsh(S)
+    err = np.abs(Pd @ S - np.eye(n)).max()
+    assert err <= 1e-13 * ev[-1] / ev[0]
+    assert np.abs(Pd - Pd.T).max() <= 1e-12 * np.abs(Pd).max()
+
+
+def test_pcg_with_learned_preconditioner_reaches_cholesky_solution():
+    n, d = 512, 16
+    pr = make_problem(n, d, 1e-3, seed=24)
+    prob = _gp(pr)
+    model, _ = _model(d, 24, log_delta0=-3.0, scale=0.3)
+    pc = L().learned_precond(prob, model)
+    alpha, st = L().pcg_solve(prob, pr.y, pc, tol=1e-12, max_iter=20000)
+    ref = O.solve_direct(O.system_matrix(pr.E, pr.scale, pr.lam), pr.y)
+    assert np.linalg.norm(alpha.cpu().numpy() - ref) <= 1e-10 * np.linalg.norm(ref)
+    # mixed precision with refinement uses the same preconditioner
+    a2, st2 = L().pcg_solve(prob, pr.y, pc, tol=1e-10, max_iter=20000, precision="bf16", refine=True,
+                            inner_tol=0.1)
+    assert st2.relres_true <= 1e-10
+
+
+def test_training_gains_over_plain_cg_and_fallback():
+    """A/B: a network trained on CCCP fits of small maps needs far fewer PCG
+    iterations than plain CG on larger held-out maps; a solve whose budget runs
+    out falls back to CCCP and still converges."""
+    from paper_2604_25138_amd import learned as LR
+    d, m = 16, 64
+    rng = np.random.default_rng(0)
+    exs = []
+    for k in range(12):
+        lam = float(10 ** rng.uniform(-4, -2))
+        pr = make_problem(1024, d, lam, n_tx=int(rng.integers(1, 5)), seed=100 + k)
+        prob = _gp(pr)
+        exs.append(LR.make_example(prob, torch.tensor(make_directions(pr.n, 128, 100 + k), device=DEV),
+                                   make_probes(pr.n, m, 100 + k), gamma=1e-3, precision="f64"))
+    model = L().MlpModel(d, DEV)
+    model.set_params(make_mlp_init(LO.input_dim(d), LO.HIDDEN, LO.RANK + 1, 0))
+    hist = LR.train(model, exs, epochs=25, lr=1e-3)
+    assert hist[-1] < 0.5 * hist[0]
+    gains = []
+    for k in range(2):
+        pr = make_problem(2048, d, 3e-4, n_tx=2, seed=900 + k)
+        prob = _gp(pr)
+        _, s_cg = L().pcg_solve(prob, pr.y, None, tol=1e-6, max_iter=50000)
+        _, s_lr = L().pcg_solve(prob, pr.y, L().learned_precond(prob, model), tol=1e-6, max_iter=50000)
+        gains.append(s_lr.iters / s_cg.iters)
+    assert max(gains) <= 0.7, gains
+    # fallback: an iteration budget far below what the learned solve needs
+    pr = make_problem(2048, d, 3e-4, n_tx=2, seed=950)
+    prob = _gp(pr)
+    res = LR.solve_with_fallback(prob, pr.y, model, torch.tensor(make_directions(pr.n, 128, 950), device=DEV),
+                                 tol=1e-8, budget=5, precision="f64", refine=False)
+    assert res.fell_back and res.stats.relres_true <= 1e-8
