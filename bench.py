@@ -1,14 +1,20 @@
 """Benchmark of the LAKER solve path on one MI355X.
 
-A step is one full pass of the method over one synthetic map: CCCP
-preconditioner fit (random directions -> shrinkage-CCCP -> Sigma^{-1/2}),
-PCG to a float64 relative residual of 1e-6 (float32 products inside float64
-iterative refinement), and reconstruction on the 45 x 45 grid.  Inputs are
-resident in HBM before the timed region.  Beside the timed product path the
-run reports: the same solve done entirely in float64 (FP64 CCCP-PCG), the
-roofline position of the dominant kernel (the fused kernel product) measured
-with HIP events on the library's stream, and the FP64 CPU oracle timed on a
-bounded sample of the same workload.
+A step is one full pass of the production path over one synthetic map:
+the learned rank-64-plus-diagonal preconditioner (network inference and the
+Woodbury factors), PCG to a float64 true relative residual of 1e-6 with
+bfloat16 score tiles inside float64 iterative refinement (falling back to a
+CCCP fit if PCG stalls), and reconstruction on the 45 x 45 grid.  Inputs are
+resident in HBM before the timed region.  The network is trained beforehand
+(outside the timed region, reported) on CCCP fits of smaller maps drawn from the
+same generator with random lambda and transmitter counts.
+
+Beside the timed path the run reports: the same map solved entirely in float64
+with the paper's CCCP preconditioner (FP64 CCCP-PCG, the metric's comparison),
+the CCCP + mixed-precision step, the roofline position of the dominant kernel
+(the fused kernel product, timed with HIP events around every product of the
+solve on the library's stream), and the FP64 CPU oracle timed on a bounded
+sample of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -16,7 +22,6 @@ from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -34,12 +39,14 @@ WORKLOADS = {
     "n512_d16": dict(n=512, d=16, n_tx=1, lam=1e-3, tol=1e-6, seed=0),
 }
 
+# training set of the learned preconditioner: maps of TRAIN_N sites with
+# lambda log-uniform in [1e-5, 1e-2] and 1..8 transmitters
+TRAIN_N, TRAIN_MAPS, TRAIN_EPOCHS, TRAIN_PROBES = 4096, 96, 30, 128
+
 # VALU issue rate: 256 CUs x 64 lanes x 2.4 GHz, one lane operation per slot
 PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
-PEAK_FP32_VECTOR_TFLOPS = 157.3
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_BF16_MFMA_TFLOPS = 2500.0
-PEAK_HBM_GBS = 8000.0
 
 
 def parse():
@@ -51,9 +58,40 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-f64", action="store_true", help="skip the float64 comparison leg")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work in the CPU sample")
-    ap.add_argument("--precision", default="bf16", choices=["bf16", "f32"],
-                    help="arithmetic of the kernel products inside float64 refinement")
+    ap.add_argument("--train-maps", type=int, default=TRAIN_MAPS)
+    ap.add_argument("--train-epochs", type=int, default=TRAIN_EPOCHS)
     return ap.parse_args()
+
+
+def train_model(L, LR, d, dev, n_maps, epochs):
+    """Untimed: CCCP fits of n_maps training maps, then Adam epochs."""
+    import numpy as np
+    import torch
+
+    from synth import default_n_r, make_directions, make_mlp_init, make_probes, make_problem
+    rng = np.random.default_rng(12345)
+    t0 = time.perf_counter()
+    exs = []
+    for k in range(n_maps):
+        lam = float(10 ** rng.uniform(-5, -2))
+        ntx = int(rng.integers(1, 9))
+        pr = make_problem(TRAIN_N, d, lam, n_tx=ntx, seed=1000 + k)
+        prob = L.Problem(torch.tensor(pr.E, device=dev), pr.lam, pr.scale)
+        Zd = torch.tensor(make_directions(TRAIN_N, default_n_r(TRAIN_N), 1000 + k), device=dev)
+        exs.append(LR.make_example(prob, Zd, make_probes(TRAIN_N, TRAIN_PROBES, 1000 + k), gamma=1e-3,
+                                   precision="bf16"))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    in_dim = L.mlp_layout(d).in_dim
+    model = L.MlpModel(d, dev)
+    model.set_params(make_mlp_init(in_dim, L.MLP_HIDDEN, L.MLP_RANK + 1, 0))
+    hist = LR.train(model, exs, epochs=epochs, lr=1e-3, seed=0)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    info = {"maps": n_maps, "n": TRAIN_N, "epochs": epochs, "probes": TRAIN_PROBES,
+            "targets_s": t1 - t0, "train_s": t2 - t1, "ms_per_step": (t2 - t1) * 1e3 / (epochs * n_maps),
+            "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1]}
+    return model, info
 
 
 def main():
@@ -62,10 +100,10 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
-    import numpy as np
     import torch
 
     from paper_2604_25138_amd import laker as L
+    from paper_2604_25138_amd import learned as LR
     from synth import default_n_r, make_directions, make_problem
 
     L.load()
@@ -79,54 +117,53 @@ def main():
     Zd = torch.tensor(Z, device=dev)
     Eq = torch.tensor(pr.Eq, device=dev)
     tol = wl["tol"]
+    inner = 0.1
+    budget = 20000
 
-    prec = args.precision
-    inner = 1e-1 if prec == "bf16" else 1e-2
-
-    def solve(pc):
-        return L.pcg_solve(prob, y, pc, tol=tol, max_iter=100000, precision=prec, refine=True,
-                           inner_tol=inner, ir_max=64, check_every=32)
+    model, train_info = train_model(L, LR, pr.d, dev, args.train_maps, args.train_epochs)
 
     def step():
-        pc = L.fit_precond(prob, Zd, gamma=0.1, rho=0.0, precision=prec)
-        alpha, st = solve(pc)
-        rhat = L.predict(prob, alpha, Eq, precision="f64")
-        return pc, alpha, st, rhat
+        res = LR.solve_with_fallback(prob, y, model, Zd, tol=tol, budget=budget, precision="bf16", refine=True,
+                                     inner_tol=inner, gamma=0.1, check_every=32)
+        rhat = L.predict(prob, res.alpha, Eq, precision="f64")
+        return res, rhat
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    stats = []
+    runs = []
     for _ in range(args.steps):
-        pc, alpha, st, rhat = step()
-        stats.append((pc.stats.cccp_iters, st.iters, st.ir_steps, st.relres_true))
+        res, rhat = step()
+        runs.append(res)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = 1e3 / ms_per_step
     rmse = float(torch.sqrt(torch.mean((rhat.cpu() - torch.tensor(pr.r_true)) ** 2)))
-
+    last = runs[-1]
     extra = {
-        "cccp_iters": stats[-1][0], "pcg_iters": stats[-1][1], "ir_steps": stats[-1][2],
-        "relres_true": stats[-1][3], "n_r": nr, "map_rmse_db": rmse,
+        "pcg_iters": last.stats.iters, "ir_steps": last.stats.ir_steps, "relres_true": last.stats.relres_true,
+        "fell_back": any(r.fell_back for r in runs), "learned_precond_ms": last.precond_ms,
+        "map_rmse_db": rmse, "training": train_info,
     }
 
-    # phase times of one step (fit / solve / predict)
+    # CCCP + mixed precision on the same map (the paper's preconditioner, fitted)
     torch.cuda.synchronize()
     a = time.perf_counter()
-    pc = L.fit_precond(prob, Zd, gamma=0.1, rho=0.0, precision=prec)
+    pc = L.fit_precond(prob, Zd, gamma=0.1, rho=0.0, precision="bf16")
     torch.cuda.synchronize()
     b = time.perf_counter()
-    alpha, st = solve(pc)
+    alc, stc = L.pcg_solve(prob, y, pc, tol=tol, max_iter=100000, precision="bf16", refine=True, inner_tol=inner,
+                           ir_max=64, check_every=32)
     torch.cuda.synchronize()
     c = time.perf_counter()
-    L.predict(prob, alpha, Eq, precision="f64")
+    L.predict(prob, alc, Eq, precision="f64")
     torch.cuda.synchronize()
     d_ = time.perf_counter()
-    extra["fit_ms"] = (b - a) * 1e3
-    extra["solve_ms"] = (c - b) * 1e3
-    extra["predict_ms"] = (d_ - c) * 1e3
+    extra["cccp_mixed"] = {"fit_ms": (b - a) * 1e3, "solve_ms": (c - b) * 1e3, "predict_ms": (d_ - c) * 1e3,
+                           "solves_per_s": 1.0 / (d_ - a), "pcg_iters": stc.iters,
+                           "ir_steps": stc.ir_steps, "cccp_iters": pc.stats.cccp_iters, "n_r": nr}
 
     # float64 CCCP-PCG on the same map (the method with every product in float64)
     if not args.no_f64:
@@ -134,18 +171,19 @@ def main():
         a = time.perf_counter()
         pc64 = L.fit_precond(prob, Zd, gamma=0.1, rho=0.0)
         al64, st64 = L.pcg_solve(prob, y, pc64, tol=tol, max_iter=100000, precision="f64", check_every=32)
+        L.predict(prob, al64, Eq, precision="f64")
         torch.cuda.synchronize()
         b = time.perf_counter()
         extra["f64_cccp_pcg"] = {"solves_per_s": 1.0 / (b - a), "ms_per_solve": (b - a) * 1e3,
                                  "pcg_iters": st64.iters, "relres_true": st64.relres_true}
         extra["speedup_vs_f64_cccp_pcg"] = (b - a) * 1e3 / ms_per_step
 
-    # roofline of the dominant kernel: the fused product exp(<e_i, e_j>) p inside
+    # roofline of the dominant kernel: the fused product exp2(<e_i, e_j>) p of
     # the solve, timed by the library with HIP events on the stream it launches
     # on (one pair of events around every product of the loop)
-    pc = L.fit_precond(prob, Zd, gamma=0.1, rho=0.0, precision=prec)
-    _, stp = L.pcg_solve(prob, y, pc, tol=tol, max_iter=100000, precision=prec, refine=True,
-                         inner_tol=inner, ir_max=64, check_every=32, profile=True)
+    pcl = L.learned_precond(prob, model)
+    _, stp = L.pcg_solve(prob, y, pcl, tol=tol, max_iter=100000, precision="bf16", refine=True, inner_tol=inner,
+                         ir_max=64, check_every=32, profile=True)
     kms = stp.kmv_ms
     pairs = float(pr.n) * pr.n
     # VALU issue slots per kernel entry: exp2 on the half-rate transcendental
@@ -153,15 +191,13 @@ def main():
     slots = 3.0 * pairs
     achieved = slots / (kms * 1e-3) / 1e12
     mfma_flops = 2.0 * pr.d * pairs
-    kname = {"bf16": "kmv32_kernel<BF16,64>", "f32": "kmv32_kernel<F32,64>"}[prec]
-    roofline = {"kernel": f"{kname} (fused exp2(<e_i,e_j>) p product, {prec} score tiles on MFMA)",
+    roofline = {"kernel": "kmv32_kernel<BF16,64> (fused exp2(<e_i,e_j>) p product, bf16 score tiles on MFMA)",
                 "bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TOPS, "unit": "TOP/s",
                 "frac": achieved / PEAK_VALU_TOPS, "traffic": None,
                 "per_launch": {"pairs": pairs, "valu_slot_ops": slots, "mfma_flops": mfma_flops,
                                "ms": kms, "products_timed": stp.kmv_count,
                                "launches": stp.kmv_launches, "ms_all_launches": stp.kmv_launch_ms},
-                "mfma": {"achieved": mfma_flops / (kms * 1e-3) / 1e12,
-                         "peak": PEAK_BF16_MFMA_TFLOPS if prec == "bf16" else PEAK_FP32_MFMA_TFLOPS,
+                "mfma": {"achieved": mfma_flops / (kms * 1e-3) / 1e12, "peak": PEAK_BF16_MFMA_TFLOPS,
                          "unit": "TFLOP/s"}}
     roofline["mfma"]["frac"] = roofline["mfma"]["achieved"] / roofline["mfma"]["peak"]
 
@@ -189,11 +225,13 @@ def main():
     out = {
         "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": f"{prec}+f64", "data": "synthetic",
+        "vs_baseline": None, "dtype": "bf16+f64", "data": "synthetic",
         "config": {"workload": f"{args.workload}: n={pr.n} d={pr.d} n_tx={wl['n_tx']} lambda={pr.lam} "
-                               f"scale=1/sqrt(d) tol={tol} n_r={nr} gamma=0.1 rho=0",
-                   "path": f"CCCP fit ({prec} directions, f64 CCCP) + PCG with {prec} products inside f64 "
-                           f"refinement + predict 45x45"},
+                               f"scale=1/sqrt(d) tol={tol}",
+                   "path": "learned rank-64+diag preconditioner (BF16 MLP) + PCG with bf16 products inside f64 "
+                           "refinement (CCCP fallback on stall) + predict 45x45",
+                   "training": f"{args.train_maps} maps n={TRAIN_N} lambda~logU[1e-5,1e-2] n_tx~U{{1..8}}, "
+                               f"{args.train_epochs} epochs, CCCP targets gamma=1e-3"},
         "roofline": roofline,
         "extra": extra,
     }
@@ -208,7 +246,6 @@ def cpu_baseline(pr, Z, tol, iters_hint, budget):
     """The FP64 oracle on the host cores: kernel construction, the CCCP fit, and
     as many PCG iterations as fit the budget; the solve time is scaled to the
     iteration count the float64 GPU solve needed on the same map."""
-    import numpy as np
     from oracle import laker_oracle as O
     threads = os.cpu_count()
     try:
@@ -233,7 +270,7 @@ def cpu_baseline(pr, Z, tol, iters_hint, budget):
     iters = iters_hint if iters_hint else it_done
     solve_s = (t1 - t0) + (t2 - t1) + per_iter * iters
     return {"value": 1.0 / solve_s, "unit": "solves/s", "cores": threads, "kind": "oracle",
-            "sample": f"oracle FP64 on n={pr.n}: kernel matrix {t1 - t0:.1f}s + CCCP fit {t2 - t1:.1f}s "
+            "sample": f"oracle FP64 CCCP-PCG on n={pr.n}: kernel matrix {t1 - t0:.1f}s + CCCP fit {t2 - t1:.1f}s "
                       f"(measured) + {it_done} PCG iterations measured at {per_iter * 1e3:.1f} ms each, "
                       f"scaled to {iters} iterations",
             "seconds_measured": t3 - t0}

@@ -167,7 +167,16 @@ laker_status laker_pcg_solve(const laker_problem* prob, const laker_precond* pre
       if (precond->n_r < 1 || precond->n_r > kMaxNr) return LAKER_EINVAL;
       view.B = f64 ? (const void*)L.B64 : (const void*)L.B32;
       view.Bt = f64 ? (const void*)L.Bt64 : (const void*)L.Bt32;
-      if (precond->kind == LAKER_PRECOND_LEARNED) view.dinv = L.dinv64;
+      if (precond->kind == LAKER_PRECOND_LEARNED) {
+        // D^{-1} + Bt B^T cancels to the ratio of the largest to the smallest
+        // eigenvalue of S on range(V); per-point diagonals can make that ratio
+        // exceed what float32 factors resolve, so the rank-64 factors are read
+        // in float64 in every precision (2 n 64 doubles per apply)
+        view.dinv = L.dinv64;
+        view.f32 = 0;
+        view.B = (const void*)L.B64;
+        view.Bt = (const void*)L.Bt64;
+      }
     } else {
       return LAKER_EINVAL;
     }
