@@ -251,6 +251,39 @@ size_t laker_sigma_half_workspace_bytes(int64_t n, int32_t n_r, int32_t m);
 laker_status laker_precond_sigma_half(const laker_precond* precond, int32_t m, const double* Z, double* U,
                                       void* workspace, size_t workspace_bytes, void* stream);
 
+/* ---- batched solve --------------------------------------------------------
+ *
+ * Many independent maps of uneven size (bands, snapshots) solved together: each
+ * pass of a PCG iteration is one launch for the whole batch (the kernel products
+ * as one grid of (map, row block, column range) tiles), each map keeps its own
+ * scalars and retires at its own tolerance (Alg. 1 per map), with the same
+ * float64 refinement as laker_pcg_solve when opts->refine is set. */
+typedef struct {
+  int32_t cols_per_split; /* -1: autotuned (one product sweep timed per candidate
+                             length on this batch, cached per batch shape);
+                             0: the single-map plan of each map (bitwise the same
+                             iterates as laker_pcg_solve); > 0: this many columns */
+  int32_t xcd_order;      /* 1: tiles ordered so that each XCD walks its own
+                             contiguous stretch of the tile list                */
+  int32_t cols_used;      /* out: the length used (0: single-map plans)         */
+  int32_t reserved;
+} laker_batch_opts;
+
+/* Workspace bytes of laker_pcg_solve_batched for maps of n[0..count) sites and
+ * embedding dimension d. */
+size_t laker_batch_workspace_bytes(int32_t count, const int64_t* n, int32_t d);
+
+/* Solve (lambda_b I + G_b) alpha_b = y_b for b < count.  probs: count problems
+ * with the same d; preconds: NULL (plain CG) or count preconditioners of one
+ * kind; y, alpha: host arrays of count device float64 pointers.  opts as for
+ * laker_pcg_solve (warm_start must be 0; profile is ignored); stats: host array
+ * of count entries.  Returns LAKER_OK when every map converged, else the worst
+ * status (each map's status is in its stats entry). */
+laker_status laker_pcg_solve_batched(int32_t count, const laker_problem* probs, const laker_precond* preconds,
+                                     const double* const* y, double* const* alpha, const laker_pcg_opts* opts,
+                                     laker_batch_opts* bopts, void* workspace, size_t workspace_bytes,
+                                     laker_stats* stats, void* stream);
+
 /* Human-readable name of a status code (static string). */
 const char* laker_status_str(int32_t status);
 

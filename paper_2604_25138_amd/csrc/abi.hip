@@ -4,6 +4,10 @@
 
 #include "fit.hpp"
 
+#include <vector>
+
+#include "bpcg.hpp"
+
 using namespace lk;
 
 namespace {
@@ -29,6 +33,43 @@ Problem to_problem(const laker_problem* p) {
 }
 
 bool valid_precision(int32_t prec) { return prec == LAKER_F64 || prec == LAKER_F32 || prec == LAKER_BF16; }
+
+laker_status make_view(const laker_precond* precond, int64_t n, int32_t precision, PrecondView* out) {
+  PrecondView view{};
+  view.kind = LAKER_PRECOND_NONE;
+  if (precond != nullptr && precond->kind != LAKER_PRECOND_NONE) {
+    if (precond->data == nullptr || precond->n != n) return LAKER_EINVAL;
+    PrecondLayout L = precond_layout(precond->data, n, precond->n_r);
+    if (precond->bytes < L.total) return LAKER_ENOMEM;
+    const bool f64 = precision == LAKER_F64;
+    view.f32 = f64 ? 0 : 1;
+    view.kind = precond->kind;
+    view.nr = precond->n_r;
+    view.nrp = pad_nr(precond->n_r);
+    view.c0p = L.hdr;
+    if (precond->kind == LAKER_PRECOND_JACOBI) {
+      view.dinv = L.dinv64;
+    } else if (precond->kind == LAKER_PRECOND_CCCP || precond->kind == LAKER_PRECOND_LEARNED) {
+      if (precond->n_r < 1 || precond->n_r > kMaxNr) return LAKER_EINVAL;
+      view.B = f64 ? (const void*)L.B64 : (const void*)L.B32;
+      view.Bt = f64 ? (const void*)L.Bt64 : (const void*)L.Bt32;
+      if (precond->kind == LAKER_PRECOND_LEARNED) {
+        // D^{-1} + Bt B^T cancels to the ratio of the largest to the smallest
+        // eigenvalue of S on range(V); per-point diagonals can make that ratio
+        // exceed what float32 factors resolve, so the rank-64 factors are read
+        // in float64 in every precision (2 n 64 doubles per apply)
+        view.dinv = L.dinv64;
+        view.f32 = 0;
+        view.B = (const void*)L.B64;
+        view.Bt = (const void*)L.Bt64;
+      }
+    } else {
+      return LAKER_EINVAL;
+    }
+  }
+  *out = view;
+  return LAKER_OK;
+}
 
 }  // namespace
 
@@ -150,37 +191,8 @@ laker_status laker_pcg_solve(const laker_problem* prob, const laker_precond* pre
   if (!(opts->tol >= 0.0) || opts->max_iter < 1) return LAKER_EINVAL;
   if (opts->refine && (opts->ir_max < 1 || opts->ir_max > 64 || !(opts->inner_tol > 0.0))) return LAKER_EINVAL;
   PrecondView view{};
-  view.kind = LAKER_PRECOND_NONE;
-  if (precond != nullptr && precond->kind != LAKER_PRECOND_NONE) {
-    if (precond->data == nullptr || precond->n != prob->n) return LAKER_EINVAL;
-    PrecondLayout L = precond_layout(precond->data, prob->n, precond->n_r);
-    if (precond->bytes < L.total) return LAKER_ENOMEM;
-    const bool f64 = opts->precision == LAKER_F64;
-    view.f32 = f64 ? 0 : 1;
-    view.kind = precond->kind;
-    view.nr = precond->n_r;
-    view.nrp = pad_nr(precond->n_r);
-    view.c0p = L.hdr;
-    if (precond->kind == LAKER_PRECOND_JACOBI) {
-      view.dinv = L.dinv64;
-    } else if (precond->kind == LAKER_PRECOND_CCCP || precond->kind == LAKER_PRECOND_LEARNED) {
-      if (precond->n_r < 1 || precond->n_r > kMaxNr) return LAKER_EINVAL;
-      view.B = f64 ? (const void*)L.B64 : (const void*)L.B32;
-      view.Bt = f64 ? (const void*)L.Bt64 : (const void*)L.Bt32;
-      if (precond->kind == LAKER_PRECOND_LEARNED) {
-        // D^{-1} + Bt B^T cancels to the ratio of the largest to the smallest
-        // eigenvalue of S on range(V); per-point diagonals can make that ratio
-        // exceed what float32 factors resolve, so the rank-64 factors are read
-        // in float64 in every precision (2 n 64 doubles per apply)
-        view.dinv = L.dinv64;
-        view.f32 = 0;
-        view.B = (const void*)L.B64;
-        view.Bt = (const void*)L.Bt64;
-      }
-    } else {
-      return LAKER_EINVAL;
-    }
-  }
+  e = make_view(precond, prob->n, opts->precision, &view);
+  if (e != LAKER_OK) return e;
   SolveWs W = plan_solve_ws(workspace, prob->n, prob->d, 0);
   if (workspace_bytes < W.total) return LAKER_ENOMEM;
   Problem pb = to_problem(prob);
@@ -405,6 +417,61 @@ laker_status laker_precond_sigma_half(const laker_precond* precond, int32_t m, c
   SigmaHalfWs W = plan_sigma_half_ws(workspace, precond->n, precond->n_r, m);
   if (workspace_bytes < W.total) return LAKER_ENOMEM;
   return sigma_half(P, precond->n, precond->n_r, m, Z, U, W, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+// ---- batched solve ------------------------------------------------------------
+
+extern "C" {
+
+size_t laker_batch_workspace_bytes(int32_t count, const int64_t* n, int32_t d) {
+  if (count < 1 || n == nullptr || d < 1 || d > kMaxD) return 0;
+  for (int b = 0; b < count; ++b)
+    if (n[b] < 1) return 0;
+  return plan_batch_ws(count, n, d, nullptr, nullptr, nullptr);
+}
+
+laker_status laker_pcg_solve_batched(int32_t count, const laker_problem* probs, const laker_precond* preconds,
+                                     const double* const* y, double* const* alpha, const laker_pcg_opts* opts,
+                                     laker_batch_opts* bopts, void* workspace, size_t workspace_bytes,
+                                     laker_stats* stats, void* stream) {
+  if (count < 1 || probs == nullptr || y == nullptr || alpha == nullptr || opts == nullptr || workspace == nullptr ||
+      stats == nullptr)
+    return LAKER_EINVAL;
+  if (!valid_precision(opts->precision) || !(opts->tol >= 0.0) || opts->max_iter < 1) return LAKER_EINVAL;
+  if (opts->refine && (opts->ir_max < 1 || opts->ir_max > 64 || !(opts->inner_tol > 0.0))) return LAKER_EINVAL;
+  if (opts->warm_start) return LAKER_EINVAL;
+  std::vector<int64_t> ns(count);
+  std::vector<Problem> pbs(count);
+  std::vector<PrecondView> views(count);
+  for (int b = 0; b < count; ++b) {
+    laker_status e = check_problem(&probs[b]);
+    if (e != LAKER_OK) return e;
+    if (probs[b].d != probs[0].d || y[b] == nullptr || alpha[b] == nullptr) return LAKER_EINVAL;
+    ns[b] = probs[b].n;
+    pbs[b] = to_problem(&probs[b]);
+    e = make_view(preconds != nullptr ? &preconds[b] : nullptr, probs[b].n, opts->precision, &views[b]);
+    if (e != LAKER_OK) return e;
+    if (views[b].kind != views[0].kind || views[b].f32 != views[0].f32) return LAKER_EINVAL;
+  }
+  std::vector<size_t> off(count);
+  BatchWs bw{};
+  const size_t need = plan_batch_ws(count, ns.data(), probs[0].d, off.data(), workspace, &bw);
+  if (workspace_bytes < need) return LAKER_ENOMEM;
+  std::vector<SolveWs> wss(count);
+  for (int b = 0; b < count; ++b) wss[b] = plan_solve_ws((char*)workspace + off[b], ns[b], probs[0].d, 0);
+  BatchOpts bo{};
+  bo.cps = bopts != nullptr ? bopts->cols_per_split : 0;
+  bo.xcd_order = bopts != nullptr ? bopts->xcd_order : 0;
+  if (bo.cps > 0 && bo.cps < 32) return LAKER_EINVAL;
+  for (int b = 0; b < count && bo.cps > 0; ++b)
+    if ((ns[b] + bo.cps - 1) / bo.cps > kMaxSplit) return LAKER_EINVAL;
+  int used = 0;
+  laker_status r = pcg_batch(count, pbs.data(), wss.data(), views.data(), y, alpha, *opts, bo, bw, stats, &used,
+                             (hipStream_t)stream);
+  if (bopts != nullptr) bopts->cols_used = used;
+  return r;
 }
 
 }  // extern "C"

@@ -1,0 +1,599 @@
+// Batched PCG: many independent maps of uneven size solved together.
+//
+// Every pass of an iteration is one launch for the whole batch: the kernel
+// products of all maps run as one grid of (map, row block, column range) tiles
+// from a table (tiles in a fixed order, optionally arranged so that each XCD
+// works through its own contiguous stretch of the table and keeps the key rows
+// of its column ranges in its own L2), and the vector passes run on a grid
+// whose row y is the map.  Each map keeps its own scalars; a map that has
+// converged (or retired from the outer refinement) makes every later pass of
+// its row return at once, so maps retire at their own tolerance.  The chunk of
+// iterations between host checks can be captured into a HIP graph and
+// replayed.  The per-block bodies are the ones of the single-map solver, with
+// the same block counts, so a map gives bitwise the same iterates in a batch as
+// alone when the product uses the single-map column ranges.
+#include "bpcg.hpp"
+
+#include <math.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "pcg_body.hpp"
+
+namespace lk {
+
+namespace {
+
+using namespace pcgk;
+
+// ---- batched passes (grid: x = blocks of the largest map, y = map) ----
+
+__global__ __launch_bounds__(kThreads) void b_zero_kernel(const BDesc* __restrict__ D) {
+  const BDesc& d = D[blockIdx.y];
+  if (!d.active) return;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < d.n; i += (int64_t)gridDim.x * kThreads)
+    d.x[i] = 0.0;
+}
+
+__global__ __launch_bounds__(kThreads) void b_init_kernel(const BDesc* __restrict__ D) {
+  const BDesc& d = D[blockIdx.y];
+  if (!d.active || (int)blockIdx.x >= d.g) return;
+  pcg_init_body(blockIdx.x, d.g, d.rhs, nullptr, d.r, d.p, d.n, d.yyp, d.rrp);
+}
+
+__global__ __launch_bounds__(kThreads) void b_start_kernel(const BDesc* __restrict__ D) {
+  const BDesc& d = D[blockIdx.y];
+  if (!d.active) {
+    if (threadIdx.x == 0) d.S->done = 4;   // retired: every pass of this map returns at once
+    return;
+  }
+  pcg_start_body(0, 1, d.S, d.yyp, d.rrp, d.g, d.tol, d.max_iter);
+}
+
+__global__ __launch_bounds__(kThreads) void b_ap_kernel(const BDesc* __restrict__ D) {
+  const BDesc& d = D[blockIdx.y];
+  if ((int)blockIdx.x >= d.g) return;
+  pcg_ap_body(blockIdx.x, d.g, d.p, d.part, d.nsplit, d.Ap, d.n, d.lam, d.papp, d.S);
+}
+
+template <int KIND>
+__global__ __launch_bounds__(kThreads) void b_update_kernel(const BDesc* __restrict__ D) {
+  const BDesc& d = D[blockIdx.y];
+  if ((int)blockIdx.x >= d.g) return;
+  pcg_update_body<KIND>(blockIdx.x, d.g, d.x, d.r, d.p, d.Ap, d.dinv, d.th, d.n, d.S, d.papp, d.g, d.rrp, d.rzp);
+}
+
+template <typename MT>
+__global__ __launch_bounds__(kThreads) void b_update_t_kernel(const BDesc* __restrict__ D) {
+  const BDesc& d = D[blockIdx.y];
+  if ((int)blockIdx.x >= d.nbt) return;
+  pcg_update_t_body<MT>(blockIdx.x, d.nbt, d.x, d.r, d.p, d.Ap, (const MT*)d.B, d.nrp, d.n, d.S, d.papp, d.g, d.rrp,
+                        d.tpart);
+}
+
+template <typename MT>
+__global__ __launch_bounds__(kThreads) void b_lr_t_partial_kernel(const BDesc* __restrict__ D) {
+  const BDesc& d = D[blockIdx.y];
+  if ((int)blockIdx.x >= d.nbt) return;
+  lr_t_partial_body<MT>(blockIdx.x, d.nbt, (const MT*)d.B, d.r, d.n, d.nrp, d.tpart, d.S);
+}
+
+__global__ __launch_bounds__(kThreads) void b_lr_t_finish_kernel(const BDesc* __restrict__ D, int decide) {
+  const BDesc& d = D[blockIdx.y];
+  const int nb = (d.nrp + 15) / 16;
+  if ((int)blockIdx.x >= nb) return;
+  lr_t_finish_body(blockIdx.x, nb, d.tpart, d.nbt, d.nrp, d.t, d.S, decide ? d.rrp : nullptr, d.nbt);
+}
+
+template <typename MT>
+__global__ __launch_bounds__(kThreads) void b_lr_apply_kernel(const BDesc* __restrict__ D) {
+  const BDesc& d = D[blockIdx.y];
+  if ((int)blockIdx.x >= d.ga) return;
+  lr_apply_body<MT>(blockIdx.x, d.ga, (const MT*)d.Bt, d.t, d.r, d.th, d.n, d.nrp, d.c0p, d.dinv, d.S, d.rzp);
+}
+
+__global__ __launch_bounds__(kThreads) void b_jacobi_apply_kernel(const BDesc* __restrict__ D) {
+  const BDesc& d = D[blockIdx.y];
+  if ((int)blockIdx.x >= d.g) return;
+  jacobi_apply_body(blockIdx.x, d.g, d.r, d.dinv, d.th, d.n, d.S, d.rzp);
+}
+
+template <int KIND>
+__global__ __launch_bounds__(kThreads) void b_pupdate_kernel(const BDesc* __restrict__ D, int init) {
+  const BDesc& d = D[blockIdx.y];
+  if ((int)blockIdx.x >= d.g) return;
+  const double* src = KIND == LAKER_PRECOND_NONE ? d.r : d.th;
+  const int grz = KIND == LAKER_PRECOND_CCCP ? d.ga : d.g;
+  pcg_pupdate_body<KIND>(blockIdx.x, d.g, init, src, d.p, d.n, d.S, d.rrp, d.g, d.rzp, grz);
+}
+
+__global__ __launch_bounds__(kThreads) void b_resid_kernel(const BDesc* __restrict__ D) {
+  const BDesc& d = D[blockIdx.y];
+  if (!d.active || (int)blockIdx.x >= d.g) return;
+  resid_body(blockIdx.x, d.g, d.y, d.have_alpha ? d.w64 : nullptr, d.rout, d.n, d.bpart, d.cnt, d.misc);
+}
+
+__global__ __launch_bounds__(kThreads) void b_axpy_kernel(const BDesc* __restrict__ D) {
+  const BDesc& d = D[blockIdx.y];
+  if (!d.active || (int)blockIdx.x >= d.g) return;
+  axpy_body(blockIdx.x, d.g, d.alpha, d.x, d.n);
+}
+
+// scalars of every map, and the outer residual norms, gathered for one copy
+__global__ void b_gather_kernel(const BDesc* __restrict__ D, int count, PcgScalars* __restrict__ hs,
+                                double* __restrict__ misc) {
+  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < count; b += gridDim.x * blockDim.x) {
+    hs[b] = *D[b].S;
+    misc[2 * b] = D[b].misc[0];
+    misc[2 * b + 1] = D[b].misc[1];
+  }
+}
+
+// ---- host helpers ----
+
+struct Plan1 {
+  int rowblocks;
+  int nsplit;
+  int64_t cps;
+};
+
+Plan1 plan_for(int64_t n, int prec, int cps) {
+  Plan1 p;
+  const int rpb = kmv_rows_per_block(prec);
+  p.rowblocks = (int)((n + rpb - 1) / rpb);
+  if (cps <= 0) {
+    KmvPlan k = kmv_plan(n, n, prec);
+    p.nsplit = k.nsplit;
+    p.cps = k.cols_per_split;
+  } else {
+    p.cps = cps;
+    p.nsplit = (int)((n + cps - 1) / cps);
+  }
+  return p;
+}
+
+// Tiles (map, row block, column range), map-major then column range then row
+// block; with xcd, block b takes entry (b % 8) * (T / 8) + b / 8 of that list
+// (T padded to a multiple of 8 with empty tiles), so the blocks an XCD receives
+// (every 8th block id) walk one contiguous stretch of the list.
+std::vector<int> build_tiles(int count, const std::vector<Plan1>& pl, const std::vector<int>& use, bool xcd) {
+  std::vector<int> L;
+  for (int b = 0; b < count; ++b) {
+    if (!use[b]) continue;
+    for (int sp = 0; sp < pl[b].nsplit; ++sp)
+      for (int rb = 0; rb < pl[b].rowblocks; ++rb) {
+        L.push_back(b);
+        L.push_back(rb);
+        L.push_back(sp);
+      }
+  }
+  if (!xcd) return L;
+  const int64_t T = (int64_t)L.size() / 3;
+  const int64_t T8 = (T + 7) / 8 * 8;
+  const int64_t per = T8 / 8;
+  std::vector<int> out((size_t)T8 * 3, -1);
+  for (int64_t blk = 0; blk < T8; ++blk) {
+    const int64_t src = (blk % 8) * per + blk / 8;
+    if (src < T) {
+      out[3 * blk + 0] = L[3 * src + 0];
+      out[3 * blk + 1] = L[3 * src + 1];
+      out[3 * blk + 2] = L[3 * src + 2];
+    }
+  }
+  return out;
+}
+
+int max_of(const std::vector<BDesc>& h, int BDesc::*f) {
+  int m = 1;
+  for (const BDesc& d : h) m = std::max(m, d.*f);
+  return m;
+}
+
+// Autotuned column-range length per (precision, dp, batch shape); chosen by
+// timing one batched product sweep for each candidate.
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int64_t>, int> g_tuned;
+
+}  // namespace
+
+size_t plan_batch_ws(int count, const int64_t* n, int d, size_t* offsets, void* base, BatchWs* out) {
+  WsCarver c(base);
+  for (int b = 0; b < count; ++b) {
+    const size_t bytes = plan_solve_ws(nullptr, n[b], d, 0).total;
+    unsigned char* p = c.take<unsigned char>(bytes);
+    if (offsets) offsets[b] = base ? (size_t)(p - (unsigned char*)base) : 0;
+  }
+  BatchWs w{};
+  int64_t tiles = 0;
+  for (int b = 0; b < count; ++b) {
+    // the most tiles a map can produce: float32/bfloat16 rows of 128, float64
+    // rows of 64, at most kMaxSplit column ranges
+    tiles += ((n[b] + 63) / 64) * kMaxSplit;
+  }
+  tiles += 8;
+  w.desc = c.take<BDesc>(count);
+  w.inner = c.take<KmvArgs>(count);
+  w.outer = c.take<KmvArgs>(count);
+  w.tiles_in = c.take<int>((size_t)tiles * 3);
+  w.tiles_out = c.take<int>((size_t)tiles * 3);
+  w.hs = c.take<PcgScalars>(count);
+  w.misc = c.take<double>((size_t)2 * count);
+  w.total = c.bytes();
+  if (out) *out = w;
+  return w.total;
+}
+
+laker_status pcg_batch(int count, const Problem* pbs, const SolveWs* wss, const PrecondView* Ps,
+                       const double* const* y, double* const* alpha, const laker_pcg_opts& o, const BatchOpts& bo,
+                       const BatchWs& bw, laker_stats* stats, int* cps_used, hipStream_t st) {
+  const int prec = o.precision;
+  const int kind = Ps[0].kind;
+  const int f32 = Ps[0].f32;
+  const int dp = pbs[0].dp;
+  const bool lowrank = kind == LAKER_PRECOND_CCCP || kind == LAKER_PRECOND_LEARNED;
+  const bool xcd = bo.xcd_order != 0;
+  const int check = o.check_every > 0 ? o.check_every : 16;
+
+  // per-map descriptors
+  std::vector<BDesc> hd(count);
+  int64_t max_n = 1;
+  for (int b = 0; b < count; ++b) {
+    const Problem& pb = pbs[b];
+    const SolveWs& w = wss[b];
+    BDesc& d = hd[b];
+    d = BDesc{};
+    d.n = pb.n;
+    d.lam = pb.lambda;
+    d.g = red_blocks(pb.n);
+    d.ga = apply_blocks(pb.n);
+    d.nbt = (int)((pb.n + kTRows - 1) / kTRows);
+    d.S = w.S;
+    d.r = w.r;
+    d.p = w.p;
+    d.Ap = w.ap;
+    d.th = w.theta;
+    d.part = w.part;
+    d.yyp = w.yyp;
+    d.rrp = w.rrp;
+    d.rzp = w.rzp;
+    d.papp = w.papp;
+    d.tpart = w.tpart;
+    d.t = w.t;
+    d.B = Ps[b].B;
+    d.Bt = Ps[b].Bt;
+    d.c0p = Ps[b].c0p;
+    d.dinv = (const double*)Ps[b].dinv;
+    d.nrp = lowrank ? Ps[b].nrp : 4;
+    d.y = y[b];
+    d.alpha = alpha[b];
+    d.rout = w.rout;
+    d.w64 = w.w64;
+    d.bpart = w.bpart;
+    d.cnt = w.cnt;
+    d.misc = w.misc;
+    d.active = 1;
+    max_n = std::max<int64_t>(max_n, pb.n);
+    LK_TRY(hipMemsetAsync(w.S, 0, sizeof(PcgScalars), st));
+    LK_TRY(hipMemsetAsync(w.cnt, 0, 16 * sizeof(unsigned), st));
+    LK_TRY(prep_embed(pb.E, pb.n, pb.d, pb.dp, pb.scale, LAKER_F64, w.e64, st));
+    if (prec != LAKER_F64)
+      LK_TRY(prep_embed(pb.E, pb.n, pb.d, pb.dp, pb.scale, prec, prec == LAKER_F32 ? (void*)w.e32 : (void*)w.e16, st));
+  }
+
+  // column ranges of the inner products: the single-map plan, a given length,
+  // or the autotuned one
+  int cps = bo.cps;
+  std::vector<int> all(count, 1);
+  std::vector<KmvArgs> hin(count), hout(count);
+  auto make_inner = [&](int cps_req, std::vector<Plan1>& pl) {
+    pl.resize(count);
+    for (int b = 0; b < count; ++b) {
+      pl[b] = plan_for(pbs[b].n, prec, cps_req);
+      KmvArgs A = kmv_args(prepared(wss[b], prec), pbs[b].n, prepared(wss[b], prec), pbs[b].n, wss[b].p, wss[b]);
+      A.mode = 0;
+      A.S = wss[b].S;
+      A.pcg_step = 1;
+      A.cps = pl[b].cps;
+      A.nsplit = pl[b].nsplit;
+      hin[b] = A;
+      hd[b].nsplit = pl[b].nsplit;
+    }
+  };
+  if (cps < 0) {
+    int64_t sum_n = 0;
+    for (int b = 0; b < count; ++b) sum_n += pbs[b].n;
+    const auto key2 = std::make_tuple(prec, dp, count, sum_n);
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tuned.find(key2);
+    if (it != g_tuned.end()) {
+      cps = it->second;
+    } else {
+      // time one sweep per candidate (arguments without scalars: nothing skips)
+      const int cands[] = {0, 1024, 2048, 4096, 8192};
+      float best = 1e30f;
+      int best_c = 0;
+      hipEvent_t e0, e1;
+      LK_TRY(hipEventCreate(&e0));
+      LK_TRY(hipEventCreate(&e1));
+      for (int cand : cands) {
+        bool ok = true;
+        for (int b = 0; b < count && ok; ++b)
+          if (cand > 0 && (pbs[b].n + cand - 1) / cand > kMaxSplit) ok = false;
+        if (!ok) continue;
+        std::vector<Plan1> pl;
+        make_inner(cand, pl);
+        for (int b = 0; b < count; ++b) {
+          hin[b].S = nullptr;
+          hin[b].pcg_step = 0;
+        }
+        std::vector<int> tl = build_tiles(count, pl, all, xcd);
+        LK_TRY(hipMemcpyAsync(bw.inner, hin.data(), sizeof(KmvArgs) * count, hipMemcpyHostToDevice, st));
+        LK_TRY(hipMemcpyAsync(bw.tiles_in, tl.data(), sizeof(int) * tl.size(), hipMemcpyHostToDevice, st));
+        const int nt = (int)(tl.size() / 3);
+        LK_TRY(kmv_run_batch(prec, dp, count, bw.inner, bw.tiles_in, nt, false, max_n, st));
+        LK_TRY(hipEventRecord(e0, st));
+        for (int rep = 0; rep < 2; ++rep) LK_TRY(kmv_run_batch(prec, dp, count, bw.inner, bw.tiles_in, nt, false, max_n, st));
+        LK_TRY(hipEventRecord(e1, st));
+        LK_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        LK_TRY(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) {
+          best = ms;
+          best_c = cand;
+        }
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      cps = best_c;
+      g_tuned[key2] = cps;
+    }
+  }
+  std::vector<Plan1> pl_in;
+  make_inner(cps, pl_in);
+  if (cps_used) *cps_used = cps;
+  std::vector<int> tin = build_tiles(count, pl_in, all, xcd);
+  const int nt_in = (int)(tin.size() / 3);
+  LK_TRY(hipMemcpyAsync(bw.inner, hin.data(), sizeof(KmvArgs) * count, hipMemcpyHostToDevice, st));
+  LK_TRY(hipMemcpyAsync(bw.tiles_in, tin.data(), sizeof(int) * tin.size(), hipMemcpyHostToDevice, st));
+
+  // float64 products of the outer residual: single-map plans
+  std::vector<Plan1> pl_out(count);
+  for (int b = 0; b < count; ++b) {
+    pl_out[b] = plan_for(pbs[b].n, LAKER_F64, 0);
+    KmvArgs A = kmv_args(wss[b].e64, pbs[b].n, wss[b].e64, pbs[b].n, alpha[b], wss[b]);
+    A.lam = pbs[b].lambda;
+    A.pself = alpha[b];
+    A.out = wss[b].w64;
+    A.cps = pl_out[b].cps;
+    A.nsplit = pl_out[b].nsplit;
+    hout[b] = A;
+  }
+
+  const int gx = max_of(hd, &BDesc::g);
+  const int gax = max_of(hd, &BDesc::ga);
+  const int gtx = max_of(hd, &BDesc::nbt);
+  int gfx = 1;
+  for (const BDesc& d : hd) gfx = std::max(gfx, (d.nrp + 15) / 16);
+  const dim3 G(gx, count), GA(gax, count), GT(gtx, count), GF(gfx, count), G1(1, count);
+
+  auto upload_desc = [&]() -> laker_status {
+    LK_TRY(hipMemcpyAsync(bw.desc, hd.data(), sizeof(BDesc) * count, hipMemcpyHostToDevice, st));
+    return LAKER_OK;
+  };
+
+  // one inner iteration for the whole batch
+  auto enqueue_iteration = [&](hipStream_t s2) -> laker_status {
+    LK_TRY(kmv_run_batch(prec, dp, count, bw.inner, bw.tiles_in, nt_in, false, max_n, s2));
+    b_ap_kernel<<<G, kThreads, 0, s2>>>(bw.desc);
+    LK_CHECK_LAUNCH();
+    if (lowrank) {
+      if (f32) b_update_t_kernel<float><<<GT, kThreads, 0, s2>>>(bw.desc);
+      else b_update_t_kernel<double><<<GT, kThreads, 0, s2>>>(bw.desc);
+      LK_CHECK_LAUNCH();
+      b_lr_t_finish_kernel<<<GF, kThreads, 0, s2>>>(bw.desc, 1);
+      LK_CHECK_LAUNCH();
+      if (f32) b_lr_apply_kernel<float><<<GA, kThreads, 0, s2>>>(bw.desc);
+      else b_lr_apply_kernel<double><<<GA, kThreads, 0, s2>>>(bw.desc);
+      LK_CHECK_LAUNCH();
+      b_pupdate_kernel<LAKER_PRECOND_CCCP><<<G, kThreads, 0, s2>>>(bw.desc, 0);
+    } else if (kind == LAKER_PRECOND_JACOBI) {
+      b_update_kernel<LAKER_PRECOND_JACOBI><<<G, kThreads, 0, s2>>>(bw.desc);
+      LK_CHECK_LAUNCH();
+      b_pupdate_kernel<LAKER_PRECOND_JACOBI><<<G, kThreads, 0, s2>>>(bw.desc, 0);
+    } else {
+      b_update_kernel<LAKER_PRECOND_NONE><<<G, kThreads, 0, s2>>>(bw.desc);
+      LK_CHECK_LAUNCH();
+      b_pupdate_kernel<LAKER_PRECOND_NONE><<<G, kThreads, 0, s2>>>(bw.desc, 0);
+    }
+    LK_CHECK_LAUNCH();
+    return LAKER_OK;
+  };
+
+  // inner PCG on every active map from x = 0; returns when all are done
+  std::vector<PcgScalars> hs(count);
+  auto inner_solve = [&](std::vector<int>& iters_out) -> laker_status {
+    LK_TRY(upload_desc() == LAKER_OK ? hipSuccess : hipErrorUnknown);
+    b_zero_kernel<<<G, kThreads, 0, st>>>(bw.desc);
+    LK_CHECK_LAUNCH();
+    b_init_kernel<<<G, kThreads, 0, st>>>(bw.desc);
+    LK_CHECK_LAUNCH();
+    b_start_kernel<<<G1, kThreads, 0, st>>>(bw.desc);
+    LK_CHECK_LAUNCH();
+    if (lowrank) {
+      if (f32) b_lr_t_partial_kernel<float><<<GT, kThreads, 0, st>>>(bw.desc);
+      else b_lr_t_partial_kernel<double><<<GT, kThreads, 0, st>>>(bw.desc);
+      LK_CHECK_LAUNCH();
+      b_lr_t_finish_kernel<<<GF, kThreads, 0, st>>>(bw.desc, 0);
+      LK_CHECK_LAUNCH();
+      if (f32) b_lr_apply_kernel<float><<<GA, kThreads, 0, st>>>(bw.desc);
+      else b_lr_apply_kernel<double><<<GA, kThreads, 0, st>>>(bw.desc);
+      LK_CHECK_LAUNCH();
+      b_pupdate_kernel<LAKER_PRECOND_CCCP><<<G, kThreads, 0, st>>>(bw.desc, 1);
+    } else if (kind == LAKER_PRECOND_JACOBI) {
+      b_jacobi_apply_kernel<<<G, kThreads, 0, st>>>(bw.desc);
+      LK_CHECK_LAUNCH();
+      b_pupdate_kernel<LAKER_PRECOND_JACOBI><<<G, kThreads, 0, st>>>(bw.desc, 1);
+    } else {
+      b_pupdate_kernel<LAKER_PRECOND_NONE><<<G, kThreads, 0, st>>>(bw.desc, 1);
+    }
+    LK_CHECK_LAUNCH();
+    hipGraphExec_t gexec = nullptr;
+    if (o.graph) {
+      hipStream_t cs = pcg_capture_stream();
+      hipGraph_t graph = nullptr;
+      bool ok = cs != nullptr && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+      if (ok) {
+        laker_status e = LAKER_OK;
+        for (int c = 0; c < check && e == LAKER_OK; ++c) e = enqueue_iteration(cs);
+        ok = hipStreamEndCapture(cs, &graph) == hipSuccess && e == LAKER_OK;
+        if (ok) ok = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0) == hipSuccess;
+        if (graph != nullptr) (void)hipGraphDestroy(graph);
+      }
+      if (!ok) {
+        (void)hipGetLastError();
+        if (gexec != nullptr) (void)hipGraphExecDestroy(gexec);
+        return LAKER_EHIP;
+      }
+    }
+    int max_cap = 0;
+    for (const BDesc& d : hd)
+      if (d.active) max_cap = std::max(max_cap, d.max_iter);
+    laker_status status = LAKER_OK;
+    for (int k = 0;;) {
+      if (gexec != nullptr) {
+        if (hipGraphLaunch(gexec, st) != hipSuccess) {
+          status = LAKER_EHIP;
+          break;
+        }
+      } else {
+        for (int c = 0; c < check && status == LAKER_OK; ++c) status = enqueue_iteration(st);
+        if (status != LAKER_OK) break;
+      }
+      k += check;
+      bool all_done = true;
+      b_gather_kernel<<<(count + 63) / 64, 64, 0, st>>>(bw.desc, count, bw.hs, bw.misc);
+      if (hipGetLastError() != hipSuccess ||
+          hipMemcpyAsync(hs.data(), bw.hs, sizeof(PcgScalars) * count, hipMemcpyDeviceToHost, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess) {
+        status = LAKER_EHIP;
+        break;
+      }
+      for (int b = 0; b < count; ++b)
+        if (hs[b].done == 0) all_done = false;
+      if (all_done || k >= max_cap + check) break;
+    }
+    if (gexec != nullptr) (void)hipGraphExecDestroy(gexec);
+    for (int b = 0; b < count; ++b) iters_out[b] = hd[b].active ? hs[b].iters : 0;
+    return status;
+  };
+
+  // outer residual of the active maps: y - A alpha in float64 (alpha = 0: y)
+  auto outer_residual = [&](bool have_alpha, std::vector<double>& rel) -> laker_status {
+    for (int b = 0; b < count; ++b) {
+      hd[b].have_alpha = have_alpha ? 1 : 0;
+      hout[b].mode = hd[b].active ? 1 : 2;
+    }
+    LK_TRY(upload_desc() == LAKER_OK ? hipSuccess : hipErrorUnknown);
+    if (have_alpha) {
+      std::vector<int> act(count);
+      for (int b = 0; b < count; ++b) act[b] = hd[b].active;
+      std::vector<int> tl = build_tiles(count, pl_out, act, xcd);
+      LK_TRY(hipMemcpyAsync(bw.outer, hout.data(), sizeof(KmvArgs) * count, hipMemcpyHostToDevice, st));
+      LK_TRY(hipMemcpyAsync(bw.tiles_out, tl.data(), sizeof(int) * tl.size(), hipMemcpyHostToDevice, st));
+      LK_TRY(kmv_run_batch(LAKER_F64, dp, count, bw.outer, bw.tiles_out, (int)(tl.size() / 3), true, max_n, st));
+    }
+    b_resid_kernel<<<G, kThreads, 0, st>>>(bw.desc);
+    LK_CHECK_LAUNCH();
+    std::vector<double> h(2 * count);
+    b_gather_kernel<<<(count + 63) / 64, 64, 0, st>>>(bw.desc, count, bw.hs, bw.misc);
+    LK_CHECK_LAUNCH();
+    LK_TRY(hipMemcpyAsync(h.data(), bw.misc, sizeof(double) * 2 * count, hipMemcpyDeviceToHost, st));
+    LK_TRY(hipStreamSynchronize(st));
+    for (int b = 0; b < count; ++b)
+      if (hd[b].active) rel[b] = h[2 * b + 1] > 0 ? sqrt(h[2 * b] / h[2 * b + 1]) : 0.0;
+    return LAKER_OK;
+  };
+
+  std::vector<int> used(count, 0), it(count, 0);
+  std::vector<double> rel(count, 0.0);
+  std::vector<laker_status> res(count, LAKER_ENOCONV);
+  for (int b = 0; b < count; ++b) {
+    stats[b] = laker_stats{};
+  }
+  if (!o.refine) {
+    for (int b = 0; b < count; ++b) {
+      hd[b].rhs = y[b];
+      hd[b].x = alpha[b];
+      hd[b].tol = o.tol;
+      hd[b].max_iter = o.max_iter;
+    }
+    laker_status e = inner_solve(it);
+    if (e != LAKER_OK) return e;
+    for (int b = 0; b < count; ++b) {
+      stats[b].iters = it[b];
+      stats[b].relres = hs[b].yy > 0 ? sqrt(hs[b].rr / hs[b].yy) : 0.0;
+      res[b] = hs[b].done == 1 ? LAKER_OK : (hs[b].done == 2 ? LAKER_EBREAKDOWN : LAKER_ENOCONV);
+    }
+    e = outer_residual(true, rel);
+    if (e != LAKER_OK) return e;
+    for (int b = 0; b < count; ++b) stats[b].relres_true = rel[b];
+  } else {
+    for (int b = 0; b < count; ++b) {
+      LK_TRY(hipMemsetAsync(alpha[b], 0, sizeof(double) * pbs[b].n, st));
+      hd[b].rhs = wss[b].rout;
+      hd[b].x = wss[b].dalpha;
+    }
+    for (int s = 0; s <= o.ir_max; ++s) {
+      laker_status e = outer_residual(s > 0, rel);
+      if (e != LAKER_OK) return e;
+      bool any = false;
+      for (int b = 0; b < count; ++b) {
+        if (!hd[b].active) continue;
+        if (s < 64) stats[b].ir_relres[s] = rel[b];
+        stats[b].relres_true = rel[b];
+        stats[b].relres = rel[b];
+        stats[b].ir_steps = s;
+        if (rel[b] <= o.tol) {
+          res[b] = LAKER_OK;
+          hd[b].active = 0;
+        } else if (s == o.ir_max || used[b] >= o.max_iter) {
+          hd[b].active = 0;
+        } else {
+          const double need = 0.5 * o.tol / rel[b];
+          hd[b].tol = std::max(o.inner_tol, need);
+          hd[b].max_iter = o.max_iter - used[b];
+          any = true;
+        }
+      }
+      if (!any) break;
+      e = inner_solve(it);
+      if (e != LAKER_OK) return e;
+      for (int b = 0; b < count; ++b) {
+        if (!hd[b].active) continue;
+        used[b] += it[b];
+        stats[b].iters = used[b];
+        if (hs[b].done == 2) {
+          res[b] = LAKER_EBREAKDOWN;
+          hd[b].active = 0;
+        }
+      }
+      LK_TRY(upload_desc() == LAKER_OK ? hipSuccess : hipErrorUnknown);
+      b_axpy_kernel<<<G, kThreads, 0, st>>>(bw.desc);
+      LK_CHECK_LAUNCH();
+    }
+  }
+  LK_TRY(hipStreamSynchronize(st));
+  laker_status worst = LAKER_OK;
+  for (int b = 0; b < count; ++b) {
+    stats[b].status = res[b];
+    if (res[b] == LAKER_EBREAKDOWN) worst = LAKER_EBREAKDOWN;
+    else if (res[b] == LAKER_ENOCONV && worst == LAKER_OK) worst = LAKER_ENOCONV;
+  }
+  return worst;
+}
+
+}  // namespace lk

@@ -81,6 +81,20 @@ __device__ __forceinline__ bool last_block_arrived(unsigned* cnt) {
   return am_last != 0;
 }
 
+// As last_block_arrived, for a grid whose first `total` blocks take part.
+__device__ __forceinline__ bool last_block_arrived_of(unsigned* cnt, unsigned total) {
+  __shared__ int am_last;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    unsigned t = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    am_last = (t == total - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  if (am_last) __threadfence();
+  return am_last != 0;
+}
+
 // Sum of `count` doubles written by other blocks, in index order, by the whole
 // block; valid in every thread.
 __device__ __forceinline__ double ordered_sum(const double* part, int count, double* sh) {

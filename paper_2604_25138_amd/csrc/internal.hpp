@@ -49,6 +49,14 @@ struct KmvArgs {
 };
 hipError_t kmv_run(int prec, int dp, const KmvPlan& pl, KmvArgs A, hipStream_t st);
 
+// Products of several problems in one launch: block b computes tile
+// (problem, row block, column range) = tiles_dev[3 b .. 3 b + 2] with the
+// problem's arguments As_dev[problem] (cps and nsplit filled in).  With
+// `finish`, a second launch writes out = lam pself + the partials for every
+// problem whose mode is 1 (max_m: the largest row count).
+hipError_t kmv_run_batch(int prec, int dp, int count, const KmvArgs* As_dev, const int* tiles_dev, int ntiles,
+                         bool finish, int64_t max_m, hipStream_t st);
+
 // ---- multi right-hand-side product and the fit (fit.hip) ----
 
 }  // namespace lk

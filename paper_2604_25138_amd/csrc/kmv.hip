@@ -184,20 +184,20 @@ struct Stage32 {
 };
 
 template <int PREC, int DP>
-__global__ __launch_bounds__(256) void kmv32_kernel(KmvArgs A) {
+__device__ __forceinline__ void kmv32_body(const KmvArgs& A, int64_t bx, int64_t by) {
   using St = Stage32<PREC, DP>;
   using ET = typename St::ET;
   using Frag = typename std::conditional<PREC == LAKER_F32, FragF32<DP>, FragBF16<DP>>::type;
   constexpr int KT = St::KT;
   __shared__ __attribute__((aligned(16))) unsigned char lds[2][St::BYTES];
   if (A.S != nullptr && A.S->done) return;
-  if (A.pcg_step && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) A.S->kcur += 1;
+  if (A.pcg_step && bx == 0 && by == 0 && threadIdx.x == 0) A.S->kcur += 1;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const int h = lane >> 5, c = lane & 31;
-  const int64_t rb0 = (int64_t)blockIdx.x * 128;
+  const int64_t rb0 = bx * 128;
   const int64_t row0 = rb0 + wv * 32;
-  const int64_t j0 = (int64_t)blockIdx.y * A.cps;
+  const int64_t j0 = by * A.cps;
   const int64_t j1 = j0 + A.cps < A.n ? j0 + A.cps : A.n;
   const double* __restrict__ p = A.p;
   const ET* __restrict__ Q = reinterpret_cast<const ET*>(A.Q);
@@ -305,22 +305,36 @@ __global__ __launch_bounds__(256) void kmv32_kernel(KmvArgs A) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) v = (r == c) ? acc[r] : v;
     const int64_t row = row0 + (c >> 2) * 8 + h * 4 + (c & 3);
-    if (row < A.m) part[(int64_t)blockIdx.y * A.m + row] = v;
+    if (row < A.m) part[by * A.m + row] = v;
   }
+}
+
+template <int PREC, int DP>
+__global__ __launch_bounds__(256) void kmv32_kernel(KmvArgs A) {
+  kmv32_body<PREC, DP>(A, blockIdx.x, blockIdx.y);
+}
+
+// Batched: block b takes tile (problem, row block, column range) = tiles[3 b ..].
+template <int PREC, int DP>
+__global__ __launch_bounds__(256) void kmv32_batch_kernel(const KmvArgs* __restrict__ As, const int* __restrict__ tiles) {
+  const int* t = tiles + 3 * (int64_t)blockIdx.x;
+  if (t[0] < 0) return;   // padding tile
+  const KmvArgs A = As[t[0]];
+  kmv32_body<PREC, DP>(A, t[1], t[2]);
 }
 
 // ---------------------------------------------------------------------------
 // float64 kernel: 16x16 score tiles, exp in float64.
 // ---------------------------------------------------------------------------
 template <int DP>
-__global__ __launch_bounds__(256) void kmv64_kernel(KmvArgs A) {
+__device__ __forceinline__ void kmv64_body(const KmvArgs& A, int64_t bx, int64_t by) {
   if (A.S != nullptr && A.S->done) return;
-  if (A.pcg_step && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) A.S->kcur += 1;
+  if (A.pcg_step && bx == 0 && by == 0 && threadIdx.x == 0) A.S->kcur += 1;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int h = lane >> 4, c = lane & 15;
-  const int64_t rb0 = (int64_t)blockIdx.x * 64;
+  const int64_t rb0 = bx * 64;
   const int64_t row0 = rb0 + wv * 16;
-  const int64_t j0 = (int64_t)blockIdx.y * A.cps;
+  const int64_t j0 = by * A.cps;
   const int64_t j1 = j0 + A.cps < A.n ? j0 + A.cps : A.n;
   const double* __restrict__ p = A.p;
   const double* __restrict__ Q = reinterpret_cast<const double*>(A.Q);
@@ -368,7 +382,32 @@ __global__ __launch_bounds__(256) void kmv64_kernel(KmvArgs A) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) v = (r == c) ? acc[r] : v;
     const int64_t row = row0 + 4 * c + h;   // 16x16x4 f64 output: register r holds row 4 r + lane / 16
-    if (row < A.m) part[(int64_t)blockIdx.y * A.m + row] = v;
+    if (row < A.m) part[by * A.m + row] = v;
+  }
+}
+
+template <int DP>
+__global__ __launch_bounds__(256) void kmv64_kernel(KmvArgs A) {
+  kmv64_body<DP>(A, blockIdx.x, blockIdx.y);
+}
+
+template <int DP>
+__global__ __launch_bounds__(256) void kmv64_batch_kernel(const KmvArgs* __restrict__ As, const int* __restrict__ tiles) {
+  const int* t = tiles + 3 * (int64_t)blockIdx.x;
+  if (t[0] < 0) return;   // padding tile
+  const KmvArgs A = As[t[0]];
+  kmv64_body<DP>(A, t[1], t[2]);
+}
+
+// Batched finish: grid (blocks, problems); problems without a finished output skip.
+__global__ __launch_bounds__(256) void kmv_finish_batch_kernel(const KmvArgs* __restrict__ As) {
+  const KmvArgs A = As[blockIdx.y];
+  if (A.mode != 1) return;
+  if (A.S != nullptr && A.S->done) return;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < A.m; i += (int64_t)gridDim.x * 256) {
+    double s = 0.0;
+    for (int sp = 0; sp < A.nsplit; ++sp) s += A.part[(int64_t)sp * A.m + i];
+    A.out[i] = A.pself != nullptr ? fma(A.lam, A.pself[i], s) : s;
   }
 }
 
@@ -390,6 +429,29 @@ hipError_t launch64(int dp, dim3 grid, const KmvArgs& A, hipStream_t st) {
     case 32: kmv64_kernel<32><<<grid, 256, 0, st>>>(A); break;
     case 64: kmv64_kernel<64><<<grid, 256, 0, st>>>(A); break;
     case 128: kmv64_kernel<128><<<grid, 256, 0, st>>>(A); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int PREC>
+hipError_t launch32_batch(int dp, unsigned ntiles, const KmvArgs* As, const int* tiles, hipStream_t st) {
+  switch (dp) {
+    case 16: kmv32_batch_kernel<PREC, 16><<<ntiles, 256, 0, st>>>(As, tiles); break;
+    case 32: kmv32_batch_kernel<PREC, 32><<<ntiles, 256, 0, st>>>(As, tiles); break;
+    case 64: kmv32_batch_kernel<PREC, 64><<<ntiles, 256, 0, st>>>(As, tiles); break;
+    case 128: kmv32_batch_kernel<PREC, 128><<<ntiles, 256, 0, st>>>(As, tiles); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch64_batch(int dp, unsigned ntiles, const KmvArgs* As, const int* tiles, hipStream_t st) {
+  switch (dp) {
+    case 16: kmv64_batch_kernel<16><<<ntiles, 256, 0, st>>>(As, tiles); break;
+    case 32: kmv64_batch_kernel<32><<<ntiles, 256, 0, st>>>(As, tiles); break;
+    case 64: kmv64_batch_kernel<64><<<ntiles, 256, 0, st>>>(As, tiles); break;
+    case 128: kmv64_batch_kernel<128><<<ntiles, 256, 0, st>>>(As, tiles); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -450,6 +512,22 @@ hipError_t kmv_run(int prec, int dp, const KmvPlan& pl, KmvArgs A, hipStream_t s
   int64_t g = (A.m + 255) / 256;
   if (g > 4096) g = 4096;
   kmv_finish_kernel<<<(unsigned)g, 256, 0, st>>>(A.part, A.nsplit, A.m, A.lam, A.pself, A.out);
+  return hipGetLastError();
+}
+
+hipError_t kmv_run_batch(int prec, int dp, int count, const KmvArgs* As_dev, const int* tiles_dev, int ntiles,
+                         bool finish, int64_t max_m, hipStream_t st) {
+  hipError_t e;
+  if (ntiles > 0) {
+    if (prec == LAKER_F64) e = launch64_batch(dp, (unsigned)ntiles, As_dev, tiles_dev, st);
+    else if (prec == LAKER_F32) e = launch32_batch<LAKER_F32>(dp, (unsigned)ntiles, As_dev, tiles_dev, st);
+    else e = launch32_batch<LAKER_BF16>(dp, (unsigned)ntiles, As_dev, tiles_dev, st);
+    if (e != hipSuccess) return e;
+  }
+  if (!finish) return hipSuccess;
+  int64_t g = (max_m + 255) / 256;
+  if (g > 1024) g = 1024;
+  kmv_finish_batch_kernel<<<dim3((unsigned)g, (unsigned)count), 256, 0, st>>>(As_dev);
   return hipGetLastError();
 }
 

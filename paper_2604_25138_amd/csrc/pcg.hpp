@@ -82,6 +82,9 @@ laker_status pcg_run(const Problem& pb, const SolveWs& ws, const PrecondView& P,
 laker_status true_residual(const Problem& pb, const SolveWs& ws, const double* y, const double* alpha,
                            double* r_out, double* relres, bool have_alpha, hipStream_t st);
 laker_status axpy_inplace(double* x, const double* d, int64_t n, hipStream_t st);
+// The library's non-blocking stream (per device) on which iteration chunks are
+// captured into HIP graphs.
+hipStream_t pcg_capture_stream();
 laker_status apply_lowrank_once(const PrecondView& P, const double* r, double* theta, int64_t n,
                                 const SolveWs& ws, hipStream_t st);
 

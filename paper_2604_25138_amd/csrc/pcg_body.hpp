@@ -1,0 +1,469 @@
+// Per-block bodies of the PCG kernels (pcg.hip launches them one problem per
+// grid, bpcg.hip with a problem index per grid row).  Each body receives its
+// block index `blk` and the block count `nblk` of its problem's grid, so the
+// same body gives the same partial sums in either launch form.
+#pragma once
+
+#include "pcg.hpp"
+
+namespace lk {
+namespace pcgk {
+
+constexpr int kThreads = 256;
+
+// blocks of the low-rank apply: 16 rows per block pass, at most kMaxBlocks blocks
+inline int apply_blocks(int64_t n) {
+  int64_t g = (n + 15) / 16;
+  if (g > kMaxBlocks) g = kMaxBlocks;
+  return (int)(g < 1 ? 1 : g);
+}
+
+inline int red_blocks(int64_t n) {
+  int64_t g = (n + kThreads - 1) / kThreads;
+  if (g > kMaxBlocks) g = kMaxBlocks;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+
+// Grid reductions: every kernel writes one float64 partial per block with a
+// plain store; the kernel that needs the total (launched after it, so the
+// partials are visible) adds them in a fixed order in each of its blocks, and
+// block 0 records the scalar.  No atomics or fences inside the loop.
+
+// r = y - w (or y when w is null); p = 0; partials of ||y||^2 and ||r||^2.
+__device__ __forceinline__ void pcg_init_body(int blk, int nblk, const double* __restrict__ y, const double* __restrict__ w,
+                                                            double* __restrict__ r, double* __restrict__ p, int64_t n,
+                                                            double* __restrict__ yyp, double* __restrict__ rrp) {
+  __shared__ double sh[16];
+  double yy = 0.0, rr = 0.0;
+  for (int64_t i = (int64_t)blk * kThreads + threadIdx.x; i < n; i += (int64_t)nblk * kThreads) {
+    const double yi = y[i];
+    const double ri = w != nullptr ? yi - w[i] : yi;
+    r[i] = ri;
+    p[i] = 0.0;
+    yy += yi * yi;
+    rr += ri * ri;
+  }
+  yy = block_sum(yy, sh);
+  rr = block_sum(rr, sh);
+  if (threadIdx.x == 0) {
+    yyp[blk] = yy;
+    rrp[blk] = rr;
+  }
+}
+
+// One block: ||y||^2, ||r^0||^2, the tolerance and the initial state.
+__device__ __forceinline__ void pcg_start_body(int blk, int nblk, PcgScalars* S, const double* __restrict__ yyp,
+                                                             const double* __restrict__ rrp, int g, double tol,
+                                                             int max_iter) {
+  __shared__ double sh[16];
+  const double yy = ordered_sum(yyp, g, sh);
+  const double rr = ordered_sum(rrp, g, sh);
+  if (threadIdx.x == 0) {
+    S->yy = yy;
+    S->rr = rr;
+    S->tol2 = tol * tol * yy;
+    S->iters = 0;
+    S->max_iter = max_iter;
+    S->beta = 0.0;
+    S->kcur = 0;
+    S->done = (yy == 0.0 || rr <= tol * tol * yy) ? 1 : 0;
+  }
+}
+
+// Ap = lambda p + sum of the column-range partials; partials of p^T A p.
+__device__ __forceinline__ void pcg_ap_body(int blk, int nblk, const double* __restrict__ p, const double* __restrict__ part,
+                                                          int nsplit, double* __restrict__ Ap, int64_t n, double lam,
+                                                          double* __restrict__ pap_p, const PcgScalars* S) {
+  if (S->done) return;
+  __shared__ double sh[16];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blk * kThreads + threadIdx.x; i < n; i += (int64_t)nblk * kThreads) {
+    double s = 0.0;
+    for (int k = 0; k < nsplit; ++k) s += part[(int64_t)k * n + i];
+    const double pi = p[i];
+    const double a = fma(lam, pi, s);
+    Ap[i] = a;
+    acc += pi * a;
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) pap_p[blk] = acc;
+}
+
+// delta = r^T theta / p^T A p; alpha += delta p; r -= delta Ap (Alg. 1);
+// partials of ||r||^2 and, for Jacobi, theta = r / diag and r^T theta.
+template <int KIND>
+__device__ __forceinline__ void pcg_update_body(int blk, int nblk, double* __restrict__ alpha, double* __restrict__ r,
+                                                              const double* __restrict__ p,
+                                                              const double* __restrict__ Ap,
+                                                              const double* __restrict__ dinv,
+                                                              double* __restrict__ theta, int64_t n, PcgScalars* S,
+                                                              const double* __restrict__ pap_p, int gp,
+                                                              double* __restrict__ rrp, double* __restrict__ rzp) {
+  if (S->done) return;
+  __shared__ double sh[16];
+  const int k = S->kcur - 1;
+  const double pap = ordered_sum(pap_p, gp, sh);
+  const double dl = S->rzbuf[k & 1] / pap;
+  if (!(pap > 0.0) || !isfinite(dl)) {
+    if (blk == 0 && threadIdx.x == 0) S->done = 2;
+    return;
+  }
+  if (blk == 0 && threadIdx.x == 0) {
+    S->pap = pap;
+    S->delta = dl;
+  }
+  double rr = 0.0, rz = 0.0;
+  for (int64_t i = (int64_t)blk * kThreads + threadIdx.x; i < n; i += (int64_t)nblk * kThreads) {
+    alpha[i] = fma(dl, p[i], alpha[i]);
+    const double ri = fma(-dl, Ap[i], r[i]);
+    r[i] = ri;
+    rr += ri * ri;
+    if (KIND == LAKER_PRECOND_JACOBI) {
+      const double ti = ri * dinv[i];
+      theta[i] = ti;
+      rz += ri * ti;
+    }
+  }
+  rr = block_sum(rr, sh);
+  if (KIND == LAKER_PRECOND_JACOBI) rz = block_sum(rz, sh);
+  if (threadIdx.x == 0) {
+    rrp[blk] = rr;
+    rzp[blk] = rz;
+  }
+}
+
+// Stopping test of iteration k on the recursive residual (Alg. 1), evaluated
+// identically by every block; block 0 records it.  Returns true to continue.
+__device__ __forceinline__ bool pcg_decide(int blk, int k, PcgScalars* S, const double* __restrict__ rrp, int g,
+                                           double* sh) {
+  const double rr = ordered_sum(rrp, g, sh);
+  int d = 0;
+  if (!isfinite(rr)) d = 2;
+  else if (rr <= S->tol2) d = 1;
+  else if (k + 1 >= S->max_iter) d = 3;
+  if (blk == 0 && threadIdx.x == 0) {
+    S->rr = rr;
+    S->iters = k + 1;
+    if (d) S->done = d;
+  }
+  return d == 0;
+}
+
+// p = theta + beta p with beta = r_new^T theta_new / r^T theta.  With
+// init set: p = theta and r^T theta is stored for iteration 0.  For P = I and
+// Jacobi this kernel also takes the stopping decision of iteration k.
+template <int KIND>
+__device__ __forceinline__ void pcg_pupdate_body(int blk, int nblk, int init, const double* __restrict__ theta,
+                                                               double* __restrict__ p, int64_t n, PcgScalars* S,
+                                                               const double* __restrict__ rrp, int grr,
+                                                               const double* __restrict__ rzp, int grz) {
+  if (S->done) return;
+  __shared__ double sh[16];
+  const int k = S->kcur - 1;
+  if (!init && KIND != LAKER_PRECOND_CCCP && !pcg_decide(blk, k, S, rrp, grr, sh)) return;
+  const double rz = ordered_sum(KIND == LAKER_PRECOND_NONE ? rrp : rzp, KIND == LAKER_PRECOND_NONE ? grr : grz, sh);
+  const int slot = init ? 0 : ((k + 1) & 1);
+  const double b = init ? 0.0 : rz / S->rzbuf[k & 1];
+  if (blk == 0 && threadIdx.x == 0) {
+    S->rzbuf[slot] = rz;
+    S->beta = b;
+  }
+  for (int64_t i = (int64_t)blk * kThreads + threadIdx.x; i < n; i += (int64_t)nblk * kThreads)
+    p[i] = fma(b, p[i], theta[i]);
+}
+
+// theta = r / diag (Jacobi) with r^T theta partials, for the start of the iteration.
+__device__ __forceinline__ void jacobi_apply_body(int blk, int nblk, const double* __restrict__ r,
+                                                                const double* __restrict__ dinv,
+                                                                double* __restrict__ theta, int64_t n,
+                                                                const PcgScalars* S, double* __restrict__ rzp) {
+  if (S->done) return;
+  __shared__ double sh[16];
+  double rz = 0.0;
+  for (int64_t i = (int64_t)blk * kThreads + threadIdx.x; i < n; i += (int64_t)nblk * kThreads) {
+    const double ri = r[i];
+    const double ti = ri * dinv[i];
+    theta[i] = ti;
+    rz += ri * ti;
+  }
+  rz = block_sum(rz, sh);
+  if (threadIdx.x == 0) rzp[blk] = rz;
+}
+
+// Low-rank preconditioner  theta = c0 r + Bt (B^T r)  with B, Bt stored n x nrp
+// row-major (nrp = N_r rounded up to a multiple of 4, zero padding), as float64
+// or float32 (MT); products are accumulated in float64.
+//
+// t = B^T r, first half: block b owns rows [64 b, 64 b + 64).  A thread owns
+// four consecutive columns (one 16-byte load per row, 8 bytes for float64
+// pairs twice) and the block's threads are split into row groups when fewer
+// than 256 threads cover the columns; groups are combined in LDS in a fixed
+// order into one float64 partial row per block.
+constexpr int kTRows = 64;
+
+template <typename MT>
+__device__ __forceinline__ void lr_t_partial_body(int blk, int nblk, const MT* __restrict__ B, const double* __restrict__ r,
+                                                                int64_t n, int nrp, double* __restrict__ tpart,
+                                                                const PcgScalars* S) {
+  if (S != nullptr && S->done) return;
+  __shared__ double red[kMaxNr];
+  const int tid = threadIdx.x;
+  const int cq = nrp / 4;                       // column quads
+  int tpr = 1;                                  // threads per row group (power of two >= cq)
+  while (tpr < cq) tpr <<= 1;
+  const int groups = kThreads / tpr;
+  const int g = tid / tpr, q = tid % tpr;
+  const int64_t i0 = (int64_t)blk * kTRows;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  if (q < cq) {
+#pragma unroll 8
+    for (int rr = g; rr < kTRows; rr += groups) {
+      const int64_t i = i0 + rr;
+      if (i < n) {
+        const double ri = r[i];
+        const MT* row = B + i * nrp + 4 * q;
+        a0 = fma((double)row[0], ri, a0);
+        a1 = fma((double)row[1], ri, a1);
+        a2 = fma((double)row[2], ri, a2);
+        a3 = fma((double)row[3], ri, a3);
+      }
+    }
+  }
+  // fixed-order combination of the row groups
+  for (int gg = 0; gg < groups; ++gg) {
+    if (g == gg && q < cq) {
+      if (gg == 0) {
+        red[4 * q + 0] = a0;
+        red[4 * q + 1] = a1;
+        red[4 * q + 2] = a2;
+        red[4 * q + 3] = a3;
+      } else {
+        red[4 * q + 0] += a0;
+        red[4 * q + 1] += a1;
+        red[4 * q + 2] += a2;
+        red[4 * q + 3] += a3;
+      }
+    }
+    __syncthreads();
+  }
+  for (int k = tid; k < nrp; k += kThreads) tpart[(int64_t)blk * nrp + k] = red[k];
+}
+
+// PCG update fused with the first half of the low-rank preconditioner: block
+// b owns rows [64 b, 64 b + 64): delta from the p^T A p partials, alpha += delta p,
+// r -= delta Ap, the ||r||^2 partial, and t_b = B[rows]^T r[rows] from the
+// fresh r kept in LDS.  The stopping decision is taken by the next pass.
+template <typename MT>
+__device__ __forceinline__ void pcg_update_t_body(int blk, int nblk, double* __restrict__ alpha,
+                                                                double* __restrict__ r, const double* __restrict__ p,
+                                                                const double* __restrict__ Ap,
+                                                                const MT* __restrict__ B, int nrp, int64_t n,
+                                                                PcgScalars* S, const double* __restrict__ pap_p,
+                                                                int gp, double* __restrict__ rrp,
+                                                                double* __restrict__ tpart) {
+  if (S->done) return;
+  __shared__ double sh[16];
+  __shared__ double rs[kTRows];
+  __shared__ double red[kMaxNr];
+  const int tid = threadIdx.x;
+  const int k = S->kcur - 1;
+  const double pap = ordered_sum(pap_p, gp, sh);
+  const double dl = S->rzbuf[k & 1] / pap;
+  if (!(pap > 0.0) || !isfinite(dl)) {
+    if (blk == 0 && tid == 0) S->done = 2;
+    return;
+  }
+  if (blk == 0 && tid == 0) {
+    S->pap = pap;
+    S->delta = dl;
+  }
+  const int64_t i0 = (int64_t)blk * kTRows;
+  double rr = 0.0;
+  if (tid < kTRows) {
+    const int64_t i = i0 + tid;
+    double ri = 0.0;
+    if (i < n) {
+      alpha[i] = fma(dl, p[i], alpha[i]);
+      ri = fma(-dl, Ap[i], r[i]);
+      r[i] = ri;
+    }
+    rs[tid] = ri;
+    rr = ri * ri;
+  }
+  rr = block_sum(rr, sh);     // contains the barrier that publishes rs
+  if (tid == 0) rrp[blk] = rr;
+  const int cq = nrp / 4;
+  int tpr = 1;
+  while (tpr < cq) tpr <<= 1;
+  const int groups = kThreads / tpr;
+  const int g = tid / tpr, q = tid % tpr;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  if (q < cq) {
+#pragma unroll 8
+    for (int rr2 = g; rr2 < kTRows; rr2 += groups) {
+      const int64_t i = i0 + rr2;
+      if (i < n) {
+        const double ri = rs[rr2];
+        const MT* row = B + i * nrp + 4 * q;
+        a0 = fma((double)row[0], ri, a0);
+        a1 = fma((double)row[1], ri, a1);
+        a2 = fma((double)row[2], ri, a2);
+        a3 = fma((double)row[3], ri, a3);
+      }
+    }
+  }
+  for (int gg = 0; gg < groups; ++gg) {
+    if (g == gg && q < cq) {
+      if (gg == 0) {
+        red[4 * q + 0] = a0;
+        red[4 * q + 1] = a1;
+        red[4 * q + 2] = a2;
+        red[4 * q + 3] = a3;
+      } else {
+        red[4 * q + 0] += a0;
+        red[4 * q + 1] += a1;
+        red[4 * q + 2] += a2;
+        red[4 * q + 3] += a3;
+      }
+    }
+    __syncthreads();
+  }
+  for (int c = tid; c < nrp; c += kThreads) tpart[(int64_t)blk * nrp + c] = red[c];
+}
+
+// t[k] = sum_b tpart[b][k] in a fixed order: a block owns 16 columns; its 16
+// row groups of 16 threads each sum every 16th partial row, then combine in LDS.
+__device__ __forceinline__ void lr_t_finish_body(int blk, int nblk, const double* __restrict__ tpart, int nb, int nrp,
+                                                               double* __restrict__ t, PcgScalars* S,
+                                                               const double* __restrict__ rrp, int grr) {
+  if (S != nullptr && S->done) return;
+  __shared__ double red[16][17];
+  __shared__ double shd[16];
+  // inside the loop this pass takes the stopping decision of the current iteration first
+  if (rrp != nullptr && !pcg_decide(blk, S->kcur - 1, S, rrp, grr, shd)) return;
+  const int g = threadIdx.x >> 4, cl = threadIdx.x & 15;
+  const int col = blk * 16 + cl;
+  double s = 0.0;
+  if (col < nrp)
+    for (int b = g; b < nb; b += 16) s += tpart[(int64_t)b * nrp + col];
+  red[g][cl] = s;
+  __syncthreads();
+  if (g == 0 && col < nrp) {
+    double v = 0.0;
+    for (int gg = 0; gg < 16; ++gg) v += red[gg][cl];
+    t[col] = v;
+  }
+}
+
+// theta = c r + Bt t (c = c0, or dinv_i for a diagonal-plus-low-rank
+// preconditioner): 16 lanes per row (four rows per wave), 16-byte loads,
+// t in LDS; partials of r^T theta.
+template <typename MT>
+__device__ __forceinline__ void lr_apply_body(int blk, int nblk, const MT* __restrict__ Bt, const double* __restrict__ t,
+                                                            const double* __restrict__ r, double* __restrict__ theta,
+                                                            int64_t n, int nrp, const double* __restrict__ c0p,
+                                                            const double* __restrict__ dinv, const PcgScalars* S,
+                                                            double* __restrict__ rzp) {
+  if (S != nullptr && S->done) return;
+  constexpr int VEC = 16 / (int)sizeof(MT);
+  __shared__ double sh[16];
+  __shared__ double ts[kMaxNr];
+  const double c0 = c0p[0];
+  for (int k = threadIdx.x; k < nrp; k += kThreads) ts[k] = t[k];
+  __syncthreads();
+  const int sub = threadIdx.x & 15;
+  const int rl = threadIdx.x >> 4;                  // row slot within the block (16 per pass)
+  const int nvec = nrp / VEC;
+  double rz = 0.0;
+  for (int64_t i0 = (int64_t)blk * 16; i0 < n; i0 += (int64_t)nblk * 16) {
+    const int64_t i = i0 + rl;
+    double acc = 0.0;
+    if (i < n) {
+      // all of the lane's loads are issued before the first use
+      constexpr int MAXV = kMaxNr / VEC / 16;
+      const MT* row = Bt + i * nrp;
+      if constexpr (VEC == 4) {
+        float4 x[MAXV];
+#pragma unroll
+        for (int j = 0; j < MAXV; ++j)
+          if (sub + 16 * j < nvec) x[j] = *reinterpret_cast<const float4*>(row + 4 * (sub + 16 * j));
+#pragma unroll
+        for (int j = 0; j < MAXV; ++j) {
+          if (sub + 16 * j < nvec) {
+            const int v = sub + 16 * j;
+            acc = fma((double)x[j].x, ts[4 * v + 0], acc);
+            acc = fma((double)x[j].y, ts[4 * v + 1], acc);
+            acc = fma((double)x[j].z, ts[4 * v + 2], acc);
+            acc = fma((double)x[j].w, ts[4 * v + 3], acc);
+          }
+        }
+      } else {
+        double2 x[MAXV];
+#pragma unroll
+        for (int j = 0; j < MAXV; ++j)
+          if (sub + 16 * j < nvec) x[j] = *reinterpret_cast<const double2*>(row + 2 * (sub + 16 * j));
+#pragma unroll
+        for (int j = 0; j < MAXV; ++j) {
+          if (sub + 16 * j < nvec) {
+            const int v = sub + 16 * j;
+            acc = fma(x[j].x, ts[2 * v + 0], acc);
+            acc = fma(x[j].y, ts[2 * v + 1], acc);
+          }
+        }
+      }
+    }
+    acc += __shfl_xor(acc, 1, 64);
+    acc += __shfl_xor(acc, 2, 64);
+    acc += __shfl_xor(acc, 4, 64);
+    acc += __shfl_xor(acc, 8, 64);
+    if (sub == 0 && i < n) {
+      const double ri = r[i];
+      const double th = fma(dinv != nullptr ? dinv[i] : c0, ri, acc);
+      theta[i] = th;
+      rz += ri * th;
+    }
+  }
+  rz = block_sum(rz, sh);
+  if (threadIdx.x == 0 && rzp != nullptr) rzp[blk] = rz;
+}
+
+// ||y - w||^2 and ||y||^2 (float64), for the true residual; r = y - w if r is set.
+__device__ __forceinline__ void resid_body(int blk, int nblk, const double* __restrict__ y, const double* __restrict__ w,
+                                                         double* __restrict__ r, int64_t n,
+                                                         double* __restrict__ bpart, unsigned* cnt, double* out2) {
+  __shared__ double sh[16];
+  double rr = 0.0, yy = 0.0;
+  for (int64_t i = (int64_t)blk * kThreads + threadIdx.x; i < n; i += (int64_t)nblk * kThreads) {
+    const double yi = y[i];
+    const double ri = w != nullptr ? yi - w[i] : yi;
+    if (r != nullptr) r[i] = ri;
+    rr += ri * ri;
+    yy += yi * yi;
+  }
+  rr = block_sum(rr, sh);
+  yy = block_sum(yy, sh);
+  if (threadIdx.x == 0) {
+    bpart[blk] = rr;
+    bpart[kMaxBlocks + blk] = yy;
+  }
+  if (last_block_arrived_of(cnt, (unsigned)nblk)) {
+    const double srr = ordered_sum(bpart, nblk, sh);
+    const double syy = ordered_sum(bpart + kMaxBlocks, nblk, sh);
+    if (threadIdx.x == 0) {
+      out2[0] = srr;
+      out2[1] = syy;
+      *cnt = 0;
+    }
+  }
+}
+
+__device__ __forceinline__ void axpy_body(int blk, int nblk, double* __restrict__ x, const double* __restrict__ d, int64_t n) {
+  for (int64_t i = (int64_t)blk * kThreads + threadIdx.x; i < n; i += (int64_t)nblk * kThreads)
+    x[i] += d[i];
+}
+
+
+}  // namespace pcgk
+}  // namespace lk

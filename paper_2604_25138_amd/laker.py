@@ -27,7 +27,8 @@ EXPORTS = (
     "laker_kernel_matvec", "laker_fit_precond", "laker_jacobi_precond", "laker_pcg_solve",
     "laker_predict", "laker_status_str", "laker_mlp_layout_query", "laker_learned_workspace_bytes",
     "laker_learned_forward", "laker_learned_train_step", "laker_learned_precond",
-    "laker_sigma_half_workspace_bytes", "laker_precond_sigma_half",
+    "laker_sigma_half_workspace_bytes", "laker_precond_sigma_half", "laker_batch_workspace_bytes",
+    "laker_pcg_solve_batched",
 )
 MLP_KEYS = ("W1", "b1", "W2", "b2", "W3", "b3")
 MLP_HIDDEN, MLP_RANK = 256, 64
@@ -69,6 +70,11 @@ class laker_mlp_layout(C.Structure):
 class laker_train_opts(C.Structure):
     _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
                 ("step", C.c_int32), ("update", C.c_int32)]
+
+
+class laker_batch_opts(C.Structure):
+    _fields_ = [("cols_per_split", C.c_int32), ("xcd_order", C.c_int32), ("cols_used", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class LakerError(RuntimeError):
@@ -125,6 +131,11 @@ def load(path: str = LIB_PATH):
     lib.laker_sigma_half_workspace_bytes.restype = sz
     lib.laker_precond_sigma_half.argtypes = [P(laker_precond), i32, vp, vp, vp, sz, vp]
     lib.laker_precond_sigma_half.restype = i32
+    lib.laker_batch_workspace_bytes.argtypes = [i32, P(i64), i32]
+    lib.laker_batch_workspace_bytes.restype = sz
+    lib.laker_pcg_solve_batched.argtypes = [i32, P(laker_problem), P(laker_precond), P(vp), P(vp),
+                                            P(laker_pcg_opts), P(laker_batch_opts), vp, sz, P(laker_stats), vp]
+    lib.laker_pcg_solve_batched.restype = i32
     _lib = lib
     return lib
 
@@ -423,3 +434,36 @@ def sigma_half(pc: Precond, Z: torch.Tensor) -> torch.Tensor:
     s = lib.laker_precond_sigma_half(C.byref(pc.c), m, _ptr(Z), _ptr(U), _ptr(ws), ws.numel(), _stream())
     _check(s, "laker_precond_sigma_half")
     return U
+
+
+# ---------------------------------------------------------------------------
+# batched solve
+# ---------------------------------------------------------------------------
+
+def pcg_solve_batched(probs: list, ys: list, preconds: list | None = None, tol: float = 1e-10,
+                      max_iter: int = 10000, precision="f64", refine: bool = False, inner_tol: float = 1e-2,
+                      ir_max: int = 64, check_every: int = 16, graph: bool = False, cols_per_split: int = 0,
+                      xcd_order: bool = False, allow_noconv: bool = False):
+    """Solve every problem of the batch; returns (alphas, stats list, columns per range used)."""
+    lib = load()
+    count = len(probs)
+    dev = probs[0].device
+    ys = [_dev_f64(v, dev) for v in ys]
+    alphas = [torch.empty_like(v) for v in ys]
+    pa = (laker_problem * count)(*[p.c for p in probs])
+    pc = None
+    if preconds is not None:
+        pc = (laker_precond * count)(*[q.c for q in preconds])
+    yp = (C.c_void_p * count)(*[v.data_ptr() for v in ys])
+    ap = (C.c_void_p * count)(*[v.data_ptr() for v in alphas])
+    opts = laker_pcg_opts(tol, max_iter, _PREC[precision], 1 if refine else 0, ir_max, inner_tol, 0, check_every,
+                          1 if graph else 0, 0)
+    bo = laker_batch_opts(cols_per_split, 1 if xcd_order else 0, 0, 0)
+    ns = (C.c_int64 * count)(*[p.n for p in probs])
+    nb = lib.laker_batch_workspace_bytes(count, ns, probs[0].d)
+    ws = _workspace("batch", nb, dev)
+    st = (laker_stats * count)()
+    s = lib.laker_pcg_solve_batched(count, pa, pc, yp, ap, C.byref(opts), C.byref(bo), _ptr(ws), ws.numel(), st,
+                                    _stream())
+    _check(s, "laker_pcg_solve_batched", (LAKER_OK, LAKER_ENOCONV) if allow_noconv else (LAKER_OK,))
+    return alphas, list(st), bo.cols_used
