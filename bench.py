@@ -13,7 +13,8 @@ Beside the timed path the run reports: the same map solved entirely in float64
 with the paper's CCCP preconditioner (FP64 CCCP-PCG, the metric's comparison),
 the CCCP + mixed-precision step, the roofline position of the dominant kernel
 (the fused kernel product, timed with HIP events around every product of the
-solve on the library's stream), and the FP64 CPU oracle timed on a bounded
+solve on the library's stream), a batched leg (maps of uneven size solved
+together vs one after the other), and the FP64 CPU oracle timed on a bounded
 sample of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -60,6 +61,8 @@ def parse():
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work in the CPU sample")
     ap.add_argument("--train-maps", type=int, default=TRAIN_MAPS)
     ap.add_argument("--train-epochs", type=int, default=TRAIN_EPOCHS)
+    ap.add_argument("--batch-maps", type=int, default=32,
+                    help="maps in the batched leg (n ~ U[1024, 16384], d = 32); 0 skips it")
     return ap.parse_args()
 
 
@@ -92,6 +95,44 @@ def train_model(L, LR, d, dev, n_maps, epochs):
             "targets_s": t1 - t0, "train_s": t2 - t1, "ms_per_step": (t2 - t1) * 1e3 / (epochs * n_maps),
             "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1]}
     return model, info
+
+
+def batched_leg(L, LR, dev, count, train_maps, train_epochs):
+    """Maps of uneven size (n ~ U[1024, 16384], d = 32, lambda log-uniform in
+    [1e-5, 1e-2], 1..8 transmitters) solved together to float64 relative
+    residual 1e-6 with learned preconditioners, against the same maps solved
+    one after the other with the same kernels."""
+    import torch
+
+    from synth import make_batch_specs, make_problem
+    model, _ = train_model(L, LR, 32, dev, max(16, train_maps // 2), train_epochs)
+    probs, ys = [], []
+    for (n, lam, ntx, seed) in make_batch_specs(count, 1024, 16384, 1e-5, 1e-2, 1, 8, seed=4):
+        pr = make_problem(n, 32, lam, n_tx=ntx, seed=seed)
+        probs.append(L.Problem(torch.tensor(pr.E, device=dev), pr.lam, pr.scale))
+        ys.append(torch.tensor(pr.y, device=dev))
+    kw = dict(tol=1e-6, max_iter=200000, precision="bf16", refine=True, inner_tol=0.1, ir_max=64, check_every=32)
+    # autotune once (cached per size class), then time
+    precs = [L.learned_precond(p, model) for p in probs]
+    L.pcg_solve_batched(probs, ys, precs, cols_per_split=-1, xcd_order=False, allow_noconv=True, **kw)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    precs = [L.learned_precond(p, model) for p in probs]
+    _, st, used = L.pcg_solve_batched(probs, ys, precs, cols_per_split=-1, xcd_order=False, allow_noconv=True, **kw)
+    torch.cuda.synchronize()
+    b = time.perf_counter()
+    its_serial = []
+    for p, y in zip(probs, ys):
+        pc = L.learned_precond(p, model)
+        _, s1 = L.pcg_solve(p, y, pc, allow_noconv=True, **kw)
+        its_serial.append(s1.iters)
+    torch.cuda.synchronize()
+    c = time.perf_counter()
+    return {"maps": count, "pairs_per_sweep": float(sum(p.n * p.n for p in probs)),
+            "batched_s": b - a, "maps_per_s": count / (b - a), "serial_s": c - b, "serial_maps_per_s": count / (c - b),
+            "speedup_vs_serial": (c - b) / (b - a), "converged": sum(1 for x in st if x.status == 0),
+            "worst_relres_true": max(x.relres_true for x in st), "escalations": sum(x.escalations for x in st),
+            "max_iters": max(x.iters for x in st), "cols_per_split_largest": used}
 
 
 def main():
@@ -235,6 +276,9 @@ def main():
         "roofline": roofline,
         "extra": extra,
     }
+
+    if args.batch_maps > 0:
+        extra["batched"] = batched_leg(L, LR, dev, args.batch_maps, args.train_maps, args.train_epochs)
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(pr, Z, tol, extra.get("f64_cccp_pcg", {}).get("pcg_iters"),

@@ -132,6 +132,10 @@ typedef struct {
   int32_t kmv_launches; /* profile: product launches, including the ones enqueued
                            after convergence, which return at entry              */
   double kmv_launch_ms; /* profile: mean duration over all kmv_launches          */
+  int32_t escalations;  /* refinement: times the inner product arithmetic was made
+                           finer (bfloat16 -> float32 -> float64) after two
+                           refinement steps without progress                    */
+  int32_t reserved;
 } laker_stats;
 
 /* ---- sizes ---------------------------------------------------------------- */
@@ -259,13 +263,15 @@ laker_status laker_precond_sigma_half(const laker_precond* precond, int32_t m, c
  * scalars and retires at its own tolerance (Alg. 1 per map), with the same
  * float64 refinement as laker_pcg_solve when opts->refine is set. */
 typedef struct {
-  int32_t cols_per_split; /* -1: autotuned (one product sweep timed per candidate
-                             length on this batch, cached per batch shape);
+  int32_t cols_per_split; /* -1: autotuned per size class (maps with the same
+                             floor(log2 n); the product of the class's largest
+                             map timed per candidate length, cached per class);
                              0: the single-map plan of each map (bitwise the same
                              iterates as laker_pcg_solve); > 0: this many columns */
   int32_t xcd_order;      /* 1: tiles ordered so that each XCD walks its own
                              contiguous stretch of the tile list                */
-  int32_t cols_used;      /* out: the length used (0: single-map plans)         */
+  int32_t cols_used;      /* out: the length used for the largest map
+                             (0: its single-map plan)                          */
   int32_t reserved;
 } laker_batch_opts;
 

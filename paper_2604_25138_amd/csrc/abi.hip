@@ -207,6 +207,7 @@ laker_status laker_pcg_solve(const laker_problem* prob, const laker_precond* pre
   sp->kmv_count = 0;
   sp->kmv_launches = 0;
   sp->kmv_launch_ms = 0.0;
+  sp->escalations = 0;
   const int check = opts->check_every > 0 ? opts->check_every : 16;
   LK_TRY(hipMemsetAsync(W.S, 0, sizeof(PcgScalars), st));
   LK_TRY(hipMemsetAsync(W.cnt, 0, 16 * sizeof(unsigned), st));
@@ -229,6 +230,7 @@ laker_status laker_pcg_solve(const laker_problem* prob, const laker_precond* pre
     if (!opts->warm_start) LK_TRY(hipMemsetAsync(alpha, 0, sizeof(double) * pb.n, st));
     r = LAKER_ENOCONV;
     int used = 0;
+    int prec_now = opts->precision;
     for (int s = 0; s <= opts->ir_max; ++s) {
       double rel = 0.0;
       laker_status r2 = true_residual(pb, W, y, alpha, W.rout, &rel, s > 0 || opts->warm_start, st);
@@ -242,6 +244,14 @@ laker_status laker_pcg_solve(const laker_problem* prob, const laker_precond* pre
         break;
       }
       if (s == opts->ir_max || used >= opts->max_iter) break;
+      // no progress over two refinement steps: the inner products are too
+      // coarse for this system (the correction they give does not contract the
+      // float64 residual); continue with the next finer arithmetic
+      if (s >= 2 && rel > sp->ir_relres[s - 2] && prec_now != LAKER_F64) {
+        prec_now = prec_now == LAKER_BF16 ? LAKER_F32 : LAKER_F64;
+        sp->escalations += 1;
+        if (prec_now == LAKER_F32) LK_TRY(prep_embed(pb.E, pb.n, pb.d, pb.dp, pb.scale, LAKER_F32, W.e32, st));
+      }
       // the correction need not be solved more accurately than the outer
       // tolerance still requires
       double itol = opts->inner_tol;
@@ -249,7 +259,7 @@ laker_status laker_pcg_solve(const laker_problem* prob, const laker_precond* pre
       if (need > itol) itol = need;
       laker_stats inner{};
       laker_status ri = pcg_run(pb, W, view, W.rout, W.dalpha, false, itol, opts->max_iter - used, check,
-                                opts->precision, opts->graph != 0, opts->profile != 0, &inner, st);
+                                prec_now, opts->graph != 0, opts->profile != 0, &inner, st);
       used += inner.iters;
       sp->iters = used;
       if (inner.kmv_count > 0) {

@@ -30,95 +30,93 @@ namespace {
 
 using namespace pcgk;
 
-// ---- batched passes (grid: x = blocks of the largest map, y = map) ----
+// ---- batched passes (grid: x = blocks of the largest map, y = entry of the map
+// list R: the maps a pass works on) ----
 
-__global__ __launch_bounds__(kThreads) void b_zero_kernel(const BDesc* __restrict__ D) {
-  const BDesc& d = D[blockIdx.y];
+__global__ __launch_bounds__(kThreads) void b_zero_kernel(const BDesc* __restrict__ D, const int* __restrict__ R) {
+  const BDesc& d = D[R[blockIdx.y]];
   if (!d.active) return;
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < d.n; i += (int64_t)gridDim.x * kThreads)
     d.x[i] = 0.0;
 }
 
-__global__ __launch_bounds__(kThreads) void b_init_kernel(const BDesc* __restrict__ D) {
-  const BDesc& d = D[blockIdx.y];
+__global__ __launch_bounds__(kThreads) void b_init_kernel(const BDesc* __restrict__ D, const int* __restrict__ R) {
+  const BDesc& d = D[R[blockIdx.y]];
   if (!d.active || (int)blockIdx.x >= d.g) return;
   pcg_init_body(blockIdx.x, d.g, d.rhs, nullptr, d.r, d.p, d.n, d.yyp, d.rrp);
 }
 
-__global__ __launch_bounds__(kThreads) void b_start_kernel(const BDesc* __restrict__ D) {
-  const BDesc& d = D[blockIdx.y];
-  if (!d.active) {
-    if (threadIdx.x == 0) d.S->done = 4;   // retired: every pass of this map returns at once
-    return;
-  }
+__global__ __launch_bounds__(kThreads) void b_start_kernel(const BDesc* __restrict__ D, const int* __restrict__ R) {
+  const BDesc& d = D[R[blockIdx.y]];
+  if (!d.active) return;
   pcg_start_body(0, 1, d.S, d.yyp, d.rrp, d.g, d.tol, d.max_iter);
 }
 
-__global__ __launch_bounds__(kThreads) void b_ap_kernel(const BDesc* __restrict__ D) {
-  const BDesc& d = D[blockIdx.y];
+__global__ __launch_bounds__(kThreads) void b_ap_kernel(const BDesc* __restrict__ D, const int* __restrict__ R) {
+  const BDesc& d = D[R[blockIdx.y]];
   if ((int)blockIdx.x >= d.g) return;
   pcg_ap_body(blockIdx.x, d.g, d.p, d.part, d.nsplit, d.Ap, d.n, d.lam, d.papp, d.S);
 }
 
 template <int KIND>
-__global__ __launch_bounds__(kThreads) void b_update_kernel(const BDesc* __restrict__ D) {
-  const BDesc& d = D[blockIdx.y];
+__global__ __launch_bounds__(kThreads) void b_update_kernel(const BDesc* __restrict__ D, const int* __restrict__ R) {
+  const BDesc& d = D[R[blockIdx.y]];
   if ((int)blockIdx.x >= d.g) return;
   pcg_update_body<KIND>(blockIdx.x, d.g, d.x, d.r, d.p, d.Ap, d.dinv, d.th, d.n, d.S, d.papp, d.g, d.rrp, d.rzp);
 }
 
 template <typename MT>
-__global__ __launch_bounds__(kThreads) void b_update_t_kernel(const BDesc* __restrict__ D) {
-  const BDesc& d = D[blockIdx.y];
+__global__ __launch_bounds__(kThreads) void b_update_t_kernel(const BDesc* __restrict__ D, const int* __restrict__ R) {
+  const BDesc& d = D[R[blockIdx.y]];
   if ((int)blockIdx.x >= d.nbt) return;
   pcg_update_t_body<MT>(blockIdx.x, d.nbt, d.x, d.r, d.p, d.Ap, (const MT*)d.B, d.nrp, d.n, d.S, d.papp, d.g, d.rrp,
                         d.tpart);
 }
 
 template <typename MT>
-__global__ __launch_bounds__(kThreads) void b_lr_t_partial_kernel(const BDesc* __restrict__ D) {
-  const BDesc& d = D[blockIdx.y];
-  if ((int)blockIdx.x >= d.nbt) return;
+__global__ __launch_bounds__(kThreads) void b_lr_t_partial_kernel(const BDesc* __restrict__ D, const int* __restrict__ R) {
+  const BDesc& d = D[R[blockIdx.y]];
+  if (!d.active || (int)blockIdx.x >= d.nbt) return;
   lr_t_partial_body<MT>(blockIdx.x, d.nbt, (const MT*)d.B, d.r, d.n, d.nrp, d.tpart, d.S);
 }
 
-__global__ __launch_bounds__(kThreads) void b_lr_t_finish_kernel(const BDesc* __restrict__ D, int decide) {
-  const BDesc& d = D[blockIdx.y];
+__global__ __launch_bounds__(kThreads) void b_lr_t_finish_kernel(const BDesc* __restrict__ D, const int* __restrict__ R, int decide, int masked) {
+  const BDesc& d = D[R[blockIdx.y]];
   const int nb = (d.nrp + 15) / 16;
-  if ((int)blockIdx.x >= nb) return;
+  if ((masked && !d.active) || (int)blockIdx.x >= nb) return;
   lr_t_finish_body(blockIdx.x, nb, d.tpart, d.nbt, d.nrp, d.t, d.S, decide ? d.rrp : nullptr, d.nbt);
 }
 
 template <typename MT>
-__global__ __launch_bounds__(kThreads) void b_lr_apply_kernel(const BDesc* __restrict__ D) {
-  const BDesc& d = D[blockIdx.y];
-  if ((int)blockIdx.x >= d.ga) return;
+__global__ __launch_bounds__(kThreads) void b_lr_apply_kernel(const BDesc* __restrict__ D, const int* __restrict__ R, int masked) {
+  const BDesc& d = D[R[blockIdx.y]];
+  if ((masked && !d.active) || (int)blockIdx.x >= d.ga) return;
   lr_apply_body<MT>(blockIdx.x, d.ga, (const MT*)d.Bt, d.t, d.r, d.th, d.n, d.nrp, d.c0p, d.dinv, d.S, d.rzp);
 }
 
-__global__ __launch_bounds__(kThreads) void b_jacobi_apply_kernel(const BDesc* __restrict__ D) {
-  const BDesc& d = D[blockIdx.y];
-  if ((int)blockIdx.x >= d.g) return;
+__global__ __launch_bounds__(kThreads) void b_jacobi_apply_kernel(const BDesc* __restrict__ D, const int* __restrict__ R) {
+  const BDesc& d = D[R[blockIdx.y]];
+  if (!d.active || (int)blockIdx.x >= d.g) return;
   jacobi_apply_body(blockIdx.x, d.g, d.r, d.dinv, d.th, d.n, d.S, d.rzp);
 }
 
 template <int KIND>
-__global__ __launch_bounds__(kThreads) void b_pupdate_kernel(const BDesc* __restrict__ D, int init) {
-  const BDesc& d = D[blockIdx.y];
-  if ((int)blockIdx.x >= d.g) return;
+__global__ __launch_bounds__(kThreads) void b_pupdate_kernel(const BDesc* __restrict__ D, const int* __restrict__ R, int init, int masked) {
+  const BDesc& d = D[R[blockIdx.y]];
+  if ((masked && !d.active) || (int)blockIdx.x >= d.g) return;
   const double* src = KIND == LAKER_PRECOND_NONE ? d.r : d.th;
   const int grz = KIND == LAKER_PRECOND_CCCP ? d.ga : d.g;
   pcg_pupdate_body<KIND>(blockIdx.x, d.g, init, src, d.p, d.n, d.S, d.rrp, d.g, d.rzp, grz);
 }
 
-__global__ __launch_bounds__(kThreads) void b_resid_kernel(const BDesc* __restrict__ D) {
-  const BDesc& d = D[blockIdx.y];
+__global__ __launch_bounds__(kThreads) void b_resid_kernel(const BDesc* __restrict__ D, const int* __restrict__ R) {
+  const BDesc& d = D[R[blockIdx.y]];
   if (!d.active || (int)blockIdx.x >= d.g) return;
   resid_body(blockIdx.x, d.g, d.y, d.have_alpha ? d.w64 : nullptr, d.rout, d.n, d.bpart, d.cnt, d.misc);
 }
 
-__global__ __launch_bounds__(kThreads) void b_axpy_kernel(const BDesc* __restrict__ D) {
-  const BDesc& d = D[blockIdx.y];
+__global__ __launch_bounds__(kThreads) void b_axpy_kernel(const BDesc* __restrict__ D, const int* __restrict__ R) {
+  const BDesc& d = D[R[blockIdx.y]];
   if (!d.active || (int)blockIdx.x >= d.g) return;
   axpy_body(blockIdx.x, d.g, d.alpha, d.x, d.n);
 }
@@ -193,8 +191,8 @@ int max_of(const std::vector<BDesc>& h, int BDesc::*f) {
   return m;
 }
 
-// Autotuned column-range length per (precision, dp, batch shape); chosen by
-// timing one batched product sweep for each candidate.
+// Autotuned column-range length per (precision, dp, size class, maps in the
+// class); chosen by timing one product sweep of the class for each candidate.
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int, int64_t>, int> g_tuned;
 
@@ -214,12 +212,14 @@ size_t plan_batch_ws(int count, const int64_t* n, int d, size_t* offsets, void* 
     // rows of 64, at most kMaxSplit column ranges
     tiles += ((n[b] + 63) / 64) * kMaxSplit;
   }
-  tiles += 8;
+  tiles += 32;
   w.desc = c.take<BDesc>(count);
   w.inner = c.take<KmvArgs>(count);
   w.outer = c.take<KmvArgs>(count);
   w.tiles_in = c.take<int>((size_t)tiles * 3);
   w.tiles_out = c.take<int>((size_t)tiles * 3);
+  w.run_it = c.take<int>(count);
+  w.run_op = c.take<int>(count);
   w.hs = c.take<PcgScalars>(count);
   w.misc = c.take<double>((size_t)2 * count);
   w.total = c.bytes();
@@ -285,58 +285,64 @@ laker_status pcg_batch(int count, const Problem* pbs, const SolveWs* wss, const 
   }
 
   // column ranges of the inner products: the single-map plan, a given length,
-  // or the autotuned one
-  int cps = bo.cps;
-  std::vector<int> all(count, 1);
+  // or autotuned per size class (maps with the same floor(log2 n)): the product
+  // of the class's largest map is timed for each candidate length
   std::vector<KmvArgs> hin(count), hout(count);
-  auto make_inner = [&](int cps_req, std::vector<Plan1>& pl) {
-    pl.resize(count);
+  std::vector<int> cps_map(count, bo.cps > 0 ? bo.cps : 0);
+  if (bo.cps < 0) {
+    std::map<int, std::vector<int>> classes;
     for (int b = 0; b < count; ++b) {
-      pl[b] = plan_for(pbs[b].n, prec, cps_req);
-      KmvArgs A = kmv_args(prepared(wss[b], prec), pbs[b].n, prepared(wss[b], prec), pbs[b].n, wss[b].p, wss[b]);
-      A.mode = 0;
-      A.S = wss[b].S;
-      A.pcg_step = 1;
-      A.cps = pl[b].cps;
-      A.nsplit = pl[b].nsplit;
-      hin[b] = A;
-      hd[b].nsplit = pl[b].nsplit;
+      int c = 0;
+      while ((int64_t(1) << (c + 1)) <= pbs[b].n) ++c;
+      classes[c].push_back(b);
     }
-  };
-  if (cps < 0) {
-    int64_t sum_n = 0;
-    for (int b = 0; b < count; ++b) sum_n += pbs[b].n;
-    const auto key2 = std::make_tuple(prec, dp, count, sum_n);
-    std::lock_guard<std::mutex> lock(g_tune_mu);
-    auto it = g_tuned.find(key2);
-    if (it != g_tuned.end()) {
-      cps = it->second;
-    } else {
-      // time one sweep per candidate (arguments without scalars: nothing skips)
-      const int cands[] = {0, 1024, 2048, 4096, 8192};
+    hipEvent_t e0, e1;
+    LK_TRY(hipEventCreate(&e0));
+    LK_TRY(hipEventCreate(&e1));
+    for (auto& kv : classes) {
+      const std::vector<int>& members = kv.second;
+      const auto key = std::make_tuple(prec, dp, kv.first, (int64_t)members.size());
+      {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        auto it = g_tuned.find(key);
+        if (it != g_tuned.end()) {
+          for (int b : members) cps_map[b] = it->second;
+          continue;
+        }
+      }
+      const int cands[] = {0, 512, 1024, 2048, 4096};
       float best = 1e30f;
       int best_c = 0;
-      hipEvent_t e0, e1;
-      LK_TRY(hipEventCreate(&e0));
-      LK_TRY(hipEventCreate(&e1));
       for (int cand : cands) {
         bool ok = true;
-        for (int b = 0; b < count && ok; ++b)
+        for (int b : members)
           if (cand > 0 && (pbs[b].n + cand - 1) / cand > kMaxSplit) ok = false;
         if (!ok) continue;
-        std::vector<Plan1> pl;
-        make_inner(cand, pl);
-        for (int b = 0; b < count; ++b) {
-          hin[b].S = nullptr;
-          hin[b].pcg_step = 0;
+        // timed on the class's largest map alone: the refinement's tail, where
+        // a few large maps run by themselves, is where the batch spends its time
+        int big = members[0];
+        for (int b : members)
+          if (pbs[b].n > pbs[big].n) big = b;
+        std::vector<Plan1> pl(count);
+        std::vector<int> use(count, 0);
+        for (int b : {big}) {
+          use[b] = 1;
+          pl[b] = plan_for(pbs[b].n, prec, cand);
+          KmvArgs A = kmv_args(prepared(wss[b], prec), pbs[b].n, prepared(wss[b], prec), pbs[b].n, wss[b].p,
+                               wss[b]);
+          A.mode = 0;
+          A.cps = pl[b].cps;
+          A.nsplit = pl[b].nsplit;
+          hin[b] = A;   // no scalars: nothing skips
         }
-        std::vector<int> tl = build_tiles(count, pl, all, xcd);
+        std::vector<int> tl = build_tiles(count, pl, use, xcd);
+        const int nt = (int)(tl.size() / 3);
         LK_TRY(hipMemcpyAsync(bw.inner, hin.data(), sizeof(KmvArgs) * count, hipMemcpyHostToDevice, st));
         LK_TRY(hipMemcpyAsync(bw.tiles_in, tl.data(), sizeof(int) * tl.size(), hipMemcpyHostToDevice, st));
-        const int nt = (int)(tl.size() / 3);
         LK_TRY(kmv_run_batch(prec, dp, count, bw.inner, bw.tiles_in, nt, false, max_n, st));
         LK_TRY(hipEventRecord(e0, st));
-        for (int rep = 0; rep < 2; ++rep) LK_TRY(kmv_run_batch(prec, dp, count, bw.inner, bw.tiles_in, nt, false, max_n, st));
+        for (int rep = 0; rep < 2; ++rep)
+          LK_TRY(kmv_run_batch(prec, dp, count, bw.inner, bw.tiles_in, nt, false, max_n, st));
         LK_TRY(hipEventRecord(e1, st));
         LK_TRY(hipEventSynchronize(e1));
         float ms = 0.f;
@@ -346,19 +352,58 @@ laker_status pcg_batch(int count, const Problem* pbs, const SolveWs* wss, const 
           best_c = cand;
         }
       }
-      (void)hipEventDestroy(e0);
-      (void)hipEventDestroy(e1);
-      cps = best_c;
-      g_tuned[key2] = cps;
+      for (int b : members) cps_map[b] = best_c;
+      std::lock_guard<std::mutex> lock(g_tune_mu);
+      g_tuned[key] = best_c;
     }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
   }
-  std::vector<Plan1> pl_in;
-  make_inner(cps, pl_in);
-  if (cps_used) *cps_used = cps;
-  std::vector<int> tin = build_tiles(count, pl_in, all, xcd);
-  const int nt_in = (int)(tin.size() / 3);
-  LK_TRY(hipMemcpyAsync(bw.inner, hin.data(), sizeof(KmvArgs) * count, hipMemcpyHostToDevice, st));
-  LK_TRY(hipMemcpyAsync(bw.tiles_in, tin.data(), sizeof(int) * tin.size(), hipMemcpyHostToDevice, st));
+  if (cps_used) {
+    int big = 0;
+    for (int b = 0; b < count; ++b)
+      if (pbs[b].n > pbs[big].n) big = b;
+    *cps_used = cps_map[big];
+  }
+
+  // per-map inner arithmetic (refinement can make it finer per map) and the
+  // product tiles grouped by arithmetic: group q holds the maps computing in
+  // precision kPrecOrder[q]
+  const int kPrecOrder[3] = {LAKER_BF16, LAKER_F32, LAKER_F64};
+  std::vector<int> pm(count, prec);
+  int grp_off[3] = {0, 0, 0}, grp_nt[3] = {0, 0, 0};
+  // arguments of every map; tiles only for the maps in `members`
+  auto rebuild_inner = [&](const std::vector<int>& members) -> laker_status {
+    std::vector<int> in_list(count, 0);
+    for (int b : members) in_list[b] = 1;
+    std::vector<int> tl_all;
+    for (int q = 0; q < 3; ++q) {
+      const int pq = kPrecOrder[q];
+      std::vector<Plan1> pl(count);
+      std::vector<int> use(count, 0);
+      for (int b = 0; b < count; ++b) {
+        if (pm[b] != pq) continue;
+        use[b] = in_list[b];
+        pl[b] = plan_for(pbs[b].n, pq, pq == prec ? cps_map[b] : 0);
+        KmvArgs A = kmv_args(prepared(wss[b], pq), pbs[b].n, prepared(wss[b], pq), pbs[b].n, wss[b].p, wss[b]);
+        A.mode = 0;
+        A.S = wss[b].S;
+        A.pcg_step = 1;
+        A.cps = pl[b].cps;
+        A.nsplit = pl[b].nsplit;
+        hin[b] = A;
+        hd[b].nsplit = pl[b].nsplit;
+      }
+      std::vector<int> tl = build_tiles(count, pl, use, xcd);
+      grp_off[q] = (int)(tl_all.size() / 3);
+      grp_nt[q] = (int)(tl.size() / 3);
+      tl_all.insert(tl_all.end(), tl.begin(), tl.end());
+    }
+    LK_TRY(hipMemcpyAsync(bw.inner, hin.data(), sizeof(KmvArgs) * count, hipMemcpyHostToDevice, st));
+    if (!tl_all.empty())
+      LK_TRY(hipMemcpyAsync(bw.tiles_in, tl_all.data(), sizeof(int) * tl_all.size(), hipMemcpyHostToDevice, st));
+    return LAKER_OK;
+  };
 
   // float64 products of the outer residual: single-map plans
   std::vector<Plan1> pl_out(count);
@@ -378,135 +423,158 @@ laker_status pcg_batch(int count, const Problem* pbs, const SolveWs* wss, const 
   const int gtx = max_of(hd, &BDesc::nbt);
   int gfx = 1;
   for (const BDesc& d : hd) gfx = std::max(gfx, (d.nrp + 15) / 16);
-  const dim3 G(gx, count), GA(gax, count), GT(gtx, count), GF(gfx, count), G1(1, count);
-
-  auto upload_desc = [&]() -> laker_status {
-    LK_TRY(hipMemcpyAsync(bw.desc, hd.data(), sizeof(BDesc) * count, hipMemcpyHostToDevice, st));
-    return LAKER_OK;
+  // map lists: the maps the iteration passes work on (inner solve running)
+  // and the maps of the current host-side operation (restart, correction,
+  // residual)
+  std::vector<int> it_list, op_list;
+  unsigned nit = 0, nop = 0;
+  auto set_it_list = [&](const std::vector<int>& l) -> hipError_t {
+    it_list = l;
+    nit = (unsigned)l.size();
+    return l.empty() ? hipSuccess : hipMemcpyAsync(bw.run_it, l.data(), sizeof(int) * l.size(), hipMemcpyHostToDevice, st);
+  };
+  auto set_op_list = [&]() -> hipError_t {
+    op_list.clear();
+    for (int b = 0; b < count; ++b)
+      if (hd[b].active) op_list.push_back(b);
+    nop = (unsigned)op_list.size();
+    return op_list.empty() ? hipSuccess
+                           : hipMemcpyAsync(bw.run_op, op_list.data(), sizeof(int) * op_list.size(), hipMemcpyHostToDevice, st);
   };
 
-  // one inner iteration for the whole batch
+  auto upload_desc = [&]() -> hipError_t {
+    return hipMemcpyAsync(bw.desc, hd.data(), sizeof(BDesc) * count, hipMemcpyHostToDevice, st);
+  };
+
+  // one inner iteration for the whole batch (maps whose inner solve is over
+  // return at once in every pass)
   auto enqueue_iteration = [&](hipStream_t s2) -> laker_status {
-    LK_TRY(kmv_run_batch(prec, dp, count, bw.inner, bw.tiles_in, nt_in, false, max_n, s2));
-    b_ap_kernel<<<G, kThreads, 0, s2>>>(bw.desc);
+    if (nit == 0) return LAKER_OK;
+    for (int q = 0; q < 3; ++q)
+      if (grp_nt[q] > 0)
+        LK_TRY(kmv_run_batch(kPrecOrder[q], dp, count, bw.inner, bw.tiles_in + 3 * (int64_t)grp_off[q], grp_nt[q],
+                             false, max_n, s2));
+    b_ap_kernel<<<dim3(gx, nit), kThreads, 0, s2>>>(bw.desc, bw.run_it);
     LK_CHECK_LAUNCH();
     if (lowrank) {
-      if (f32) b_update_t_kernel<float><<<GT, kThreads, 0, s2>>>(bw.desc);
-      else b_update_t_kernel<double><<<GT, kThreads, 0, s2>>>(bw.desc);
+      if (f32) b_update_t_kernel<float><<<dim3(gtx, nit), kThreads, 0, s2>>>(bw.desc, bw.run_it);
+      else b_update_t_kernel<double><<<dim3(gtx, nit), kThreads, 0, s2>>>(bw.desc, bw.run_it);
       LK_CHECK_LAUNCH();
-      b_lr_t_finish_kernel<<<GF, kThreads, 0, s2>>>(bw.desc, 1);
+      b_lr_t_finish_kernel<<<dim3(gfx, nit), kThreads, 0, s2>>>(bw.desc, bw.run_it, 1, 0);
       LK_CHECK_LAUNCH();
-      if (f32) b_lr_apply_kernel<float><<<GA, kThreads, 0, s2>>>(bw.desc);
-      else b_lr_apply_kernel<double><<<GA, kThreads, 0, s2>>>(bw.desc);
+      if (f32) b_lr_apply_kernel<float><<<dim3(gax, nit), kThreads, 0, s2>>>(bw.desc, bw.run_it, 0);
+      else b_lr_apply_kernel<double><<<dim3(gax, nit), kThreads, 0, s2>>>(bw.desc, bw.run_it, 0);
       LK_CHECK_LAUNCH();
-      b_pupdate_kernel<LAKER_PRECOND_CCCP><<<G, kThreads, 0, s2>>>(bw.desc, 0);
+      b_pupdate_kernel<LAKER_PRECOND_CCCP><<<dim3(gx, nit), kThreads, 0, s2>>>(bw.desc, bw.run_it, 0, 0);
     } else if (kind == LAKER_PRECOND_JACOBI) {
-      b_update_kernel<LAKER_PRECOND_JACOBI><<<G, kThreads, 0, s2>>>(bw.desc);
+      b_update_kernel<LAKER_PRECOND_JACOBI><<<dim3(gx, nit), kThreads, 0, s2>>>(bw.desc, bw.run_it);
       LK_CHECK_LAUNCH();
-      b_pupdate_kernel<LAKER_PRECOND_JACOBI><<<G, kThreads, 0, s2>>>(bw.desc, 0);
+      b_pupdate_kernel<LAKER_PRECOND_JACOBI><<<dim3(gx, nit), kThreads, 0, s2>>>(bw.desc, bw.run_it, 0, 0);
     } else {
-      b_update_kernel<LAKER_PRECOND_NONE><<<G, kThreads, 0, s2>>>(bw.desc);
+      b_update_kernel<LAKER_PRECOND_NONE><<<dim3(gx, nit), kThreads, 0, s2>>>(bw.desc, bw.run_it);
       LK_CHECK_LAUNCH();
-      b_pupdate_kernel<LAKER_PRECOND_NONE><<<G, kThreads, 0, s2>>>(bw.desc, 0);
+      b_pupdate_kernel<LAKER_PRECOND_NONE><<<dim3(gx, nit), kThreads, 0, s2>>>(bw.desc, bw.run_it, 0, 0);
     }
     LK_CHECK_LAUNCH();
     return LAKER_OK;
   };
 
-  // inner PCG on every active map from x = 0; returns when all are done
-  std::vector<PcgScalars> hs(count);
-  auto inner_solve = [&](std::vector<int>& iters_out) -> laker_status {
-    LK_TRY(upload_desc() == LAKER_OK ? hipSuccess : hipErrorUnknown);
-    b_zero_kernel<<<G, kThreads, 0, st>>>(bw.desc);
+  // (re)start the inner PCG of the maps marked active, from x = 0; the other
+  // maps are not touched
+  auto restart = [&]() -> laker_status {
+    LK_TRY(upload_desc());
+    LK_TRY(set_op_list());
+    if (nop == 0) return LAKER_OK;
+    b_zero_kernel<<<dim3(gx, nop), kThreads, 0, st>>>(bw.desc, bw.run_op);
     LK_CHECK_LAUNCH();
-    b_init_kernel<<<G, kThreads, 0, st>>>(bw.desc);
+    b_init_kernel<<<dim3(gx, nop), kThreads, 0, st>>>(bw.desc, bw.run_op);
     LK_CHECK_LAUNCH();
-    b_start_kernel<<<G1, kThreads, 0, st>>>(bw.desc);
+    b_start_kernel<<<dim3(1, nop), kThreads, 0, st>>>(bw.desc, bw.run_op);
     LK_CHECK_LAUNCH();
     if (lowrank) {
-      if (f32) b_lr_t_partial_kernel<float><<<GT, kThreads, 0, st>>>(bw.desc);
-      else b_lr_t_partial_kernel<double><<<GT, kThreads, 0, st>>>(bw.desc);
+      if (f32) b_lr_t_partial_kernel<float><<<dim3(gtx, nop), kThreads, 0, st>>>(bw.desc, bw.run_op);
+      else b_lr_t_partial_kernel<double><<<dim3(gtx, nop), kThreads, 0, st>>>(bw.desc, bw.run_op);
       LK_CHECK_LAUNCH();
-      b_lr_t_finish_kernel<<<GF, kThreads, 0, st>>>(bw.desc, 0);
+      b_lr_t_finish_kernel<<<dim3(gfx, nop), kThreads, 0, st>>>(bw.desc, bw.run_op, 0, 1);
       LK_CHECK_LAUNCH();
-      if (f32) b_lr_apply_kernel<float><<<GA, kThreads, 0, st>>>(bw.desc);
-      else b_lr_apply_kernel<double><<<GA, kThreads, 0, st>>>(bw.desc);
+      if (f32) b_lr_apply_kernel<float><<<dim3(gax, nop), kThreads, 0, st>>>(bw.desc, bw.run_op, 1);
+      else b_lr_apply_kernel<double><<<dim3(gax, nop), kThreads, 0, st>>>(bw.desc, bw.run_op, 1);
       LK_CHECK_LAUNCH();
-      b_pupdate_kernel<LAKER_PRECOND_CCCP><<<G, kThreads, 0, st>>>(bw.desc, 1);
+      b_pupdate_kernel<LAKER_PRECOND_CCCP><<<dim3(gx, nop), kThreads, 0, st>>>(bw.desc, bw.run_op, 1, 1);
     } else if (kind == LAKER_PRECOND_JACOBI) {
-      b_jacobi_apply_kernel<<<G, kThreads, 0, st>>>(bw.desc);
+      b_jacobi_apply_kernel<<<dim3(gx, nop), kThreads, 0, st>>>(bw.desc, bw.run_op);
       LK_CHECK_LAUNCH();
-      b_pupdate_kernel<LAKER_PRECOND_JACOBI><<<G, kThreads, 0, st>>>(bw.desc, 1);
+      b_pupdate_kernel<LAKER_PRECOND_JACOBI><<<dim3(gx, nop), kThreads, 0, st>>>(bw.desc, bw.run_op, 1, 1);
     } else {
-      b_pupdate_kernel<LAKER_PRECOND_NONE><<<G, kThreads, 0, st>>>(bw.desc, 1);
+      b_pupdate_kernel<LAKER_PRECOND_NONE><<<dim3(gx, nop), kThreads, 0, st>>>(bw.desc, bw.run_op, 1, 1);
     }
     LK_CHECK_LAUNCH();
-    hipGraphExec_t gexec = nullptr;
-    if (o.graph) {
-      hipStream_t cs = pcg_capture_stream();
-      hipGraph_t graph = nullptr;
-      bool ok = cs != nullptr && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
-      if (ok) {
-        laker_status e = LAKER_OK;
-        for (int c = 0; c < check && e == LAKER_OK; ++c) e = enqueue_iteration(cs);
-        ok = hipStreamEndCapture(cs, &graph) == hipSuccess && e == LAKER_OK;
-        if (ok) ok = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0) == hipSuccess;
-        if (graph != nullptr) (void)hipGraphDestroy(graph);
-      }
-      if (!ok) {
-        (void)hipGetLastError();
-        if (gexec != nullptr) (void)hipGraphExecDestroy(gexec);
-        return LAKER_EHIP;
-      }
-    }
-    int max_cap = 0;
-    for (const BDesc& d : hd)
-      if (d.active) max_cap = std::max(max_cap, d.max_iter);
-    laker_status status = LAKER_OK;
-    for (int k = 0;;) {
-      if (gexec != nullptr) {
-        if (hipGraphLaunch(gexec, st) != hipSuccess) {
-          status = LAKER_EHIP;
-          break;
-        }
-      } else {
-        for (int c = 0; c < check && status == LAKER_OK; ++c) status = enqueue_iteration(st);
-        if (status != LAKER_OK) break;
-      }
-      k += check;
-      bool all_done = true;
-      b_gather_kernel<<<(count + 63) / 64, 64, 0, st>>>(bw.desc, count, bw.hs, bw.misc);
-      if (hipGetLastError() != hipSuccess ||
-          hipMemcpyAsync(hs.data(), bw.hs, sizeof(PcgScalars) * count, hipMemcpyDeviceToHost, st) != hipSuccess ||
-          hipStreamSynchronize(st) != hipSuccess) {
-        status = LAKER_EHIP;
-        break;
-      }
-      for (int b = 0; b < count; ++b)
-        if (hs[b].done == 0) all_done = false;
-      if (all_done || k >= max_cap + check) break;
-    }
-    if (gexec != nullptr) (void)hipGraphExecDestroy(gexec);
-    for (int b = 0; b < count; ++b) iters_out[b] = hd[b].active ? hs[b].iters : 0;
-    return status;
+    return LAKER_OK;
   };
 
-  // outer residual of the active maps: y - A alpha in float64 (alpha = 0: y)
-  auto outer_residual = [&](bool have_alpha, std::vector<double>& rel) -> laker_status {
+  hipGraphExec_t gexec = nullptr;
+  auto drop_graph = [&]() {
+    if (gexec != nullptr) (void)hipGraphExecDestroy(gexec);
+    gexec = nullptr;
+  };
+  auto capture = [&]() -> laker_status {
+    drop_graph();
+    if (!o.graph) return LAKER_OK;
+    hipStream_t cs = pcg_capture_stream();
+    hipGraph_t graph = nullptr;
+    bool ok = cs != nullptr && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+      laker_status e = LAKER_OK;
+      for (int c = 0; c < check && e == LAKER_OK; ++c) e = enqueue_iteration(cs);
+      ok = hipStreamEndCapture(cs, &graph) == hipSuccess && e == LAKER_OK;
+      if (ok) ok = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0) == hipSuccess;
+      if (graph != nullptr) (void)hipGraphDestroy(graph);
+    }
+    if (!ok) {
+      (void)hipGetLastError();
+      drop_graph();
+      return LAKER_EHIP;
+    }
+    return LAKER_OK;
+  };
+  // one chunk of iterations, then the scalars of every map on the host
+  std::vector<PcgScalars> hs(count);
+  auto run_chunk = [&]() -> laker_status {
+    if (gexec != nullptr) {
+      LK_TRY(hipGraphLaunch(gexec, st));
+    } else {
+      for (int c = 0; c < check; ++c) {
+        laker_status e = enqueue_iteration(st);
+        if (e != LAKER_OK) return e;
+      }
+    }
+    b_gather_kernel<<<(count + 63) / 64, 64, 0, st>>>(bw.desc, count, bw.hs, bw.misc);
+    LK_CHECK_LAUNCH();
+    LK_TRY(hipMemcpyAsync(hs.data(), bw.hs, sizeof(PcgScalars) * count, hipMemcpyDeviceToHost, st));
+    LK_TRY(hipStreamSynchronize(st));
+    return LAKER_OK;
+  };
+
+  // outer residual y - A alpha (float64) of the maps marked active
+  std::vector<double> rel(count, 0.0);
+  auto outer_residual = [&](bool have_alpha) -> laker_status {
+    std::vector<int> act(count);
     for (int b = 0; b < count; ++b) {
+      act[b] = hd[b].active;
       hd[b].have_alpha = have_alpha ? 1 : 0;
       hout[b].mode = hd[b].active ? 1 : 2;
     }
-    LK_TRY(upload_desc() == LAKER_OK ? hipSuccess : hipErrorUnknown);
+    LK_TRY(upload_desc());
+    LK_TRY(set_op_list());
+    if (nop == 0) return LAKER_OK;
     if (have_alpha) {
-      std::vector<int> act(count);
-      for (int b = 0; b < count; ++b) act[b] = hd[b].active;
       std::vector<int> tl = build_tiles(count, pl_out, act, xcd);
       LK_TRY(hipMemcpyAsync(bw.outer, hout.data(), sizeof(KmvArgs) * count, hipMemcpyHostToDevice, st));
-      LK_TRY(hipMemcpyAsync(bw.tiles_out, tl.data(), sizeof(int) * tl.size(), hipMemcpyHostToDevice, st));
+      if (!tl.empty())
+        LK_TRY(hipMemcpyAsync(bw.tiles_out, tl.data(), sizeof(int) * tl.size(), hipMemcpyHostToDevice, st));
       LK_TRY(kmv_run_batch(LAKER_F64, dp, count, bw.outer, bw.tiles_out, (int)(tl.size() / 3), true, max_n, st));
     }
-    b_resid_kernel<<<G, kThreads, 0, st>>>(bw.desc);
+    b_resid_kernel<<<dim3(gx, nop), kThreads, 0, st>>>(bw.desc, bw.run_op);
     LK_CHECK_LAUNCH();
     std::vector<double> h(2 * count);
     b_gather_kernel<<<(count + 63) / 64, 64, 0, st>>>(bw.desc, count, bw.hs, bw.misc);
@@ -518,73 +586,156 @@ laker_status pcg_batch(int count, const Problem* pbs, const SolveWs* wss, const 
     return LAKER_OK;
   };
 
-  std::vector<int> used(count, 0), it(count, 0);
-  std::vector<double> rel(count, 0.0);
   std::vector<laker_status> res(count, LAKER_ENOCONV);
-  for (int b = 0; b < count; ++b) {
-    stats[b] = laker_stats{};
-  }
+  for (int b = 0; b < count; ++b) stats[b] = laker_stats{};
+  laker_status status = LAKER_OK;
+
   if (!o.refine) {
+    // PCG on y directly, every map at once
     for (int b = 0; b < count; ++b) {
       hd[b].rhs = y[b];
       hd[b].x = alpha[b];
       hd[b].tol = o.tol;
       hd[b].max_iter = o.max_iter;
+      hd[b].active = 1;
     }
-    laker_status e = inner_solve(it);
-    if (e != LAKER_OK) return e;
+    std::vector<int> everyone(count);
+    for (int b = 0; b < count; ++b) everyone[b] = b;
+    status = set_it_list(everyone) == hipSuccess ? rebuild_inner(everyone) : LAKER_EHIP;
+    if (status == LAKER_OK) status = restart();
+    if (status == LAKER_OK) status = capture();
+    for (int k = 0; status == LAKER_OK;) {
+      status = run_chunk();
+      k += check;
+      bool all = true;
+      for (int b = 0; b < count; ++b)
+        if (hs[b].done == 0) all = false;
+      if (all || k >= o.max_iter + check) break;
+    }
+    drop_graph();
+    if (status != LAKER_OK) return status;
     for (int b = 0; b < count; ++b) {
-      stats[b].iters = it[b];
+      stats[b].iters = hs[b].iters;
       stats[b].relres = hs[b].yy > 0 ? sqrt(hs[b].rr / hs[b].yy) : 0.0;
       res[b] = hs[b].done == 1 ? LAKER_OK : (hs[b].done == 2 ? LAKER_EBREAKDOWN : LAKER_ENOCONV);
     }
-    e = outer_residual(true, rel);
-    if (e != LAKER_OK) return e;
+    status = outer_residual(true);
+    if (status != LAKER_OK) return status;
     for (int b = 0; b < count; ++b) stats[b].relres_true = rel[b];
   } else {
+    // Refinement with every map on its own schedule: when a map's inner PCG
+    // ends, its correction is added, its float64 residual formed and its next
+    // inner PCG started at the following check, while the other maps keep
+    // iterating.
+    std::vector<int> step(count, 0), used(count, 0), running(count, 0);
     for (int b = 0; b < count; ++b) {
       LK_TRY(hipMemsetAsync(alpha[b], 0, sizeof(double) * pbs[b].n, st));
       hd[b].rhs = wss[b].rout;
       hd[b].x = wss[b].dalpha;
+      hd[b].active = 1;
     }
-    for (int s = 0; s <= o.ir_max; ++s) {
-      laker_status e = outer_residual(s > 0, rel);
-      if (e != LAKER_OK) return e;
-      bool any = false;
+    // decide, for the maps marked active whose residual was just formed:
+    // finished, or the next inner solve (finer arithmetic after two steps
+    // without progress)
+    bool tables_changed = false;
+    auto decide = [&]() {
       for (int b = 0; b < count; ++b) {
         if (!hd[b].active) continue;
+        const int s = step[b];
         if (s < 64) stats[b].ir_relres[s] = rel[b];
         stats[b].relres_true = rel[b];
         stats[b].relres = rel[b];
         stats[b].ir_steps = s;
+        bool go = true;
         if (rel[b] <= o.tol) {
           res[b] = LAKER_OK;
-          hd[b].active = 0;
-        } else if (s == o.ir_max || used[b] >= o.max_iter) {
-          hd[b].active = 0;
-        } else {
-          const double need = 0.5 * o.tol / rel[b];
-          hd[b].tol = std::max(o.inner_tol, need);
-          hd[b].max_iter = o.max_iter - used[b];
-          any = true;
+          go = false;
+        } else if (s >= o.ir_max || used[b] >= o.max_iter || res[b] == LAKER_EBREAKDOWN) {
+          go = false;
         }
+        if (!go) {
+          hd[b].active = 0;
+          running[b] = 0;
+          continue;
+        }
+        if (s >= 2 && rel[b] > stats[b].ir_relres[s - 2] && pm[b] != LAKER_F64) {
+          pm[b] = pm[b] == LAKER_BF16 ? LAKER_F32 : LAKER_F64;
+          stats[b].escalations += 1;
+          tables_changed = true;
+        }
+        hd[b].tol = std::max(o.inner_tol, 0.5 * o.tol / rel[b]);
+        hd[b].max_iter = o.max_iter - used[b];
+        running[b] = 1;
       }
+    };
+    status = outer_residual(false);
+    if (status != LAKER_OK) return status;
+    decide();
+    auto prepare_escalated = [&]() -> laker_status {
+      for (int b = 0; b < count; ++b)
+        if (hd[b].active && pm[b] == LAKER_F32)
+          LK_TRY(prep_embed(pbs[b].E, pbs[b].n, pbs[b].d, pbs[b].dp, pbs[b].scale, LAKER_F32, wss[b].e32, st));
+      return LAKER_OK;
+    };
+    auto running_list = [&]() {
+      std::vector<int> l;
+      for (int b = 0; b < count; ++b)
+        if (running[b]) l.push_back(b);
+      return l;
+    };
+    status = prepare_escalated();
+    if (status == LAKER_OK) status = set_it_list(running_list()) == hipSuccess ? LAKER_OK : LAKER_EHIP;
+    if (status == LAKER_OK) status = rebuild_inner(it_list);
+    tables_changed = false;
+    if (status == LAKER_OK) status = restart();
+    if (status == LAKER_OK) status = capture();
+    int64_t chunks = 0;
+    const int64_t max_chunks = ((int64_t)o.max_iter + check - 1) / check + 2 * (int64_t)(o.ir_max + 1);
+    while (status == LAKER_OK) {
+      bool any = false;
+      for (int b = 0; b < count; ++b)
+        if (running[b]) any = true;
       if (!any) break;
-      e = inner_solve(it);
-      if (e != LAKER_OK) return e;
+      status = run_chunk();
+      if (status != LAKER_OK) break;
+      if (++chunks > max_chunks) break;
+      // maps whose inner solve ended in this chunk
+      bool ended = false;
       for (int b = 0; b < count; ++b) {
-        if (!hd[b].active) continue;
-        used[b] += it[b];
+        hd[b].active = 0;
+        if (!running[b] || hs[b].done == 0) continue;
+        hd[b].active = 1;
+        ended = true;
+        used[b] += hs[b].iters;
         stats[b].iters = used[b];
-        if (hs[b].done == 2) {
-          res[b] = LAKER_EBREAKDOWN;
-          hd[b].active = 0;
-        }
+        if (hs[b].done == 2) res[b] = LAKER_EBREAKDOWN;
       }
-      LK_TRY(upload_desc() == LAKER_OK ? hipSuccess : hipErrorUnknown);
-      b_axpy_kernel<<<G, kThreads, 0, st>>>(bw.desc);
-      LK_CHECK_LAUNCH();
+      if (!ended) continue;
+      status = (upload_desc() == hipSuccess && set_op_list() == hipSuccess) ? LAKER_OK : LAKER_EHIP;
+      if (status != LAKER_OK) break;
+      b_axpy_kernel<<<dim3(gx, nop), kThreads, 0, st>>>(bw.desc, bw.run_op);
+      if (hipGetLastError() != hipSuccess) {
+        status = LAKER_EHIP;
+        break;
+      }
+      for (int b = 0; b < count; ++b)
+        if (hd[b].active) step[b] += 1;
+      status = outer_residual(true);
+      if (status != LAKER_OK) break;
+      decide();
+      const std::vector<int> now = running_list();
+      if (tables_changed || now != it_list) {
+        status = prepare_escalated();
+        if (status == LAKER_OK) status = set_it_list(now) == hipSuccess ? LAKER_OK : LAKER_EHIP;
+        if (status == LAKER_OK) status = rebuild_inner(it_list);
+        if (status == LAKER_OK) status = capture();
+        tables_changed = false;
+        if (status != LAKER_OK) break;
+      }
+      status = restart();
     }
+    drop_graph();
+    if (status != LAKER_OK) return status;
   }
   LK_TRY(hipStreamSynchronize(st));
   laker_status worst = LAKER_OK;

@@ -52,6 +52,8 @@ struct BatchWs {
   KmvArgs* outer;        // float64 products of the outer residual (mode 1)
   int* tiles_in;         // 3 ints per tile
   int* tiles_out;
+  int* run_it;           // maps of the iteration passes
+  int* run_op;           // maps of the current host-side operation
   PcgScalars* hs;        // gathered scalars of every map
   double* misc;          // gathered outer residual norms (2 per map)
   size_t total;

@@ -29,8 +29,11 @@ KmvPlan kmv_plan(int64_t m, int64_t n, int prec);
 int kmv_rows_per_block(int prec);
 
 // One fused product  out_i = lam * pself_i + sum_j exp(<q_i, k_j>) p_j  (exp2 for
-// the float32 / bfloat16 prepared copies).  All vectors are float64; the
-// products exp(.) p_j are accumulated in float64 in every precision.
+// the float32 / bfloat16 prepared copies).  All vectors are float64.  The
+// float64 kernel accumulates in float64; the float32 / bfloat16 kernels sum the
+// products of one LDS stage (4 per lane and row) in float32 and add each stage
+// sum into a float64 accumulator, so the rounding of the sums does not grow
+// with n.
 struct KmvArgs {
   const void* Q;        // prepared query rows (m x dp)
   int64_t m;

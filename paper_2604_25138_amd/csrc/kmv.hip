@@ -12,8 +12,9 @@
 // Work split: a wave owns 32 rows (16 for float64) and sweeps the key tiles of
 // one column range; a block holds four waves.  The score tile S = Q K^T comes
 // from MFMA (32x32x2 f32, 32x32x16 bf16, 16x16x4 f64); each lane then applies
-// exp to its S entries and accumulates exp(S) p_j into per-row partial sums,
-// which are combined across lanes once at the end.  Column ranges write
+// exp to its S entries and accumulates exp(S) p_j into per-row partial sums
+// (float64 across stages, float32 within a stage), which are combined across
+// lanes once at the end.  Column ranges write
 // partial sums; a following pass adds them in a fixed order and applies
 // lambda p (inside PCG that pass also forms the p^T A p partials).
 #include <type_traits>
@@ -262,6 +263,11 @@ __device__ __forceinline__ void kmv32_body(const KmvArgs& A, int64_t bx, int64_t
     if (sidx + 2 < nstages) fetch(j0 + (int64_t)(sidx + 2) * KT);
     const unsigned char* base = lds[buf];
     const double* pw = reinterpret_cast<const double*>(base + KT * St::PITCH);
+    // the stage's products are summed in float32 (KT / 32 terms per lane and
+    // row) and the stage sum is added into the float64 accumulator
+    float accf[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) accf[r] = 0.f;
 #pragma unroll
     for (int u = 0; u < KT / 32; ++u) {
       Frag b;
@@ -283,9 +289,12 @@ __device__ __forceinline__ void kmv32_body(const KmvArgs& A, int64_t bx, int64_t
       v16f sc;
       if constexpr (PREC == LAKER_F32) sc = tile_f32<DP>(a, b);
       else sc = tile_bf16<DP>(a, b);
+      const float pvf = (float)pv;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc[r] = fma((double)kexp2(sc[r]), pv, acc[r]);
+      for (int r = 0; r < 16; ++r) accf[r] = fmaf(kexp2(sc[r]), pvf, accf[r]);
     }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] += (double)accf[r];
     __syncthreads();
   }
   // sum over the 32 lanes of each half (the key columns of the tiles)
@@ -486,8 +495,9 @@ KmvPlan kmv_plan(int64_t m, int64_t n, int prec) {
   const int tile = prec == LAKER_F64 ? 16 : 32;
   const int64_t rowblocks = (m + rpb - 1) / rpb;
   const int64_t coltiles = (n + tile - 1) / tile;
-  // aim for ~8192 waves (32 per CU) across row blocks x column ranges
-  int64_t ns = (2048 + rowblocks - 1) / rowblocks;
+  // about 512 blocks: two per CU of four waves each (the product kernels run
+  // two waves per SIMD), with few column ranges to add up afterwards
+  int64_t ns = (512 + rowblocks - 1) / rowblocks;
   if (ns > coltiles) ns = coltiles;
   if (ns > kMaxSplit) ns = kMaxSplit;
   if (ns < 1) ns = 1;

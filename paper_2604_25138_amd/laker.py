@@ -59,7 +59,7 @@ class laker_stats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("ir_steps", C.c_int32), ("cccp_iters", C.c_int32), ("status", C.c_int32),
                 ("relres", C.c_double), ("relres_true", C.c_double), ("ir_relres", C.c_double * 64),
                 ("kmv_ms", C.c_double), ("kmv_count", C.c_int32), ("kmv_launches", C.c_int32),
-                ("kmv_launch_ms", C.c_double)]
+                ("kmv_launch_ms", C.c_double), ("escalations", C.c_int32), ("reserved", C.c_int32)]
 
 
 class laker_mlp_layout(C.Structure):

@@ -88,3 +88,20 @@ def test_batched_rejects_mixed_dimensions():
     ps = [L().Problem(torch.tensor(x.E, device=DEV), x.lam, x.scale) for x in (pr1, pr2)]
     with pytest.raises(L().LakerError):
         L().pcg_solve_batched(ps, [pr1.y, pr2.y])
+
+
+def test_refinement_escalates_and_converges_on_hard_maps():
+    """Small lambda at the largest sizes of the batch: bfloat16 corrections stop
+    contracting the float64 residual, the map moves to finer inner products and
+    still reaches the tolerance; the batch and the single solves agree."""
+    specs = [(4096, 1e-6, 3), (2048, 3e-6, 5), (1024, 1e-2, 1), (3000, 1e-5, 8)]
+    maps = []
+    for k, (n, lam, ntx) in enumerate(specs):
+        pr = make_problem(n, 32, lam, n_tx=ntx, seed=40 + k)
+        maps.append((pr, L().Problem(torch.tensor(pr.E, device=DEV), pr.lam, pr.scale)))
+    kw = dict(tol=1e-8, max_iter=200000, precision="bf16", refine=True, inner_tol=0.1, check_every=16)
+    alphas, stats, _ = L().pcg_solve_batched([p for _, p in maps], [pr.y for pr, _ in maps], None, **kw)
+    for b, (pr, p) in enumerate(maps):
+        assert stats[b].status == 0 and stats[b].relres_true <= 1e-8, (b, stats[b].relres_true)
+        a1, s1 = L().pcg_solve(p, pr.y, None, **kw)
+        assert s1.escalations == stats[b].escalations and torch.equal(alphas[b], a1), b

@@ -6,7 +6,9 @@ sampled rows the oracle computes one by one.  Tolerances:
     rounding of d-term dot products, exp and n-term sums);
   * float32 products: 2e-6 relative to the same magnitude (float32 inputs
     rounded once, a d-term float32 MFMA dot product of the pre-scaled rows,
-    exp2 within 2 ulp; the exp(.) p_j products are accumulated in float64);
+    exp2 within 2 ulp; the exp(.) p_j products of one stage, 4 per lane and
+    row, are summed in float32 with weights rounded to float32, 4 u relative,
+    then accumulated in float64);
   * bfloat16 products: compared with the oracle evaluated on the same
     bfloat16-rounded pre-scaled rows (G_ij = 2^{<e^_i, e^_j>}), 2e-6 relative
     (bfloat16 products are exact in float32; float32 MFMA accumulation over d
@@ -85,12 +87,15 @@ def test_matvec_bf16_parity(n, d):
 
 
 def test_matvec_zero_embeddings_exact():
-    """E = 0: G = 1 1^T in every precision, w = lam p + (sum p) 1."""
+    """E = 0: G = 1 1^T exactly in every precision (exp2(0) = 1), so
+    w = lam p + (sum p) 1 up to summation rounding: float64 to 1e-13; the
+    float32 / bfloat16 kernels round the weights p_j and the per-stage sums to
+    float32 (at most a few float32 units, 3e-7, relative to sum |p|)."""
     n = 1000
     E = np.zeros((n, 8))
     p = np.random.default_rng(0).normal(size=n)
     prob = L().Problem(torch.tensor(E, device=DEV), 0.25, 1.0)
-    for prec, tol in (("f64", 1e-13), ("f32", 1e-13), ("bf16", 1e-13)):
+    for prec, tol in (("f64", 1e-13), ("f32", 3e-7), ("bf16", 3e-7)):
         w = L().kernel_matvec(prob, torch.tensor(p, device=DEV), prec).cpu().numpy()
         ref = 0.25 * p + p.sum()
         assert np.abs(w - ref).max() <= tol * (np.abs(p).sum() + 1), prec
