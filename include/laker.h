@@ -105,8 +105,11 @@ typedef struct {
   double tol;         /* stop when ||r|| / ||y|| <= tol (recursive r, Alg. 1)  */
   int32_t max_iter;   /* PCG iteration cap (total over refinement steps)       */
   int32_t precision;  /* laker_precision of the inner products A p             */
-  int32_t refine;     /* 1: float64 iterative refinement around an F32/BF16 PCG */
-  int32_t ir_max;     /* refinement step cap (<= 64)                            */
+  int32_t refine;     /* 1: float64 iterative refinement around an F32/BF16 PCG;
+                         2: flexible CG in float64 whose preconditioner is that
+                         inner PCG (robust when lambda is far below the
+                         rounding of the reduced-precision product)             */
+  int32_t ir_max;     /* outer step cap (refine 1: <= 64)                       */
   double inner_tol;   /* inner PCG tolerance per refinement step, relative to the
                          step's residual; raised to 0.5 tol / (current outer
                          residual) when that is larger                          */
@@ -116,6 +119,9 @@ typedef struct {
                          into a HIP graph and replayed (same results)          */
   int32_t profile;    /* 1: time every kernel product of the loop with HIP events
                          on `stream` (eager launches; fills stats->kmv_ms)      */
+  int32_t inner_max_iter; /* refinement: cap on the iterations of one inner PCG
+                         (0: only max_iter)                                    */
+  int32_t reserved;
 } laker_pcg_opts;
 
 typedef struct {
@@ -134,7 +140,10 @@ typedef struct {
   double kmv_launch_ms; /* profile: mean duration over all kmv_launches          */
   int32_t escalations;  /* refinement: times the inner product arithmetic was made
                            finer (bfloat16 -> float32 -> float64) after two
-                           refinement steps without progress                    */
+                           refinement steps without progress (an inner PCG that
+                           breaks down in reduced precision ends with the
+                           correction it has; only a float64 breakdown is an
+                           error)                                               */
   int32_t reserved;
 } laker_stats;
 
@@ -283,8 +292,8 @@ size_t laker_batch_workspace_bytes(int32_t count, const int64_t* n, int32_t d);
  * with the same d; preconds: NULL (plain CG) or count preconditioners of one
  * kind; y, alpha: host arrays of count device float64 pointers.  opts as for
  * laker_pcg_solve (warm_start must be 0; profile is ignored); stats: host array
- * of count entries.  Returns LAKER_OK when every map converged, else the worst
- * status (each map's status is in its stats entry). */
+ * of count entries; refine 0 or 1.  Returns LAKER_OK when every map converged,
+ * else the worst status (each map's status is in its stats entry). */
 laker_status laker_pcg_solve_batched(int32_t count, const laker_problem* probs, const laker_precond* preconds,
                                      const double* const* y, double* const* alpha, const laker_pcg_opts* opts,
                                      laker_batch_opts* bopts, void* workspace, size_t workspace_bytes,

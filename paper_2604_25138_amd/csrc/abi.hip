@@ -189,7 +189,9 @@ laker_status laker_pcg_solve(const laker_problem* prob, const laker_precond* pre
   if (y == nullptr || alpha == nullptr || opts == nullptr || workspace == nullptr) return LAKER_EINVAL;
   if (!valid_precision(opts->precision)) return LAKER_EINVAL;
   if (!(opts->tol >= 0.0) || opts->max_iter < 1) return LAKER_EINVAL;
-  if (opts->refine && (opts->ir_max < 1 || opts->ir_max > 64 || !(opts->inner_tol > 0.0))) return LAKER_EINVAL;
+  if (opts->refine < 0 || opts->refine > 2 || opts->inner_max_iter < 0) return LAKER_EINVAL;
+  if (opts->refine && (opts->ir_max < 1 || !(opts->inner_tol > 0.0))) return LAKER_EINVAL;
+  if (opts->refine == 1 && opts->ir_max > 64) return LAKER_EINVAL;
   PrecondView view{};
   e = make_view(precond, prob->n, opts->precision, &view);
   if (e != LAKER_OK) return e;
@@ -226,6 +228,9 @@ laker_status laker_pcg_solve(const laker_problem* prob, const laker_precond* pre
       if (r2 != LAKER_OK) return r2;
       sp->relres_true = rt;
     }
+  } else if (opts->refine == 2) {
+    r = fcg_run(pb, W, view, y, alpha, *opts, check, sp, st);
+    if (r == LAKER_EHIP) return r;
   } else {
     if (!opts->warm_start) LK_TRY(hipMemsetAsync(alpha, 0, sizeof(double) * pb.n, st));
     r = LAKER_ENOCONV;
@@ -247,7 +252,7 @@ laker_status laker_pcg_solve(const laker_problem* prob, const laker_precond* pre
       // no progress over two refinement steps: the inner products are too
       // coarse for this system (the correction they give does not contract the
       // float64 residual); continue with the next finer arithmetic
-      if (s >= 2 && rel > sp->ir_relres[s - 2] && prec_now != LAKER_F64) {
+      if (s >= 2 && rel >= sp->ir_relres[s - 2] && prec_now != LAKER_F64) {
         prec_now = prec_now == LAKER_BF16 ? LAKER_F32 : LAKER_F64;
         sp->escalations += 1;
         if (prec_now == LAKER_F32) LK_TRY(prep_embed(pb.E, pb.n, pb.d, pb.dp, pb.scale, LAKER_F32, W.e32, st));
@@ -258,7 +263,9 @@ laker_status laker_pcg_solve(const laker_problem* prob, const laker_precond* pre
       const double need = 0.5 * opts->tol / rel;
       if (need > itol) itol = need;
       laker_stats inner{};
-      laker_status ri = pcg_run(pb, W, view, W.rout, W.dalpha, false, itol, opts->max_iter - used, check,
+      int cap = opts->max_iter - used;
+      if (opts->inner_max_iter > 0 && cap > opts->inner_max_iter) cap = opts->inner_max_iter;
+      laker_status ri = pcg_run(pb, W, view, W.rout, W.dalpha, false, itol, cap, check,
                                 prec_now, opts->graph != 0, opts->profile != 0, &inner, st);
       used += inner.iters;
       sp->iters = used;
@@ -272,7 +279,12 @@ laker_status laker_pcg_solve(const laker_problem* prob, const laker_precond* pre
         sp->kmv_launches += inner.kmv_launches;
         sp->kmv_launch_ms = (prev + inner.kmv_launch_ms * inner.kmv_launches) / sp->kmv_launches;
       }
-      if (ri == LAKER_EBREAKDOWN || ri == LAKER_EHIP || ri == LAKER_EINVAL) return ri;
+      // A breakdown of the inner PCG (p^T A p <= 0 in the reduced-precision
+      // product: its rounding exceeds lambda in the near-null directions) ends
+      // that inner solve with the correction accumulated so far, which the
+      // float64 residual then judges like any other.
+      if (ri == LAKER_EHIP || ri == LAKER_EINVAL) return ri;
+      if (ri == LAKER_EBREAKDOWN && prec_now == LAKER_F64) return ri;
       r2 = axpy_inplace(alpha, W.dalpha, pb.n, st);
       if (r2 != LAKER_OK) return r2;
     }
@@ -450,6 +462,7 @@ laker_status laker_pcg_solve_batched(int32_t count, const laker_problem* probs, 
       stats == nullptr)
     return LAKER_EINVAL;
   if (!valid_precision(opts->precision) || !(opts->tol >= 0.0) || opts->max_iter < 1) return LAKER_EINVAL;
+  if (opts->refine < 0 || opts->refine > 1) return LAKER_EINVAL;
   if (opts->refine && (opts->ir_max < 1 || opts->ir_max > 64 || !(opts->inner_tol > 0.0))) return LAKER_EINVAL;
   if (opts->warm_start) return LAKER_EINVAL;
   std::vector<int64_t> ns(count);

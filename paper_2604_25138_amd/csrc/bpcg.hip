@@ -658,7 +658,7 @@ laker_status pcg_batch(int count, const Problem* pbs, const SolveWs* wss, const 
           running[b] = 0;
           continue;
         }
-        if (s >= 2 && rel[b] > stats[b].ir_relres[s - 2] && pm[b] != LAKER_F64) {
+        if (s >= 2 && rel[b] >= stats[b].ir_relres[s - 2] && pm[b] != LAKER_F64) {
           pm[b] = pm[b] == LAKER_BF16 ? LAKER_F32 : LAKER_F64;
           stats[b].escalations += 1;
           tables_changed = true;
@@ -708,7 +708,8 @@ laker_status pcg_batch(int count, const Problem* pbs, const SolveWs* wss, const 
         ended = true;
         used[b] += hs[b].iters;
         stats[b].iters = used[b];
-        if (hs[b].done == 2) res[b] = LAKER_EBREAKDOWN;
+        // an inner breakdown ends that inner solve; only in float64 is it final
+        if (hs[b].done == 2 && pm[b] == LAKER_F64) res[b] = LAKER_EBREAKDOWN;
       }
       if (!ended) continue;
       status = (upload_desc() == hipSuccess && set_op_list() == hipSuccess) ? LAKER_OK : LAKER_EHIP;

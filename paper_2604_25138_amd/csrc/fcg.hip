@@ -1,0 +1,170 @@
+// Flexible conjugate gradients in float64 around a reduced-precision inner PCG.
+//
+// The method's solve (Alg. 1) runs inside: each outer step takes the inner
+// PCG's approximate solution z of (lambda I + G) z = r, computed with bfloat16
+// or float32 score tiles, as its preconditioned residual.  Because the inner
+// solve changes from step to step, the direction is made conjugate to the
+// previous one explicitly (flexible CG with one stored direction):
+//     beta = -(z^T q_prev) / (p_prev^T q_prev),   p = z + beta p_prev,
+//     q = (lambda I + G) p   (float64 product),
+//     gamma = p^T r / p^T q,  alpha += gamma p,  r -= gamma q.
+// Compared with plain refinement (alpha += z), the float64 outer Krylov
+// recurrence also resolves the directions where the reduced-precision product
+// is no longer accurate (lambda far below its rounding relative to ||G||),
+// where refinement stalls or diverges.
+#include <math.h>
+
+#include "internal.hpp"
+#include "pcg.hpp"
+
+namespace lk {
+
+namespace {
+
+constexpr int kT = 256;
+
+inline int blocks_for(int64_t n) {
+  int64_t g = (n + kT - 1) / kT;
+  if (g > kMaxBlocks) g = kMaxBlocks;
+  return (int)(g < 1 ? 1 : g);
+}
+
+// out[0] = a1^T b1, out[1] = a2^T b2 (fixed-order reduction, last block finishes)
+__global__ __launch_bounds__(kT) void dot2_kernel(const double* __restrict__ a1, const double* __restrict__ b1,
+                                                  const double* __restrict__ a2, const double* __restrict__ b2,
+                                                  int64_t n, double* __restrict__ part, unsigned* cnt,
+                                                  double* __restrict__ out) {
+  __shared__ double sh[16];
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
+    s1 = fma(a1[i], b1[i], s1);
+    s2 = fma(a2[i], b2[i], s2);
+  }
+  s1 = block_sum(s1, sh);
+  s2 = block_sum(s2, sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = s1;
+    part[kMaxBlocks + blockIdx.x] = s2;
+  }
+  if (last_block_arrived(cnt)) {
+    const double t1 = ordered_sum(part, gridDim.x, sh);
+    const double t2 = ordered_sum(part + kMaxBlocks, gridDim.x, sh);
+    if (threadIdx.x == 0) {
+      out[0] = t1;
+      out[1] = t2;
+      *cnt = 0;
+    }
+  }
+}
+
+// p = z + beta p
+__global__ void pdir_kernel(const double* __restrict__ z, double* __restrict__ p, double beta, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT)
+    p[i] = fma(beta, p[i], z[i]);
+}
+
+// alpha += gamma p; r -= gamma q
+__global__ void step_kernel(double* __restrict__ alpha, double* __restrict__ r, const double* __restrict__ p,
+                            const double* __restrict__ q, double gamma, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
+    alpha[i] = fma(gamma, p[i], alpha[i]);
+    r[i] = fma(-gamma, q[i], r[i]);
+  }
+}
+
+}  // namespace
+
+laker_status fcg_run(const Problem& pb, const SolveWs& W, const PrecondView& P, const double* y, double* alpha,
+                     const laker_pcg_opts& o, int check, laker_stats* sp, hipStream_t st) {
+  const int64_t n = pb.n;
+  const int g = blocks_for(n);
+  double* r = W.rout;
+  double* z = W.dalpha;
+  double* p = W.fp;
+  double* q = W.fq;
+  auto dots = [&](const double* a1, const double* b1, const double* a2, const double* b2, double* h) -> hipError_t {
+    dot2_kernel<<<g, kT, 0, st>>>(a1, b1, a2, b2, n, W.bpart, W.cnt, W.misc + 8);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(h, W.misc + 8, 2 * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(st);
+  };
+  // q = (lambda I + G) p in float64
+  const KmvPlan pl = kmv_plan(n, n, LAKER_F64);
+  auto product = [&](const double* v, double* out) -> hipError_t {
+    KmvArgs A = kmv_args(W.e64, n, W.e64, n, v, W);
+    A.lam = pb.lambda;
+    A.pself = v;
+    A.out = out;
+    return kmv_run(LAKER_F64, pb.dp, pl, A, st);
+  };
+
+  if (!o.warm_start) LK_TRY(hipMemsetAsync(alpha, 0, sizeof(double) * n, st));
+  double rel = 0.0;
+  laker_status e = true_residual(pb, W, y, alpha, r, &rel, o.warm_start != 0, st);
+  if (e != LAKER_OK) return e;
+  double h[2];
+  LK_TRY(dots(y, y, y, y, h));
+  const double ynorm = sqrt(h[0]);
+  sp->ir_relres[0] = rel;
+  sp->relres_true = rel;
+  sp->relres = rel;
+  sp->ir_steps = 0;
+  if (rel <= o.tol) return LAKER_OK;
+  int used = 0;
+  double pq_prev = 0.0;
+  const int inner_cap = o.inner_max_iter > 0 ? o.inner_max_iter : o.max_iter;
+  for (int k = 0; k < o.ir_max; ++k) {
+    if (used >= o.max_iter) break;
+    // z = inner solve of A z = r; a reduced-precision breakdown or cap keeps
+    // the z it has
+    laker_stats inner{};
+    int cap = o.max_iter - used;
+    if (cap > inner_cap) cap = inner_cap;
+    const double itol = fmax(o.inner_tol, 0.5 * o.tol / rel);
+    laker_status ri = pcg_run(pb, W, P, r, z, false, itol, cap, check, o.precision, o.graph != 0, false, &inner, st);
+    if (ri == LAKER_EHIP || ri == LAKER_EINVAL) return ri;
+    used += inner.iters;
+    sp->iters = used;
+    // p = z + beta p_prev, beta = -(z^T q_prev) / (p_prev^T q_prev)
+    if (k == 0) {
+      LK_TRY(hipMemcpyAsync(p, z, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    } else {
+      LK_TRY(dots(z, q, z, q, h));
+      const double beta = -h[0] / pq_prev;
+      pdir_kernel<<<g, kT, 0, st>>>(z, p, beta, n);
+      LK_CHECK_LAUNCH();
+    }
+    LK_TRY(product(p, q));
+    LK_TRY(dots(p, q, p, r, h));
+    const double pq = h[0], pr = h[1];
+    if (!(pq > 0.0) || !isfinite(pr)) return LAKER_EBREAKDOWN;
+    const double gamma = pr / pq;
+    step_kernel<<<g, kT, 0, st>>>(alpha, r, p, q, gamma, n);
+    LK_CHECK_LAUNCH();
+    pq_prev = pq;
+    LK_TRY(dots(r, r, r, r, h));
+    rel = ynorm > 0.0 ? sqrt(h[0]) / ynorm : 0.0;
+    if (k + 1 < 64) sp->ir_relres[k + 1] = rel;
+    sp->ir_steps = k + 1;
+    sp->relres = rel;
+    if (rel <= o.tol) {
+      // confirm on the true residual (and continue from it if the recursion drifted)
+      double rt = 0.0;
+      e = true_residual(pb, W, y, alpha, r, &rt, true, st);
+      if (e != LAKER_OK) return e;
+      sp->relres_true = rt;
+      rel = rt;
+      if (rt <= o.tol) return LAKER_OK;
+    }
+    sp->relres_true = rel;
+  }
+  double rt = 0.0;
+  e = true_residual(pb, W, y, alpha, nullptr, &rt, true, st);
+  if (e != LAKER_OK) return e;
+  sp->relres_true = rt;
+  return rt <= o.tol ? LAKER_OK : LAKER_ENOCONV;
+}
+
+}  // namespace lk

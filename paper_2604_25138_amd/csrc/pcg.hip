@@ -179,6 +179,8 @@ SolveWs plan_solve_ws(void* base, int64_t n, int d, int64_t m) {
   w.w64 = c.take<double>(rows);
   w.rout = c.take<double>(n);
   w.dalpha = c.take<double>(n);
+  w.fp = c.take<double>(n);
+  w.fq = c.take<double>(n);
   w.S = c.take<PcgScalars>(1);
   w.bpart = c.take<double>(2 * kMaxBlocks);
   w.yyp = c.take<double>(kMaxBlocks);

@@ -30,6 +30,8 @@ struct SolveWs {
   double* w64;
   double* rout;
   double* dalpha;
+  double* fp;       // flexible outer CG: direction and its product (float64)
+  double* fq;
   PcgScalars* S;
   double* bpart;
   double* yyp;      // per-block partials of ||y||^2, ||r||^2, r^T theta, p^T A p
@@ -82,6 +84,11 @@ laker_status pcg_run(const Problem& pb, const SolveWs& ws, const PrecondView& P,
 laker_status true_residual(const Problem& pb, const SolveWs& ws, const double* y, const double* alpha,
                            double* r_out, double* relres, bool have_alpha, hipStream_t st);
 laker_status axpy_inplace(double* x, const double* d, int64_t n, hipStream_t st);
+
+// Flexible outer CG in float64 whose preconditioner is the inner PCG in
+// `precision` (fcg.hip); stats as for the refinement loop.
+laker_status fcg_run(const Problem& pb, const SolveWs& ws, const PrecondView& P, const double* y, double* alpha,
+                     const laker_pcg_opts& o, int check, laker_stats* sp, hipStream_t st);
 // The library's non-blocking stream (per device) on which iteration chunks are
 // captured into HIP graphs.
 hipStream_t pcg_capture_stream();

@@ -52,7 +52,8 @@ class laker_precond(C.Structure):
 class laker_pcg_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("precision", C.c_int32), ("refine", C.c_int32),
                 ("ir_max", C.c_int32), ("inner_tol", C.c_double), ("warm_start", C.c_int32),
-                ("check_every", C.c_int32), ("graph", C.c_int32), ("profile", C.c_int32)]
+                ("check_every", C.c_int32), ("graph", C.c_int32), ("profile", C.c_int32),
+                ("inner_max_iter", C.c_int32), ("reserved", C.c_int32)]
 
 
 class laker_stats(C.Structure):
@@ -263,7 +264,7 @@ def jacobi_precond(prob: Problem) -> Precond:
 def pcg_solve(prob: Problem, y, precond: Precond | None = None, tol: float = 1e-10, max_iter: int = 10000,
               precision="f64", refine: bool = False, inner_tol: float = 1e-2, ir_max: int = 64,
               alpha0: torch.Tensor | None = None, check_every: int = 16, allow_noconv: bool = False,
-              graph: bool = False, profile: bool = False):
+              graph: bool = False, profile: bool = False, inner_max_iter: int = 0):
     """Returns (alpha, stats)."""
     lib = load()
     y = _dev_f64(y, prob.device)
@@ -271,8 +272,9 @@ def pcg_solve(prob: Problem, y, precond: Precond | None = None, tol: float = 1e-
         alpha = _dev_f64(alpha0, prob.device).clone()
     else:
         alpha = torch.empty_like(y)
-    opts = laker_pcg_opts(tol, max_iter, _PREC[precision], 1 if refine else 0, ir_max, inner_tol,
-                          1 if alpha0 is not None else 0, check_every, 1 if graph else 0, 1 if profile else 0)
+    opts = laker_pcg_opts(tol, max_iter, _PREC[precision], int(refine), ir_max, inner_tol,
+                          1 if alpha0 is not None else 0, check_every, 1 if graph else 0, 1 if profile else 0,
+                          inner_max_iter, 0)
     nb = lib.laker_solve_workspace_bytes(prob.n, prob.d, 0)
     ws = _workspace("solve", nb, prob.device)
     st = laker_stats()
@@ -457,7 +459,7 @@ def pcg_solve_batched(probs: list, ys: list, preconds: list | None = None, tol: 
     yp = (C.c_void_p * count)(*[v.data_ptr() for v in ys])
     ap = (C.c_void_p * count)(*[v.data_ptr() for v in alphas])
     opts = laker_pcg_opts(tol, max_iter, _PREC[precision], 1 if refine else 0, ir_max, inner_tol, 0, check_every,
-                          1 if graph else 0, 0)
+                          1 if graph else 0, 0, 0, 0)
     bo = laker_batch_opts(cols_per_split, 1 if xcd_order else 0, 0, 0)
     ns = (C.c_int64 * count)(*[p.n for p in probs])
     nb = lib.laker_batch_workspace_bytes(count, ns, probs[0].d)
