@@ -129,7 +129,7 @@ laker_status laker_kernel_matvec(const laker_problem* prob, const double* p, dou
   if (workspace_bytes < W.total) return LAKER_ENOMEM;
   Problem pb = to_problem(prob);
   hipStream_t st = (hipStream_t)stream;
-  KmvPlan pl = kmv_plan(pb.n, pb.n, precision);
+  KmvPlan pl = kmv_plan_square(pb.n, pb.dp, precision);
   void* eh = precision == LAKER_F64 ? (void*)W.e64 : (precision == LAKER_F32 ? (void*)W.e32 : (void*)W.e16);
   LK_TRY(prep_embed(pb.E, pb.n, pb.d, pb.dp, pb.scale, precision, eh, st));
   KmvArgs A = kmv_args(eh, pb.n, eh, pb.n, p, W);

@@ -55,7 +55,9 @@ __global__ __launch_bounds__(kThreads) void b_start_kernel(const BDesc* __restri
 __global__ __launch_bounds__(kThreads) void b_ap_kernel(const BDesc* __restrict__ D, const int* __restrict__ R) {
   const BDesc& d = D[R[blockIdx.y]];
   if ((int)blockIdx.x >= d.g) return;
-  pcg_ap_body(blockIdx.x, d.g, d.p, d.part, d.nsplit, d.Ap, d.n, d.lam, d.papp, d.S);
+  PartSum ps{};
+  ps.nsplit = d.nsplit;
+  pcg_ap_body(blockIdx.x, d.g, d.p, d.part, ps, d.Ap, d.n, d.lam, d.papp, d.S);
 }
 
 template <int KIND>

@@ -19,14 +19,100 @@ hipError_t prep_embed(const double* E, int64_t rows, int d, int dp, double scale
 
 constexpr int kMaxSplit = 64;   // largest number of column ranges of one product
 
-// Row blocks x column ranges of one product.
+// Schedule of the symmetric square product  (bfloat16 / float32, dp <= 64).
+// G = exp2(s E E^T) is symmetric, so each off-diagonal entry is formed once
+// and used twice: row blocks of kSymRows rows meet column stages of kSymCols
+// key rows only on or right of the block diagonal (T stages in all); the
+// stages right of the diagonal also add their transposed products into the
+// stage's columns.  The stage list runs through the row blocks in the order
+// 0, nrb - 1, 1, nrb - 2, ... (a long row block, then a short one), each
+// block's stages in column order; a fixed grid of kSymGrid blocks takes equal
+// contiguous runs of it, so that every block does the same work and meets few
+// row blocks.
+// Partials: `rs` row slots per row block (one per block whose run meets it),
+// then one column slot per row block:
+//   part[k n + i]          k < slots(block of i):   row sums of i
+//   part[(rs + I) n + i]   I < row block of i:       transposed sums of i
+constexpr int kSymRows = 256;
+constexpr int kSymCols = 128;
+constexpr int kSymGrid = 256;
+constexpr int kSymMaxRowBlocks = 512;
+struct SymPlan {
+  int nrb;      // row blocks
+  int ncs;      // column stages
+  int grid;     // blocks of the launch
+  int rs;       // row slots (largest count over the row blocks)
+  int64_t T;    // stages
+};
+// row block at position t of the order, and the position of row block I
+__host__ __device__ inline int64_t sym_rowblock_at(int64_t t, int64_t nrb) { return (t & 1) ? nrb - 1 - (t >> 1) : (t >> 1); }
+__host__ __device__ inline int64_t sym_pos_of(int64_t I, int64_t nrb) { return 2 * I <= nrb - 1 ? 2 * I : 2 * (nrb - 1 - I) + 1; }
+// first stage of the row block at position t (row block I has ncs - 2 I stages;
+// the pair at positions 2k, 2k + 1 has 2 ncs - 2 nrb + 2)
+__host__ __device__ inline int64_t sym_pos_start(int64_t t, int64_t nrb, int64_t ncs) {
+  const int64_t k = t >> 1;
+  const int64_t P = 2 * ncs - 2 * nrb + 2;
+  return (t & 1) ? k * P + (ncs - 2 * k) : k * P;
+}
+// block whose run [T b / G, T (b + 1) / G) holds stage s
+__host__ __device__ inline int64_t sym_block_of(int64_t s, int64_t G, int64_t T) { return ((s + 1) * G - 1) / T; }
+
+// Row blocks x column ranges of one product (sym: the symmetric schedule).
 struct KmvPlan {
   int nsplit;
   int64_t cols_per_split;
   int rowblocks;
+  int sym;
+  SymPlan sp;
 };
 KmvPlan kmv_plan(int64_t m, int64_t n, int prec);
+// plan of the square product of n rows with itself (symmetric when it applies)
+KmvPlan kmv_plan_square(int64_t n, int dp, int prec);
 int kmv_rows_per_block(int prec);
+// doubles of the partial buffer the products of an (m x n) problem may use
+size_t kmv_part_elems(int64_t m, int64_t n);
+
+// Layout of the partial sums of one product, and their fixed-order sum.
+struct PartSum {
+  int nsplit;
+  int sym;
+  SymPlan sp;
+  // s += part[(first + k) m + i] for k < count, in order; the loads are
+  // issued eight at a time so that their latencies overlap
+  __device__ __forceinline__ static void add_run(double& s, const double* __restrict__ part, int64_t m, int64_t i,
+                                                 int64_t first, int64_t count) {
+    int64_t k = 0;
+    for (; k + 8 <= count; k += 8) {
+      double v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = part[(first + k + q) * m + i];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) s += v[q];
+    }
+    for (; k < count; ++k) s += part[(first + k) * m + i];
+  }
+  __device__ __forceinline__ double row(const double* __restrict__ part, int64_t m, int64_t i) const {
+    double s = 0.0;
+    if (!sym) {
+      add_run(s, part, m, i, 0, nsplit);
+      return s;
+    }
+    const int64_t I = i / kSymRows;
+    const int64_t t = sym_pos_of(I, sp.nrb);
+    const int64_t b0 = sym_block_of(sym_pos_start(t, sp.nrb, sp.ncs), sp.grid, sp.T);
+    const int64_t b1 = sym_block_of(sym_pos_start(t + 1, sp.nrb, sp.ncs) - 1, sp.grid, sp.T);
+    add_run(s, part, m, i, 0, b1 - b0 + 1);
+    add_run(s, part, m, i, sp.rs, I);
+    return s;
+  }
+};
+inline PartSum part_sum(const KmvPlan& pl) {
+  PartSum ps;
+  ps.nsplit = pl.nsplit;
+  ps.sym = pl.sym;
+  ps.sp = pl.sp;
+  return ps;
+}
 
 // One fused product  out_i = lam * pself_i + sum_j exp(<q_i, k_j>) p_j  (exp2 for
 // the float32 / bfloat16 prepared copies).  All vectors are float64.  The
@@ -49,6 +135,7 @@ struct KmvArgs {
   double* out;          // output vector (mode 1)
   PcgScalars* S;        // when set, the launch is skipped once S->done
   int pcg_step;         // 1: this product starts a PCG iteration (advances S->kcur)
+  PartSum ps;           // filled by kmv_run
 };
 hipError_t kmv_run(int prec, int dp, const KmvPlan& pl, KmvArgs A, hipStream_t st);
 

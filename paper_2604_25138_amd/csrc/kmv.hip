@@ -147,12 +147,11 @@ __device__ __forceinline__ v4d tile_f64(const FragF64<DP>& a, const FragF64<DP>&
 // with per-block atomic tickets serializes ~40 ns of fence and atomic per
 // block, more than this pass costs.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void kmv_finish_kernel(const double* __restrict__ part, int nsplit, int64_t m,
+__global__ __launch_bounds__(256) void kmv_finish_kernel(const double* __restrict__ part, PartSum ps, int64_t m,
                                                          double lam, const double* __restrict__ pself,
                                                          double* __restrict__ out) {
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < m; i += (int64_t)gridDim.x * 256) {
-    double s = 0.0;
-    for (int sp = 0; sp < nsplit; ++sp) s += part[(int64_t)sp * m + i];
+    const double s = ps.row(part, m, i);
     out[i] = pself != nullptr ? fma(lam, pself[i], s) : s;
   }
 }
@@ -181,7 +180,7 @@ struct Stage32 {
   static constexpr int PITCH = ROWB + 16;                            // padded LDS row pitch
   static constexpr int CHUNKS = KT * ROWB / 16;                      // 16-byte chunks per stage
   static constexpr int PER_T = (CHUNKS + 255) / 256;                 // chunks per thread
-  static constexpr int BYTES = KT * PITCH + KT * 8;                  // rows + weights
+  static constexpr int BYTES = KT * PITCH + KT * 4;                  // rows + weights (float)
 };
 
 template <int PREC, int DP>
@@ -216,23 +215,35 @@ __device__ __forceinline__ void kmv32_body(const KmvArgs& A, int64_t bx, int64_t
   const int nstages = (int)((j1 - j0 + KT - 1) / KT);
   u32x4 stg[St::PER_T];
   double stp = 0.0;
-  // global -> registers for the stage starting at key row js (rows clamped to n - 1,
-  // weights zero past the column range)
+  bool stv = false;
+  // global -> registers for the stage starting at key row js.  Rows are
+  // contiguous, so chunk ch of a stage sits ch * 16 bytes past its first row;
+  // only the last stage of the key rows clamps its rows to n - 1.  The weight
+  // is converted and masked (zero past the column range, so that clamped rows
+  // add nothing) when it is written to LDS, which keeps the loads in flight.
   auto fetch = [&](int64_t js) {
+    const unsigned char* sb = Kb + js * St::ROWB;
+    if (js + KT <= A.n) {
 #pragma unroll
-    for (int q = 0; q < St::PER_T; ++q) {
-      const int ch = tid + 256 * q;
-      if (St::CHUNKS % 256 == 0 || ch < St::CHUNKS) {
-        const int rr = ch / (St::ROWB / 16);
-        const int cc = ch - rr * (St::ROWB / 16);
-        int64_t kr = js + rr;
-        if (kr > A.n - 1) kr = A.n - 1;
-        stg[q] = *reinterpret_cast<const u32x4*>(Kb + kr * St::ROWB + cc * 16);
+      for (int q = 0; q < St::PER_T; ++q) {
+        const int ch = tid + 256 * q;
+        if (St::CHUNKS % 256 == 0 || ch < St::CHUNKS) stg[q] = *reinterpret_cast<const u32x4*>(sb + ch * 16);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < St::PER_T; ++q) {
+        const int ch = tid + 256 * q;
+        if (St::CHUNKS % 256 == 0 || ch < St::CHUNKS) {
+          const int rr = ch / (St::ROWB / 16);
+          const int cc = ch - rr * (St::ROWB / 16);
+          int64_t kr = js + rr;
+          if (kr > A.n - 1) kr = A.n - 1;
+          stg[q] = *reinterpret_cast<const u32x4*>(Kb + kr * St::ROWB + cc * 16);
+        }
       }
     }
-    // every thread loads (clamped index) so that no branch separates the loads;
-    // weights past the column range are masked when they are used
     const int64_t kj = js + (tid % KT);
+    stv = kj < j1;
     stp = p[kj < A.n ? kj : A.n - 1];
   };
   auto store = [&](int buf) {
@@ -245,7 +256,7 @@ __device__ __forceinline__ void kmv32_body(const KmvArgs& A, int64_t bx, int64_t
         *reinterpret_cast<u32x4*>(&lds[buf][rr * St::PITCH + cc * 16]) = stg[q];
       }
     }
-    if (tid < KT) reinterpret_cast<double*>(&lds[buf][KT * St::PITCH])[tid] = stp;
+    if (tid < KT) reinterpret_cast<float*>(&lds[buf][KT * St::PITCH])[tid] = stv ? (float)stp : 0.f;
   };
   // Pipeline: at the top of iteration s the registers hold stage s + 1; they
   // are written to the free LDS buffer, the loads of stage s + 2 are issued,
@@ -262,7 +273,7 @@ __device__ __forceinline__ void kmv32_body(const KmvArgs& A, int64_t bx, int64_t
     if (sidx + 1 < nstages) store(buf ^ 1);
     if (sidx + 2 < nstages) fetch(j0 + (int64_t)(sidx + 2) * KT);
     const unsigned char* base = lds[buf];
-    const double* pw = reinterpret_cast<const double*>(base + KT * St::PITCH);
+    const float* pw = reinterpret_cast<const float*>(base + KT * St::PITCH);
     // the stage's products are summed in float32 (KT / 32 terms per lane and
     // row) and the stage sum is added into the float64 accumulator
     float accf[16];
@@ -285,11 +296,10 @@ __device__ __forceinline__ void kmv32_body(const KmvArgs& A, int64_t bx, int64_t
 #pragma unroll
         for (int q = 0; q < DP / 16; ++q) b.v[q] = __builtin_bit_cast(v8bf, *reinterpret_cast<const u32x4*>(rowp + 16 * q));
       }
-      const double pv = (j0 + (int64_t)sidx * KT + u * 32 + c < j1) ? pw[u * 32 + c] : 0.0;
+      const float pvf = pw[u * 32 + c];
       v16f sc;
       if constexpr (PREC == LAKER_F32) sc = tile_f32<DP>(a, b);
       else sc = tile_bf16<DP>(a, b);
-      const float pvf = (float)pv;
 #pragma unroll
       for (int r = 0; r < 16; ++r) accf[r] = fmaf(kexp2(sc[r]), pvf, accf[r]);
     }
@@ -330,6 +340,271 @@ __global__ __launch_bounds__(256) void kmv32_batch_kernel(const KmvArgs* __restr
   if (t[0] < 0) return;   // padding tile
   const KmvArgs A = As[t[0]];
   kmv32_body<PREC, DP>(A, t[1], t[2]);
+}
+
+// ---------------------------------------------------------------------------
+// Symmetric square product (float32 / bfloat16, dp <= 64).  Block b runs the
+// stages [T b / G, T (b + 1) / G) of the list of (row block I, column stage
+// J >= 2 I), row blocks in the order 0, nrb - 1, 1, nrb - 2, ...  Its eight
+// waves own 32 rows each of the 256-row block I; the 128 key rows of a stage are staged through LDS as in the
+// rectangular kernel.  For a stage right of the diagonal (J >= 2 I + 2) every
+// tile exp2(S) feeds the row sums (weights p_j of the stage's columns) and the
+// column sums (weights p_i of the wave's rows); the column sums of the 16
+// wave-halves go through LDS and are added in a fixed order by the first 128
+// threads while the next stage runs.
+// ---------------------------------------------------------------------------
+template <int PREC, int DP>
+struct SymStage {
+  using ET = typename std::conditional<PREC == LAKER_F32, float, uint16_t>::type;
+  static constexpr int ES = (int)sizeof(ET);
+  static constexpr int ROWB = DP * ES;
+  static constexpr int KT = kSymCols;
+  static constexpr int PITCH = ROWB + 16;
+  static constexpr int CHUNKS = KT * ROWB / 16;
+  static constexpr int PER_T = (CHUNKS + 511) / 512;
+  static constexpr int BYTES = KT * PITCH + KT * 4;
+  static constexpr int CPITCH = 160;   // column-sum rows: wave-halves alternate bank halves
+};
+
+template <int PREC, int DP>
+__global__ __launch_bounds__(512) void kmvsym_kernel(KmvArgs A, SymPlan P) {
+  using St = SymStage<PREC, DP>;
+  using ET = typename St::ET;
+  using Frag = typename std::conditional<PREC == LAKER_F32, FragF32<DP>, FragBF16<DP>>::type;
+  constexpr int KT = St::KT;
+  __shared__ __attribute__((aligned(16))) unsigned char lds[2][St::BYTES];
+  __shared__ float colbuf[2][16 * St::CPITCH];
+  if (A.S != nullptr && A.S->done) return;
+  const int64_t b = blockIdx.x;
+  if (A.pcg_step && b == 0 && threadIdx.x == 0) A.S->kcur += 1;
+  const int64_t s0 = P.T * b / P.grid, s1 = P.T * (b + 1) / P.grid;
+  if (s0 >= s1) return;
+  const int64_t L = s1 - s0;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int h = lane >> 5, c = lane & 31;
+  const int64_t n = A.n;
+  const int64_t ncs = P.ncs;
+  const double* __restrict__ p = A.p;
+  const ET* __restrict__ Q = reinterpret_cast<const ET*>(A.K);
+  const unsigned char* __restrict__ Kb = reinterpret_cast<const unsigned char*>(A.K);
+  double* __restrict__ part = A.part;
+
+  // cursor of the first stage: position in the row-block order, row block, column stage
+  const int64_t nrb = P.nrb;
+  int64_t t0 = 0;
+  while (sym_pos_start(t0 + 1, nrb, ncs) <= s0) ++t0;
+  const int64_t I0 = sym_rowblock_at(t0, nrb);
+  const int64_t J0 = 2 * I0 + (s0 - sym_pos_start(t0, nrb, ncs));
+
+  // ---- LDS staging of the key rows of column stage J (as the rectangular kernel)
+  u32x4 stg[St::PER_T];
+  double stp = 0.0;
+  bool stv = false;
+  auto fetch = [&](int64_t J) {
+    const int64_t js = J * KT;
+    const unsigned char* sb = Kb + js * St::ROWB;
+    if (js + KT <= n) {
+#pragma unroll
+      for (int q = 0; q < St::PER_T; ++q) {
+        const int ch = tid + 512 * q;
+        if (St::CHUNKS % 512 == 0 || ch < St::CHUNKS) stg[q] = *reinterpret_cast<const u32x4*>(sb + ch * 16);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < St::PER_T; ++q) {
+        const int ch = tid + 512 * q;
+        if (St::CHUNKS % 512 == 0 || ch < St::CHUNKS) {
+          const int rr = ch / (St::ROWB / 16);
+          const int cc = ch - rr * (St::ROWB / 16);
+          int64_t kr = js + rr;
+          if (kr > n - 1) kr = n - 1;
+          stg[q] = *reinterpret_cast<const u32x4*>(Kb + kr * St::ROWB + cc * 16);
+        }
+      }
+    }
+    const int64_t kj = js + (tid % KT);
+    stv = kj < n;
+    stp = p[kj < n ? kj : n - 1];
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < St::PER_T; ++q) {
+      const int ch = tid + 512 * q;
+      if (St::CHUNKS % 512 == 0 || ch < St::CHUNKS) {
+        const int rr = ch / (St::ROWB / 16);
+        const int cc = ch - rr * (St::ROWB / 16);
+        *reinterpret_cast<u32x4*>(&lds[buf][rr * St::PITCH + cc * 16]) = stg[q];
+      }
+    }
+    if (tid < KT) reinterpret_cast<float*>(&lds[buf][KT * St::PITCH])[tid] = stv ? (float)stp : 0.f;
+  };
+  auto advance = [&](int64_t& t, int64_t& I, int64_t& J) {
+    if (++J == ncs) {
+      ++t;
+      I = sym_rowblock_at(t, nrb);
+      J = 2 * I;
+    }
+  };
+
+  // ---- per row block state: query fragment, row weights, float64 row sums
+  Frag a;
+  float rw[16];
+  double acc[16];
+  int64_t Icur = -1;
+  auto open_rows = [&](int64_t I) {
+    const int64_t row0 = I * kSymRows + wv * 32;
+    int64_t qi = row0 + c;
+    if (qi > n - 1) qi = n - 1;
+    a.load(Q, qi, h);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int64_t row = row0 + (r >> 2) * 8 + h * 4 + (r & 3);
+      rw[r] = row < n ? (float)p[row] : 0.f;
+      acc[r] = 0.0;
+    }
+    Icur = I;
+  };
+  auto flush_rows = [&]() {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      double v = acc[r];
+      v += __shfl_xor(v, 1, 64);
+      v += __shfl_xor(v, 2, 64);
+      v += __shfl_xor(v, 4, 64);
+      v += __shfl_xor(v, 8, 64);
+      v += __shfl_xor(v, 16, 64);
+      acc[r] = v;
+    }
+    const int64_t slot = b - sym_block_of(sym_pos_start(sym_pos_of(Icur, nrb), nrb, ncs), P.grid, P.T);
+    if (c < 16) {
+      double v = 0.0;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) v = (r == c) ? acc[r] : v;
+      const int64_t row = Icur * kSymRows + wv * 32 + (c >> 2) * 8 + h * 4 + (c & 3);
+      if (row < n) part[slot * n + row] = v;
+    }
+  };
+  // column sums of the stage held in colbuf[buf] (16 wave-halves, fixed order)
+  auto flush_cols = [&](int buf, int64_t I, int64_t J) {
+    if (tid < KT) {
+      const int64_t col = J * KT + tid;
+      double v = 0.0;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) v += (double)colbuf[buf][k * St::CPITCH + tid];
+      if (col < n) part[(P.rs + I) * n + col] = v;
+    }
+  };
+
+  // one stage: tiles of the 32 wave rows against the 128 staged key rows.  All
+  // key fragments of the stage are read from LDS first, so that the later
+  // tiles' reads complete behind the products of the earlier ones.
+  auto load_b = [&](Frag& bf, const unsigned char* base, int u) {
+    const unsigned char* rowp = base + (u * 32 + c) * St::PITCH + h * (St::ROWB / 2);
+    if constexpr (PREC == LAKER_F32) {
+#pragma unroll
+      for (int q = 0; q < DP / 8; ++q) {
+        const float4 t = *reinterpret_cast<const float4*>(rowp + 16 * q);
+        bf.v[4 * q + 0] = t.x;
+        bf.v[4 * q + 1] = t.y;
+        bf.v[4 * q + 2] = t.z;
+        bf.v[4 * q + 3] = t.w;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < DP / 16; ++q)
+        bf.v[q] = __builtin_bit_cast(v8bf, *reinterpret_cast<const u32x4*>(rowp + 16 * q));
+    }
+  };
+  auto stage = [&](int buf, auto mirror) {
+    constexpr bool MIR = decltype(mirror)::value;
+    const unsigned char* base = lds[buf];
+    const float* pw = reinterpret_cast<const float*>(base + KT * St::PITCH);
+    float accf[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) accf[r] = 0.f;
+    // (float32 fragments of dp = 64 do not fit in registers four at a time:
+    // there each tile reads its own)
+    constexpr int NB = (PREC == LAKER_F32 && DP > 32) ? 1 : KT / 32;
+    Frag bq[NB];
+    float pv[KT / 32];
+#pragma unroll
+    for (int u = 0; u < KT / 32; ++u) {
+      if (NB > 1) load_b(bq[u % NB], base, u);
+      pv[u] = pw[u * 32 + c];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < KT / 32; ++u) {
+      if (NB == 1) load_b(bq[0], base, u);
+      const float pvf = pv[u];
+      v16f sc;
+      if constexpr (PREC == LAKER_F32) sc = tile_f32<DP>(a, bq[u % NB]);
+      else sc = tile_bf16<DP>(a, bq[u % NB]);
+      if constexpr (MIR) {
+        float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float t0 = kexp2(sc[r]), t1 = kexp2(sc[4 + r]), t2 = kexp2(sc[8 + r]), t3 = kexp2(sc[12 + r]);
+          accf[r] = fmaf(t0, pvf, accf[r]);
+          accf[4 + r] = fmaf(t1, pvf, accf[4 + r]);
+          accf[8 + r] = fmaf(t2, pvf, accf[8 + r]);
+          accf[12 + r] = fmaf(t3, pvf, accf[12 + r]);
+          g0 = fmaf(t0, rw[r], g0);
+          g1 = fmaf(t1, rw[4 + r], g1);
+          g2 = fmaf(t2, rw[8 + r], g2);
+          g3 = fmaf(t3, rw[12 + r], g3);
+        }
+        colbuf[buf][(wv * 2 + h) * St::CPITCH + u * 32 + c] = (g0 + g1) + (g2 + g3);
+      } else {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) accf[r] = fmaf(kexp2(sc[r]), pvf, accf[r]);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] += (double)accf[r];
+  };
+
+  // ---- pipeline (as the rectangular kernel): registers hold stage k + 1 at
+  // the top of iteration k; one barrier per stage
+  int64_t tc = t0, Ic = I0, Jc = J0;   // stage k
+  int64_t tf = t0, If = I0, Jf = J0;   // next stage to fetch
+  fetch(Jf);
+  advance(tf, If, Jf);
+  store(0);
+  if (L > 1) {
+    fetch(Jf);
+    advance(tf, If, Jf);
+  }
+  __syncthreads();
+  int64_t Ip = -1, Jp = -1;   // previous off-diagonal stage whose columns are pending
+  for (int64_t k = 0; k < L; ++k) {
+    const int buf = (int)(k & 1);
+    if (k + 1 < L) store(buf ^ 1);
+    if (k + 2 < L) {
+      fetch(Jf);
+      advance(tf, If, Jf);
+    }
+    if (Ip >= 0) {
+      flush_cols(buf ^ 1, Ip, Jp);
+      Ip = -1;
+    }
+    if (Ic != Icur) {
+      if (Icur >= 0) flush_rows();
+      open_rows(Ic);
+    }
+    if (Jc >= 2 * Ic + 2) {
+      stage(buf, std::true_type{});
+      Ip = Ic;
+      Jp = Jc;
+    } else {
+      stage(buf, std::false_type{});
+    }
+    advance(tc, Ic, Jc);
+    __syncthreads();
+  }
+  if (Ip >= 0) flush_cols((int)((L - 1) & 1), Ip, Jp);
+  flush_rows();
 }
 
 // ---------------------------------------------------------------------------
@@ -495,14 +770,17 @@ KmvPlan kmv_plan(int64_t m, int64_t n, int prec) {
   const int tile = prec == LAKER_F64 ? 16 : 32;
   const int64_t rowblocks = (m + rpb - 1) / rpb;
   const int64_t coltiles = (n + tile - 1) / tile;
-  // about 512 blocks: two per CU of four waves each (the product kernels run
-  // two waves per SIMD), with few column ranges to add up afterwards
-  int64_t ns = (512 + rowblocks - 1) / rowblocks;
+  // about LAKER_KMV_BLOCKS blocks of four waves (512: two per CU, two waves
+  // per SIMD), with few column ranges to add up afterwards
+#ifndef LAKER_KMV_BLOCKS
+#define LAKER_KMV_BLOCKS 512
+#endif
+  int64_t ns = (LAKER_KMV_BLOCKS + rowblocks - 1) / rowblocks;
   if (ns > coltiles) ns = coltiles;
   if (ns > kMaxSplit) ns = kMaxSplit;
   if (ns < 1) ns = 1;
   int64_t cps = ((coltiles + ns - 1) / ns) * tile;
-  KmvPlan pl;
+  KmvPlan pl{};
   pl.cols_per_split = cps;
   pl.nsplit = (int)((n + cps - 1) / cps);
   if (pl.nsplit < 1) pl.nsplit = 1;
@@ -510,18 +788,82 @@ KmvPlan kmv_plan(int64_t m, int64_t n, int prec) {
   return pl;
 }
 
+// Symmetric schedule for the square product of n rows, or sym = 0 when the
+// rectangular one applies: float64, dp > 64, fewer stages than blocks, or more
+// row blocks than the column slots are sized for.
+static SymPlan sym_plan(int64_t n) {
+  SymPlan sp{};
+  sp.nrb = (int)((n + kSymRows - 1) / kSymRows);
+  sp.ncs = (int)((n + kSymCols - 1) / kSymCols);
+  sp.T = (int64_t)sp.nrb * sp.ncs - (int64_t)sp.nrb * (sp.nrb - 1);
+  sp.grid = kSymGrid;
+  sp.rs = 0;
+  for (int64_t t = 0; t < sp.nrb; ++t) {
+    const int64_t b0 = sym_block_of(sym_pos_start(t, sp.nrb, sp.ncs), sp.grid, sp.T);
+    const int64_t b1 = sym_block_of(sym_pos_start(t + 1, sp.nrb, sp.ncs) - 1, sp.grid, sp.T);
+    if (b1 - b0 + 1 > sp.rs) sp.rs = (int)(b1 - b0 + 1);
+  }
+  return sp;
+}
+
+static bool sym_applies(int64_t n, int dp, int prec) {
+  if (prec == LAKER_F64 || dp > 64) return false;
+  const int64_t nrb = (n + kSymRows - 1) / kSymRows;
+  if (nrb > kSymMaxRowBlocks) return false;
+  const int64_t ncs = (n + kSymCols - 1) / kSymCols;
+  return nrb * ncs - nrb * (nrb - 1) >= kSymGrid;
+}
+
+KmvPlan kmv_plan_square(int64_t n, int dp, int prec) {
+  KmvPlan pl = kmv_plan(n, n, prec);
+  if (sym_applies(n, dp, prec)) {
+    pl.sym = 1;
+    pl.sp = sym_plan(n);
+  }
+  return pl;
+}
+
+size_t kmv_part_elems(int64_t m, int64_t n) {
+  const int64_t rows = n > m ? n : m;
+  size_t e = (size_t)kMaxSplit * rows;
+  if (sym_applies(n, 64, LAKER_BF16)) {
+    const SymPlan sp = sym_plan(n);
+    const size_t es = (size_t)(sp.rs + sp.nrb) * n;
+    if (es > e) e = es;
+  }
+  return e;
+}
+
+template <int PREC>
+hipError_t launch_sym(int dp, const KmvArgs& A, const SymPlan& sp, hipStream_t st) {
+  switch (dp) {
+    case 16: kmvsym_kernel<PREC, 16><<<sp.grid, 512, 0, st>>>(A, sp); break;
+    case 32: kmvsym_kernel<PREC, 32><<<sp.grid, 512, 0, st>>>(A, sp); break;
+    case 64: kmvsym_kernel<PREC, 64><<<sp.grid, 512, 0, st>>>(A, sp); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t kmv_run(int prec, int dp, const KmvPlan& pl, KmvArgs A, hipStream_t st) {
   A.cps = pl.cols_per_split;
   A.nsplit = pl.nsplit;
-  dim3 grid((unsigned)pl.rowblocks, (unsigned)pl.nsplit);
+  A.ps = part_sum(pl);
   hipError_t e;
-  if (prec == LAKER_F64) e = launch64(dp, grid, A, st);
-  else if (prec == LAKER_F32) e = launch32<LAKER_F32>(dp, grid, A, st);
-  else e = launch32<LAKER_BF16>(dp, grid, A, st);
+  if (pl.sym) {
+    // the symmetric schedule covers the square self-product only
+    if (A.Q != A.K || A.m != A.n || prec == LAKER_F64) return hipErrorInvalidValue;
+    e = prec == LAKER_F32 ? launch_sym<LAKER_F32>(dp, A, pl.sp, st) : launch_sym<LAKER_BF16>(dp, A, pl.sp, st);
+  } else {
+    dim3 grid((unsigned)pl.rowblocks, (unsigned)pl.nsplit);
+    if (prec == LAKER_F64) e = launch64(dp, grid, A, st);
+    else if (prec == LAKER_F32) e = launch32<LAKER_F32>(dp, grid, A, st);
+    else e = launch32<LAKER_BF16>(dp, grid, A, st);
+  }
   if (e != hipSuccess || A.mode == 0) return e;
   int64_t g = (A.m + 255) / 256;
   if (g > 4096) g = 4096;
-  kmv_finish_kernel<<<(unsigned)g, 256, 0, st>>>(A.part, A.nsplit, A.m, A.lam, A.pself, A.out);
+  kmv_finish_kernel<<<(unsigned)g, 256, 0, st>>>(A.part, A.ps, A.m, A.lam, A.pself, A.out);
   return hipGetLastError();
 }
 

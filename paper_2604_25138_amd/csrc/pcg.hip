@@ -55,9 +55,9 @@ __global__ __launch_bounds__(kThreads) void pcg_start_kernel(PcgScalars* S, cons
 }
 
 __global__ __launch_bounds__(kThreads) void pcg_ap_kernel(const double* __restrict__ p, const double* __restrict__ part,
-                                                          int nsplit, double* __restrict__ Ap, int64_t n, double lam,
+                                                          PartSum ps, double* __restrict__ Ap, int64_t n, double lam,
                                                           double* __restrict__ pap_p, const PcgScalars* S) {
-  pcg_ap_body(blockIdx.x, gridDim.x, p, part, nsplit, Ap, n, lam, pap_p, S);
+  pcg_ap_body(blockIdx.x, gridDim.x, p, part, ps, Ap, n, lam, pap_p, S);
 }
 
 template <int KIND>
@@ -171,7 +171,7 @@ SolveWs plan_solve_ws(void* base, int64_t n, int d, int64_t m) {
   w.q64 = c.take<double>((size_t)mq * dp);
   w.q32 = c.take<float>((size_t)mq * dp);
   w.q16 = c.take<uint16_t>((size_t)mq * dp);
-  w.part = c.take<double>((size_t)kMaxSplit * rows);
+  w.part = c.take<double>(kmv_part_elems(m, n));
   w.r = c.take<double>(n);
   w.p = c.take<double>(n);
   w.ap = c.take<double>(n);
@@ -247,7 +247,7 @@ laker_status pcg_run(const Problem& pb, const SolveWs& ws, const PrecondView& P,
   double* th = ws.theta;
   PcgScalars* S = ws.S;
   const void* eh = prepared(ws, prec);
-  const KmvPlan pl = kmv_plan(n, n, prec);
+  const KmvPlan pl = kmv_plan_square(n, pb.dp, prec);
   const bool lowrank = P.kind == LAKER_PRECOND_CCCP || P.kind == LAKER_PRECOND_LEARNED;
   const double* dinv = (const double*)P.dinv;
 
@@ -303,7 +303,7 @@ laker_status pcg_run(const Problem& pb, const SolveWs& ws, const PrecondView& P,
     } else {
       LK_TRY(kmv_run(prec, pb.dp, pl, Ak, s2));
     }
-    pcg_ap_kernel<<<g, kThreads, 0, s2>>>(p, ws.part, pl.nsplit, Ap, n, pb.lambda, ws.papp, S);
+    pcg_ap_kernel<<<g, kThreads, 0, s2>>>(p, ws.part, part_sum(pl), Ap, n, pb.lambda, ws.papp, S);
     LK_CHECK_LAUNCH();
     if (P.kind == LAKER_PRECOND_JACOBI) {
       pcg_update_kernel<LAKER_PRECOND_JACOBI><<<g, kThreads, 0, s2>>>(alpha, r, p, Ap, dinv, th, n, S, ws.papp, g,

@@ -74,14 +74,13 @@ __device__ __forceinline__ void pcg_start_body(int blk, int nblk, PcgScalars* S,
 
 // Ap = lambda p + sum of the column-range partials; partials of p^T A p.
 __device__ __forceinline__ void pcg_ap_body(int blk, int nblk, const double* __restrict__ p, const double* __restrict__ part,
-                                                          int nsplit, double* __restrict__ Ap, int64_t n, double lam,
+                                                          const PartSum& ps, double* __restrict__ Ap, int64_t n, double lam,
                                                           double* __restrict__ pap_p, const PcgScalars* S) {
   if (S->done) return;
   __shared__ double sh[16];
   double acc = 0.0;
   for (int64_t i = (int64_t)blk * kThreads + threadIdx.x; i < n; i += (int64_t)nblk * kThreads) {
-    double s = 0.0;
-    for (int k = 0; k < nsplit; ++k) s += part[(int64_t)k * n + i];
+    const double s = ps.row(part, n, i);
     const double pi = p[i];
     const double a = fma(lam, pi, s);
     Ap[i] = a;

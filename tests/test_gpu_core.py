@@ -86,6 +86,41 @@ def test_matvec_bf16_parity(n, d):
     assert (np.abs(w - ref64) / _mag(pr.E, pr.scale, pr.lam, p)).max() <= 2e-2
 
 
+@pytest.mark.parametrize("n,d,prec", [(4096 + 37, 64, "f32"), (4096 + 37, 64, "bf16"), (5000, 64, "bf16"),
+                                      (6000, 16, "bf16"), (6000, 32, "f32")])
+def test_matvec_symmetric_schedule_parity(n, d, prec):
+    """Sizes with at least one stage per block take the symmetric schedule
+    (each off-diagonal tile formed once, used for its rows and its columns);
+    ragged n leaves a partial last row block and column stage.  Same
+    tolerances as the rectangular schedule: the column sums add 16 products
+    per lane in float32 (four of four, then pairwise), then the 16 lane
+    halves in float64."""
+    pr = make_problem(n, d, 1e-3, seed=n + d)
+    p = np.random.default_rng(n).normal(size=n)
+    w = L().kernel_matvec(_gp(pr), torch.tensor(p, device=DEV), prec).cpu().numpy()
+    if prec == "f32":
+        ref = O.matvec(pr.E, pr.scale, pr.lam, p)
+        err = np.abs(w - ref) / _mag(pr.E, pr.scale, pr.lam, p)
+    else:
+        Eb = _bf16_rows(pr.E, pr.scale)
+        ref = O.matvec(Eb, np.log(2.0), pr.lam, p)
+        err = np.abs(w - ref) / _mag(Eb, np.log(2.0), pr.lam, p)
+    assert err.max() <= 2e-6, (n, d, prec, err.max())
+
+
+def test_matvec_symmetric_schedule_zero_embeddings():
+    """E = 0 on the symmetric schedule: w = lam p + (sum p) 1 within a few
+    float32 units of sum |p|."""
+    n = 5000
+    E = np.zeros((n, 8))
+    p = np.random.default_rng(5).normal(size=n)
+    prob = L().Problem(torch.tensor(E, device=DEV), 0.25, 1.0)
+    for prec in ("f32", "bf16"):
+        w = L().kernel_matvec(prob, torch.tensor(p, device=DEV), prec).cpu().numpy()
+        ref = 0.25 * p + p.sum()
+        assert np.abs(w - ref).max() <= 3e-7 * (np.abs(p).sum() + 1), prec
+
+
 def test_matvec_zero_embeddings_exact():
     """E = 0: G = 1 1^T exactly in every precision (exp2(0) = 1), so
     w = lam p + (sum p) 1 up to summation rounding: float64 to 1e-13; the
