@@ -44,8 +44,11 @@ WORKLOADS = {
 # lambda log-uniform in [1e-5, 1e-2] and 1..8 transmitters
 TRAIN_N, TRAIN_MAPS, TRAIN_EPOCHS, TRAIN_PROBES = 4096, 96, 30, 128
 
-# VALU issue rate: 256 CUs x 64 lanes x 2.4 GHz, one lane operation per slot
-PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
+# fp32 vector rate: 256 CUs x 128 lanes x 2.4 GHz single-issue multiply-adds
+# (the 157.3 TFLOP/s fp32 vector peak counts 2 flops each); exp2 issues at a
+# quarter of that rate, so it takes 4 of these slots
+PEAK_VALU_TOPS = 256 * 128 * 2.4e9 / 1e12
+EXP2_SLOTS = 4.0
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_BF16_MFMA_TFLOPS = 2500.0
 
@@ -57,6 +60,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="n16384_d64", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--counters", action="store_true",
+                    help="only 20 bfloat16 products of the workload and 5 copies of a 256 MiB buffer (the "
+                         "calibration), for hardware counter runs")
     ap.add_argument("--no-f64", action="store_true", help="skip the float64 comparison leg")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work in the CPU sample")
     ap.add_argument("--train-maps", type=int, default=TRAIN_MAPS)
@@ -161,6 +167,20 @@ def main():
     inner = 0.1
     budget = 20000
 
+    if args.counters:
+        # the product kernel alone, then a plain copy of known size whose
+        # counter readings calibrate FETCH_SIZE / WRITE_SIZE
+        p1 = torch.ones(pr.n, dtype=torch.float64, device=dev)
+        for _ in range(20):
+            L.kernel_matvec(prob, p1, "bf16")
+        a = torch.empty(64 << 20, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"counters": "done", "products": 20, "copy_bytes": 4 * (64 << 20)}))
+        return
+
     model, train_info = train_model(L, LR, pr.d, dev, args.train_maps, args.train_epochs)
 
     def step():
@@ -227,16 +247,20 @@ def main():
                          ir_max=64, check_every=32, profile=True)
     kms = stp.kmv_ms
     pairs = float(pr.n) * pr.n
-    # VALU issue slots per kernel entry: exp2 on the half-rate transcendental
-    # path (2 slots) and one multiply-add into the row sum (1 slot)
-    slots = 3.0 * pairs
+    # the symmetric product forms each of the n (n + 1) / 2 distinct kernel
+    # entries once (one exp2) and uses it for both of its ordered pairs (one
+    # multiply-add each); its score tiles cost 2 d flops per distinct entry
+    distinct = pr.n * (pr.n + 1) / 2.0
+    slots = EXP2_SLOTS * distinct + pairs
     achieved = slots / (kms * 1e-3) / 1e12
-    mfma_flops = 2.0 * pr.d * pairs
-    roofline = {"kernel": "kmv32_kernel<BF16,64> (fused exp2(<e_i,e_j>) p product, bf16 score tiles on MFMA)",
+    mfma_flops = 2.0 * pr.d * distinct
+    traffic = measured_traffic()
+    roofline = {"kernel": "kmvsym_kernel<BF16,64> (fused exp2(<e_i,e_j>) p product over the symmetric tile "
+                          "schedule, bf16 score tiles on MFMA)",
                 "bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TOPS, "unit": "TOP/s",
-                "frac": achieved / PEAK_VALU_TOPS, "traffic": None,
-                "per_launch": {"pairs": pairs, "valu_slot_ops": slots, "mfma_flops": mfma_flops,
-                               "ms": kms, "products_timed": stp.kmv_count,
+                "frac": achieved / PEAK_VALU_TOPS, "traffic": traffic,
+                "per_launch": {"pairs": pairs, "distinct_entries": distinct, "valu_slot_ops": slots,
+                               "mfma_flops": mfma_flops, "ms": kms, "products_timed": stp.kmv_count,
                                "launches": stp.kmv_launches, "ms_all_launches": stp.kmv_launch_ms},
                 "mfma": {"achieved": mfma_flops / (kms * 1e-3) / 1e12, "peak": PEAK_BF16_MFMA_TFLOPS,
                          "unit": "TFLOP/s"}}
@@ -284,6 +308,28 @@ def main():
         out["cpu_baseline"] = cpu_baseline(pr, Z, tol, extra.get("f64_cccp_pcg", {}).get("pcg_iters"),
                                            args.cpu_budget)
     print(json.dumps(out))
+
+
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "kmvsym_bf16_n16384_d64_pmc.json")
+KMV_SOURCE = os.path.join(ROOT, "paper_2604_25138_amd", "csrc", "kmv.hip")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the product kernel from the committed counter
+    runs (FETCH_SIZE and WRITE_SIZE, scaled by the same counters' reading for a
+    plain copy), or None when the kernel source has changed since they were
+    taken (the summary records the source's SHA-256)."""
+    import hashlib
+    try:
+        with open(PMC_SUMMARY) as f:
+            m = json.load(f)
+        with open(KMV_SOURCE, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if m.get("kmv_source_sha256") != sha:
+        return None
+    return m.get("traffic_bytes_per_launch")
 
 
 def cpu_baseline(pr, Z, tol, iters_hint, budget):

@@ -202,6 +202,29 @@ __device__ __forceinline__ void jacobi_apply_body(int blk, int nblk, const doubl
 // order into one float64 partial row per block.
 constexpr int kTRows = 64;
 
+// red[k] = sum over row groups gg = 0, 1, ... of group gg's column sums, added
+// in group order: every group stores its four sums into its own LDS row, one
+// barrier, then each column is added up by one thread (the loads are
+// independent and issue back to back).  Ends with the result in red[0 .. nrp).
+__device__ __forceinline__ void combine_groups(double* red, int g, int q, int cq, int groups, int nrp, double a0,
+                                               double a1, double a2, double a3) {
+  __shared__ double rows[kThreads * 4];   // groups x (4 tpr) <= 4 kThreads
+  const int w = 4 * (kThreads / groups);  // row width 4 tpr
+  if (q < cq) {
+    rows[g * w + 4 * q + 0] = a0;
+    rows[g * w + 4 * q + 1] = a1;
+    rows[g * w + 4 * q + 2] = a2;
+    rows[g * w + 4 * q + 3] = a3;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < nrp; k += kThreads) {
+    double v = rows[k];
+    for (int gg = 1; gg < groups; ++gg) v += rows[gg * w + k];
+    red[k] = v;
+  }
+  __syncthreads();
+}
+
 template <typename MT>
 __device__ __forceinline__ void lr_t_partial_body(int blk, int nblk, const MT* __restrict__ B, const double* __restrict__ r,
                                                                 int64_t n, int nrp, double* __restrict__ tpart,
@@ -230,23 +253,8 @@ __device__ __forceinline__ void lr_t_partial_body(int blk, int nblk, const MT* _
       }
     }
   }
-  // fixed-order combination of the row groups
-  for (int gg = 0; gg < groups; ++gg) {
-    if (g == gg && q < cq) {
-      if (gg == 0) {
-        red[4 * q + 0] = a0;
-        red[4 * q + 1] = a1;
-        red[4 * q + 2] = a2;
-        red[4 * q + 3] = a3;
-      } else {
-        red[4 * q + 0] += a0;
-        red[4 * q + 1] += a1;
-        red[4 * q + 2] += a2;
-        red[4 * q + 3] += a3;
-      }
-    }
-    __syncthreads();
-  }
+  // fixed-order combination of the row groups (group 0 first)
+  combine_groups(red, g, q, cq, groups, nrp, a0, a1, a2, a3);
   for (int k = tid; k < nrp; k += kThreads) tpart[(int64_t)blk * nrp + k] = red[k];
 }
 
@@ -313,22 +321,7 @@ __device__ __forceinline__ void pcg_update_t_body(int blk, int nblk, double* __r
       }
     }
   }
-  for (int gg = 0; gg < groups; ++gg) {
-    if (g == gg && q < cq) {
-      if (gg == 0) {
-        red[4 * q + 0] = a0;
-        red[4 * q + 1] = a1;
-        red[4 * q + 2] = a2;
-        red[4 * q + 3] = a3;
-      } else {
-        red[4 * q + 0] += a0;
-        red[4 * q + 1] += a1;
-        red[4 * q + 2] += a2;
-        red[4 * q + 3] += a3;
-      }
-    }
-    __syncthreads();
-  }
+  combine_groups(red, g, q, cq, groups, nrp, a0, a1, a2, a3);
   for (int c = tid; c < nrp; c += kThreads) tpart[(int64_t)blk * nrp + c] = red[c];
 }
 
@@ -345,8 +338,18 @@ __device__ __forceinline__ void lr_t_finish_body(int blk, int nblk, const double
   const int g = threadIdx.x >> 4, cl = threadIdx.x & 15;
   const int col = blk * 16 + cl;
   double s = 0.0;
-  if (col < nrp)
-    for (int b = g; b < nb; b += 16) s += tpart[(int64_t)b * nrp + col];
+  if (col < nrp) {
+    // partial rows g, g + 16, ... added in order; loads issued eight at a time
+    int b = g;
+    for (; b + 16 * 7 < nb; b += 16 * 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = tpart[(int64_t)(b + 16 * u) * nrp + col];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; b < nb; b += 16) s += tpart[(int64_t)b * nrp + col];
+  }
   red[g][cl] = s;
   __syncthreads();
   if (g == 0 && col < nrp) {
