@@ -40,6 +40,12 @@ WORKLOADS = {
     "n512_d16": dict(n=512, d=16, n_tx=1, lam=1e-3, tol=1e-6, seed=0),
 }
 
+# the solve: flexible float64 outer CG around bf16 inner PCG solves of at most
+# INNER_CAP iterations each (a sweep of the cap on the n16384_d64 map:
+# 15 -> 110 ms, 20 -> 96, 25 -> 96, 30 -> 85, 40 -> 90; iterative refinement
+# with inner tolerance 0.1: 100 ms)
+INNER_CAP = 30
+
 # training set of the learned preconditioner: maps of TRAIN_N sites with
 # lambda log-uniform in [1e-5, 1e-2] and 1..8 transmitters
 TRAIN_N, TRAIN_MAPS, TRAIN_EPOCHS, TRAIN_PROBES = 4096, 96, 30, 128
@@ -184,8 +190,8 @@ def main():
     model, train_info = train_model(L, LR, pr.d, dev, args.train_maps, args.train_epochs)
 
     def step():
-        res = LR.solve_with_fallback(prob, y, model, Zd, tol=tol, budget=budget, precision="bf16", refine=True,
-                                     inner_tol=inner, gamma=0.1, check_every=32)
+        res = LR.solve_with_fallback(prob, y, model, Zd, tol=tol, budget=budget, precision="bf16", refine=2,
+                                     inner_tol=inner, gamma=0.1, check_every=32, inner_max_iter=INNER_CAP)
         rhat = L.predict(prob, res.alpha, Eq, precision="f64")
         return res, rhat
 
@@ -243,8 +249,8 @@ def main():
     # the solve, timed by the library with HIP events on the stream it launches
     # on (one pair of events around every product of the loop)
     pcl = L.learned_precond(prob, model)
-    _, stp = L.pcg_solve(prob, y, pcl, tol=tol, max_iter=100000, precision="bf16", refine=True, inner_tol=inner,
-                         ir_max=64, check_every=32, profile=True)
+    _, stp = L.pcg_solve(prob, y, pcl, tol=tol, max_iter=100000, precision="bf16", refine=2, inner_tol=inner,
+                         ir_max=1000, check_every=32, inner_max_iter=INNER_CAP, profile=True)
     kms = stp.kmv_ms
     pairs = float(pr.n) * pr.n
     # the symmetric product forms each of the n (n + 1) / 2 distinct kernel
@@ -293,8 +299,8 @@ def main():
         "vs_baseline": None, "dtype": "bf16+f64", "data": "synthetic",
         "config": {"workload": f"{args.workload}: n={pr.n} d={pr.d} n_tx={wl['n_tx']} lambda={pr.lam} "
                                f"scale=1/sqrt(d) tol={tol}",
-                   "path": "learned rank-64+diag preconditioner (BF16 MLP) + PCG with bf16 products inside f64 "
-                           "refinement (CCCP fallback on stall) + predict 45x45",
+                   "path": "learned rank-64+diag preconditioner (BF16 MLP) + flexible f64 outer CG around bf16 "
+                           f"inner PCG (<= {INNER_CAP} iterations each; CCCP fallback on stall) + predict 45x45",
                    "training": f"{args.train_maps} maps n={TRAIN_N} lambda~logU[1e-5,1e-2] n_tx~U{{1..8}}, "
                                f"{args.train_epochs} epochs, CCCP targets gamma=1e-3"},
         "roofline": roofline,

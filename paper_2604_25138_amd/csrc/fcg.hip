@@ -91,7 +91,7 @@ laker_status fcg_run(const Problem& pb, const SolveWs& W, const PrecondView& P, 
     return hipStreamSynchronize(st);
   };
   // q = (lambda I + G) p in float64
-  const KmvPlan pl = kmv_plan(n, n, LAKER_F64);
+  const KmvPlan pl = kmv_plan_square(n, pb.dp, LAKER_F64);
   auto product = [&](const double* v, double* out) -> hipError_t {
     KmvArgs A = kmv_args(W.e64, n, W.e64, n, v, W);
     A.lam = pb.lambda;
@@ -123,10 +123,21 @@ laker_status fcg_run(const Problem& pb, const SolveWs& W, const PrecondView& P, 
     int cap = o.max_iter - used;
     if (cap > inner_cap) cap = inner_cap;
     const double itol = fmax(o.inner_tol, 0.5 * o.tol / rel);
-    laker_status ri = pcg_run(pb, W, P, r, z, false, itol, cap, check, o.precision, o.graph != 0, false, &inner, st);
+    laker_status ri =
+        pcg_run(pb, W, P, r, z, false, itol, cap, check, o.precision, o.graph != 0, o.profile != 0, &inner, st);
     if (ri == LAKER_EHIP || ri == LAKER_EINVAL) return ri;
     used += inner.iters;
     sp->iters = used;
+    if (inner.kmv_count > 0) {
+      const double prev = sp->kmv_ms * sp->kmv_count;
+      sp->kmv_count += inner.kmv_count;
+      sp->kmv_ms = (prev + inner.kmv_ms * inner.kmv_count) / sp->kmv_count;
+    }
+    if (inner.kmv_launches > 0) {
+      const double prev = sp->kmv_launch_ms * sp->kmv_launches;
+      sp->kmv_launches += inner.kmv_launches;
+      sp->kmv_launch_ms = (prev + inner.kmv_launch_ms * inner.kmv_launches) / sp->kmv_launches;
+    }
     // p = z + beta p_prev, beta = -(z^T q_prev) / (p_prev^T q_prev)
     if (k == 0) {
       LK_TRY(hipMemcpyAsync(p, z, sizeof(double) * n, hipMemcpyDeviceToDevice, st));

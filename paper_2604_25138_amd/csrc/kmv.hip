@@ -608,6 +608,167 @@ __global__ __launch_bounds__(512) void kmvsym_kernel(KmvArgs A, SymPlan P) {
 }
 
 // ---------------------------------------------------------------------------
+// Symmetric square product in float64 (dp <= 64): the schedule of the
+// float32 / bfloat16 kernel (256-row blocks against 128-column stages on or
+// right of the block diagonal, interleaved row-block order, fixed 256-block
+// grid).  A wave owns 32 rows as two 16-row tiles of the 16x16x4 f64 MFMA; the
+// key fragments come straight from global memory (the f64 MFMA leaves the
+// loads ample time), one tile ahead across stage boundaries.  Off-diagonal
+// tiles add exp(S)^T p_rows into the stage's columns: each lane sums its
+// eight entries, the four lane groups combine by shuffles, the eight waves
+// through LDS in a fixed order.
+// ---------------------------------------------------------------------------
+template <int DP>
+__global__ __launch_bounds__(512) void kmvsym64_kernel(KmvArgs A, SymPlan P) {
+  constexpr int CT = kSymCols / 16;   // column tiles per stage
+  __shared__ double colbuf[2][8 * kSymCols];
+  if (A.S != nullptr && A.S->done) return;
+  const int64_t b = blockIdx.x;
+  if (A.pcg_step && b == 0 && threadIdx.x == 0) A.S->kcur += 1;
+  const int64_t s0 = P.T * b / P.grid, s1 = P.T * (b + 1) / P.grid;
+  if (s0 >= s1) return;
+  const int64_t L = s1 - s0;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int h = lane >> 4, c = lane & 15;
+  const int64_t n = A.n;
+  const int64_t ncs = P.ncs, nrb = P.nrb;
+  const double* __restrict__ p = A.p;
+  const double* __restrict__ K = reinterpret_cast<const double*>(A.K);
+  double* __restrict__ part = A.part;
+
+  int64_t t0 = 0;
+  while (sym_pos_start(t0 + 1, nrb, ncs) <= s0) ++t0;
+  const int64_t I0 = sym_rowblock_at(t0, nrb);
+  const int64_t J0 = 2 * I0 + (s0 - sym_pos_start(t0, nrb, ncs));
+  auto advance = [&](int64_t& t, int64_t& I, int64_t& J) {
+    if (++J == ncs) {
+      ++t;
+      I = sym_rowblock_at(t, nrb);
+      J = 2 * I;
+    }
+  };
+
+  FragF64<DP> a[2];
+  double rw[2][4];
+  double acc[2][4];
+  int64_t Icur = -1;
+  auto open_rows = [&](int64_t I) {
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+      const int64_t row0 = I * kSymRows + wv * 32 + rt * 16;
+      int64_t qi = row0 + c;
+      if (qi > n - 1) qi = n - 1;
+      a[rt].load(K, qi, h);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = row0 + 4 * r + h;
+        rw[rt][r] = row < n ? p[row] : 0.0;
+        acc[rt][r] = 0.0;
+      }
+    }
+    Icur = I;
+  };
+  auto flush_rows = [&]() {
+    const int64_t slot = b - sym_block_of(sym_pos_start(sym_pos_of(Icur, nrb), nrb, ncs), P.grid, P.T);
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+      double v4[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        double v = acc[rt][r];
+        v += __shfl_xor(v, 1, 64);
+        v += __shfl_xor(v, 2, 64);
+        v += __shfl_xor(v, 4, 64);
+        v += __shfl_xor(v, 8, 64);
+        v4[r] = v;
+      }
+      if (c < 4) {
+        double v = 0.0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v = (r == c) ? v4[r] : v;
+        const int64_t row = Icur * kSymRows + wv * 32 + rt * 16 + 4 * c + h;
+        if (row < n) part[slot * n + row] = v;
+      }
+    }
+  };
+  auto flush_cols = [&](int buf, int64_t I, int64_t J) {
+    if (tid < kSymCols) {
+      const int64_t col = J * kSymCols + tid;
+      double v = 0.0;
+#pragma unroll
+      for (int w = 0; w < 8; ++w) v += colbuf[buf][w * kSymCols + tid];
+      if (col < n) part[(P.rs + I) * n + col] = v;
+    }
+  };
+
+  // key tile cursor, one tile ahead of the compute
+  int64_t tf = t0, If = I0, Jf = J0;
+  int ctf = 0;
+  FragF64<DP> bcur, bnext;
+  double pcur = 0.0, pnext = 0.0;
+  auto load_tile = [&](FragF64<DP>& bf, double& pj) {
+    int64_t kj = Jf * kSymCols + ctf * 16 + c;
+    pj = kj < n ? p[kj] : 0.0;
+    if (kj > n - 1) kj = n - 1;
+    bf.load(K, kj, h);
+    if (++ctf == CT) {
+      ctf = 0;
+      advance(tf, If, Jf);
+    }
+  };
+  load_tile(bcur, pcur);
+
+  int64_t tc = t0, Ic = I0, Jc = J0;
+  int64_t Ip = -1, Jp = -1;
+  for (int64_t k = 0; k < L; ++k) {
+    const int buf = (int)(k & 1);
+    if (Ip >= 0) {
+      flush_cols(buf ^ 1, Ip, Jp);
+      Ip = -1;
+    }
+    if (Ic != Icur) {
+      if (Icur >= 0) flush_rows();
+      open_rows(Ic);
+    }
+    const bool mir = Jc >= 2 * Ic + 2;
+#pragma unroll 1
+    for (int ct = 0; ct < CT; ++ct) {
+      const bool more = k + 1 < L || ct + 1 < CT;
+      if (more) load_tile(bnext, pnext);
+      double g = 0.0;
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt) {
+        const v4d s = tile_f64<DP>(a[rt], bcur);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const double e = exp(s[r]);
+          acc[rt][r] = fma(e, pcur, acc[rt][r]);
+          g = fma(e, rw[rt][r], g);
+        }
+      }
+      if (mir) {
+        g += __shfl_xor(g, 16, 64);
+        g += __shfl_xor(g, 32, 64);
+        if (h == 0) colbuf[buf][wv * kSymCols + ct * 16 + c] = g;
+      }
+      if (more) {
+        bcur = bnext;
+        pcur = pnext;
+      }
+    }
+    if (mir) {
+      Ip = Ic;
+      Jp = Jc;
+    }
+    advance(tc, Ic, Jc);
+    __syncthreads();
+  }
+  if (Ip >= 0) flush_cols((int)((L - 1) & 1), Ip, Jp);
+  flush_rows();
+}
+
+// ---------------------------------------------------------------------------
 // float64 kernel: 16x16 score tiles, exp in float64.
 // ---------------------------------------------------------------------------
 template <int DP>
@@ -789,8 +950,8 @@ KmvPlan kmv_plan(int64_t m, int64_t n, int prec) {
 }
 
 // Symmetric schedule for the square product of n rows, or sym = 0 when the
-// rectangular one applies: float64, dp > 64, fewer stages than blocks, or more
-// row blocks than the column slots are sized for.
+// rectangular one applies: dp > 64, fewer stages than blocks, or more row
+// blocks than the column slots are sized for.
 static SymPlan sym_plan(int64_t n) {
   SymPlan sp{};
   sp.nrb = (int)((n + kSymRows - 1) / kSymRows);
@@ -807,7 +968,8 @@ static SymPlan sym_plan(int64_t n) {
 }
 
 static bool sym_applies(int64_t n, int dp, int prec) {
-  if (prec == LAKER_F64 || dp > 64) return false;
+  (void)prec;
+  if (dp > 64) return false;
   const int64_t nrb = (n + kSymRows - 1) / kSymRows;
   if (nrb > kSymMaxRowBlocks) return false;
   const int64_t ncs = (n + kSymCols - 1) / kSymCols;
@@ -834,6 +996,16 @@ size_t kmv_part_elems(int64_t m, int64_t n) {
   return e;
 }
 
+hipError_t launch_sym64(int dp, const KmvArgs& A, const SymPlan& sp, hipStream_t st) {
+  switch (dp) {
+    case 16: kmvsym64_kernel<16><<<sp.grid, 512, 0, st>>>(A, sp); break;
+    case 32: kmvsym64_kernel<32><<<sp.grid, 512, 0, st>>>(A, sp); break;
+    case 64: kmvsym64_kernel<64><<<sp.grid, 512, 0, st>>>(A, sp); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <int PREC>
 hipError_t launch_sym(int dp, const KmvArgs& A, const SymPlan& sp, hipStream_t st) {
   switch (dp) {
@@ -852,8 +1024,10 @@ hipError_t kmv_run(int prec, int dp, const KmvPlan& pl, KmvArgs A, hipStream_t s
   hipError_t e;
   if (pl.sym) {
     // the symmetric schedule covers the square self-product only
-    if (A.Q != A.K || A.m != A.n || prec == LAKER_F64) return hipErrorInvalidValue;
-    e = prec == LAKER_F32 ? launch_sym<LAKER_F32>(dp, A, pl.sp, st) : launch_sym<LAKER_BF16>(dp, A, pl.sp, st);
+    if (A.Q != A.K || A.m != A.n) return hipErrorInvalidValue;
+    if (prec == LAKER_F64) e = launch_sym64(dp, A, pl.sp, st);
+    else if (prec == LAKER_F32) e = launch_sym<LAKER_F32>(dp, A, pl.sp, st);
+    else e = launch_sym<LAKER_BF16>(dp, A, pl.sp, st);
   } else {
     dim3 grid((unsigned)pl.rowblocks, (unsigned)pl.nsplit);
     if (prec == LAKER_F64) e = launch64(dp, grid, A, st);

@@ -218,7 +218,7 @@ laker_status true_residual(const Problem& pb, const SolveWs& ws, const double* y
   const int g = red_blocks(pb.n);
   const double* wv = nullptr;
   if (have_alpha) {
-    KmvPlan pl = kmv_plan(pb.n, pb.n, LAKER_F64);
+    KmvPlan pl = kmv_plan_square(pb.n, pb.dp, LAKER_F64);
     KmvArgs A = kmv_args(ws.e64, pb.n, ws.e64, pb.n, alpha, ws);
     A.lam = pb.lambda;
     A.pself = alpha;

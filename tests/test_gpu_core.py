@@ -87,17 +87,23 @@ def test_matvec_bf16_parity(n, d):
 
 
 @pytest.mark.parametrize("n,d,prec", [(4096 + 37, 64, "f32"), (4096 + 37, 64, "bf16"), (5000, 64, "bf16"),
-                                      (6000, 16, "bf16"), (6000, 32, "f32")])
+                                      (6000, 16, "bf16"), (6000, 32, "f32"), (4096 + 37, 64, "f64"),
+                                      (6000, 16, "f64"), (5000, 32, "f64")])
 def test_matvec_symmetric_schedule_parity(n, d, prec):
     """Sizes with at least one stage per block take the symmetric schedule
     (each off-diagonal tile formed once, used for its rows and its columns);
     ragged n leaves a partial last row block and column stage.  Same
-    tolerances as the rectangular schedule: the column sums add 16 products
-    per lane in float32 (four of four, then pairwise), then the 16 lane
-    halves in float64."""
+    tolerances as the rectangular schedule: the float32 / bfloat16 column sums
+    add 16 products per lane in float32 (four of four, then pairwise), then
+    the 16 lane halves in float64; the float64 kernel sums in float64."""
     pr = make_problem(n, d, 1e-3, seed=n + d)
     p = np.random.default_rng(n).normal(size=n)
     w = L().kernel_matvec(_gp(pr), torch.tensor(p, device=DEV), prec).cpu().numpy()
+    if prec == "f64":
+        ref = O.matvec(pr.E, pr.scale, pr.lam, p)
+        err = np.abs(w - ref) / _mag(pr.E, pr.scale, pr.lam, p)
+        assert err.max() <= 1e-13, (n, d, prec, err.max())
+        return
     if prec == "f32":
         ref = O.matvec(pr.E, pr.scale, pr.lam, p)
         err = np.abs(w - ref) / _mag(pr.E, pr.scale, pr.lam, p)
@@ -115,10 +121,10 @@ def test_matvec_symmetric_schedule_zero_embeddings():
     E = np.zeros((n, 8))
     p = np.random.default_rng(5).normal(size=n)
     prob = L().Problem(torch.tensor(E, device=DEV), 0.25, 1.0)
-    for prec in ("f32", "bf16"):
+    for prec, tol in (("f64", 1e-13), ("f32", 3e-7), ("bf16", 3e-7)):
         w = L().kernel_matvec(prob, torch.tensor(p, device=DEV), prec).cpu().numpy()
         ref = 0.25 * p + p.sum()
-        assert np.abs(w - ref).max() <= 3e-7 * (np.abs(p).sum() + 1), prec
+        assert np.abs(w - ref).max() <= tol * (np.abs(p).sum() + 1), prec
 
 
 def test_matvec_zero_embeddings_exact():
@@ -364,3 +370,16 @@ def test_profiled_solve_matches_and_counts_products():
     b1, t1 = L().pcg_solve(prob, pr.y, pc, tol=1e-11, max_iter=5000, precision="bf16", refine=True,
                            inner_tol=1e-1, check_every=8, profile=True)
     assert t1.kmv_count == t1.iters and t1.kmv_launches >= t1.iters
+
+
+def test_profiled_flexible_cg_counts_inner_products():
+    """The flexible outer CG passes the profiling request to its inner solves:
+    one timed product per inner iteration, the same iterate as unprofiled."""
+    pr = make_problem(900, 16, 1e-4, seed=13)
+    prob = _gp(pr)
+    kw = dict(tol=1e-9, max_iter=20000, precision="bf16", refine=2, inner_tol=1e-1, ir_max=500, check_every=8,
+              inner_max_iter=20)
+    a1, s1 = L().pcg_solve(prob, pr.y, None, profile=True, **kw)
+    a2, s2 = L().pcg_solve(prob, pr.y, None, **kw)
+    assert s1.status == 0 and torch.equal(a1, a2) and s1.iters == s2.iters
+    assert s1.kmv_count == s1.iters and s1.kmv_ms > 0.0 and s2.kmv_count == 0
