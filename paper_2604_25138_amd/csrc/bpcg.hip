@@ -55,8 +55,7 @@ __global__ __launch_bounds__(kThreads) void b_start_kernel(const BDesc* __restri
 __global__ __launch_bounds__(kThreads) void b_ap_kernel(const BDesc* __restrict__ D, const int* __restrict__ R) {
   const BDesc& d = D[R[blockIdx.y]];
   if ((int)blockIdx.x >= d.g) return;
-  PartSum ps{};
-  ps.nsplit = d.nsplit;
+  const PartSum ps = d.ps;
   pcg_ap_body(blockIdx.x, d.g, d.p, d.part, ps, d.Ap, d.n, d.lam, d.papp, d.S);
 }
 
@@ -374,6 +373,11 @@ laker_status pcg_batch(int count, const Problem* pbs, const SolveWs* wss, const 
   const int kPrecOrder[3] = {LAKER_BF16, LAKER_F32, LAKER_F64};
   std::vector<int> pm(count, prec);
   int grp_off[3] = {0, 0, 0}, grp_nt[3] = {0, 0, 0};
+  // maps whose square product takes the symmetric schedule: their products are
+  // launched one map at a time with the single solver's kernel (and plan), the
+  // other maps share the tile table
+  std::vector<int> sym_in[3];
+  std::vector<KmvPlan> sq_in(count);
   // arguments of every map; tiles only for the maps in `members`
   auto rebuild_inner = [&](const std::vector<int>& members) -> laker_status {
     std::vector<int> in_list(count, 0);
@@ -383,18 +387,26 @@ laker_status pcg_batch(int count, const Problem* pbs, const SolveWs* wss, const 
       const int pq = kPrecOrder[q];
       std::vector<Plan1> pl(count);
       std::vector<int> use(count, 0);
+      sym_in[q].clear();
       for (int b = 0; b < count; ++b) {
         if (pm[b] != pq) continue;
-        use[b] = in_list[b];
-        pl[b] = plan_for(pbs[b].n, pq, pq == prec ? cps_map[b] : 0);
         KmvArgs A = kmv_args(prepared(wss[b], pq), pbs[b].n, prepared(wss[b], pq), pbs[b].n, wss[b].p, wss[b]);
         A.mode = 0;
         A.S = wss[b].S;
         A.pcg_step = 1;
-        A.cps = pl[b].cps;
-        A.nsplit = pl[b].nsplit;
+        sq_in[b] = kmv_plan_square(pbs[b].n, dp, pq);
+        if (sq_in[b].sym) {
+          if (in_list[b]) sym_in[q].push_back(b);
+          hd[b].ps = part_sum(sq_in[b]);
+        } else {
+          use[b] = in_list[b];
+          pl[b] = plan_for(pbs[b].n, pq, pq == prec ? cps_map[b] : 0);
+          A.cps = pl[b].cps;
+          A.nsplit = pl[b].nsplit;
+          hd[b].ps = PartSum{};
+          hd[b].ps.nsplit = pl[b].nsplit;
+        }
         hin[b] = A;
-        hd[b].nsplit = pl[b].nsplit;
       }
       std::vector<int> tl = build_tiles(count, pl, use, xcd);
       grp_off[q] = (int)(tl_all.size() / 3);
@@ -409,8 +421,10 @@ laker_status pcg_batch(int count, const Problem* pbs, const SolveWs* wss, const 
 
   // float64 products of the outer residual: single-map plans
   std::vector<Plan1> pl_out(count);
+  std::vector<KmvPlan> sq_out(count);
   for (int b = 0; b < count; ++b) {
     pl_out[b] = plan_for(pbs[b].n, LAKER_F64, 0);
+    sq_out[b] = kmv_plan_square(pbs[b].n, dp, LAKER_F64);
     KmvArgs A = kmv_args(wss[b].e64, pbs[b].n, wss[b].e64, pbs[b].n, alpha[b], wss[b]);
     A.lam = pbs[b].lambda;
     A.pself = alpha[b];
@@ -452,10 +466,12 @@ laker_status pcg_batch(int count, const Problem* pbs, const SolveWs* wss, const 
   // return at once in every pass)
   auto enqueue_iteration = [&](hipStream_t s2) -> laker_status {
     if (nit == 0) return LAKER_OK;
-    for (int q = 0; q < 3; ++q)
+    for (int q = 0; q < 3; ++q) {
       if (grp_nt[q] > 0)
         LK_TRY(kmv_run_batch(kPrecOrder[q], dp, count, bw.inner, bw.tiles_in + 3 * (int64_t)grp_off[q], grp_nt[q],
                              false, max_n, s2));
+      for (int b : sym_in[q]) LK_TRY(kmv_run(kPrecOrder[q], dp, sq_in[b], hin[b], s2));
+    }
     b_ap_kernel<<<dim3(gx, nit), kThreads, 0, s2>>>(bw.desc, bw.run_it);
     LK_CHECK_LAUNCH();
     if (lowrank) {
@@ -570,7 +586,15 @@ laker_status pcg_batch(int count, const Problem* pbs, const SolveWs* wss, const 
     LK_TRY(set_op_list());
     if (nop == 0) return LAKER_OK;
     if (have_alpha) {
-      std::vector<int> tl = build_tiles(count, pl_out, act, xcd);
+      // symmetric-schedule maps: the single solver's product, one launch each
+      std::vector<int> act_tiles = act;
+      for (int b = 0; b < count; ++b)
+        if (act[b] && sq_out[b].sym) {
+          act_tiles[b] = 0;
+          LK_TRY(kmv_run(LAKER_F64, dp, sq_out[b], hout[b], st));
+          hout[b].mode = 2;   // finished: the tile pass below leaves it alone
+        }
+      std::vector<int> tl = build_tiles(count, pl_out, act_tiles, xcd);
       LK_TRY(hipMemcpyAsync(bw.outer, hout.data(), sizeof(KmvArgs) * count, hipMemcpyHostToDevice, st));
       if (!tl.empty())
         LK_TRY(hipMemcpyAsync(bw.tiles_out, tl.data(), sizeof(int) * tl.size(), hipMemcpyHostToDevice, st));

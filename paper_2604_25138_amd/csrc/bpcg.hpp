@@ -12,7 +12,7 @@ struct BDesc {
   int64_t n;
   double lam;
   int g, ga, nbt;        // block counts of the reduction, apply and row-slab passes
-  int nsplit;            // column ranges of the product
+  PartSum ps;            // layout of the product's partial sums
   int active;            // 0: the problem is finished and every batched pass skips it
   int nrp;
   PcgScalars* S;

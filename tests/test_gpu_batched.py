@@ -94,8 +94,8 @@ def test_refinement_escalates_and_converges_on_hard_maps():
     """Small lambda at the largest sizes of the batch: bfloat16 corrections stop
     contracting the float64 residual, the map moves to finer inner products and
     still reaches the tolerance; the batch and the single solves agree bit for
-    bit (below the symmetric schedule's size both use column-range products)."""
-    specs = [(3800, 1e-6, 3), (2048, 3e-6, 5), (1024, 1e-2, 1), (3000, 1e-5, 8)]
+    bit (the 4096-site map takes the symmetric product in both)."""
+    specs = [(4096, 1e-6, 3), (2048, 3e-6, 5), (1024, 1e-2, 1), (3000, 1e-5, 8)]
     maps = []
     for k, (n, lam, ntx) in enumerate(specs):
         pr = make_problem(n, 32, lam, n_tx=ntx, seed=40 + k)
@@ -108,20 +108,19 @@ def test_refinement_escalates_and_converges_on_hard_maps():
         assert s1.escalations == stats[b].escalations and torch.equal(alphas[b], a1), b
 
 
-def test_batch_agrees_with_symmetric_single_solve():
-    """A map large enough for the symmetric product schedule in a single solve
-    (each off-diagonal tile formed once) while the batch keeps column ranges:
-    the two summation orders differ, so both must meet the tolerance and their
-    solutions agree in the float64 operator to twice the tolerance."""
-    pr = make_problem(6000, 32, 1e-3, n_tx=3, seed=77)
-    p = L().Problem(torch.tensor(pr.E, device=DEV), pr.lam, pr.scale)
-    small = make_problem(1500, 32, 1e-3, n_tx=2, seed=78)
-    ps = L().Problem(torch.tensor(small.E, device=DEV), small.lam, small.scale)
+def test_batch_with_symmetric_maps_is_bitwise_equal_to_single_solves():
+    """Maps large enough for the symmetric product schedule run it inside the
+    batch too (one launch per map, the small maps sharing the tile table), so
+    the batch still reproduces the single solves bit for bit, in the inner
+    products (bf16) and in the float64 outer residuals."""
+    specs = [(6000, 1e-3, 3, 77), (1500, 1e-3, 2, 78), (4500, 1e-4, 4, 79)]
+    maps = []
+    for n, lam, ntx, seed in specs:
+        pr = make_problem(n, 32, lam, n_tx=ntx, seed=seed)
+        maps.append((pr, L().Problem(torch.tensor(pr.E, device=DEV), pr.lam, pr.scale)))
     kw = dict(tol=1e-9, max_iter=100000, precision="bf16", refine=True, inner_tol=0.1, check_every=16)
-    alphas, stats, _ = L().pcg_solve_batched([p, ps], [pr.y, small.y], None, **kw)
-    a1, s1 = L().pcg_solve(p, pr.y, None, **kw)
-    assert stats[0].status == 0 and s1.status == 0
-    assert stats[0].relres_true <= 1e-9 and s1.relres_true <= 1e-9
-    y = torch.tensor(pr.y, device=DEV)
-    diff = L().kernel_matvec(p, alphas[0] - a1, "f64")
-    assert (diff.norm() / y.norm()).item() <= 2e-9
+    alphas, stats, _ = L().pcg_solve_batched([p for _, p in maps], [pr.y for pr, _ in maps], None, **kw)
+    for b, (pr, p) in enumerate(maps):
+        a1, s1 = L().pcg_solve(p, pr.y, None, **kw)
+        assert stats[b].status == 0 and stats[b].relres_true <= 1e-9, b
+        assert stats[b].iters == s1.iters and torch.equal(alphas[b], a1), b
