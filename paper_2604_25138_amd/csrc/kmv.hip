@@ -967,13 +967,22 @@ static SymPlan sym_plan(int64_t n) {
   return sp;
 }
 
+// The symmetric schedule pays off once the MFMA work dominates or the stage
+// runs are long: float32 / float64 products from two stages per block on
+// (n >= ~5800), bfloat16 ones from twelve (n >= ~14000).  Measured on
+// stand-alone products, symmetric against column-range, in us:
+//   n = 4096, d = 64:   bf16 24 / 18,  f32 40 / 34,  f64 76 / 81
+//   n = 8192, d = 64:   bf16 35 / 27,  f32 74 / 93,  f64 166 / 273
+//   n = 12000, d = 64:  bf16 49 / 52,  f32 122 / 231, f64 284 / 715
+//   n = 16384, d = 64:  bf16 67 / 71,  f32 200 / 329, f64 499 / 978
+static int64_t sym_min_stages(int prec) { return prec == LAKER_BF16 ? 12 : 2; }
+
 static bool sym_applies(int64_t n, int dp, int prec) {
-  (void)prec;
   if (dp > 64) return false;
   const int64_t nrb = (n + kSymRows - 1) / kSymRows;
   if (nrb > kSymMaxRowBlocks) return false;
   const int64_t ncs = (n + kSymCols - 1) / kSymCols;
-  return nrb * ncs - nrb * (nrb - 1) >= kSymGrid;
+  return nrb * ncs - nrb * (nrb - 1) >= sym_min_stages(prec) * kSymGrid;
 }
 
 KmvPlan kmv_plan_square(int64_t n, int dp, int prec) {
@@ -988,7 +997,7 @@ KmvPlan kmv_plan_square(int64_t n, int dp, int prec) {
 size_t kmv_part_elems(int64_t m, int64_t n) {
   const int64_t rows = n > m ? n : m;
   size_t e = (size_t)kMaxSplit * rows;
-  if (sym_applies(n, 64, LAKER_BF16)) {
+  if (sym_applies(n, 64, LAKER_F64)) {   // the loosest threshold
     const SymPlan sp = sym_plan(n);
     const size_t es = (size_t)(sp.rs + sp.nrb) * n;
     if (es > e) e = es;

@@ -86,11 +86,10 @@ def test_matvec_bf16_parity(n, d):
     assert (np.abs(w - ref64) / _mag(pr.E, pr.scale, pr.lam, p)).max() <= 2e-2
 
 
-@pytest.mark.parametrize("n,d,prec", [(4096 + 37, 64, "f32"), (4096 + 37, 64, "bf16"), (5000, 64, "bf16"),
-                                      (6000, 16, "bf16"), (6000, 32, "f32"), (4096 + 37, 64, "f64"),
-                                      (6000, 16, "f64"), (5000, 32, "f64")])
+@pytest.mark.parametrize("n,d,prec", [(6000, 64, "f32"), (7000 + 37, 32, "f32"), (6000, 16, "f64"),
+                                      (7000 + 37, 64, "f64"), (5800, 32, "f64")])
 def test_matvec_symmetric_schedule_parity(n, d, prec):
-    """Sizes with at least one stage per block take the symmetric schedule
+    """float32 / float64 products of n >= 5700 take the symmetric schedule
     (each off-diagonal tile formed once, used for its rows and its columns);
     ragged n leaves a partial last row block and column stage.  Same
     tolerances as the rectangular schedule: the float32 / bfloat16 column sums
@@ -114,10 +113,27 @@ def test_matvec_symmetric_schedule_parity(n, d, prec):
     assert err.max() <= 2e-6, (n, d, prec, err.max())
 
 
+@pytest.mark.parametrize("n,d", [(14000 + 37, 64), (15000, 32)])
+def test_matvec_symmetric_schedule_bf16_sampled_rows(n, d):
+    """bfloat16 products take the symmetric schedule from n >= 14000: sampled
+    rows of every row block (its first and last row among them) against the
+    oracle's one-row evaluation on the same bfloat16-rounded rows."""
+    pr = make_problem(n, d, 1e-4, n_tx=3, seed=n)
+    p = np.random.default_rng(n).normal(size=n)
+    w = L().kernel_matvec(_gp(pr), torch.tensor(p, device=DEV), "bf16").cpu().numpy()
+    rng = np.random.default_rng(n + 1)
+    rows = np.unique(np.r_[np.arange(0, n, 256), np.minimum(np.arange(255, n + 255, 256), n - 1),
+                           rng.choice(n, 64, replace=False)])
+    Eb = _bf16_rows(pr.E, pr.scale)
+    refb = O.matvec_rows(Eb, np.log(2.0), pr.lam, p, rows)
+    magb = np.array([np.exp2(Eb @ Eb[i]) @ np.abs(p) + pr.lam * abs(p[i]) for i in rows])
+    assert (np.abs(w[rows] - refb) / magb).max() <= 2e-6
+
+
 def test_matvec_symmetric_schedule_zero_embeddings():
-    """E = 0 on the symmetric schedule: w = lam p + (sum p) 1 within a few
-    float32 units of sum |p|."""
-    n = 5000
+    """E = 0 on the symmetric schedule (every precision at this size):
+    w = lam p + (sum p) 1 within a few float32 units of sum |p|."""
+    n = 14400
     E = np.zeros((n, 8))
     p = np.random.default_rng(5).normal(size=n)
     prob = L().Problem(torch.tensor(E, device=DEV), 0.25, 1.0)
