@@ -43,7 +43,8 @@ WORKLOADS = {
 # the solve: flexible float64 outer CG around bf16 inner PCG solves of at most
 # INNER_CAP iterations each (a sweep of the cap on the n16384_d64 map:
 # 15 -> 110 ms, 20 -> 96, 25 -> 96, 30 -> 85, 40 -> 90; iterative refinement
-# with inner tolerance 0.1: 100 ms)
+# with inner tolerance 0.1: 100 ms); the inner solves check for convergence
+# every INNER_CAP iterations, so no launches are enqueued past the cap
 INNER_CAP = 30
 
 # training set of the learned preconditioner: maps of TRAIN_N sites with
@@ -191,7 +192,7 @@ def main():
 
     def step():
         res = LR.solve_with_fallback(prob, y, model, Zd, tol=tol, budget=budget, precision="bf16", refine=2,
-                                     inner_tol=inner, gamma=0.1, check_every=32, inner_max_iter=INNER_CAP)
+                                     inner_tol=inner, gamma=0.1, check_every=INNER_CAP, inner_max_iter=INNER_CAP)
         rhat = L.predict(prob, res.alpha, Eq, precision="f64")
         return res, rhat
 
@@ -250,7 +251,7 @@ def main():
     # on (one pair of events around every product of the loop)
     pcl = L.learned_precond(prob, model)
     _, stp = L.pcg_solve(prob, y, pcl, tol=tol, max_iter=100000, precision="bf16", refine=2, inner_tol=inner,
-                         ir_max=1000, check_every=32, inner_max_iter=INNER_CAP, profile=True)
+                         ir_max=1000, check_every=INNER_CAP, inner_max_iter=INNER_CAP, profile=True)
     kms = stp.kmv_ms
     pairs = float(pr.n) * pr.n
     # the symmetric product forms each of the n (n + 1) / 2 distinct kernel

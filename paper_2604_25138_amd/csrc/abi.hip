@@ -282,7 +282,7 @@ laker_status laker_pcg_solve(const laker_problem* prob, const laker_precond* pre
       // A breakdown of the inner PCG (p^T A p <= 0 in the reduced-precision
       // product: its rounding exceeds lambda in the near-null directions) ends
       // that inner solve with the correction accumulated so far, which the
-      // float64 residual then judges like any other.
+      // float64 residual then evaluates like any other.
       if (ri == LAKER_EHIP || ri == LAKER_EINVAL) return ri;
       if (ri == LAKER_EBREAKDOWN && prec_now == LAKER_F64) return ri;
       r2 = axpy_inplace(alpha, W.dalpha, pb.n, st);
