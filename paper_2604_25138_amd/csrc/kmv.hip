@@ -361,7 +361,8 @@ struct SymStage {
   static constexpr int KT = kSymCols;
   static constexpr int PITCH = ROWB + 16;
   static constexpr int CHUNKS = KT * ROWB / 16;
-  static constexpr int PER_T = (CHUNKS + 511) / 512;
+  static constexpr int STAGERS = 256;  // threads (waves 0-3) that move the key rows
+  static constexpr int PER_T = (CHUNKS + STAGERS - 1) / STAGERS;
   static constexpr int BYTES = KT * PITCH + KT * 4;
   static constexpr int CPITCH = 160;   // column-sum rows: wave-halves alternate bank halves
 };
@@ -401,20 +402,25 @@ __global__ __launch_bounds__(512) void kmvsym_kernel(KmvArgs A, SymPlan P) {
   u32x4 stg[St::PER_T];
   double stp = 0.0;
   bool stv = false;
+  // Waves 0-3 move the key rows (global -> registers -> LDS) and waves 2-3 add
+  // up the column sums: in a stage the second wave of each SIMD (waves 4-7)
+  // finishes its tiles last, and waves 0-3 otherwise wait at the barrier.
+  const bool stager = tid < St::STAGERS;
   auto fetch = [&](int64_t J) {
     const int64_t js = J * KT;
     const unsigned char* sb = Kb + js * St::ROWB;
-    if (js + KT <= n) {
+    if (!stager) {
+    } else if (js + KT <= n) {
 #pragma unroll
       for (int q = 0; q < St::PER_T; ++q) {
-        const int ch = tid + 512 * q;
-        if (St::CHUNKS % 512 == 0 || ch < St::CHUNKS) stg[q] = *reinterpret_cast<const u32x4*>(sb + ch * 16);
+        const int ch = tid + St::STAGERS * q;
+        if (St::CHUNKS % St::STAGERS == 0 || ch < St::CHUNKS) stg[q] = *reinterpret_cast<const u32x4*>(sb + ch * 16);
       }
     } else {
 #pragma unroll
       for (int q = 0; q < St::PER_T; ++q) {
-        const int ch = tid + 512 * q;
-        if (St::CHUNKS % 512 == 0 || ch < St::CHUNKS) {
+        const int ch = tid + St::STAGERS * q;
+        if (St::CHUNKS % St::STAGERS == 0 || ch < St::CHUNKS) {
           const int rr = ch / (St::ROWB / 16);
           const int cc = ch - rr * (St::ROWB / 16);
           int64_t kr = js + rr;
@@ -423,18 +429,22 @@ __global__ __launch_bounds__(512) void kmvsym_kernel(KmvArgs A, SymPlan P) {
         }
       }
     }
-    const int64_t kj = js + (tid % KT);
-    stv = kj < n;
-    stp = p[kj < n ? kj : n - 1];
+    if (tid < KT) {
+      const int64_t kj = js + tid;
+      stv = kj < n;
+      stp = p[kj < n ? kj : n - 1];
+    }
   };
   auto store = [&](int buf) {
+    if (stager) {
 #pragma unroll
-    for (int q = 0; q < St::PER_T; ++q) {
-      const int ch = tid + 512 * q;
-      if (St::CHUNKS % 512 == 0 || ch < St::CHUNKS) {
-        const int rr = ch / (St::ROWB / 16);
-        const int cc = ch - rr * (St::ROWB / 16);
-        *reinterpret_cast<u32x4*>(&lds[buf][rr * St::PITCH + cc * 16]) = stg[q];
+      for (int q = 0; q < St::PER_T; ++q) {
+        const int ch = tid + St::STAGERS * q;
+        if (St::CHUNKS % St::STAGERS == 0 || ch < St::CHUNKS) {
+          const int rr = ch / (St::ROWB / 16);
+          const int cc = ch - rr * (St::ROWB / 16);
+          *reinterpret_cast<u32x4*>(&lds[buf][rr * St::PITCH + cc * 16]) = stg[q];
+        }
       }
     }
     if (tid < KT) reinterpret_cast<float*>(&lds[buf][KT * St::PITCH])[tid] = stv ? (float)stp : 0.f;
@@ -452,7 +462,10 @@ __global__ __launch_bounds__(512) void kmvsym_kernel(KmvArgs A, SymPlan P) {
   float rw[16];
   double acc[16];
   int64_t Icur = -1;
-  auto open_rows = [&](int64_t I) {
+  // query fragment and row weights of row block I; issued at the end of the
+  // stage before the row block changes (their last readers are that stage's
+  // products), so that the loads complete behind its barrier
+  auto load_rows = [&](int64_t I) {
     const int64_t row0 = I * kSymRows + wv * 32;
     int64_t qi = row0 + c;
     if (qi > n - 1) qi = n - 1;
@@ -461,37 +474,43 @@ __global__ __launch_bounds__(512) void kmvsym_kernel(KmvArgs A, SymPlan P) {
     for (int r = 0; r < 16; ++r) {
       const int64_t row = row0 + (r >> 2) * 8 + h * 4 + (r & 3);
       rw[r] = row < n ? (float)p[row] : 0.f;
-      acc[r] = 0.0;
     }
+  };
+  auto open_rows = [&](int64_t I) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.0;
     Icur = I;
   };
+  // row sums over the 32 lanes of each half: a halving exchange (lanes with
+  // bit 4 set keep rows 8..15, with bit 3 the upper half of what is left, ...)
+  // leaves lane c with row (c >> 1) summed over its 32 lanes after 16 shuffles
   auto flush_rows = [&]() {
+    double v8[8], v4[4], v2[2];
+    const bool s4 = (c & 16) != 0, s3 = (c & 8) != 0, s2 = (c & 4) != 0, s1 = (c & 2) != 0;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      double v = acc[r];
-      v += __shfl_xor(v, 1, 64);
-      v += __shfl_xor(v, 2, 64);
-      v += __shfl_xor(v, 4, 64);
-      v += __shfl_xor(v, 8, 64);
-      v += __shfl_xor(v, 16, 64);
-      acc[r] = v;
-    }
+    for (int j = 0; j < 8; ++j) v8[j] = (s4 ? acc[j + 8] : acc[j]) + __shfl_xor(s4 ? acc[j] : acc[j + 8], 16, 64);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v4[j] = (s3 ? v8[j + 4] : v8[j]) + __shfl_xor(s3 ? v8[j] : v8[j + 4], 8, 64);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) v2[j] = (s2 ? v4[j + 2] : v4[j]) + __shfl_xor(s2 ? v4[j] : v4[j + 2], 4, 64);
+    double v = (s1 ? v2[1] : v2[0]) + __shfl_xor(s1 ? v2[0] : v2[1], 2, 64);
+    v += __shfl_xor(v, 1, 64);
     const int64_t slot = b - sym_block_of(sym_pos_start(sym_pos_of(Icur, nrb), nrb, ncs), P.grid, P.T);
-    if (c < 16) {
-      double v = 0.0;
-#pragma unroll
-      for (int r = 0; r < 16; ++r) v = (r == c) ? acc[r] : v;
-      const int64_t row = Icur * kSymRows + wv * 32 + (c >> 2) * 8 + h * 4 + (c & 3);
+    if ((c & 1) == 0) {
+      const int r = c >> 1;
+      const int64_t row = Icur * kSymRows + wv * 32 + (r >> 2) * 8 + h * 4 + (r & 3);
       if (row < n) part[slot * n + row] = v;
     }
   };
-  // column sums of the stage held in colbuf[buf] (16 wave-halves, fixed order)
+  // column sums of the stage held in colbuf[buf] (16 wave-halves, fixed order),
+  // by waves 2-3
   auto flush_cols = [&](int buf, int64_t I, int64_t J) {
-    if (tid < KT) {
-      const int64_t col = J * KT + tid;
+    const int ct = tid - KT;
+    if (ct >= 0 && ct < KT) {
+      const int64_t col = J * KT + ct;
       double v = 0.0;
 #pragma unroll
-      for (int k = 0; k < 16; ++k) v += (double)colbuf[buf][k * St::CPITCH + tid];
+      for (int k = 0; k < 16; ++k) v += (double)colbuf[buf][k * St::CPITCH + ct];
       if (col < n) part[(P.rs + I) * n + col] = v;
     }
   };
@@ -576,6 +595,7 @@ __global__ __launch_bounds__(512) void kmvsym_kernel(KmvArgs A, SymPlan P) {
     fetch(Jf);
     advance(tf, If, Jf);
   }
+  load_rows(I0);
   __syncthreads();
   int64_t Ip = -1, Jp = -1;   // previous off-diagonal stage whose columns are pending
   for (int64_t k = 0; k < L; ++k) {
@@ -601,6 +621,7 @@ __global__ __launch_bounds__(512) void kmvsym_kernel(KmvArgs A, SymPlan P) {
       stage(buf, std::false_type{});
     }
     advance(tc, Ic, Jc);
+    if (k + 1 < L && Ic != Icur) load_rows(Ic);
     __syncthreads();
   }
   if (Ip >= 0) flush_cols((int)((L - 1) & 1), Ip, Jp);
