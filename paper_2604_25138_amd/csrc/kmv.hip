@@ -993,13 +993,14 @@ static SymPlan sym_plan(int64_t n) {
 
 // The symmetric schedule pays off once the MFMA work dominates or the stage
 // runs are long: float32 / float64 products from two stages per block on
-// (n >= ~5800), bfloat16 ones from twelve (n >= ~14000).  Measured on
-// stand-alone products, symmetric against column-range, in us:
-//   n = 4096, d = 64:   bf16 24 / 18,  f32 40 / 34,  f64 76 / 81
-//   n = 8192, d = 64:   bf16 35 / 27,  f32 74 / 93,  f64 166 / 273
-//   n = 12000, d = 64:  bf16 49 / 52,  f32 122 / 231, f64 284 / 715
-//   n = 16384, d = 64:  bf16 67 / 71,  f32 200 / 329, f64 499 / 978
-static int64_t sym_min_stages(int prec) { return prec == LAKER_BF16 ? 12 : 2; }
+// (n >= ~5800), bfloat16 ones from six (n >= ~9800).  Measured on stand-alone
+// products, symmetric against column-range, in us (d = 64):
+//   n = 4096:   f32 40 / 34,   f64 76 / 81
+//   n = 8192:   bf16 30 / 28,  f32 74 / 93,   f64 166 / 273
+//   n = 10000:  bf16 38 / 43
+//   n = 12000:  bf16 43 / 53,  f32 122 / 231, f64 284 / 715
+//   n = 16384:  bf16 60 / 71,  f32 200 / 329, f64 499 / 978
+static int64_t sym_min_stages(int prec) { return prec == LAKER_BF16 ? 6 : 2; }
 
 static bool sym_applies(int64_t n, int dp, int prec) {
   if (dp > 64) return false;
