@@ -52,9 +52,11 @@ __global__ __launch_bounds__(kThreads) void b_start_kernel(const BDesc* __restri
   pcg_start_body(0, 1, d.S, d.yyp, d.rrp, d.g, d.tol, d.max_iter);
 }
 
+// (maps with a symmetric product skip this pass: their product kernel forms
+// p^T A p and the step update adds the partials, as in the single solver)
 __global__ __launch_bounds__(kThreads) void b_ap_kernel(const BDesc* __restrict__ D, const int* __restrict__ R) {
   const BDesc& d = D[R[blockIdx.y]];
-  if ((int)blockIdx.x >= d.g) return;
+  if ((int)blockIdx.x >= d.g || d.ps.sym) return;
   const PartSum ps = d.ps;
   pcg_ap_body(blockIdx.x, d.g, d.p, d.part, ps, d.Ap, d.n, d.lam, d.papp, d.S);
 }
@@ -63,15 +65,18 @@ template <int KIND>
 __global__ __launch_bounds__(kThreads) void b_update_kernel(const BDesc* __restrict__ D, const int* __restrict__ R) {
   const BDesc& d = D[R[blockIdx.y]];
   if ((int)blockIdx.x >= d.g) return;
-  pcg_update_body<KIND>(blockIdx.x, d.g, d.x, d.r, d.p, d.Ap, d.dinv, d.th, d.n, d.S, d.papp, d.g, d.rrp, d.rzp);
+  const PartSum ps = d.ps;
+  pcg_update_body<KIND>(blockIdx.x, d.g, d.x, d.r, d.p, ps.sym ? nullptr : d.Ap, d.part, ps, d.lam, d.dinv, d.th, d.n,
+                        d.S, d.papp, ps.sym ? ps.sp.grid : d.g, d.rrp, d.rzp);
 }
 
 template <typename MT>
 __global__ __launch_bounds__(kThreads) void b_update_t_kernel(const BDesc* __restrict__ D, const int* __restrict__ R) {
   const BDesc& d = D[R[blockIdx.y]];
   if ((int)blockIdx.x >= d.nbt) return;
-  pcg_update_t_body<MT>(blockIdx.x, d.nbt, d.x, d.r, d.p, d.Ap, (const MT*)d.B, d.nrp, d.n, d.S, d.papp, d.g, d.rrp,
-                        d.tpart);
+  const PartSum ps = d.ps;
+  pcg_update_t_body<MT>(blockIdx.x, d.nbt, d.x, d.r, d.p, ps.sym ? nullptr : d.Ap, d.part, ps, d.lam, (const MT*)d.B,
+                        d.nrp, d.n, d.S, d.papp, ps.sym ? ps.sp.grid : d.g, d.rrp, d.tpart);
 }
 
 template <typename MT>
@@ -398,6 +403,8 @@ laker_status pcg_batch(int count, const Problem* pbs, const SolveWs* wss, const 
         if (sq_in[b].sym) {
           if (in_list[b]) sym_in[q].push_back(b);
           hd[b].ps = part_sum(sq_in[b]);
+          A.pap = wss[b].papp;
+          A.lam = pbs[b].lambda;
         } else {
           use[b] = in_list[b];
           pl[b] = plan_for(pbs[b].n, pq, pq == prec ? cps_map[b] : 0);

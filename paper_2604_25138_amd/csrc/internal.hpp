@@ -105,6 +105,35 @@ struct PartSum {
     add_run(s, part, m, i, sp.rs, I);
     return s;
   }
+  // the same list of partials of row i (row slots, then column slots), but
+  // only positions q, q + Q, q + 2 Q, ... of it, added in that order
+  __device__ __forceinline__ double row_strided(const double* __restrict__ part, int64_t m, int64_t i, int q,
+                                                int Q) const {
+    int64_t nr = nsplit, cnt = nsplit, c0 = 0;
+    if (sym) {
+      const int64_t I = i / kSymRows;
+      const int64_t t = sym_pos_of(I, sp.nrb);
+      const int64_t b0 = sym_block_of(sym_pos_start(t, sp.nrb, sp.ncs), sp.grid, sp.T);
+      const int64_t b1 = sym_block_of(sym_pos_start(t + 1, sp.nrb, sp.ncs) - 1, sp.grid, sp.T);
+      nr = b1 - b0 + 1;
+      cnt = nr + I;
+      c0 = sp.rs - nr;
+    }
+    double s = 0.0;
+    int64_t k = q;
+    for (; k + 7 * Q < cnt; k += 8 * Q) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t kk = k + u * Q;
+        v[u] = part[(kk < nr ? kk : c0 + kk) * m + i];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; k < cnt; k += Q) s += part[(k < nr ? k : c0 + k) * m + i];
+    return s;
+  }
 };
 inline PartSum part_sum(const KmvPlan& pl) {
   PartSum ps;
@@ -136,6 +165,10 @@ struct KmvArgs {
   PcgScalars* S;        // when set, the launch is skipped once S->done
   int pcg_step;         // 1: this product starts a PCG iteration (advances S->kcur)
   PartSum ps;           // filled by kmv_run
+  // symmetric schedule only (null: not formed): one float64 partial per block
+  // of  p^T (lam I + G) p  = sum_i p_i (lam p_i + partials of row i), the
+  // curvature of a CG step, taken from the partial sums as they are written
+  double* pap;
 };
 hipError_t kmv_run(int prec, int dp, const KmvPlan& pl, KmvArgs A, hipStream_t st);
 

@@ -16,7 +16,9 @@
 // (float64 across stages, float32 within a stage), which are combined across
 // lanes once at the end.  Column ranges write
 // partial sums; a following pass adds them in a fixed order and applies
-// lambda p (inside PCG that pass also forms the p^T A p partials).
+// lambda p.  Inside PCG the symmetric kernels also form p^T A p from the
+// partials they write (one float64 per block), and the step-update pass adds
+// the partials of each row itself.
 #include <type_traits>
 
 #include "internal.hpp"
@@ -353,6 +355,21 @@ __global__ __launch_bounds__(256) void kmv32_batch_kernel(const KmvArgs* __restr
 // wave-halves go through LDS and are added in a fixed order by the first 128
 // threads while the next stage runs.
 // ---------------------------------------------------------------------------
+// Block total of the per-thread p^T A p sums of a symmetric launch (512
+// threads), in a fixed order: wave 0 adds the eight waves' values lane by
+// lane, then the lanes by a shuffle tree.
+__device__ __forceinline__ void sym_pap_store(double* papl, double* out) {
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    double s = papl[threadIdx.x];
+#pragma unroll
+    for (int w = 1; w < 8; ++w) s += papl[w * 64 + threadIdx.x];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (threadIdx.x == 0) *out = s;
+  }
+}
+
 template <int PREC, int DP>
 struct SymStage {
   using ET = typename std::conditional<PREC == LAKER_F32, float, uint16_t>::type;
@@ -375,13 +392,23 @@ __global__ __launch_bounds__(512) void kmvsym_kernel(KmvArgs A, SymPlan P) {
   constexpr int KT = St::KT;
   __shared__ __attribute__((aligned(16))) unsigned char lds[2][St::BYTES];
   __shared__ float colbuf[2][16 * St::CPITCH];
+  // p^T A p partials (A.pap set): p of the staged columns of three stages in
+  // flight, p of the row each lane writes, and one running sum per thread
+  __shared__ double pdl[3][KT];
+  __shared__ double prl[512];
+  __shared__ double papl[512];
   if (A.S != nullptr && A.S->done) return;
   const int64_t b = blockIdx.x;
   if (A.pcg_step && b == 0 && threadIdx.x == 0) A.S->kcur += 1;
   const int64_t s0 = P.T * b / P.grid, s1 = P.T * (b + 1) / P.grid;
-  if (s0 >= s1) return;
+  const bool wp = A.pap != nullptr;
+  if (s0 >= s1) {
+    if (wp && threadIdx.x == 0) A.pap[b] = 0.0;
+    return;
+  }
   const int64_t L = s1 - s0;
   const int tid = threadIdx.x;
+  if (wp) papl[tid] = 0.0;
   const int lane = tid & 63, wv = tid >> 6;
   const int h = lane >> 5, c = lane & 31;
   const int64_t n = A.n;
@@ -435,7 +462,7 @@ __global__ __launch_bounds__(512) void kmvsym_kernel(KmvArgs A, SymPlan P) {
       stp = p[kj < n ? kj : n - 1];
     }
   };
-  auto store = [&](int buf) {
+  auto store = [&](int buf, int ring) {
     if (stager) {
 #pragma unroll
       for (int q = 0; q < St::PER_T; ++q) {
@@ -447,7 +474,10 @@ __global__ __launch_bounds__(512) void kmvsym_kernel(KmvArgs A, SymPlan P) {
         }
       }
     }
-    if (tid < KT) reinterpret_cast<float*>(&lds[buf][KT * St::PITCH])[tid] = stv ? (float)stp : 0.f;
+    if (tid < KT) {
+      reinterpret_cast<float*>(&lds[buf][KT * St::PITCH])[tid] = stv ? (float)stp : 0.f;
+      if (wp) pdl[ring][tid] = stv ? stp : 0.0;
+    }
   };
   auto advance = [&](int64_t& t, int64_t& I, int64_t& J) {
     if (++J == ncs) {
@@ -461,6 +491,7 @@ __global__ __launch_bounds__(512) void kmvsym_kernel(KmvArgs A, SymPlan P) {
   Frag a;
   float rw[16];
   double acc[16];
+  double prn = 0.0;   // p of the row this lane writes, for the next row block
   int64_t Icur = -1;
   // query fragment and row weights of row block I; issued at the end of the
   // stage before the row block changes (their last readers are that stage's
@@ -475,10 +506,16 @@ __global__ __launch_bounds__(512) void kmvsym_kernel(KmvArgs A, SymPlan P) {
       const int64_t row = row0 + (r >> 2) * 8 + h * 4 + (r & 3);
       rw[r] = row < n ? (float)p[row] : 0.f;
     }
+    if (wp) {
+      const int r = c >> 1;
+      const int64_t row = row0 + (r >> 2) * 8 + h * 4 + (r & 3);
+      prn = row < n ? p[row] : 0.0;
+    }
   };
   auto open_rows = [&](int64_t I) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] = 0.0;
+    if (wp) prl[tid] = prn;
     Icur = I;
   };
   // row sums over the 32 lanes of each half: a halving exchange (lanes with
@@ -499,19 +536,31 @@ __global__ __launch_bounds__(512) void kmvsym_kernel(KmvArgs A, SymPlan P) {
     if ((c & 1) == 0) {
       const int r = c >> 1;
       const int64_t row = Icur * kSymRows + wv * 32 + (r >> 2) * 8 + h * 4 + (r & 3);
-      if (row < n) part[slot * n + row] = v;
+      if (row < n) {
+        part[slot * n + row] = v;
+        if (wp) {
+          // the block holding the row block's diagonal stage adds lam p_i^2
+          const double pr = prl[tid];
+          double s = fma(pr, v, papl[tid]);
+          if (slot == 0) s = fma(A.lam * pr, pr, s);
+          papl[tid] = s;
+        }
+      }
     }
   };
   // column sums of the stage held in colbuf[buf] (16 wave-halves, fixed order),
   // by waves 2-3
-  auto flush_cols = [&](int buf, int64_t I, int64_t J) {
+  auto flush_cols = [&](int buf, int ring, int64_t I, int64_t J) {
     const int ct = tid - KT;
     if (ct >= 0 && ct < KT) {
       const int64_t col = J * KT + ct;
       double v = 0.0;
 #pragma unroll
       for (int k = 0; k < 16; ++k) v += (double)colbuf[buf][k * St::CPITCH + ct];
-      if (col < n) part[(P.rs + I) * n + col] = v;
+      if (col < n) {
+        part[(P.rs + I) * n + col] = v;
+        if (wp) papl[tid] = fma(pdl[ring][ct], v, papl[tid]);
+      }
     }
   };
 
@@ -591,9 +640,14 @@ __global__ __launch_bounds__(512) void kmvsym_kernel(KmvArgs A, SymPlan P) {
   // the top of iteration k; one barrier per stage
   int64_t tc = t0, Ic = I0, Jc = J0;   // stage k
   int64_t tf = t0, If = I0, Jf = J0;   // next stage to fetch
+  // stage s keeps the float64 p of its columns in pdl[s % 3]: written when the
+  // stage is stored (iteration s - 1), read when its columns are flushed
+  // (iteration s + 1), overwritten by stage s + 3 (iteration s + 2)
+  auto ring_next = [](int q) { return q == 2 ? 0 : q + 1; };
+  int rcur = 0;
   fetch(Jf);
   advance(tf, If, Jf);
-  store(0);
+  store(0, 0);
   if (L > 1) {
     fetch(Jf);
     advance(tf, If, Jf);
@@ -601,15 +655,16 @@ __global__ __launch_bounds__(512) void kmvsym_kernel(KmvArgs A, SymPlan P) {
   load_rows(I0);
   __syncthreads();
   int64_t Ip = -1, Jp = -1;   // previous off-diagonal stage whose columns are pending
+  int rp = 0;
   for (int64_t k = 0; k < L; ++k) {
     const int buf = (int)(k & 1);
-    if (k + 1 < L) store(buf ^ 1);
+    if (k + 1 < L) store(buf ^ 1, ring_next(rcur));
     if (k + 2 < L) {
       fetch(Jf);
       advance(tf, If, Jf);
     }
     if (Ip >= 0) {
-      flush_cols(buf ^ 1, Ip, Jp);
+      flush_cols(buf ^ 1, rp, Ip, Jp);
       Ip = -1;
     }
     if (Ic != Icur) {
@@ -620,15 +675,18 @@ __global__ __launch_bounds__(512) void kmvsym_kernel(KmvArgs A, SymPlan P) {
       stage(buf, std::true_type{});
       Ip = Ic;
       Jp = Jc;
+      rp = rcur;
     } else {
       stage(buf, std::false_type{});
     }
     advance(tc, Ic, Jc);
+    rcur = ring_next(rcur);
     if (k + 1 < L && Ic != Icur) load_rows(Ic);
     __syncthreads();
   }
-  if (Ip >= 0) flush_cols((int)((L - 1) & 1), Ip, Jp);
+  if (Ip >= 0) flush_cols((int)((L - 1) & 1), rp, Ip, Jp);
   flush_rows();
+  if (wp) sym_pap_store(papl, A.pap + b);
 }
 
 // ---------------------------------------------------------------------------
@@ -646,13 +704,22 @@ template <int DP>
 __global__ __launch_bounds__(512) void kmvsym64_kernel(KmvArgs A, SymPlan P) {
   constexpr int CT = kSymCols / 16;   // column tiles per stage
   __shared__ double colbuf[2][8 * kSymCols];
+  // p^T A p partials (A.pap set): p of the columns of the pending stage and
+  // one running sum per thread
+  __shared__ double pdl[2][kSymCols];
+  __shared__ double papl[512];
   if (A.S != nullptr && A.S->done) return;
   const int64_t b = blockIdx.x;
   if (A.pcg_step && b == 0 && threadIdx.x == 0) A.S->kcur += 1;
   const int64_t s0 = P.T * b / P.grid, s1 = P.T * (b + 1) / P.grid;
-  if (s0 >= s1) return;
+  const bool wp = A.pap != nullptr;
+  if (s0 >= s1) {
+    if (wp && threadIdx.x == 0) A.pap[b] = 0.0;
+    return;
+  }
   const int64_t L = s1 - s0;
   const int tid = threadIdx.x;
+  if (wp) papl[tid] = 0.0;
   const int lane = tid & 63, wv = tid >> 6;
   const int h = lane >> 4, c = lane & 15;
   const int64_t n = A.n;
@@ -708,11 +775,22 @@ __global__ __launch_bounds__(512) void kmvsym64_kernel(KmvArgs A, SymPlan P) {
         v4[r] = v;
       }
       if (c < 4) {
-        double v = 0.0;
+        double v = 0.0, pr = 0.0;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) v = (r == c) ? v4[r] : v;
+        for (int r = 0; r < 4; ++r) {
+          v = (r == c) ? v4[r] : v;
+          pr = (r == c) ? rw[rt][r] : pr;
+        }
         const int64_t row = Icur * kSymRows + wv * 32 + rt * 16 + 4 * c + h;
-        if (row < n) part[slot * n + row] = v;
+        if (row < n) {
+          part[slot * n + row] = v;
+          if (wp) {
+            // the block holding the row block's diagonal stage adds lam p_i^2
+            double s = fma(pr, v, papl[tid]);
+            if (slot == 0) s = fma(A.lam * pr, pr, s);
+            papl[tid] = s;
+          }
+        }
       }
     }
   };
@@ -722,7 +800,10 @@ __global__ __launch_bounds__(512) void kmvsym64_kernel(KmvArgs A, SymPlan P) {
       double v = 0.0;
 #pragma unroll
       for (int w = 0; w < 8; ++w) v += colbuf[buf][w * kSymCols + tid];
-      if (col < n) part[(P.rs + I) * n + col] = v;
+      if (col < n) {
+        part[(P.rs + I) * n + col] = v;
+        if (wp) papl[tid] = fma(pdl[buf][tid], v, papl[tid]);
+      }
     }
   };
 
@@ -775,6 +856,7 @@ __global__ __launch_bounds__(512) void kmvsym64_kernel(KmvArgs A, SymPlan P) {
         g += __shfl_xor(g, 16, 64);
         g += __shfl_xor(g, 32, 64);
         if (h == 0) colbuf[buf][wv * kSymCols + ct * 16 + c] = g;
+        if (wp && wv == 0 && h == 0) pdl[buf][ct * 16 + c] = pcur;
       }
       if (more) {
         bcur = bnext;
@@ -790,6 +872,7 @@ __global__ __launch_bounds__(512) void kmvsym64_kernel(KmvArgs A, SymPlan P) {
   }
   if (Ip >= 0) flush_cols((int)((L - 1) & 1), Ip, Jp);
   flush_rows();
+  if (wp) sym_pap_store(papl, A.pap + b);
 }
 
 // ---------------------------------------------------------------------------
@@ -1055,6 +1138,8 @@ hipError_t kmv_run(int prec, int dp, const KmvPlan& pl, KmvArgs A, hipStream_t s
   A.cps = pl.cols_per_split;
   A.nsplit = pl.nsplit;
   A.ps = part_sum(pl);
+  // the p^T A p partials are formed by the symmetric kernels only
+  if (A.pap != nullptr && !pl.sym) return hipErrorInvalidValue;
   hipError_t e;
   if (pl.sym) {
     // the symmetric schedule covers the square self-product only

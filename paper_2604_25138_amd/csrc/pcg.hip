@@ -64,11 +64,13 @@ template <int KIND>
 __global__ __launch_bounds__(kThreads) void pcg_update_kernel(double* __restrict__ alpha, double* __restrict__ r,
                                                               const double* __restrict__ p,
                                                               const double* __restrict__ Ap,
+                                                              const double* __restrict__ part, PartSum ps, double lam,
                                                               const double* __restrict__ dinv,
                                                               double* __restrict__ theta, int64_t n, PcgScalars* S,
                                                               const double* __restrict__ pap_p, int gp,
                                                               double* __restrict__ rrp, double* __restrict__ rzp) {
-  pcg_update_body<KIND>(blockIdx.x, gridDim.x, alpha, r, p, Ap, dinv, theta, n, S, pap_p, gp, rrp, rzp);
+  pcg_update_body<KIND>(blockIdx.x, gridDim.x, alpha, r, p, Ap, part, ps, lam, dinv, theta, n, S, pap_p, gp, rrp,
+                        rzp);
 }
 
 template <int KIND>
@@ -97,11 +99,13 @@ template <typename MT>
 __global__ __launch_bounds__(kThreads) void pcg_update_t_kernel(double* __restrict__ alpha,
                                                                 double* __restrict__ r, const double* __restrict__ p,
                                                                 const double* __restrict__ Ap,
+                                                                const double* __restrict__ part, PartSum ps,
+                                                                double lam,
                                                                 const MT* __restrict__ B, int nrp, int64_t n,
                                                                 PcgScalars* S, const double* __restrict__ pap_p,
                                                                 int gp, double* __restrict__ rrp,
                                                                 double* __restrict__ tpart) {
-  pcg_update_t_body<MT>(blockIdx.x, gridDim.x, alpha, r, p, Ap, B, nrp, n, S, pap_p, gp, rrp, tpart);
+  pcg_update_t_body<MT>(blockIdx.x, gridDim.x, alpha, r, p, Ap, part, ps, lam, B, nrp, n, S, pap_p, gp, rrp, tpart);
 }
 
 __global__ __launch_bounds__(kThreads) void lr_t_finish_kernel(const double* __restrict__ tpart, int nb, int nrp,
@@ -285,6 +289,16 @@ laker_status pcg_run(const Problem& pb, const SolveWs& ws, const PrecondView& P,
   Ak.mode = 0;
   Ak.S = S;
   Ak.pcg_step = 1;
+  // a symmetric product forms p^T A p itself and the step update adds each
+  // row's partials (no separate pass for A p); else a pass finishes A p and
+  // its p^T A p partials
+  const PartSum ps = part_sum(pl);
+  const double* Apu = pl.sym ? nullptr : Ap;
+  const int gp = pl.sym ? pl.sp.grid : g;
+  if (pl.sym) {
+    Ak.pap = ws.papp;
+    Ak.lam = pb.lambda;
+  }
   const int nbt = (int)((n + kTRows - 1) / kTRows);
   // one PCG iteration; every argument is fixed, the iteration index lives on the device
   // profiling: a pair of events around each kernel product (eager launches only)
@@ -303,25 +317,29 @@ laker_status pcg_run(const Problem& pb, const SolveWs& ws, const PrecondView& P,
     } else {
       LK_TRY(kmv_run(prec, pb.dp, pl, Ak, s2));
     }
-    pcg_ap_kernel<<<g, kThreads, 0, s2>>>(p, ws.part, part_sum(pl), Ap, n, pb.lambda, ws.papp, S);
-    LK_CHECK_LAUNCH();
+    if (!pl.sym) {
+      pcg_ap_kernel<<<g, kThreads, 0, s2>>>(p, ws.part, ps, Ap, n, pb.lambda, ws.papp, S);
+      LK_CHECK_LAUNCH();
+    }
     if (P.kind == LAKER_PRECOND_JACOBI) {
-      pcg_update_kernel<LAKER_PRECOND_JACOBI><<<g, kThreads, 0, s2>>>(alpha, r, p, Ap, dinv, th, n, S, ws.papp, g,
-                                                                      ws.rrp, ws.rzp);
+      pcg_update_kernel<LAKER_PRECOND_JACOBI><<<g, kThreads, 0, s2>>>(alpha, r, p, Apu, ws.part, ps, pb.lambda, dinv,
+                                                                      th, n, S, ws.papp, gp, ws.rrp, ws.rzp);
       LK_CHECK_LAUNCH();
       pcg_pupdate_kernel<LAKER_PRECOND_JACOBI><<<g, kThreads, 0, s2>>>(0, th, p, n, S, ws.rrp, g, ws.rzp, g);
     } else if (P.kind == LAKER_PRECOND_NONE) {
-      pcg_update_kernel<LAKER_PRECOND_NONE><<<g, kThreads, 0, s2>>>(alpha, r, p, Ap, nullptr, th, n, S, ws.papp, g,
-                                                                    ws.rrp, ws.rzp);
+      pcg_update_kernel<LAKER_PRECOND_NONE><<<g, kThreads, 0, s2>>>(alpha, r, p, Apu, ws.part, ps, pb.lambda, nullptr,
+                                                                    th, n, S, ws.papp, gp, ws.rrp, ws.rzp);
       LK_CHECK_LAUNCH();
       pcg_pupdate_kernel<LAKER_PRECOND_NONE><<<g, kThreads, 0, s2>>>(0, r, p, n, S, ws.rrp, g, ws.rzp, g);
     } else {
       if (P.f32)
-        pcg_update_t_kernel<float><<<nbt, kThreads, 0, s2>>>(alpha, r, p, Ap, (const float*)P.B, P.nrp, n, S,
-                                                             ws.papp, g, ws.rrp, ws.tpart);
+        pcg_update_t_kernel<float><<<nbt, kThreads, 0, s2>>>(alpha, r, p, Apu, ws.part, ps, pb.lambda,
+                                                             (const float*)P.B, P.nrp, n, S, ws.papp, gp, ws.rrp,
+                                                             ws.tpart);
       else
-        pcg_update_t_kernel<double><<<nbt, kThreads, 0, s2>>>(alpha, r, p, Ap, (const double*)P.B, P.nrp, n, S,
-                                                              ws.papp, g, ws.rrp, ws.tpart);
+        pcg_update_t_kernel<double><<<nbt, kThreads, 0, s2>>>(alpha, r, p, Apu, ws.part, ps, pb.lambda,
+                                                              (const double*)P.B, P.nrp, n, S, ws.papp, gp, ws.rrp,
+                                                              ws.tpart);
       LK_CHECK_LAUNCH();
       laker_status e = enqueue_lowrank_any(P, r, th, n, S, ws.rrp, nbt, ws.rzp, ws.tpart, ws.t, true, s2);
       if (e != LAKER_OK) return e;

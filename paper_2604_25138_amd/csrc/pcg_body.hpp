@@ -92,10 +92,14 @@ __device__ __forceinline__ void pcg_ap_body(int blk, int nblk, const double* __r
 
 // delta = r^T theta / p^T A p; alpha += delta p; r -= delta Ap (Alg. 1);
 // partials of ||r||^2 and, for Jacobi, theta = r / diag and r^T theta.
+// Ap null: the product was symmetric, its kernel wrote the p^T A p partials,
+// and Ap_i = lam p_i + the product's partials of row i is formed here.
 template <int KIND>
 __device__ __forceinline__ void pcg_update_body(int blk, int nblk, double* __restrict__ alpha, double* __restrict__ r,
                                                               const double* __restrict__ p,
                                                               const double* __restrict__ Ap,
+                                                              const double* __restrict__ part, const PartSum& ps,
+                                                              double lam,
                                                               const double* __restrict__ dinv,
                                                               double* __restrict__ theta, int64_t n, PcgScalars* S,
                                                               const double* __restrict__ pap_p, int gp,
@@ -115,8 +119,10 @@ __device__ __forceinline__ void pcg_update_body(int blk, int nblk, double* __res
   }
   double rr = 0.0, rz = 0.0;
   for (int64_t i = (int64_t)blk * kThreads + threadIdx.x; i < n; i += (int64_t)nblk * kThreads) {
-    alpha[i] = fma(dl, p[i], alpha[i]);
-    const double ri = fma(-dl, Ap[i], r[i]);
+    const double pi = p[i];
+    const double a = Ap != nullptr ? Ap[i] : fma(lam, pi, ps.row(part, n, i));
+    alpha[i] = fma(dl, pi, alpha[i]);
+    const double ri = fma(-dl, a, r[i]);
     r[i] = ri;
     rr += ri * ri;
     if (KIND == LAKER_PRECOND_JACOBI) {
@@ -262,10 +268,14 @@ __device__ __forceinline__ void lr_t_partial_body(int blk, int nblk, const MT* _
 // b owns rows [64 b, 64 b + 64): delta from the p^T A p partials, alpha += delta p,
 // r -= delta Ap, the ||r||^2 partial, and t_b = B[rows]^T r[rows] from the
 // fresh r kept in LDS.  The stopping decision is taken by the next pass.
+// Ap null: as in pcg_update_body, with the block's four waves adding every
+// fourth partial of the 64 rows (coalesced rows of the partial buffer).
 template <typename MT>
 __device__ __forceinline__ void pcg_update_t_body(int blk, int nblk, double* __restrict__ alpha,
                                                                 double* __restrict__ r, const double* __restrict__ p,
                                                                 const double* __restrict__ Ap,
+                                                                const double* __restrict__ part, const PartSum& ps,
+                                                                double lam,
                                                                 const MT* __restrict__ B, int nrp, int64_t n,
                                                                 PcgScalars* S, const double* __restrict__ pap_p,
                                                                 int gp, double* __restrict__ rrp,
@@ -287,13 +297,23 @@ __device__ __forceinline__ void pcg_update_t_body(int blk, int nblk, double* __r
     S->delta = dl;
   }
   const int64_t i0 = (int64_t)blk * kTRows;
+  __shared__ double apq[kThreads / kTRows][kTRows];
+  if (Ap == nullptr) {
+    const int64_t i = i0 + (tid % kTRows);
+    apq[tid / kTRows][tid % kTRows] = i < n ? ps.row_strided(part, n, i, tid / kTRows, kThreads / kTRows) : 0.0;
+    __syncthreads();
+  }
   double rr = 0.0;
   if (tid < kTRows) {
     const int64_t i = i0 + tid;
     double ri = 0.0;
     if (i < n) {
-      alpha[i] = fma(dl, p[i], alpha[i]);
-      ri = fma(-dl, Ap[i], r[i]);
+      const double pi = p[i];
+      static_assert(kThreads / kTRows == 4, "four partial sums per row");
+      const double a = Ap != nullptr ? Ap[i]
+                                     : fma(lam, pi, (apq[0][tid] + apq[1][tid]) + (apq[2][tid] + apq[3][tid]));
+      alpha[i] = fma(dl, pi, alpha[i]);
+      ri = fma(-dl, a, r[i]);
       r[i] = ri;
     }
     rs[tid] = ri;
