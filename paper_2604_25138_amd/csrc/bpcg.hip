@@ -75,8 +75,8 @@ __global__ __launch_bounds__(kThreads) void b_update_t_kernel(const BDesc* __res
   const BDesc& d = D[R[blockIdx.y]];
   if ((int)blockIdx.x >= d.nbt) return;
   const PartSum ps = d.ps;
-  pcg_update_t_body<MT>(blockIdx.x, d.nbt, d.x, d.r, d.p, ps.sym ? nullptr : d.Ap, d.part, ps, d.lam, (const MT*)d.B,
-                        d.nrp, d.n, d.S, d.papp, ps.sym ? ps.sp.grid : d.g, d.rrp, d.tpart);
+  pcg_update_t_body<MT>(blockIdx.x, d.nbt, d.x, d.r, d.p, ps.sym ? d.th : nullptr, ps.sym ? nullptr : d.Ap, d.part, ps,
+                        d.lam, (const MT*)d.B, d.nrp, d.n, d.S, d.papp, ps.sym ? ps.sp.grid : d.g, d.rrp, d.tpart);
 }
 
 template <typename MT>
@@ -110,6 +110,8 @@ template <int KIND>
 __global__ __launch_bounds__(kThreads) void b_pupdate_kernel(const BDesc* __restrict__ D, const int* __restrict__ R, int init, int masked) {
   const BDesc& d = D[R[blockIdx.y]];
   if ((masked && !d.active) || (int)blockIdx.x >= d.g) return;
+  // low-rank maps with a symmetric product conjugate inside the product kernel
+  if (KIND == LAKER_PRECOND_CCCP && d.ps.sym) return;
   const double* src = KIND == LAKER_PRECOND_NONE ? d.r : d.th;
   const int grz = KIND == LAKER_PRECOND_CCCP ? d.ga : d.g;
   pcg_pupdate_body<KIND>(blockIdx.x, d.g, init, src, d.p, d.n, d.S, d.rrp, d.g, d.rzp, grz);
@@ -405,6 +407,11 @@ laker_status pcg_batch(int count, const Problem* pbs, const SolveWs* wss, const 
           hd[b].ps = part_sum(sq_in[b]);
           A.pap = wss[b].papp;
           A.lam = pbs[b].lambda;
+          if (lowrank) {
+            A.theta = wss[b].theta;
+            A.rzp = wss[b].rzp;
+            A.grz = hd[b].ga;
+          }
         } else {
           use[b] = in_list[b];
           pl[b] = plan_for(pbs[b].n, pq, pq == prec ? cps_map[b] : 0);

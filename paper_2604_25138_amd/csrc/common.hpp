@@ -38,6 +38,11 @@ struct PcgScalars {
   int max_iter;
   int done;         // 0 running, 1 converged, 2 breakdown, 3 iteration cap
   int kcur;         // iterations started: the product launch of iteration k sets it to k + 1
+  // conjugation inside the product kernel (symmetric product, low-rank
+  // preconditioner): r^T theta of the previous iteration, and 1 until the
+  // first step update of a (re)started solve (beta = 0)
+  double rzold;
+  int first;
   unsigned cnt[8];  // arrival counters of the grid reductions (kept at zero between uses)
 };
 

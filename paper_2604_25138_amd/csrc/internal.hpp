@@ -169,6 +169,15 @@ struct KmvArgs {
   // of  p^T (lam I + G) p  = sum_i p_i (lam p_i + partials of row i), the
   // curvature of a CG step, taken from the partial sums as they are written
   double* pap;
+  // symmetric schedule inside PCG with a low-rank preconditioner (null: p is
+  // used as given): the kernel uses the conjugated direction theta + beta p,
+  // formed on the fly with beta = (sum of the grz <= 1024 partials rzp of
+  // r^T theta) / S->rzold (0 while S->first); block 0 records beta and the
+  // new r^T theta in S.  p itself is left unchanged (the step update stores
+  // the new direction after this launch).
+  const double* theta;
+  const double* rzp;
+  int grz;
 };
 hipError_t kmv_run(int prec, int dp, const KmvPlan& pl, KmvArgs A, hipStream_t st);
 

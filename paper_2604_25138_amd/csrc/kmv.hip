@@ -370,6 +370,41 @@ __device__ __forceinline__ void sym_pap_store(double* papl, double* out) {
   }
 }
 
+// Inputs of the on-the-fly conjugation (A.theta set), loaded at kernel entry
+// so that their latency overlaps the first key-row fetches: this thread's two
+// r^T theta partials (entries tid and tid + 512 of at most 1024; the index is
+// clamped and the value masked when summed) and S->first / S->rzold.
+struct ConjIn {
+  double a, c, rzold;
+  int first;
+};
+__device__ __forceinline__ ConjIn sym_conj_issue(const KmvArgs& A) {
+  ConjIn r{0.0, 0.0, 0.0, 1};
+  if (A.theta == nullptr) return r;
+  const int t = threadIdx.x, g = A.grz;
+  r.a = A.rzp[t < g ? t : g - 1];
+  r.c = A.rzp[t + 512 < g ? t + 512 : g - 1];
+  r.rzold = A.S->rzold;
+  r.first = A.S->first;
+  return r;
+}
+// beta = r^T theta / S->rzold (0 while S->first), the same in every block
+// (fixed-order sum over the 512-thread block); block 0 records beta and the
+// new r^T theta (slot kcur & 1, read by the step update).  Called before kcur
+// advances.
+__device__ __forceinline__ double sym_conj_finish(const KmvArgs& A, const ConjIn& in, int64_t b) {
+  if (A.theta == nullptr) return 0.0;
+  __shared__ double sh[16];
+  const int t = threadIdx.x, g = A.grz;
+  const double rz = block_sum((t < g ? in.a : 0.0) + (t + 512 < g ? in.c : 0.0), sh);
+  const double beta = in.first ? 0.0 : rz / in.rzold;
+  if (b == 0 && t == 0) {
+    A.S->rzbuf[A.S->kcur & 1] = rz;
+    A.S->beta = beta;
+  }
+  return beta;
+}
+
 template <int PREC, int DP>
 struct SymStage {
   using ET = typename std::conditional<PREC == LAKER_F32, float, uint16_t>::type;
@@ -380,7 +415,7 @@ struct SymStage {
   static constexpr int CHUNKS = KT * ROWB / 16;
   static constexpr int STAGERS = 256;  // threads (waves 0-3) that move the key rows
   static constexpr int PER_T = (CHUNKS + STAGERS - 1) / STAGERS;
-  static constexpr int BYTES = KT * PITCH + KT * 4;
+  static constexpr int BYTES = KT * PITCH + KT * 4;   // key rows, float32 column weights
   static constexpr int CPITCH = 160;   // column-sum rows: wave-halves alternate bank halves
 };
 
@@ -397,23 +432,25 @@ __global__ __launch_bounds__(512) void kmvsym_kernel(KmvArgs A, SymPlan P) {
   __shared__ double pdl[3][KT];
   __shared__ double prl[512];
   __shared__ double papl[512];
+  const ConjIn cin = sym_conj_issue(A);
   if (A.S != nullptr && A.S->done) return;
   const int64_t b = blockIdx.x;
-  if (A.pcg_step && b == 0 && threadIdx.x == 0) A.S->kcur += 1;
+  // direction entry j: p_j, or theta_j + beta p_j when conjugating (beta is
+  // known once the first key-row fetch has been issued)
+  const double* __restrict__ th = A.theta;
+  const double* __restrict__ p = A.p;
+  double beta = 0.0;
+  auto pval = [&](int64_t j) { return th != nullptr ? fma(beta, p[j], th[j]) : p[j]; };
+  // (s0 < T for every block: the cursor and first fetches below stay in range
+  // also for a block without stages)
   const int64_t s0 = P.T * b / P.grid, s1 = P.T * (b + 1) / P.grid;
   const bool wp = A.pap != nullptr;
-  if (s0 >= s1) {
-    if (wp && threadIdx.x == 0) A.pap[b] = 0.0;
-    return;
-  }
   const int64_t L = s1 - s0;
   const int tid = threadIdx.x;
-  if (wp) papl[tid] = 0.0;
   const int lane = tid & 63, wv = tid >> 6;
   const int h = lane >> 5, c = lane & 31;
   const int64_t n = A.n;
   const int64_t ncs = P.ncs;
-  const double* __restrict__ p = A.p;
   const ET* __restrict__ Q = reinterpret_cast<const ET*>(A.K);
   const unsigned char* __restrict__ Kb = reinterpret_cast<const unsigned char*>(A.K);
   double* __restrict__ part = A.part;
@@ -433,7 +470,7 @@ __global__ __launch_bounds__(512) void kmvsym_kernel(KmvArgs A, SymPlan P) {
   // up the column sums: in a stage the second wave of each SIMD (waves 4-7)
   // finishes its tiles last, and waves 0-3 otherwise wait at the barrier.
   const bool stager = tid < St::STAGERS;
-  auto fetch = [&](int64_t J) {
+  auto fetch_keys = [&](int64_t J) {
     const int64_t js = J * KT;
     const unsigned char* sb = Kb + js * St::ROWB;
     if (!stager) {
@@ -456,11 +493,17 @@ __global__ __launch_bounds__(512) void kmvsym_kernel(KmvArgs A, SymPlan P) {
         }
       }
     }
+  };
+  auto fetch_w = [&](int64_t J) {
     if (tid < KT) {
-      const int64_t kj = js + tid;
+      const int64_t kj = J * KT + tid;
       stv = kj < n;
-      stp = p[kj < n ? kj : n - 1];
+      stp = pval(kj < n ? kj : n - 1);
     }
+  };
+  auto fetch = [&](int64_t J) {
+    fetch_keys(J);
+    fetch_w(J);
   };
   auto store = [&](int buf, int ring) {
     if (stager) {
@@ -504,12 +547,12 @@ __global__ __launch_bounds__(512) void kmvsym_kernel(KmvArgs A, SymPlan P) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int64_t row = row0 + (r >> 2) * 8 + h * 4 + (r & 3);
-      rw[r] = row < n ? (float)p[row] : 0.f;
+      rw[r] = row < n ? (float)pval(row) : 0.f;
     }
     if (wp) {
       const int r = c >> 1;
       const int64_t row = row0 + (r >> 2) * 8 + h * 4 + (r & 3);
-      prn = row < n ? p[row] : 0.0;
+      prn = row < n ? pval(row) : 0.0;
     }
   };
   auto open_rows = [&](int64_t I) {
@@ -645,7 +688,15 @@ __global__ __launch_bounds__(512) void kmvsym_kernel(KmvArgs A, SymPlan P) {
   // (iteration s + 1), overwritten by stage s + 3 (iteration s + 2)
   auto ring_next = [](int q) { return q == 2 ? 0 : q + 1; };
   int rcur = 0;
-  fetch(Jf);
+  fetch_keys(Jf);
+  beta = sym_conj_finish(A, cin, b);
+  if (A.pcg_step && b == 0 && tid == 0) A.S->kcur += 1;
+  if (s0 >= s1) {
+    if (wp && tid == 0) A.pap[b] = 0.0;
+    return;
+  }
+  if (wp) papl[tid] = 0.0;
+  fetch_w(Jf);
   advance(tf, If, Jf);
   store(0, 0);
   if (L > 1) {
@@ -708,9 +759,14 @@ __global__ __launch_bounds__(512) void kmvsym64_kernel(KmvArgs A, SymPlan P) {
   // one running sum per thread
   __shared__ double pdl[2][kSymCols];
   __shared__ double papl[512];
+  const ConjIn cin = sym_conj_issue(A);
   if (A.S != nullptr && A.S->done) return;
   const int64_t b = blockIdx.x;
+  const double beta = sym_conj_finish(A, cin, b);
   if (A.pcg_step && b == 0 && threadIdx.x == 0) A.S->kcur += 1;
+  const double* __restrict__ th = A.theta;
+  const double* __restrict__ p = A.p;
+  auto pval = [&](int64_t j) { return th != nullptr ? fma(beta, p[j], th[j]) : p[j]; };
   const int64_t s0 = P.T * b / P.grid, s1 = P.T * (b + 1) / P.grid;
   const bool wp = A.pap != nullptr;
   if (s0 >= s1) {
@@ -724,7 +780,6 @@ __global__ __launch_bounds__(512) void kmvsym64_kernel(KmvArgs A, SymPlan P) {
   const int h = lane >> 4, c = lane & 15;
   const int64_t n = A.n;
   const int64_t ncs = P.ncs, nrb = P.nrb;
-  const double* __restrict__ p = A.p;
   const double* __restrict__ K = reinterpret_cast<const double*>(A.K);
   double* __restrict__ part = A.part;
 
@@ -754,7 +809,7 @@ __global__ __launch_bounds__(512) void kmvsym64_kernel(KmvArgs A, SymPlan P) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t row = row0 + 4 * r + h;
-        rw[rt][r] = row < n ? p[row] : 0.0;
+        rw[rt][r] = row < n ? pval(row) : 0.0;
         acc[rt][r] = 0.0;
       }
     }
@@ -810,19 +865,25 @@ __global__ __launch_bounds__(512) void kmvsym64_kernel(KmvArgs A, SymPlan P) {
   // key tile cursor, one tile ahead of the compute
   int64_t tf = t0, If = I0, Jf = J0;
   int ctf = 0;
+  // (the column's p and theta are loaded raw with the tile one tile ahead and
+  // combined when the tile becomes current, so no load is waited on early)
   FragF64<DP> bcur, bnext;
-  double pcur = 0.0, pnext = 0.0;
-  auto load_tile = [&](FragF64<DP>& bf, double& pj) {
+  double pcur = 0.0, pnext = 0.0, tnext = 0.0;
+  auto load_tile = [&](FragF64<DP>& bf, double& pj, double& tj) {
     int64_t kj = Jf * kSymCols + ctf * 16 + c;
-    pj = kj < n ? p[kj] : 0.0;
+    const bool in = kj < n;
     if (kj > n - 1) kj = n - 1;
+    pj = in ? p[kj] : 0.0;
+    tj = in && th != nullptr ? th[kj] : 0.0;
     bf.load(K, kj, h);
     if (++ctf == CT) {
       ctf = 0;
       advance(tf, If, Jf);
     }
   };
-  load_tile(bcur, pcur);
+  auto comb = [&](double pj, double tj) { return th != nullptr ? fma(beta, pj, tj) : pj; };
+  load_tile(bcur, pnext, tnext);
+  pcur = comb(pnext, tnext);
 
   int64_t tc = t0, Ic = I0, Jc = J0;
   int64_t Ip = -1, Jp = -1;
@@ -840,7 +901,7 @@ __global__ __launch_bounds__(512) void kmvsym64_kernel(KmvArgs A, SymPlan P) {
 #pragma unroll 1
     for (int ct = 0; ct < CT; ++ct) {
       const bool more = k + 1 < L || ct + 1 < CT;
-      if (more) load_tile(bnext, pnext);
+      if (more) load_tile(bnext, pnext, tnext);
       double g = 0.0;
 #pragma unroll
       for (int rt = 0; rt < 2; ++rt) {
@@ -860,7 +921,7 @@ __global__ __launch_bounds__(512) void kmvsym64_kernel(KmvArgs A, SymPlan P) {
       }
       if (more) {
         bcur = bnext;
-        pcur = pnext;
+        pcur = comb(pnext, tnext);
       }
     }
     if (mir) {
@@ -1138,8 +1199,10 @@ hipError_t kmv_run(int prec, int dp, const KmvPlan& pl, KmvArgs A, hipStream_t s
   A.cps = pl.cols_per_split;
   A.nsplit = pl.nsplit;
   A.ps = part_sum(pl);
-  // the p^T A p partials are formed by the symmetric kernels only
-  if (A.pap != nullptr && !pl.sym) return hipErrorInvalidValue;
+  // the p^T A p partials and the on-the-fly conjugation belong to the
+  // symmetric kernels inside PCG only
+  if ((A.pap != nullptr || A.theta != nullptr) && !pl.sym) return hipErrorInvalidValue;
+  if (A.theta != nullptr && (A.S == nullptr || !A.pcg_step)) return hipErrorInvalidValue;
   hipError_t e;
   if (pl.sym) {
     // the symmetric schedule covers the square self-product only

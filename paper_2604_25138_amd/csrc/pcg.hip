@@ -97,7 +97,8 @@ __global__ __launch_bounds__(kThreads) void lr_t_partial_kernel(const MT* __rest
 
 template <typename MT>
 __global__ __launch_bounds__(kThreads) void pcg_update_t_kernel(double* __restrict__ alpha,
-                                                                double* __restrict__ r, const double* __restrict__ p,
+                                                                double* __restrict__ r, double* __restrict__ p,
+                                                                const double* __restrict__ theta,
                                                                 const double* __restrict__ Ap,
                                                                 const double* __restrict__ part, PartSum ps,
                                                                 double lam,
@@ -105,7 +106,8 @@ __global__ __launch_bounds__(kThreads) void pcg_update_t_kernel(double* __restri
                                                                 PcgScalars* S, const double* __restrict__ pap_p,
                                                                 int gp, double* __restrict__ rrp,
                                                                 double* __restrict__ tpart) {
-  pcg_update_t_body<MT>(blockIdx.x, gridDim.x, alpha, r, p, Ap, part, ps, lam, B, nrp, n, S, pap_p, gp, rrp, tpart);
+  pcg_update_t_body<MT>(blockIdx.x, gridDim.x, alpha, r, p, theta, Ap, part, ps, lam, B, nrp, n, S, pap_p, gp, rrp,
+                        tpart);
 }
 
 __global__ __launch_bounds__(kThreads) void lr_t_finish_kernel(const double* __restrict__ tpart, int nb, int nrp,
@@ -253,6 +255,10 @@ laker_status pcg_run(const Problem& pb, const SolveWs& ws, const PrecondView& P,
   const void* eh = prepared(ws, prec);
   const KmvPlan pl = kmv_plan_square(n, pb.dp, prec);
   const bool lowrank = P.kind == LAKER_PRECOND_CCCP || P.kind == LAKER_PRECOND_LEARNED;
+  // symmetric product with a low-rank preconditioner: the product kernel
+  // conjugates the direction itself (p = theta + beta p) and the step update
+  // stores it, so the iteration has no separate direction pass
+  const bool fused = lowrank && pl.sym;
   const double* dinv = (const double*)P.dinv;
 
   // r^0 = y - A alpha^0
@@ -281,7 +287,8 @@ laker_status pcg_run(const Problem& pb, const SolveWs& ws, const PrecondView& P,
   } else {
     laker_status e = enqueue_lowrank_any(P, r, th, n, S, nullptr, 0, ws.rzp, ws.tpart, ws.t, false, st);
     if (e != LAKER_OK) return e;
-    pcg_pupdate_kernel<LAKER_PRECOND_CCCP><<<g, kThreads, 0, st>>>(1, th, p, n, S, ws.rrp, g, ws.rzp, ga);
+    // (conjugated: p^0 = theta^0 + 0 p with p = 0 from the start pass)
+    if (!fused) pcg_pupdate_kernel<LAKER_PRECOND_CCCP><<<g, kThreads, 0, st>>>(1, th, p, n, S, ws.rrp, g, ws.rzp, ga);
   }
   LK_CHECK_LAUNCH();
 
@@ -299,6 +306,12 @@ laker_status pcg_run(const Problem& pb, const SolveWs& ws, const PrecondView& P,
     Ak.pap = ws.papp;
     Ak.lam = pb.lambda;
   }
+  if (fused) {
+    Ak.theta = th;
+    Ak.rzp = ws.rzp;
+    Ak.grz = ga;
+  }
+  const double* thu = fused ? th : nullptr;
   const int nbt = (int)((n + kTRows - 1) / kTRows);
   // one PCG iteration; every argument is fixed, the iteration index lives on the device
   // profiling: a pair of events around each kernel product (eager launches only)
@@ -333,17 +346,17 @@ laker_status pcg_run(const Problem& pb, const SolveWs& ws, const PrecondView& P,
       pcg_pupdate_kernel<LAKER_PRECOND_NONE><<<g, kThreads, 0, s2>>>(0, r, p, n, S, ws.rrp, g, ws.rzp, g);
     } else {
       if (P.f32)
-        pcg_update_t_kernel<float><<<nbt, kThreads, 0, s2>>>(alpha, r, p, Apu, ws.part, ps, pb.lambda,
+        pcg_update_t_kernel<float><<<nbt, kThreads, 0, s2>>>(alpha, r, p, thu, Apu, ws.part, ps, pb.lambda,
                                                              (const float*)P.B, P.nrp, n, S, ws.papp, gp, ws.rrp,
                                                              ws.tpart);
       else
-        pcg_update_t_kernel<double><<<nbt, kThreads, 0, s2>>>(alpha, r, p, Apu, ws.part, ps, pb.lambda,
+        pcg_update_t_kernel<double><<<nbt, kThreads, 0, s2>>>(alpha, r, p, thu, Apu, ws.part, ps, pb.lambda,
                                                               (const double*)P.B, P.nrp, n, S, ws.papp, gp, ws.rrp,
                                                               ws.tpart);
       LK_CHECK_LAUNCH();
       laker_status e = enqueue_lowrank_any(P, r, th, n, S, ws.rrp, nbt, ws.rzp, ws.tpart, ws.t, true, s2);
       if (e != LAKER_OK) return e;
-      pcg_pupdate_kernel<LAKER_PRECOND_CCCP><<<g, kThreads, 0, s2>>>(0, th, p, n, S, ws.rrp, g, ws.rzp, ga);
+      if (!fused) pcg_pupdate_kernel<LAKER_PRECOND_CCCP><<<g, kThreads, 0, s2>>>(0, th, p, n, S, ws.rrp, g, ws.rzp, ga);
     }
     LK_CHECK_LAUNCH();
     return LAKER_OK;

@@ -68,6 +68,8 @@ __device__ __forceinline__ void pcg_start_body(int blk, int nblk, PcgScalars* S,
     S->max_iter = max_iter;
     S->beta = 0.0;
     S->kcur = 0;
+    S->rzold = 0.0;
+    S->first = 1;
     S->done = (yy == 0.0 || rr <= tol * tol * yy) ? 1 : 0;
   }
 }
@@ -270,9 +272,13 @@ __device__ __forceinline__ void lr_t_partial_body(int blk, int nblk, const MT* _
 // fresh r kept in LDS.  The stopping decision is taken by the next pass.
 // Ap null: as in pcg_update_body, with the block's four waves adding every
 // fourth partial of the 64 rows (coalesced rows of the partial buffer).
+// theta set: the product kernel of this iteration conjugated the direction on
+// the fly (p = theta + beta p, beta in S); this pass stores that direction in
+// place, with the same arithmetic, and moves r^T theta to S->rzold.
 template <typename MT>
 __device__ __forceinline__ void pcg_update_t_body(int blk, int nblk, double* __restrict__ alpha,
-                                                                double* __restrict__ r, const double* __restrict__ p,
+                                                                double* __restrict__ r, double* __restrict__ p,
+                                                                const double* __restrict__ theta,
                                                                 const double* __restrict__ Ap,
                                                                 const double* __restrict__ part, const PartSum& ps,
                                                                 double lam,
@@ -295,6 +301,10 @@ __device__ __forceinline__ void pcg_update_t_body(int blk, int nblk, double* __r
   if (blk == 0 && tid == 0) {
     S->pap = pap;
     S->delta = dl;
+    if (theta != nullptr) {
+      S->rzold = S->rzbuf[k & 1];
+      S->first = 0;
+    }
   }
   const int64_t i0 = (int64_t)blk * kTRows;
   __shared__ double apq[kThreads / kTRows][kTRows];
@@ -308,7 +318,11 @@ __device__ __forceinline__ void pcg_update_t_body(int blk, int nblk, double* __r
     const int64_t i = i0 + tid;
     double ri = 0.0;
     if (i < n) {
-      const double pi = p[i];
+      double pi = p[i];
+      if (theta != nullptr) {
+        pi = fma(S->beta, pi, theta[i]);
+        p[i] = pi;
+      }
       static_assert(kThreads / kTRows == 4, "four partial sums per row");
       const double a = Ap != nullptr ? Ap[i]
                                      : fma(lam, pi, (apq[0][tid] + apq[1][tid]) + (apq[2][tid] + apq[3][tid]));
