@@ -399,3 +399,78 @@ def test_profiled_flexible_cg_counts_inner_products():
     a2, s2 = L().pcg_solve(prob, pr.y, None, **kw)
     assert s1.status == 0 and torch.equal(a1, a2) and s1.iters == s2.iters
     assert s1.kmv_count == s1.iters and s1.kmv_ms > 0.0 and s2.kmv_count == 0
+
+
+# ---- PCG whose products take the symmetric schedule: the product kernel also
+# forms p^T A p, and with a low-rank preconditioner conjugates the direction
+# itself (the step update adds each row's partials and stores the direction)
+
+_SYM = {}
+
+
+def _sym_case(n):
+    """Problem, Cholesky solution and CCCP directions of one symmetric-path size."""
+    if n not in _SYM:
+        pr = make_problem(n, 16, 1e-3, seed=21)
+        A = O.system_matrix(pr.E, pr.scale, pr.lam)
+        _SYM[n] = (pr, A, O.solve_direct(A, pr.y), make_directions(pr.n, 256, 21))
+    return _SYM[n]
+
+
+def _sym_precond(kind, prob, Z):
+    if kind == "none":
+        return None
+    if kind == "jacobi":
+        return L().jacobi_precond(prob)
+    return L().fit_precond(prob, torch.tensor(Z, device=DEV), gamma=0.1, rho=0.0)
+
+
+@pytest.mark.parametrize("kind", ["none", "jacobi", "cccp"])
+def test_pcg_f64_on_symmetric_schedule(kind):
+    """n = 6000, float64 products on the symmetric schedule: alpha within 1e-8 of
+    the Cholesky solution at tol 1e-10, and (P = I, CCCP) the iteration count of
+    the oracle's PCG with the same preconditioner within 5%."""
+    pr, A, ref, Z = _sym_case(6000)
+    prob = _gp(pr)
+    pc = _sym_precond(kind, prob, Z)
+    alpha, st = L().pcg_solve(prob, pr.y, pc, tol=1e-10, max_iter=20000)
+    assert st.status == 0
+    assert np.linalg.norm(alpha.cpu().numpy() - ref) / np.linalg.norm(ref) <= 1e-8
+    assert st.relres_true <= 2e-10
+    if kind != "jacobi":
+        if kind == "none":
+            apply_p = lambda r: r
+        else:
+            Po, _ = O.fit_precond(pr.E, pr.scale, pr.lam, Z, gamma=0.1, rho=0.0)
+            apply_p = Po.apply
+        _, it_o, _ = O.pcg(lambda v: A @ v, apply_p, pr.y, 1e-10, 20000)
+        assert abs(st.iters - it_o) <= max(3, it_o // 20)
+
+
+@pytest.mark.parametrize("prec,n,kind", [("f32", 6000, "none"), ("f32", 6000, "cccp"), ("bf16", 10037, "none"),
+                                         ("bf16", 10037, "cccp")])
+def test_reduced_precision_pcg_on_symmetric_schedule(prec, n, kind):
+    """float32 (n = 6000) and bfloat16 (n = 10037) inner products on the symmetric
+    schedule inside the float64 flexible outer CG: the float64 true residual
+    reaches 1e-10 and alpha the Cholesky solution to 1e-8."""
+    pr, A, ref, Z = _sym_case(n)
+    prob = _gp(pr)
+    pc = _sym_precond(kind, prob, Z)
+    alpha, st = L().pcg_solve(prob, pr.y, pc, tol=1e-10, max_iter=50000, precision=prec, refine=2,
+                              inner_tol=1e-1, ir_max=1000, check_every=30, inner_max_iter=30)
+    assert st.status == 0 and st.relres_true <= 1e-10
+    assert np.linalg.norm(alpha.cpu().numpy() - ref) / np.linalg.norm(ref) <= 1e-8
+    assert O.relative_residual(A, alpha.cpu().numpy(), pr.y) <= 1e-10
+
+
+def test_graph_replay_matches_eager_on_symmetric_schedule():
+    """The conjugating product kernel inside captured chunks of iterations:
+    bitwise the same iterate as the eagerly enqueued launches."""
+    pr, A, ref, Z = _sym_case(6000)
+    prob = _gp(pr)
+    pc = _sym_precond("cccp", prob, Z)
+    kw = dict(tol=1e-10, max_iter=20000, precision="f32", refine=True, inner_tol=1e-1, check_every=8)
+    a1, s1 = L().pcg_solve(prob, pr.y, pc, graph=True, **kw)
+    _ = L().kernel_matvec(prob, torch.ones(pr.n, dtype=torch.float64, device=DEV))   # eager work in between
+    a2, s2 = L().pcg_solve(prob, pr.y, pc, graph=False, **kw)
+    assert s1.iters == s2.iters and s1.iters > 16 and torch.equal(a1, a2)
