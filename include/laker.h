@@ -121,7 +121,14 @@ typedef struct {
                          on `stream` (eager launches; fills stats->kmv_ms)      */
   int32_t inner_max_iter; /* refinement: cap on the iterations of one inner PCG
                          (0: only max_iter)                                    */
-  int32_t reserved;
+  int32_t materialized; /* 1: G is formed once per call and stored in the
+                         workspace (see laker_kmat_bytes); the float64 products
+                         (outer residuals, float64 PCG) and, with precision
+                         F32, the float32 products then stream it instead of
+                         recomputing it.  Applies where the symmetric product
+                         schedule does (laker_kmat_bytes > 0); bfloat16
+                         products are always recomputed (a rounded stored G
+                         need not be positive definite)                        */
 } laker_pcg_opts;
 
 typedef struct {
@@ -156,6 +163,14 @@ size_t laker_fit_workspace_bytes(int64_t n, int32_t d, int32_t n_r);
 /* Workspace bytes of laker_pcg_solve / laker_kernel_matvec / laker_predict
  * (m query points; pass m = 0 for the solver). */
 size_t laker_solve_workspace_bytes(int64_t n, int32_t d, int64_t m);
+/* Bytes of a stored G = exp(s E E^T) for opts->materialized (the tiles of the
+ * symmetric product schedule on or right of the block diagonal: about
+ * n^2 / 2 entries) in precision F64 or F32; 0 when the size is below the
+ * symmetric schedule's threshold (then nothing is stored).  With
+ * materialized set, laker_pcg_solve needs laker_solve_workspace_bytes(n, d, 0)
+ * + laker_kmat_bytes(n, d, F64) (+ laker_kmat_bytes(n, d, F32) with
+ * precision F32) bytes of workspace. */
+size_t laker_kmat_bytes(int64_t n, int32_t d, int32_t precision);
 
 /* ---- entry points ---------------------------------------------------------- */
 

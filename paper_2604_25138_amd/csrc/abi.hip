@@ -115,6 +115,13 @@ size_t laker_fit_workspace_bytes(int64_t n, int32_t d, int32_t n_r) {
   return plan_fit_ws(nullptr, n, d, n_r).total;
 }
 
+size_t laker_kmat_bytes(int64_t n, int32_t d, int32_t precision) {
+  if (n < 1 || d < 1 || d > 128) return 0;
+  if (precision != LAKER_F64 && precision != LAKER_F32) return 0;
+  if (!kmat_applies(n, pad_dim(d))) return 0;
+  return kmat_bytes(n, precision);
+}
+
 size_t laker_solve_workspace_bytes(int64_t n, int32_t d, int64_t m) {
   if (n < 1 || d < 1 || d > kMaxD || m < 0) return 0;
   return plan_solve_ws(nullptr, n, d, m).total;
@@ -195,8 +202,26 @@ laker_status laker_pcg_solve(const laker_problem* prob, const laker_precond* pre
   PrecondView view{};
   e = make_view(precond, prob->n, opts->precision, &view);
   if (e != LAKER_OK) return e;
+  if (opts->materialized < 0 || opts->materialized > 1) return LAKER_EINVAL;
   SolveWs W = plan_solve_ws(workspace, prob->n, prob->d, 0);
   if (workspace_bytes < W.total) return LAKER_ENOMEM;
+  // stored G after the carved workspace (float64; float32 too for float32 products)
+  if (opts->materialized) {
+    const size_t b64 = laker_kmat_bytes(prob->n, prob->d, LAKER_F64);
+    if (b64 > 0) {
+      size_t need = ((W.total + 255) & ~size_t(255)) + b64;
+      const size_t off64 = need - b64;
+      size_t off32 = 0;
+      if (opts->precision == LAKER_F32) {
+        const size_t b32 = laker_kmat_bytes(prob->n, prob->d, LAKER_F32);
+        off32 = (need + 255) & ~size_t(255);
+        need = off32 + b32;
+      }
+      if (workspace_bytes < need) return LAKER_ENOMEM;
+      W.kmat64 = (char*)workspace + off64;
+      if (off32 > 0) W.kmat32 = (char*)workspace + off32;
+    }
+  }
   Problem pb = to_problem(prob);
   hipStream_t st = (hipStream_t)stream;
   laker_stats local{};
@@ -218,6 +243,8 @@ laker_status laker_pcg_solve(const laker_problem* prob, const laker_precond* pre
     LK_TRY(prep_embed(pb.E, pb.n, pb.d, pb.dp, pb.scale, LAKER_F32, W.e32, st));
   else if (opts->precision == LAKER_BF16)
     LK_TRY(prep_embed(pb.E, pb.n, pb.d, pb.dp, pb.scale, LAKER_BF16, W.e16, st));
+  if (W.kmat64 != nullptr) LK_TRY(kmat_build(pb.dp, W.e64, pb.n, LAKER_F64, W.kmat64, st));
+  if (W.kmat32 != nullptr) LK_TRY(kmat_build(pb.dp, W.e64, pb.n, LAKER_F32, W.kmat32, st));
   laker_status r;
   if (!opts->refine) {
     r = pcg_run(pb, W, view, y, alpha, opts->warm_start != 0, opts->tol, opts->max_iter, check, opts->precision,

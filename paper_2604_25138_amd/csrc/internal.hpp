@@ -178,8 +178,21 @@ struct KmvArgs {
   const double* theta;
   const double* rzp;
   int grz;
+  // stored kernel matrix of this product's precision (float64 or float32
+  // tiles of the symmetric schedule, see kmat_build); null: recomputed
+  const void* kmat;
 };
 hipError_t kmv_run(int prec, int dp, const KmvPlan& pl, KmvArgs A, hipStream_t st);
+
+// Stored kernel matrix for square products that take the symmetric schedule
+// (kmat_applies): the schedule's stage tiles, 256 x 128 row-major each, in
+// stage order, entries exp(s <e_i, e_j>) computed as the float64 kernel does
+// and stored as float64 (prec F64) or rounded to float32 (prec F32); entries
+// outside n x n are zero.  kmat_bytes: its size; kmat_build: fill it from the
+// float64 prepared embeddings e64 (dp columns).
+bool kmat_applies(int64_t n, int dp);
+size_t kmat_bytes(int64_t n, int prec);
+hipError_t kmat_build(int dp, const double* e64, int64_t n, int prec, void* out, hipStream_t st);
 
 // Products of several problems in one launch: block b computes tile
 // (problem, row block, column range) = tiles_dev[3 b .. 3 b + 2] with the

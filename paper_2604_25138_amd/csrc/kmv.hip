@@ -1070,6 +1070,250 @@ hipError_t launch64_batch(int dp, unsigned ntiles, const KmvArgs* As, const int*
   return hipGetLastError();
 }
 
+
+// ---------------------------------------------------------------------------
+// Stored kernel matrix.  HBM is plentiful (the tiles on or right of the block
+// diagonal take 1.09 GB in float64 at n = 16384, of 288 GB), and a product
+// that streams them is bound by HBM instead of by the float64 MFMA and exp.
+// Layout: the stage list of the symmetric schedule, stage s as one 256 x 128
+// row-major tile at s * kSymRows * kSymCols, entries outside n x n zero.
+// kmat_build_kernel writes the float64 entries of the fused float64 kernel
+// (same fragments, MFMA and exp), rounded to the storage type; the product
+// kernel reads them with the symmetric kernel's block runs and partial-sum
+// layout, so the finishing pass and the PCG passes are shared.
+// ---------------------------------------------------------------------------
+constexpr int64_t kTileElems = (int64_t)kSymRows * kSymCols;
+
+template <int DP, typename OT>
+__global__ __launch_bounds__(512) void kmat_build_kernel(const double* __restrict__ K, int64_t n, SymPlan P,
+                                                         OT* __restrict__ out) {
+  constexpr int CT = kSymCols / 16;
+  const int64_t b = blockIdx.x;
+  const int64_t s0 = P.T * b / P.grid, s1 = P.T * (b + 1) / P.grid;
+  if (s0 >= s1) return;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int h = lane >> 4, c = lane & 15;
+  const int64_t ncs = P.ncs, nrb = P.nrb;
+  int64_t t = 0;
+  while (sym_pos_start(t + 1, nrb, ncs) <= s0) ++t;
+  int64_t I = sym_rowblock_at(t, nrb);
+  int64_t J = 2 * I + (s0 - sym_pos_start(t, nrb, ncs));
+  // key tile cursor one tile ahead of the compute (as the fused kernel)
+  int64_t tf = t, If = I, Jf = J;
+  int ctf = 0;
+  FragF64<DP> a[2], bcur, bnext;
+  auto load_tile = [&](FragF64<DP>& bf) {
+    int64_t kj = Jf * kSymCols + ctf * 16 + c;
+    if (kj > n - 1) kj = n - 1;
+    bf.load(K, kj, h);
+    if (++ctf == CT) {
+      ctf = 0;
+      if (++Jf == ncs) {
+        ++tf;
+        If = sym_rowblock_at(tf, nrb);
+        Jf = 2 * If;
+      }
+    }
+  };
+  load_tile(bcur);
+  int64_t Icur = -1;
+  for (int64_t s = s0; s < s1; ++s) {
+    if (I != Icur) {
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt) {
+        int64_t qi = I * kSymRows + wv * 32 + rt * 16 + c;
+        if (qi > n - 1) qi = n - 1;
+        a[rt].load(K, qi, h);
+      }
+      Icur = I;
+    }
+    OT* tile = out + s * kTileElems;
+#pragma unroll 1
+    for (int ct = 0; ct < CT; ++ct) {
+      const bool more = s + 1 < s1 || ct + 1 < CT;
+      if (more) load_tile(bnext);
+      const bool cin = J * kSymCols + ct * 16 + c < n;
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt) {
+        const v4d sc = tile_f64<DP>(a[rt], bcur);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int lr = wv * 32 + rt * 16 + 4 * r + h;
+          const bool in = cin && I * kSymRows + lr < n;
+          tile[(int64_t)lr * kSymCols + ct * 16 + c] = in ? (OT)exp(sc[r]) : (OT)0;
+        }
+      }
+      if (more) bcur = bnext;
+    }
+    if (++J == ncs) {
+      ++t;
+      I = sym_rowblock_at(t, nrb);
+      J = 2 * I;
+    }
+  }
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const long long u = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(u & 0xffffffffll), l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(u >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+template <typename ET> struct Pair2;
+template <> struct Pair2<double> { using type = double2; };
+template <> struct Pair2<float> { using type = float2; };
+
+// w = G p from the stored tiles (float64 products of the stored entries,
+// float64 sums).  Block runs, row slots and column slots as the symmetric
+// kernels.  A wave owns 32 rows of the stage's tile and a lane two adjacent
+// columns, so every load instruction reads one whole tile row; the rows are
+// read in two halves of 16, the next half always in flight.  Row sums stay
+// per lane across the stages of a row block and leave the lanes by a halving
+// exchange when it changes; off-diagonal stages also add K^T p_rows into the
+// stage's columns (per lane over the wave's rows, then the eight waves in LDS
+// in a fixed order, flushed after the stage's barrier).
+template <typename ET>
+__global__ __launch_bounds__(512) void kmat_matvec_kernel(KmvArgs A, SymPlan P) {
+  using E2 = typename Pair2<ET>::type;
+  __shared__ double colbuf[2][8 * kSymCols];
+  if (A.S != nullptr && A.S->done) return;
+  const int64_t b = blockIdx.x;
+  if (A.pcg_step && b == 0 && threadIdx.x == 0) A.S->kcur += 1;
+  const int64_t s0 = P.T * b / P.grid, s1 = P.T * (b + 1) / P.grid;
+  if (s0 >= s1) return;
+  const int64_t L = s1 - s0;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int64_t n = A.n;
+  const int64_t ncs = P.ncs, nrb = P.nrb;
+  const double* __restrict__ p = A.p;
+  double* __restrict__ part = A.part;
+  const ET* __restrict__ Kt = reinterpret_cast<const ET*>(A.kmat);
+
+  int64_t t0 = 0;
+  while (sym_pos_start(t0 + 1, nrb, ncs) <= s0) ++t0;
+  const int64_t I0 = sym_rowblock_at(t0, nrb);
+  const int64_t J0 = 2 * I0 + (s0 - sym_pos_start(t0, nrb, ncs));
+  auto advance = [&](int64_t& t, int64_t& I, int64_t& J) {
+    if (++J == ncs) {
+      ++t;
+      I = sym_rowblock_at(t, nrb);
+      J = 2 * I;
+    }
+  };
+  auto load_half = [&](int64_t s, int half, E2 (&v)[16]) {
+    const ET* base = Kt + s * kTileElems + (int64_t)(wv * 32 + half * 16) * kSymCols + 2 * lane;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = *reinterpret_cast<const E2*>(base + r * kSymCols);
+  };
+  auto load_w = [&](int64_t J, double& w0, double& w1) {
+    const int64_t c0 = J * kSymCols + 2 * lane;
+    w0 = c0 < n ? p[c0] : 0.0;
+    w1 = c0 + 1 < n ? p[c0 + 1] : 0.0;
+  };
+
+  double accr[32];
+  double prow = 0.0;
+  int64_t Icur = -1;
+  auto open_rows = [&](int64_t I) {
+#pragma unroll
+    for (int r = 0; r < 32; ++r) accr[r] = 0.0;
+    const int64_t row = I * kSymRows + wv * 32 + (lane & 31);
+    prow = row < n ? p[row] : 0.0;
+    Icur = I;
+  };
+  // halving exchange: lane l ends with row (l >> 1) & 31 of the wave's rows
+  auto flush_rows = [&]() {
+    double v16[16], v8[8], v4[4], v2[2];
+    const bool b5 = (lane & 32) != 0, b4 = (lane & 16) != 0, b3 = (lane & 8) != 0, b2 = (lane & 4) != 0,
+               b1 = (lane & 2) != 0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) v16[j] = (b5 ? accr[j + 16] : accr[j]) + __shfl_xor(b5 ? accr[j] : accr[j + 16], 32, 64);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v8[j] = (b4 ? v16[j + 8] : v16[j]) + __shfl_xor(b4 ? v16[j] : v16[j + 8], 16, 64);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v4[j] = (b3 ? v8[j + 4] : v8[j]) + __shfl_xor(b3 ? v8[j] : v8[j + 4], 8, 64);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) v2[j] = (b2 ? v4[j + 2] : v4[j]) + __shfl_xor(b2 ? v4[j] : v4[j + 2], 4, 64);
+    double v = (b1 ? v2[1] : v2[0]) + __shfl_xor(b1 ? v2[0] : v2[1], 2, 64);
+    v += __shfl_xor(v, 1, 64);
+    const int64_t slot = b - sym_block_of(sym_pos_start(sym_pos_of(Icur, nrb), nrb, ncs), P.grid, P.T);
+    const int64_t row = Icur * kSymRows + wv * 32 + ((lane >> 1) & 31);
+    if ((lane & 1) == 0 && row < n) part[slot * n + row] = v;
+  };
+  auto flush_cols = [&](int buf, int64_t I, int64_t J) {
+    if (tid < kSymCols) {
+      const int64_t col = J * kSymCols + tid;
+      double v = 0.0;
+#pragma unroll
+      for (int w = 0; w < 8; ++w) v += colbuf[buf][w * kSymCols + tid];
+      if (col < n) part[(P.rs + I) * n + col] = v;
+    }
+  };
+  // rows 16 half .. 16 half + 15 of the wave: row sums, and (mirror) the
+  // column sums weighted by the rows' p
+  auto half_rows = [&](const E2 (&v)[16], int half, double w0, double w1, bool mir, double& g0, double& g1) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const double x = (double)v[r].x, y = (double)v[r].y;
+      accr[half * 16 + r] = fma(y, w1, fma(x, w0, accr[half * 16 + r]));
+      if (mir) {
+        const double pr = readlane_f64(prow, half * 16 + r);
+        g0 = fma(x, pr, g0);
+        g1 = fma(y, pr, g1);
+      }
+    }
+  };
+
+  E2 v0[16], v1[16];
+  double w0 = 0.0, w1 = 0.0, wn0 = 0.0, wn1 = 0.0;
+  int64_t tc = t0, Ic = I0, Jc = J0;
+  int64_t tn = t0, In = I0, Jn = J0;   // next stage (for its column weights)
+  load_half(s0, 0, v0);
+  load_w(Jn, wn0, wn1);
+  advance(tn, In, Jn);
+  int64_t Ip = -1, Jp = -1;
+  for (int64_t k = 0; k < L; ++k) {
+    const int buf = (int)(k & 1);
+    const int64_t s = s0 + k;
+    load_half(s, 1, v1);
+    w0 = wn0;
+    w1 = wn1;
+    if (Ip >= 0) {
+      flush_cols(buf ^ 1, Ip, Jp);
+      Ip = -1;
+    }
+    if (Ic != Icur) {
+      if (Icur >= 0) flush_rows();
+      open_rows(Ic);
+    }
+    const bool mir = Jc >= 2 * Ic + 2;
+    double g0 = 0.0, g1 = 0.0;
+    if (mir) half_rows(v0, 0, w0, w1, true, g0, g1);
+    else half_rows(v0, 0, w0, w1, false, g0, g1);
+    if (k + 1 < L) {
+      load_half(s + 1, 0, v0);
+      load_w(Jn, wn0, wn1);
+      advance(tn, In, Jn);
+    }
+    if (mir) {
+      half_rows(v1, 1, w0, w1, true, g0, g1);
+      colbuf[buf][wv * kSymCols + 2 * lane] = g0;
+      colbuf[buf][wv * kSymCols + 2 * lane + 1] = g1;
+      Ip = Ic;
+      Jp = Jc;
+    } else {
+      half_rows(v1, 1, w0, w1, false, g0, g1);
+    }
+    advance(tc, Ic, Jc);
+    __syncthreads();
+  }
+  if (Ip >= 0) flush_cols((int)((L - 1) & 1), Ip, Jp);
+  flush_rows();
+}
+
 }  // namespace
 
 size_t embed_bytes(int64_t rows, int dp, int prec) {
@@ -1195,6 +1439,32 @@ hipError_t launch_sym(int dp, const KmvArgs& A, const SymPlan& sp, hipStream_t s
   return hipGetLastError();
 }
 
+bool kmat_applies(int64_t n, int dp) { return sym_applies(n, dp, LAKER_F64); }
+
+size_t kmat_bytes(int64_t n, int prec) {
+  const SymPlan sp = sym_plan(n);
+  return (size_t)sp.T * (size_t)kTileElems * (prec == LAKER_F64 ? sizeof(double) : sizeof(float));
+}
+
+template <typename OT>
+static hipError_t launch_kmat_build(int dp, const double* e64, int64_t n, const SymPlan& sp, OT* out, hipStream_t st) {
+  switch (dp) {
+    case 16: kmat_build_kernel<16, OT><<<sp.grid, 512, 0, st>>>(e64, n, sp, out); break;
+    case 32: kmat_build_kernel<32, OT><<<sp.grid, 512, 0, st>>>(e64, n, sp, out); break;
+    case 64: kmat_build_kernel<64, OT><<<sp.grid, 512, 0, st>>>(e64, n, sp, out); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t kmat_build(int dp, const double* e64, int64_t n, int prec, void* out, hipStream_t st) {
+  if (!kmat_applies(n, dp) || out == nullptr) return hipErrorInvalidValue;
+  const SymPlan sp = sym_plan(n);
+  if (prec == LAKER_F64) return launch_kmat_build<double>(dp, e64, n, sp, (double*)out, st);
+  if (prec == LAKER_F32) return launch_kmat_build<float>(dp, e64, n, sp, (float*)out, st);
+  return hipErrorInvalidValue;
+}
+
 hipError_t kmv_run(int prec, int dp, const KmvPlan& pl, KmvArgs A, hipStream_t st) {
   A.cps = pl.cols_per_split;
   A.nsplit = pl.nsplit;
@@ -1204,7 +1474,14 @@ hipError_t kmv_run(int prec, int dp, const KmvPlan& pl, KmvArgs A, hipStream_t s
   if ((A.pap != nullptr || A.theta != nullptr) && !pl.sym) return hipErrorInvalidValue;
   if (A.theta != nullptr && (A.S == nullptr || !A.pcg_step)) return hipErrorInvalidValue;
   hipError_t e;
-  if (pl.sym) {
+  if (A.kmat != nullptr) {
+    // stored tiles: float64 or float32 entries, no in-kernel p^T A p or conjugation
+    if (!pl.sym || A.Q != A.K || A.m != A.n || A.pap != nullptr || A.theta != nullptr) return hipErrorInvalidValue;
+    if (prec == LAKER_F64) kmat_matvec_kernel<double><<<pl.sp.grid, 512, 0, st>>>(A, pl.sp);
+    else if (prec == LAKER_F32) kmat_matvec_kernel<float><<<pl.sp.grid, 512, 0, st>>>(A, pl.sp);
+    else return hipErrorInvalidValue;
+    e = hipGetLastError();
+  } else if (pl.sym) {
     // the symmetric schedule covers the square self-product only
     if (A.Q != A.K || A.m != A.n) return hipErrorInvalidValue;
     if (prec == LAKER_F64) e = launch_sym64(dp, A, pl.sp, st);

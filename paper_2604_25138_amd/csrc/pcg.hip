@@ -167,7 +167,7 @@ laker_status enqueue_lowrank_any(const PrecondView& P, const double* r, double* 
 
 SolveWs plan_solve_ws(void* base, int64_t n, int d, int64_t m) {
   WsCarver c(base);
-  SolveWs w;
+  SolveWs w{};
   const int dp = pad_dim(d);
   const int64_t rows = n > m ? n : m;
   const int64_t mq = m > 0 ? m : 1;
@@ -212,6 +212,11 @@ KmvArgs kmv_args(const void* Q, int64_t m, const void* K, int64_t n, const doubl
   A.p = p;
   A.part = ws.part;
   A.mode = 1;
+  // square products of the solve stream the stored G when there is one
+  if (Q == K && m == n) {
+    if (Q == ws.e64) A.kmat = ws.kmat64;
+    else if (Q == ws.e32) A.kmat = ws.kmat32;
+  }
   return A;
 }
 
@@ -258,7 +263,9 @@ laker_status pcg_run(const Problem& pb, const SolveWs& ws, const PrecondView& P,
   // symmetric product with a low-rank preconditioner: the product kernel
   // conjugates the direction itself (p = theta + beta p) and the step update
   // stores it, so the iteration has no separate direction pass
-  const bool fused = lowrank && pl.sym;
+  const bool stored = kmv_args(eh, n, eh, n, p, ws).kmat != nullptr;
+  const bool fold = pl.sym && !stored;
+  const bool fused = lowrank && fold;
   const double* dinv = (const double*)P.dinv;
 
   // r^0 = y - A alpha^0
@@ -297,12 +304,12 @@ laker_status pcg_run(const Problem& pb, const SolveWs& ws, const PrecondView& P,
   Ak.S = S;
   Ak.pcg_step = 1;
   // a symmetric product forms p^T A p itself and the step update adds each
-  // row's partials (no separate pass for A p); else a pass finishes A p and
-  // its p^T A p partials
+  // row's partials (no separate pass for A p); else (also for a product
+  // that streams the stored G) a pass finishes A p and its p^T A p partials
   const PartSum ps = part_sum(pl);
-  const double* Apu = pl.sym ? nullptr : Ap;
-  const int gp = pl.sym ? pl.sp.grid : g;
-  if (pl.sym) {
+  const double* Apu = fold ? nullptr : Ap;
+  const int gp = fold ? pl.sp.grid : g;
+  if (fold) {
     Ak.pap = ws.papp;
     Ak.lam = pb.lambda;
   }
@@ -330,7 +337,7 @@ laker_status pcg_run(const Problem& pb, const SolveWs& ws, const PrecondView& P,
     } else {
       LK_TRY(kmv_run(prec, pb.dp, pl, Ak, s2));
     }
-    if (!pl.sym) {
+    if (!fold) {
       pcg_ap_kernel<<<g, kThreads, 0, s2>>>(p, ws.part, ps, Ap, n, pb.lambda, ws.papp, S);
       LK_CHECK_LAUNCH();
     }

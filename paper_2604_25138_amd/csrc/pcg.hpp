@@ -43,6 +43,10 @@ struct SolveWs {
   double* misc;
   unsigned* cnt;
   size_t total;
+  // stored G (float64 / float32 tiles, kmat_build) placed after the carved
+  // workspace when the solve asks for it; null otherwise
+  void* kmat64;
+  void* kmat32;
 };
 SolveWs plan_solve_ws(void* base, int64_t n, int d, int64_t m);
 KmvArgs kmv_args(const void* Q, int64_t m, const void* K, int64_t n, const double* p, const SolveWs& ws);

@@ -28,7 +28,7 @@ EXPORTS = (
     "laker_predict", "laker_status_str", "laker_mlp_layout_query", "laker_learned_workspace_bytes",
     "laker_learned_forward", "laker_learned_train_step", "laker_learned_precond",
     "laker_sigma_half_workspace_bytes", "laker_precond_sigma_half", "laker_batch_workspace_bytes",
-    "laker_pcg_solve_batched",
+    "laker_pcg_solve_batched", "laker_kmat_bytes",
 )
 MLP_KEYS = ("W1", "b1", "W2", "b2", "W3", "b3")
 MLP_HIDDEN, MLP_RANK = 256, 64
@@ -53,7 +53,7 @@ class laker_pcg_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("precision", C.c_int32), ("refine", C.c_int32),
                 ("ir_max", C.c_int32), ("inner_tol", C.c_double), ("warm_start", C.c_int32),
                 ("check_every", C.c_int32), ("graph", C.c_int32), ("profile", C.c_int32),
-                ("inner_max_iter", C.c_int32), ("reserved", C.c_int32)]
+                ("inner_max_iter", C.c_int32), ("materialized", C.c_int32)]
 
 
 class laker_stats(C.Structure):
@@ -103,6 +103,8 @@ def load(path: str = LIB_PATH):
     lib.laker_fit_workspace_bytes.restype = sz
     lib.laker_solve_workspace_bytes.argtypes = [i64, i32, i64]
     lib.laker_solve_workspace_bytes.restype = sz
+    lib.laker_kmat_bytes.argtypes = [i64, i32, i32]
+    lib.laker_kmat_bytes.restype = sz
     lib.laker_kernel_matvec.argtypes = [P(laker_problem), vp, vp, i32, vp, sz, vp]
     lib.laker_kernel_matvec.restype = i32
     lib.laker_fit_precond.argtypes = [P(laker_problem), vp, P(laker_cccp_opts), P(laker_precond), vp, sz,
@@ -264,8 +266,9 @@ def jacobi_precond(prob: Problem) -> Precond:
 def pcg_solve(prob: Problem, y, precond: Precond | None = None, tol: float = 1e-10, max_iter: int = 10000,
               precision="f64", refine: bool = False, inner_tol: float = 1e-2, ir_max: int = 64,
               alpha0: torch.Tensor | None = None, check_every: int = 16, allow_noconv: bool = False,
-              graph: bool = False, profile: bool = False, inner_max_iter: int = 0):
-    """Returns (alpha, stats)."""
+              graph: bool = False, profile: bool = False, inner_max_iter: int = 0, materialized: bool = False):
+    """Returns (alpha, stats).  materialized: store G once per call and stream it
+    in the float64 (and float32) products."""
     lib = load()
     y = _dev_f64(y, prob.device)
     if alpha0 is not None:
@@ -274,8 +277,12 @@ def pcg_solve(prob: Problem, y, precond: Precond | None = None, tol: float = 1e-
         alpha = torch.empty_like(y)
     opts = laker_pcg_opts(tol, max_iter, _PREC[precision], int(refine), ir_max, inner_tol,
                           1 if alpha0 is not None else 0, check_every, 1 if graph else 0, 1 if profile else 0,
-                          inner_max_iter, 0)
+                          inner_max_iter, 1 if materialized else 0)
     nb = lib.laker_solve_workspace_bytes(prob.n, prob.d, 0)
+    if materialized:
+        nb += 256 + lib.laker_kmat_bytes(prob.n, prob.d, F64)
+        if _PREC[precision] == F32:
+            nb += 256 + lib.laker_kmat_bytes(prob.n, prob.d, F32)
     ws = _workspace("solve", nb, prob.device)
     st = laker_stats()
     pc = None if precond is None else C.byref(precond.c)

@@ -73,3 +73,27 @@ def test_invalid_arguments_rejected_before_any_launch():
     r = lib.laker_pcg_solve(C.byref(prob), None, C.c_void_p(8), C.c_void_p(8), C.byref(opts), C.c_void_p(8),
                             16, C.byref(st), None)                  # workspace too small
     assert r == laker.LAKER_ENOMEM
+
+
+def _sym_stages(n):
+    """Stages of the symmetric schedule (256-row blocks against 128-column
+    stages on or right of the block diagonal), counted by brute force."""
+    nrb, ncs = -(-n // 256), -(-n // 128)
+    return sum(1 for I in range(nrb) for J in range(ncs) if J >= 2 * I)
+
+
+def test_stored_kernel_matrix_size_query():
+    """laker_kmat_bytes: one 256 x 128 tile per stage of the symmetric schedule
+    (float64 or float32 entries), 0 below the schedule's threshold (2 stages per
+    block of 256), for bfloat16 and for unsupported d."""
+    laker, lib = _lib()
+    for n, d in [(6000, 16), (5837, 64), (16384, 64), (65536, 32)]:
+        T = _sym_stages(n)
+        assert T >= 2 * 256
+        assert lib.laker_kmat_bytes(n, d, laker.F64) == T * 256 * 128 * 8
+        assert lib.laker_kmat_bytes(n, d, laker.F32) == T * 256 * 128 * 4
+        assert lib.laker_kmat_bytes(n, d, laker.BF16) == 0
+    assert _sym_stages(16384) == 4160 and lib.laker_kmat_bytes(16384, 64, laker.F64) == 4160 * 262144
+    assert lib.laker_kmat_bytes(4096, 16, laker.F64) == 0          # fewer than 2 stages per block
+    assert lib.laker_kmat_bytes(6000, 128, laker.F64) == 0         # dp above the schedule's 64
+    assert lib.laker_kmat_bytes(6000, 200, laker.F64) == 0

@@ -474,3 +474,54 @@ def test_graph_replay_matches_eager_on_symmetric_schedule():
     _ = L().kernel_matvec(prob, torch.ones(pr.n, dtype=torch.float64, device=DEV))   # eager work in between
     a2, s2 = L().pcg_solve(prob, pr.y, pc, graph=False, **kw)
     assert s1.iters == s2.iters and s1.iters > 16 and torch.equal(a1, a2)
+
+
+# ---- stored G (materialized): formed once per solve as float64 (and float32)
+# tiles of the symmetric schedule and streamed by the products
+
+
+@pytest.mark.parametrize("n,d", [(6000, 16), (5837, 64)])
+def test_stored_kernel_matrix_f64_pcg(n, d):
+    """Float64 PCG whose products stream the stored float64 G: alpha within
+    1e-10 of the Cholesky solution at tol 1e-12, the iteration count of the
+    recomputing products (same entries, other summation order) within 1%, and
+    the reported float64 true residual at the float64 floor with the oracle's
+    (both ~1e-11 here: their difference is rounding of the residual itself)."""
+    pr = make_problem(n, d, 1e-3, seed=31)
+    A = O.system_matrix(pr.E, pr.scale, pr.lam)
+    ref = O.solve_direct(A, pr.y)
+    prob = _gp(pr)
+    a1, s1 = L().pcg_solve(prob, pr.y, None, tol=1e-12, max_iter=20000, materialized=True)
+    a2, s2 = L().pcg_solve(prob, pr.y, None, tol=1e-12, max_iter=20000)
+    a1n = a1.cpu().numpy()
+    assert s1.status == 0
+    assert np.linalg.norm(a1n - ref) / np.linalg.norm(ref) <= 1e-10
+    assert abs(s1.iters - s2.iters) <= max(2, s2.iters // 100)
+    rt = O.relative_residual(A, a1n, pr.y)
+    assert s1.relres_true <= 5e-11 and rt <= 5e-11
+    assert abs(s1.relres_true - rt) <= 0.5 * rt + 1e-12
+
+
+@pytest.mark.parametrize("prec,kind", [("f32", "cccp"), ("bf16", "cccp"), ("f32", "none")])
+def test_stored_kernel_matrix_mixed_precision(prec, kind):
+    """Flexible outer CG with the stored G: its float64 products (and with
+    float32 inner products, those too) stream the stored tiles; the float64
+    true residual reaches 1e-10 and alpha the Cholesky solution to 1e-8."""
+    pr, A, ref, Z = _sym_case(6000)
+    prob = _gp(pr)
+    pc = _sym_precond(kind, prob, Z)
+    alpha, st = L().pcg_solve(prob, pr.y, pc, tol=1e-10, max_iter=50000, precision=prec, refine=2,
+                              inner_tol=1e-1, ir_max=1000, check_every=30, inner_max_iter=30, materialized=True)
+    assert st.status == 0 and st.relres_true <= 1e-10
+    assert np.linalg.norm(alpha.cpu().numpy() - ref) / np.linalg.norm(ref) <= 1e-8
+    assert O.relative_residual(A, alpha.cpu().numpy(), pr.y) <= 1e-10
+
+
+def test_stored_kernel_matrix_below_threshold_is_ignored():
+    """Below the symmetric schedule's size nothing is stored and the solve is
+    the recomputing one, bitwise."""
+    pr = make_problem(900, 16, 1e-3, seed=12)
+    prob = _gp(pr)
+    a1, s1 = L().pcg_solve(prob, pr.y, None, tol=1e-11, max_iter=5000, materialized=True)
+    a2, s2 = L().pcg_solve(prob, pr.y, None, tol=1e-11, max_iter=5000)
+    assert s1.iters == s2.iters and torch.equal(a1, a2)
