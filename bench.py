@@ -192,7 +192,8 @@ def main():
 
     def step():
         res = LR.solve_with_fallback(prob, y, model, Zd, tol=tol, budget=budget, precision="bf16", refine=2,
-                                     inner_tol=inner, gamma=0.1, check_every=INNER_CAP, inner_max_iter=INNER_CAP)
+                                     inner_tol=inner, gamma=0.1, check_every=INNER_CAP, inner_max_iter=INNER_CAP,
+                                     materialized=True)
         rhat = L.predict(prob, res.alpha, Eq, precision="f64")
         return res, rhat
 
@@ -223,7 +224,7 @@ def main():
     torch.cuda.synchronize()
     b = time.perf_counter()
     alc, stc = L.pcg_solve(prob, y, pc, tol=tol, max_iter=100000, precision="bf16", refine=True, inner_tol=inner,
-                           ir_max=64, check_every=32)
+                           ir_max=64, check_every=32, materialized=True)
     torch.cuda.synchronize()
     c = time.perf_counter()
     L.predict(prob, alc, Eq, precision="f64")
@@ -238,7 +239,8 @@ def main():
         torch.cuda.synchronize()
         a = time.perf_counter()
         pc64 = L.fit_precond(prob, Zd, gamma=0.1, rho=0.0)
-        al64, st64 = L.pcg_solve(prob, y, pc64, tol=tol, max_iter=100000, precision="f64", check_every=32)
+        al64, st64 = L.pcg_solve(prob, y, pc64, tol=tol, max_iter=100000, precision="f64", check_every=32,
+                                 materialized=True)
         L.predict(prob, al64, Eq, precision="f64")
         torch.cuda.synchronize()
         b = time.perf_counter()
@@ -246,12 +248,34 @@ def main():
                                  "pcg_iters": st64.iters, "relres_true": st64.relres_true}
         extra["speedup_vs_f64_cccp_pcg"] = (b - a) * 1e3 / ms_per_step
 
+    # float32 products on the same map, G recomputed in every product against
+    # G stored once per solve (float32 tiles streamed from HBM); CCCP, PCG to
+    # tol with float64 refinement
+    f32c = {}
+    for mat in (False, True):
+        kw32 = dict(tol=tol, max_iter=100000, precision="f32", refine=True, inner_tol=inner, ir_max=64,
+                    check_every=32, materialized=mat)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        _, s32 = L.pcg_solve(prob, y, pc, **kw32)
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        _, s32p = L.pcg_solve(prob, y, pc, profile=True, **kw32)
+        f32c["stored" if mat else "recomputed"] = {
+            "ms_per_solve": (b - a) * 1e3, "pcg_iters": s32.iters, "ir_steps": s32.ir_steps,
+            "relres_true": s32.relres_true, "us_per_product": s32p.kmv_ms * 1e3}
+    sb32 = L.load().laker_kmat_bytes(pr.n, pr.d, L.F32)
+    f32c["stored"]["gb_per_s"] = sb32 / (f32c["stored"]["us_per_product"] * 1e-6) / 1e9
+    f32c["stored_bytes"] = sb32
+    extra["f32_stored_vs_recomputed"] = f32c
+
     # roofline of the dominant kernel: the fused product exp2(<e_i, e_j>) p of
     # the solve, timed by the library with HIP events on the stream it launches
     # on (one pair of events around every product of the loop)
     pcl = L.learned_precond(prob, model)
     _, stp = L.pcg_solve(prob, y, pcl, tol=tol, max_iter=100000, precision="bf16", refine=2, inner_tol=inner,
-                         ir_max=1000, check_every=INNER_CAP, inner_max_iter=INNER_CAP, profile=True)
+                         ir_max=1000, check_every=INNER_CAP, inner_max_iter=INNER_CAP, profile=True,
+                         materialized=True)
     kms = stp.kmv_ms
     pairs = float(pr.n) * pr.n
     # the symmetric product forms each of the n (n + 1) / 2 distinct kernel
@@ -300,7 +324,8 @@ def main():
         "vs_baseline": None, "dtype": "bf16+f64", "data": "synthetic",
         "config": {"workload": f"{args.workload}: n={pr.n} d={pr.d} n_tx={wl['n_tx']} lambda={pr.lam} "
                                f"scale=1/sqrt(d) tol={tol}",
-                   "path": "learned rank-64+diag preconditioner (BF16 MLP) + flexible f64 outer CG around bf16 "
+                   "path": "learned rank-64+diag preconditioner (BF16 MLP) + flexible f64 outer CG (its float64 "
+                           "products stream G stored once per solve) around bf16 "
                            f"inner PCG (<= {INNER_CAP} iterations each; CCCP fallback on stall) + predict 45x45",
                    "training": f"{args.train_maps} maps n={TRAIN_N} lambda~logU[1e-5,1e-2] n_tx~U{{1..8}}, "
                                f"{args.train_epochs} epochs, CCCP targets gamma=1e-3"},

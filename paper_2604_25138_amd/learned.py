@@ -67,11 +67,13 @@ class LearnedSolve:
 
 def solve_with_fallback(prob: L.Problem, y, model: L.MlpModel, fallback_directions, tol: float = 1e-6,
                         budget: int = 4000, precision: str = "bf16", refine=True, inner_tol: float = 0.1,
-                        gamma: float = 0.1, check_every: int = 32, inner_max_iter: int = 0) -> LearnedSolve:
+                        gamma: float = 0.1, check_every: int = 32, inner_max_iter: int = 0,
+                        materialized: bool = False) -> LearnedSolve:
     """PCG with the learned preconditioner; on a stall (budget exhausted) fit
     CCCP and continue from the current iterate.  refine: False, True
     (iterative refinement) or 2 (flexible float64 outer CG, inner solves capped
-    at inner_max_iter iterations)."""
+    at inner_max_iter iterations).  materialized: the float64 products stream a
+    G stored once per solve."""
     t0 = time.perf_counter()
     pc = L.learned_precond(prob, model)
     torch.cuda.synchronize()
@@ -79,12 +81,12 @@ def solve_with_fallback(prob: L.Problem, y, model: L.MlpModel, fallback_directio
     ir_max = 1000 if refine == 2 else 64   # outer steps (refinement keeps at most 64)
     alpha, st = L.pcg_solve(prob, y, pc, tol=tol, max_iter=budget, precision=precision, refine=refine,
                             inner_tol=inner_tol, ir_max=ir_max, check_every=check_every, allow_noconv=True,
-                            inner_max_iter=inner_max_iter)
+                            inner_max_iter=inner_max_iter, materialized=materialized)
     if st.status == L.LAKER_OK:
         return LearnedSolve(alpha, st, False, st.iters, pms)
     used = st.iters
     pc2 = L.fit_precond(prob, fallback_directions, gamma=gamma, rho=0.0, precision=precision)
     alpha, st2 = L.pcg_solve(prob, y, pc2, tol=tol, max_iter=100000, precision=precision, refine=refine,
                              inner_tol=inner_tol, ir_max=ir_max, alpha0=alpha, check_every=check_every,
-                             inner_max_iter=inner_max_iter)
+                             inner_max_iter=inner_max_iter, materialized=materialized)
     return LearnedSolve(alpha, st2, True, used, pms)
