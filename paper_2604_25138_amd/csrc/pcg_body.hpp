@@ -290,9 +290,41 @@ __device__ __forceinline__ void pcg_update_t_body(int blk, int nblk, double* __r
   __shared__ double sh[16];
   __shared__ double rs[kTRows];
   __shared__ double red[kMaxNr];
+  __shared__ double apq[kThreads / kTRows][kTRows];
   const int tid = threadIdx.x;
+  const int64_t i0 = (int64_t)blk * kTRows;
+  // Loads that do not depend on this iteration's scalars go first, so that
+  // their latencies overlap: this thread's stripe of the p^T A p partials (as
+  // ordered_sum takes them; gp <= 4 kThreads), the block's rows of p, theta,
+  // alpha, r (or Ap), then the row sums of the product's partials.
+  static_assert(kMaxBlocks <= 4 * kThreads, "four partials per thread");
+  const int per = (gp + kThreads - 1) / kThreads;
+  double pv[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int idx = tid * per + u;
+    pv[u] = u < per && idx < gp ? pap_p[idx] : 0.0;
+  }
+  const int64_t iw = i0 + tid;
+  const bool row_in = tid < kTRows && iw < n;
+  double pi = 0.0, ti = 0.0, ali = 0.0, ri0 = 0.0, api = 0.0;
+  if (row_in) {
+    pi = p[iw];
+    if (theta != nullptr) ti = theta[iw];
+    ali = alpha[iw];
+    ri0 = r[iw];
+    if (Ap != nullptr) api = Ap[iw];
+  }
+  if (Ap == nullptr) {
+    const int64_t i = i0 + (tid % kTRows);
+    apq[tid / kTRows][tid % kTRows] = i < n ? ps.row_strided(part, n, i, tid / kTRows, kThreads / kTRows) : 0.0;
+  }
+  double v = 0.0;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+    if (u < per && tid * per + u < gp) v += pv[u];
+  const double pap = block_sum(v, sh);   // (its barriers also publish apq)
   const int k = S->kcur - 1;
-  const double pap = ordered_sum(pap_p, gp, sh);
   const double dl = S->rzbuf[k & 1] / pap;
   if (!(pap > 0.0) || !isfinite(dl)) {
     if (blk == 0 && tid == 0) S->done = 2;
@@ -306,29 +338,20 @@ __device__ __forceinline__ void pcg_update_t_body(int blk, int nblk, double* __r
       S->first = 0;
     }
   }
-  const int64_t i0 = (int64_t)blk * kTRows;
-  __shared__ double apq[kThreads / kTRows][kTRows];
-  if (Ap == nullptr) {
-    const int64_t i = i0 + (tid % kTRows);
-    apq[tid / kTRows][tid % kTRows] = i < n ? ps.row_strided(part, n, i, tid / kTRows, kThreads / kTRows) : 0.0;
-    __syncthreads();
-  }
   double rr = 0.0;
   if (tid < kTRows) {
-    const int64_t i = i0 + tid;
     double ri = 0.0;
-    if (i < n) {
-      double pi = p[i];
+    if (row_in) {
       if (theta != nullptr) {
-        pi = fma(S->beta, pi, theta[i]);
-        p[i] = pi;
+        pi = fma(S->beta, pi, ti);
+        p[iw] = pi;
       }
       static_assert(kThreads / kTRows == 4, "four partial sums per row");
-      const double a = Ap != nullptr ? Ap[i]
+      const double a = Ap != nullptr ? api
                                      : fma(lam, pi, (apq[0][tid] + apq[1][tid]) + (apq[2][tid] + apq[3][tid]));
-      alpha[i] = fma(dl, pi, alpha[i]);
-      ri = fma(-dl, a, r[i]);
-      r[i] = ri;
+      alpha[iw] = fma(dl, pi, ali);
+      ri = fma(-dl, a, ri0);
+      r[iw] = ri;
     }
     rs[tid] = ri;
     rr = ri * ri;
