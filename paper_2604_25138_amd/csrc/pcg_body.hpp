@@ -315,6 +315,24 @@ __device__ __forceinline__ void pcg_update_t_body(int blk, int nblk, double* __r
     ri0 = r[iw];
     if (Ap != nullptr) api = Ap[iw];
   }
+  // the thread's rows of B for t = B^T r (when they fit in registers: at
+  // most four rows, N_r <= 64), loaded now, used once r is updated
+  const int cq = nrp / 4;
+  int tpr = 1;
+  while (tpr < cq) tpr <<= 1;
+  const int groups = kThreads / tpr;
+  const int g = tid / tpr, q = tid % tpr;
+  constexpr int PRE = 4;
+  const bool pre = kTRows <= PRE * groups;
+  MT bv[PRE][4];
+#pragma unroll
+  for (int j = 0; j < PRE; ++j) {
+    const int rr2 = g + j * groups;
+    const bool in = pre && q < cq && rr2 < kTRows && i0 + rr2 < n;
+    const MT* row = B + (in ? (i0 + rr2) * nrp + 4 * q : 0);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) bv[j][c] = in ? row[c] : (MT)0;
+  }
   if (Ap == nullptr) {
     const int64_t i = i0 + (tid % kTRows);
     apq[tid / kTRows][tid % kTRows] = i < n ? ps.row_strided(part, n, i, tid / kTRows, kThreads / kTRows) : 0.0;
@@ -358,13 +376,20 @@ __device__ __forceinline__ void pcg_update_t_body(int blk, int nblk, double* __r
   }
   rr = block_sum(rr, sh);     // contains the barrier that publishes rs
   if (tid == 0) rrp[blk] = rr;
-  const int cq = nrp / 4;
-  int tpr = 1;
-  while (tpr < cq) tpr <<= 1;
-  const int groups = kThreads / tpr;
-  const int g = tid / tpr, q = tid % tpr;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  if (q < cq) {
+  if (pre && q < cq) {
+#pragma unroll
+    for (int j = 0; j < PRE; ++j) {
+      const int rr2 = g + j * groups;
+      if (rr2 < kTRows && i0 + rr2 < n) {
+        const double ri = rs[rr2];
+        a0 = fma((double)bv[j][0], ri, a0);
+        a1 = fma((double)bv[j][1], ri, a1);
+        a2 = fma((double)bv[j][2], ri, a2);
+        a3 = fma((double)bv[j][3], ri, a3);
+      }
+    }
+  } else if (q < cq) {
 #pragma unroll 8
     for (int rr2 = g; rr2 < kTRows; rr2 += groups) {
       const int64_t i = i0 + rr2;
