@@ -4,6 +4,8 @@
 // same body gives the same partial sums in either launch form.
 #pragma once
 
+#include <type_traits>
+
 #include "pcg.hpp"
 
 namespace lk {
@@ -143,9 +145,7 @@ __device__ __forceinline__ void pcg_update_body(int blk, int nblk, double* __res
 
 // Stopping test of iteration k on the recursive residual (Alg. 1), evaluated
 // identically by every block; block 0 records it.  Returns true to continue.
-__device__ __forceinline__ bool pcg_decide(int blk, int k, PcgScalars* S, const double* __restrict__ rrp, int g,
-                                           double* sh) {
-  const double rr = ordered_sum(rrp, g, sh);
+__device__ __forceinline__ bool pcg_decide_rr(int blk, int k, PcgScalars* S, double rr) {
   int d = 0;
   if (!isfinite(rr)) d = 2;
   else if (rr <= S->tol2) d = 1;
@@ -156,6 +156,10 @@ __device__ __forceinline__ bool pcg_decide(int blk, int k, PcgScalars* S, const 
     if (d) S->done = d;
   }
   return d == 0;
+}
+__device__ __forceinline__ bool pcg_decide(int blk, int k, PcgScalars* S, const double* __restrict__ rrp, int g,
+                                           double* sh) {
+  return pcg_decide_rr(blk, k, S, ordered_sum(rrp, g, sh));
 }
 
 // p = theta + beta p with beta = r_new^T theta_new / r^T theta.  With
@@ -415,12 +419,42 @@ __device__ __forceinline__ void lr_t_finish_body(int blk, int nblk, const double
   if (S != nullptr && S->done) return;
   __shared__ double red[16][17];
   __shared__ double shd[16];
-  // inside the loop this pass takes the stopping decision of the current iteration first
-  if (rrp != nullptr && !pcg_decide(blk, S->kcur - 1, S, rrp, grr, shd)) return;
-  const int g = threadIdx.x >> 4, cl = threadIdx.x & 15;
+  const int tid = threadIdx.x;
+  const int g = tid >> 4, cl = tid & 15;
   const int col = blk * 16 + cl;
+  // Inside the loop this pass first takes the stopping decision of the
+  // current iteration.  Its ||r||^2 partials (this thread's stripe, as
+  // ordered_sum takes them; grr <= 4 kThreads) and, for up to 256 partial
+  // rows, the t partials are loaded before it, so that the latencies overlap.
+  static_assert(kMaxBlocks <= 4 * kThreads, "four partials per thread");
+  const int per = rrp != nullptr ? (grr + kThreads - 1) / kThreads : 0;
+  double rv[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int idx = tid * per + u;
+    rv[u] = u < per && idx < grr ? rrp[idx] : 0.0;
+  }
+  constexpr int PRE = 16;
+  const bool pre = nb <= 16 * PRE;
+  double tv[PRE];
+#pragma unroll
+  for (int u = 0; u < PRE; ++u) {
+    const int b = g + 16 * u;
+    tv[u] = pre && col < nrp && b < nb ? tpart[(int64_t)b * nrp + col] : 0.0;
+  }
+  if (rrp != nullptr) {
+    double v = 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (u < per && tid * per + u < grr) v += rv[u];
+    if (!pcg_decide_rr(blk, S->kcur - 1, S, block_sum(v, shd))) return;
+  }
   double s = 0.0;
-  if (col < nrp) {
+  if (pre) {
+#pragma unroll
+    for (int u = 0; u < PRE; ++u)
+      if (col < nrp && g + 16 * u < nb) s += tv[u];
+  } else if (col < nrp) {
     // partial rows g, g + 16, ... added in order; loads issued eight at a time
     int b = g;
     for (; b + 16 * 7 < nb; b += 16 * 8) {
