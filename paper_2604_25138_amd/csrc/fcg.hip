@@ -57,19 +57,33 @@ __global__ __launch_bounds__(kT) void dot2_kernel(const double* __restrict__ a1,
   }
 }
 
-// p = z + beta p
-__global__ void pdir_kernel(const double* __restrict__ z, double* __restrict__ p, double beta, int64_t n) {
+// The outer scalars stay on the device, s = 4 doubles: s[0], s[1] the last
+// dot2 results, s[2] = p_prev^T q_prev, s[3] = 1 after a breakdown.  The host
+// reads them once per outer step, with ||r||^2.
+
+// p = z + beta p, beta = -(z^T q_prev) / (p_prev^T q_prev) = -s[0] / s[2]
+__global__ void pdir_kernel(const double* __restrict__ z, double* __restrict__ p, const double* __restrict__ s,
+                            int64_t n) {
+  const double beta = -s[0] / s[2];
   for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT)
     p[i] = fma(beta, p[i], z[i]);
 }
 
-// alpha += gamma p; r -= gamma q
+// gamma = p^T r / p^T q (s[1] / s[0]); alpha += gamma p; r -= gamma q; s[2] =
+// p^T q.  p^T q <= 0 or a non-finite p^T r: nothing is updated and s[3] = 1.
 __global__ void step_kernel(double* __restrict__ alpha, double* __restrict__ r, const double* __restrict__ p,
-                            const double* __restrict__ q, double gamma, int64_t n) {
+                            const double* __restrict__ q, double* __restrict__ s, int64_t n) {
+  const double pq = s[0], pr = s[1];
+  if (!(pq > 0.0) || !isfinite(pr)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) s[3] = 1.0;
+    return;
+  }
+  const double gamma = pr / pq;
   for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
     alpha[i] = fma(gamma, p[i], alpha[i]);
     r[i] = fma(-gamma, q[i], r[i]);
   }
+  if (blockIdx.x == 0 && threadIdx.x == 0) s[2] = pq;
 }
 
 }  // namespace
@@ -82,11 +96,15 @@ laker_status fcg_run(const Problem& pb, const SolveWs& W, const PrecondView& P, 
   double* z = W.dalpha;
   double* p = W.fp;
   double* q = W.fq;
+  double* s = W.misc + 8;
+  auto dots_dev = [&](const double* a1, const double* b1, const double* a2, const double* b2) -> hipError_t {
+    dot2_kernel<<<g, kT, 0, st>>>(a1, b1, a2, b2, n, W.bpart, W.cnt, s);
+    return hipGetLastError();
+  };
   auto dots = [&](const double* a1, const double* b1, const double* a2, const double* b2, double* h) -> hipError_t {
-    dot2_kernel<<<g, kT, 0, st>>>(a1, b1, a2, b2, n, W.bpart, W.cnt, W.misc + 8);
-    hipError_t e = hipGetLastError();
+    hipError_t e = dots_dev(a1, b1, a2, b2);
     if (e != hipSuccess) return e;
-    e = hipMemcpyAsync(h, W.misc + 8, 2 * sizeof(double), hipMemcpyDeviceToHost, st);
+    e = hipMemcpyAsync(h, s, 4 * sizeof(double), hipMemcpyDeviceToHost, st);
     if (e != hipSuccess) return e;
     return hipStreamSynchronize(st);
   };
@@ -104,7 +122,8 @@ laker_status fcg_run(const Problem& pb, const SolveWs& W, const PrecondView& P, 
   double rel = 0.0;
   laker_status e = true_residual(pb, W, y, alpha, r, &rel, o.warm_start != 0, st);
   if (e != LAKER_OK) return e;
-  double h[2];
+  double h[4];
+  LK_TRY(hipMemsetAsync(s, 0, 4 * sizeof(double), st));
   LK_TRY(dots(y, y, y, y, h));
   const double ynorm = sqrt(h[0]);
   sp->ir_relres[0] = rel;
@@ -113,7 +132,6 @@ laker_status fcg_run(const Problem& pb, const SolveWs& W, const PrecondView& P, 
   sp->ir_steps = 0;
   if (rel <= o.tol) return LAKER_OK;
   int used = 0;
-  double pq_prev = 0.0;
   const int inner_cap = o.inner_max_iter > 0 ? o.inner_max_iter : o.max_iter;
   for (int k = 0; k < o.ir_max; ++k) {
     if (used >= o.max_iter) break;
@@ -139,23 +157,20 @@ laker_status fcg_run(const Problem& pb, const SolveWs& W, const PrecondView& P, 
       sp->kmv_launch_ms = (prev + inner.kmv_launch_ms * inner.kmv_launches) / sp->kmv_launches;
     }
     // p = z + beta p_prev, beta = -(z^T q_prev) / (p_prev^T q_prev)
+    // (beta, gamma and the breakdown test on the device: one host read per step)
     if (k == 0) {
       LK_TRY(hipMemcpyAsync(p, z, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
     } else {
-      LK_TRY(dots(z, q, z, q, h));
-      const double beta = -h[0] / pq_prev;
-      pdir_kernel<<<g, kT, 0, st>>>(z, p, beta, n);
+      LK_TRY(dots_dev(z, q, z, q));
+      pdir_kernel<<<g, kT, 0, st>>>(z, p, s, n);
       LK_CHECK_LAUNCH();
     }
     LK_TRY(product(p, q));
-    LK_TRY(dots(p, q, p, r, h));
-    const double pq = h[0], pr = h[1];
-    if (!(pq > 0.0) || !isfinite(pr)) return LAKER_EBREAKDOWN;
-    const double gamma = pr / pq;
-    step_kernel<<<g, kT, 0, st>>>(alpha, r, p, q, gamma, n);
+    LK_TRY(dots_dev(p, q, p, r));
+    step_kernel<<<g, kT, 0, st>>>(alpha, r, p, q, s, n);
     LK_CHECK_LAUNCH();
-    pq_prev = pq;
     LK_TRY(dots(r, r, r, r, h));
+    if (h[3] != 0.0) return LAKER_EBREAKDOWN;
     rel = ynorm > 0.0 ? sqrt(h[0]) / ynorm : 0.0;
     if (k + 1 < 64) sp->ir_relres[k + 1] = rel;
     sp->ir_steps = k + 1;
