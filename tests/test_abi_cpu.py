@@ -97,3 +97,21 @@ def test_stored_kernel_matrix_size_query():
     assert lib.laker_kmat_bytes(4096, 16, laker.F64) == 0          # fewer than 2 stages per block
     assert lib.laker_kmat_bytes(6000, 128, laker.F64) == 0         # dp above the schedule's 64
     assert lib.laker_kmat_bytes(6000, 200, laker.F64) == 0
+
+
+def test_stored_kernel_matrix_options_validated_on_the_host():
+    """materialized outside {0, 1} is rejected, and a workspace without room
+    for the stored G is LAKER_ENOMEM, both before any device work."""
+    laker, lib = _lib()
+    n, d = 6000, 16
+    prob = laker.laker_problem(n, d, 0, 8, 1e-2, 0.5)
+    st = laker.laker_stats()
+    ws = lib.laker_solve_workspace_bytes(n, d, 0)
+    opts = laker.laker_pcg_opts(1e-8, 10, 0, 0, 1, 1e-2, 0, 16, 0, 0, 0, 2)
+    r = lib.laker_pcg_solve(C.byref(prob), None, C.c_void_p(8), C.c_void_p(8), C.byref(opts), C.c_void_p(8),
+                            ws, C.byref(st), None)
+    assert r == laker.LAKER_EINVAL
+    opts = laker.laker_pcg_opts(1e-8, 10, 0, 0, 1, 1e-2, 0, 16, 0, 0, 0, 1)
+    r = lib.laker_pcg_solve(C.byref(prob), None, C.c_void_p(8), C.c_void_p(8), C.byref(opts), C.c_void_p(8),
+                            ws + lib.laker_kmat_bytes(n, d, laker.F64) // 2, C.byref(st), None)
+    assert r == laker.LAKER_ENOMEM
