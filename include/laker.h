@@ -128,7 +128,11 @@ typedef struct {
                          recomputing it.  Applies where the symmetric product
                          schedule does (laker_kmat_bytes > 0); bfloat16
                          products are always recomputed (a rounded stored G
-                         need not be positive definite)                        */
+                         need not be positive definite).  In
+                         laker_pcg_solve_batched: the float64 outer residuals
+                         of the maps it applies to; workspace
+                         laker_batch_workspace_bytes + the sum over those maps
+                         of (256 + laker_kmat_bytes(n_b, d, F64)) bytes        */
 } laker_pcg_opts;
 
 typedef struct {

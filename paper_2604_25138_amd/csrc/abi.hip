@@ -492,6 +492,7 @@ laker_status laker_pcg_solve_batched(int32_t count, const laker_problem* probs, 
   if (opts->refine < 0 || opts->refine > 1) return LAKER_EINVAL;
   if (opts->refine && (opts->ir_max < 1 || opts->ir_max > 64 || !(opts->inner_tol > 0.0))) return LAKER_EINVAL;
   if (opts->warm_start) return LAKER_EINVAL;
+  if (opts->materialized < 0 || opts->materialized > 1) return LAKER_EINVAL;
   std::vector<int64_t> ns(count);
   std::vector<Problem> pbs(count);
   std::vector<PrecondView> views(count);
@@ -507,10 +508,23 @@ laker_status laker_pcg_solve_batched(int32_t count, const laker_problem* probs, 
   }
   std::vector<size_t> off(count);
   BatchWs bw{};
-  const size_t need = plan_batch_ws(count, ns.data(), probs[0].d, off.data(), workspace, &bw);
+  size_t need = plan_batch_ws(count, ns.data(), probs[0].d, off.data(), workspace, &bw);
+  // stored G of the maps it applies to, after the batch workspace, in map order
+  std::vector<size_t> koff(count, 0);
+  if (opts->materialized) {
+    for (int b = 0; b < count; ++b) {
+      const size_t kb = laker_kmat_bytes(ns[b], probs[0].d, LAKER_F64);
+      if (kb == 0) continue;
+      koff[b] = (need + 255) & ~size_t(255);
+      need = koff[b] + kb;
+    }
+  }
   if (workspace_bytes < need) return LAKER_ENOMEM;
   std::vector<SolveWs> wss(count);
-  for (int b = 0; b < count; ++b) wss[b] = plan_solve_ws((char*)workspace + off[b], ns[b], probs[0].d, 0);
+  for (int b = 0; b < count; ++b) {
+    wss[b] = plan_solve_ws((char*)workspace + off[b], ns[b], probs[0].d, 0);
+    if (koff[b] > 0) wss[b].kmat64 = (char*)workspace + koff[b];
+  }
   BatchOpts bo{};
   bo.cps = bopts != nullptr ? bopts->cols_per_split : 0;
   bo.xcd_order = bopts != nullptr ? bopts->xcd_order : 0;

@@ -288,6 +288,7 @@ laker_status pcg_batch(int count, const Problem* pbs, const SolveWs* wss, const 
     LK_TRY(hipMemsetAsync(w.S, 0, sizeof(PcgScalars), st));
     LK_TRY(hipMemsetAsync(w.cnt, 0, 16 * sizeof(unsigned), st));
     LK_TRY(prep_embed(pb.E, pb.n, pb.d, pb.dp, pb.scale, LAKER_F64, w.e64, st));
+    if (w.kmat64 != nullptr) LK_TRY(kmat_build(pb.dp, w.e64, pb.n, LAKER_F64, w.kmat64, st));
     if (prec != LAKER_F64)
       LK_TRY(prep_embed(pb.E, pb.n, pb.d, pb.dp, pb.scale, prec, prec == LAKER_F32 ? (void*)w.e32 : (void*)w.e16, st));
   }
@@ -338,6 +339,7 @@ laker_status pcg_batch(int count, const Problem* pbs, const SolveWs* wss, const 
           pl[b] = plan_for(pbs[b].n, prec, cand);
           KmvArgs A = kmv_args(prepared(wss[b], prec), pbs[b].n, prepared(wss[b], prec), pbs[b].n, wss[b].p,
                                wss[b]);
+          A.kmat = nullptr;   // the inner products recompute G
           A.mode = 0;
           A.cps = pl[b].cps;
           A.nsplit = pl[b].nsplit;
@@ -398,6 +400,7 @@ laker_status pcg_batch(int count, const Problem* pbs, const SolveWs* wss, const 
       for (int b = 0; b < count; ++b) {
         if (pm[b] != pq) continue;
         KmvArgs A = kmv_args(prepared(wss[b], pq), pbs[b].n, prepared(wss[b], pq), pbs[b].n, wss[b].p, wss[b]);
+        A.kmat = nullptr;   // the inner products recompute G (a stored G serves the outer residuals)
         A.mode = 0;
         A.S = wss[b].S;
         A.pcg_step = 1;

@@ -452,8 +452,10 @@ def sigma_half(pc: Precond, Z: torch.Tensor) -> torch.Tensor:
 def pcg_solve_batched(probs: list, ys: list, preconds: list | None = None, tol: float = 1e-10,
                       max_iter: int = 10000, precision="f64", refine: bool = False, inner_tol: float = 1e-2,
                       ir_max: int = 64, check_every: int = 16, graph: bool = False, cols_per_split: int = 0,
-                      xcd_order: bool = False, allow_noconv: bool = False):
-    """Solve every problem of the batch; returns (alphas, stats list, columns per range used)."""
+                      xcd_order: bool = False, allow_noconv: bool = False, materialized: bool = False):
+    """Solve every problem of the batch; returns (alphas, stats list, columns per range used).
+    materialized: the float64 outer residuals of the maps large enough stream a G
+    stored once per call."""
     lib = load()
     count = len(probs)
     dev = probs[0].device
@@ -466,10 +468,12 @@ def pcg_solve_batched(probs: list, ys: list, preconds: list | None = None, tol: 
     yp = (C.c_void_p * count)(*[v.data_ptr() for v in ys])
     ap = (C.c_void_p * count)(*[v.data_ptr() for v in alphas])
     opts = laker_pcg_opts(tol, max_iter, _PREC[precision], 1 if refine else 0, ir_max, inner_tol, 0, check_every,
-                          1 if graph else 0, 0, 0, 0)
+                          1 if graph else 0, 0, 0, 1 if materialized else 0)
     bo = laker_batch_opts(cols_per_split, 1 if xcd_order else 0, 0, 0)
     ns = (C.c_int64 * count)(*[p.n for p in probs])
     nb = lib.laker_batch_workspace_bytes(count, ns, probs[0].d)
+    if materialized:
+        nb += sum(256 + lib.laker_kmat_bytes(p.n, p.d, F64) for p in probs)
     ws = _workspace("batch", nb, dev)
     st = (laker_stats * count)()
     s = lib.laker_pcg_solve_batched(count, pa, pc, yp, ap, C.byref(opts), C.byref(bo), _ptr(ws), ws.numel(), st,

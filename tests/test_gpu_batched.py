@@ -125,3 +125,31 @@ def test_batch_with_symmetric_maps_is_bitwise_equal_to_single_solves():
         a1, s1 = L().pcg_solve(p, pr.y, None, **kw)
         assert stats[b].status == 0 and stats[b].relres_true <= 1e-9, b
         assert stats[b].iters == s1.iters and torch.equal(alphas[b], a1), b
+
+
+def test_batch_with_stored_kernel_matrices_matches_single_solves():
+    """materialized: the 14500- and 6000-site maps' float64 outer residuals
+    stream a G stored once per call, in the batch as in the single solver, so
+    the batch reproduces the single solves with the same option bit for bit
+    (no map here moves its inner products to float64, where the single solver
+    would also stream the stored G); the results agree with the recomputing
+    batch to the solve's tolerance."""
+    specs = [(14500, 1e-3, 3, 77), (1500, 1e-3, 2, 78), (6000, 1e-4, 4, 79)]
+    maps = []
+    for n, lam, ntx, seed in specs:
+        pr = make_problem(n, 32, lam, n_tx=ntx, seed=seed)
+        maps.append((pr, L().Problem(torch.tensor(pr.E, device=DEV), pr.lam, pr.scale)))
+    kw = dict(tol=1e-9, max_iter=100000, precision="bf16", refine=True, inner_tol=0.1, check_every=16)
+    alphas, stats, _ = L().pcg_solve_batched([p for _, p in maps], [pr.y for pr, _ in maps], None,
+                                             materialized=True, **kw)
+    ref, _, _ = L().pcg_solve_batched([p for _, p in maps], [pr.y for pr, _ in maps], None, **kw)
+    for b, (pr, p) in enumerate(maps):
+        a1, s1 = L().pcg_solve(p, pr.y, None, materialized=True, **kw)
+        assert stats[b].status == 0 and stats[b].relres_true <= 1e-9, b
+        assert s1.escalations < 2, b
+        assert stats[b].iters == s1.iters and torch.equal(alphas[b], a1), b
+        err = float((alphas[b] - ref[b]).norm() / ref[b].norm())
+        A = O.system_matrix(pr.E, pr.scale, pr.lam) if pr.n <= 6000 else None
+        if A is not None:
+            assert O.relative_residual(A, alphas[b].cpu().numpy(), pr.y) <= 2e-9, b
+        assert err <= 1e-6, (b, err)
