@@ -124,7 +124,8 @@ def batched_leg(L, LR, dev, count, train_maps, train_epochs):
         pr = make_problem(n, 32, lam, n_tx=ntx, seed=seed)
         probs.append(L.Problem(torch.tensor(pr.E, device=dev), pr.lam, pr.scale))
         ys.append(torch.tensor(pr.y, device=dev))
-    kw = dict(tol=1e-6, max_iter=200000, precision="bf16", refine=True, inner_tol=0.1, ir_max=64, check_every=32)
+    kw = dict(tol=1e-6, max_iter=200000, precision="bf16", refine=True, inner_tol=0.1, ir_max=64, check_every=32,
+              materialized=True)
     # autotune once (cached per size class), then time
     precs = [L.learned_precond(p, model) for p in probs]
     L.pcg_solve_batched(probs, ys, precs, cols_per_split=-1, xcd_order=False, allow_noconv=True, **kw)
