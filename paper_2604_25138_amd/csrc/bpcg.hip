@@ -89,15 +89,21 @@ __global__ __launch_bounds__(kThreads) void b_lr_t_partial_kernel(const BDesc* _
 __global__ __launch_bounds__(kThreads) void b_lr_t_finish_kernel(const BDesc* __restrict__ D, const int* __restrict__ R, int decide, int masked) {
   const BDesc& d = D[R[blockIdx.y]];
   const int nb = (d.nrp + 15) / 16;
-  if ((masked && !d.active) || (int)blockIdx.x >= nb) return;
+  if ((masked && !d.active) || (int)blockIdx.x >= nb || lr_fused_t(d.n, d.nrp)) return;
   lr_t_finish_body(blockIdx.x, nb, d.tpart, d.nbt, d.nrp, d.t, d.S, decide ? d.rrp : nullptr, d.nbt);
 }
 
 template <typename MT>
-__global__ __launch_bounds__(kThreads) void b_lr_apply_kernel(const BDesc* __restrict__ D, const int* __restrict__ R, int masked) {
+__global__ __launch_bounds__(kThreads) void b_lr_apply_kernel(const BDesc* __restrict__ D, const int* __restrict__ R, int masked,
+                                                              int decide) {
   const BDesc& d = D[R[blockIdx.y]];
   if ((masked && !d.active) || (int)blockIdx.x >= d.ga) return;
-  lr_apply_body<MT>(blockIdx.x, d.ga, (const MT*)d.Bt, d.t, d.r, d.th, d.n, d.nrp, d.c0p, d.dinv, d.S, d.rzp);
+  // (as the single solver: t finished inside the apply for N_r <= 64 on up to 16384 sites)
+  if (lr_fused_t(d.n, d.nrp))
+    lr_apply_t_body<MT>(blockIdx.x, d.tpart, d.nbt, (const MT*)d.Bt, d.r, d.th, d.n, d.nrp, d.c0p, d.dinv, d.S,
+                        decide ? d.rrp : nullptr, d.nbt, d.rzp);
+  else
+    lr_apply_body<MT>(blockIdx.x, d.ga, (const MT*)d.Bt, d.t, d.r, d.th, d.n, d.nrp, d.c0p, d.dinv, d.S, d.rzp);
 }
 
 __global__ __launch_bounds__(kThreads) void b_jacobi_apply_kernel(const BDesc* __restrict__ D, const int* __restrict__ R) {
@@ -257,7 +263,8 @@ laker_status pcg_batch(int count, const Problem* pbs, const SolveWs* wss, const 
     d.n = pb.n;
     d.lam = pb.lambda;
     d.g = red_blocks(pb.n);
-    d.ga = apply_blocks(pb.n);
+    // blocks of the preconditioner apply (one r^T theta partial each)
+    d.ga = lowrank && lr_fused_t(pb.n, Ps[b].nrp) ? (int)((pb.n + kTRows - 1) / kTRows) : apply_blocks(pb.n);
     d.nbt = (int)((pb.n + kTRows - 1) / kTRows);
     d.S = w.S;
     d.r = w.r;
@@ -497,8 +504,8 @@ laker_status pcg_batch(int count, const Problem* pbs, const SolveWs* wss, const 
       LK_CHECK_LAUNCH();
       b_lr_t_finish_kernel<<<dim3(gfx, nit), kThreads, 0, s2>>>(bw.desc, bw.run_it, 1, 0);
       LK_CHECK_LAUNCH();
-      if (f32) b_lr_apply_kernel<float><<<dim3(gax, nit), kThreads, 0, s2>>>(bw.desc, bw.run_it, 0);
-      else b_lr_apply_kernel<double><<<dim3(gax, nit), kThreads, 0, s2>>>(bw.desc, bw.run_it, 0);
+      if (f32) b_lr_apply_kernel<float><<<dim3(gax, nit), kThreads, 0, s2>>>(bw.desc, bw.run_it, 0, 1);
+      else b_lr_apply_kernel<double><<<dim3(gax, nit), kThreads, 0, s2>>>(bw.desc, bw.run_it, 0, 1);
       LK_CHECK_LAUNCH();
       b_pupdate_kernel<LAKER_PRECOND_CCCP><<<dim3(gx, nit), kThreads, 0, s2>>>(bw.desc, bw.run_it, 0, 0);
     } else if (kind == LAKER_PRECOND_JACOBI) {
@@ -532,8 +539,8 @@ laker_status pcg_batch(int count, const Problem* pbs, const SolveWs* wss, const 
       LK_CHECK_LAUNCH();
       b_lr_t_finish_kernel<<<dim3(gfx, nop), kThreads, 0, st>>>(bw.desc, bw.run_op, 0, 1);
       LK_CHECK_LAUNCH();
-      if (f32) b_lr_apply_kernel<float><<<dim3(gax, nop), kThreads, 0, st>>>(bw.desc, bw.run_op, 1);
-      else b_lr_apply_kernel<double><<<dim3(gax, nop), kThreads, 0, st>>>(bw.desc, bw.run_op, 1);
+      if (f32) b_lr_apply_kernel<float><<<dim3(gax, nop), kThreads, 0, st>>>(bw.desc, bw.run_op, 1, 0);
+      else b_lr_apply_kernel<double><<<dim3(gax, nop), kThreads, 0, st>>>(bw.desc, bw.run_op, 1, 0);
       LK_CHECK_LAUNCH();
       b_pupdate_kernel<LAKER_PRECOND_CCCP><<<dim3(gx, nop), kThreads, 0, st>>>(bw.desc, bw.run_op, 1, 1);
     } else if (kind == LAKER_PRECOND_JACOBI) {

@@ -125,6 +125,17 @@ __global__ __launch_bounds__(kThreads) void lr_apply_kernel(const MT* __restrict
   lr_apply_body<MT>(blockIdx.x, gridDim.x, Bt, t, r, theta, n, nrp, c0p, dinv, S, rzp);
 }
 
+template <typename MT>
+__global__ __launch_bounds__(kThreads) void lr_apply_t_kernel(const double* __restrict__ tpart, int nb,
+                                                              const MT* __restrict__ Bt, const double* __restrict__ r,
+                                                              double* __restrict__ theta, int64_t n, int nrp,
+                                                              const double* __restrict__ c0p,
+                                                              const double* __restrict__ dinv, PcgScalars* S,
+                                                              const double* __restrict__ rrp, int grr,
+                                                              double* __restrict__ rzp) {
+  lr_apply_t_body<MT>(blockIdx.x, tpart, nb, Bt, r, theta, n, nrp, c0p, dinv, S, rrp, grr, rzp);
+}
+
 __global__ __launch_bounds__(kThreads) void resid_kernel(const double* __restrict__ y, const double* __restrict__ w,
                                                          double* __restrict__ r, int64_t n,
                                                          double* __restrict__ bpart, unsigned* cnt, double* out2) {
@@ -147,6 +158,13 @@ laker_status enqueue_lowrank(const PrecondView& P, const double* r, double* thet
   if (!skip_partial) {
     lr_t_partial_kernel<MT><<<nb, kThreads, 0, st>>>((const MT*)P.B, r, n, P.nrp, tpart, S);
     LK_CHECK_LAUNCH();
+  }
+  if (lr_fused_t(n, P.nrp)) {
+    // t finished inside the apply (nb blocks of 64 rows; r^T theta partials: nb)
+    lr_apply_t_kernel<MT><<<nb, kThreads, 0, st>>>(tpart, nb, (const MT*)P.Bt, r, theta, n, P.nrp, P.c0p,
+                                                   (const double*)P.dinv, S, rrp, grr, rzp);
+    LK_CHECK_LAUNCH();
+    return LAKER_OK;
   }
   lr_t_finish_kernel<<<(P.nrp + 15) / 16, kThreads, 0, st>>>(tpart, nb, P.nrp, t, S, rrp, grr);
   LK_CHECK_LAUNCH();
@@ -251,7 +269,9 @@ laker_status pcg_run(const Problem& pb, const SolveWs& ws, const PrecondView& P,
                      laker_stats* stats, hipStream_t st) {
   const int64_t n = pb.n;
   const int g = red_blocks(n);
-  const int ga = apply_blocks(n);
+  const bool lowrank0 = P.kind == LAKER_PRECOND_CCCP || P.kind == LAKER_PRECOND_LEARNED;
+  // partials of r^T theta: one per block of the preconditioner apply
+  const int ga = lowrank0 && lr_fused_t(n, P.nrp) ? (int)((n + kTRows - 1) / kTRows) : apply_blocks(n);
   double* r = ws.r;
   double* p = ws.p;
   double* Ap = ws.ap;

@@ -547,6 +547,106 @@ __device__ __forceinline__ void lr_apply_body(int blk, int nblk, const MT* __res
   if (threadIdx.x == 0 && rzp != nullptr) rzp[blk] = rz;
 }
 
+// theta = c r + Bt t with t = B^T r finished here, for N_r <= 64 and at most
+// kFuseRows partial rows of t: every block adds all the partial rows itself,
+// in one fixed order (thread (q, c) takes column c of rows q, q + 4, ...; the
+// four sums are then added in q order), so t needs no pass and launch of its
+// own.  Block b owns rows [64 b, 64 b + 64), four passes of 16 rows (16 lanes
+// per row, as lr_apply_body).  With rrp set it first takes the stopping
+// decision of iteration k, as the separate finishing pass does; the loads of
+// the decision's and of t's partials are issued before it.
+constexpr int kFuseRows = 256;
+__host__ __device__ inline bool lr_fused_t(int64_t n, int nrp) { return nrp <= 64 && (n + kTRows - 1) / kTRows <= kFuseRows; }
+
+template <typename MT>
+__device__ __forceinline__ void lr_apply_t_body(int blk, const double* __restrict__ tpart, int nb,
+                                                const MT* __restrict__ Bt, const double* __restrict__ r,
+                                                double* __restrict__ theta, int64_t n, int nrp,
+                                                const double* __restrict__ c0p, const double* __restrict__ dinv,
+                                                PcgScalars* S, const double* __restrict__ rrp, int grr,
+                                                double* __restrict__ rzp) {
+  if (S != nullptr && S->done) return;
+  constexpr int VEC = 16 / (int)sizeof(MT);
+  constexpr int MAXR = kFuseRows / 4;
+  constexpr int MAXV = 64 / VEC / 16;
+  using VT = typename std::conditional<VEC == 4, float4, double2>::type;
+  __shared__ double sh[16];
+  __shared__ double ts[64];
+  __shared__ double red[4][64];
+  const int tid = threadIdx.x;
+  const int q = tid >> 6, c = tid & 63;
+  static_assert(kMaxBlocks <= 4 * kThreads, "four partials per thread");
+  const int per = rrp != nullptr ? (grr + kThreads - 1) / kThreads : 0;
+  double rv[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int idx = tid * per + u;
+    rv[u] = u < per && idx < grr ? rrp[idx] : 0.0;
+  }
+  double tv[MAXR];
+#pragma unroll
+  for (int u = 0; u < MAXR; ++u) {
+    const int row = q + 4 * u;
+    tv[u] = c < nrp && row < nb ? tpart[(int64_t)row * nrp + c] : 0.0;
+  }
+  if (rrp != nullptr) {
+    double v = 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (u < per && tid * per + u < grr) v += rv[u];
+    if (!pcg_decide_rr(blk, S->kcur - 1, S, block_sum(v, sh))) return;
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int u = 0; u < MAXR; ++u)
+    if (c < nrp && q + 4 * u < nb) s += tv[u];
+  red[q][c] = s;
+  __syncthreads();
+  if (tid < nrp) ts[tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+  __syncthreads();
+  const int sub = tid & 15, rl = tid >> 4;
+  const int nvec = nrp / VEC;
+  double rz = 0.0;
+  for (int pass = 0; pass < 4; ++pass) {
+    const int64_t i = (int64_t)blk * 64 + pass * 16 + rl;
+    double acc = 0.0;
+    if (i < n) {
+      const MT* row = Bt + i * nrp;
+      VT x[MAXV];
+#pragma unroll
+      for (int j = 0; j < MAXV; ++j)
+        if (sub + 16 * j < nvec) x[j] = *reinterpret_cast<const VT*>(row + VEC * (sub + 16 * j));
+#pragma unroll
+      for (int j = 0; j < MAXV; ++j) {
+        if (sub + 16 * j < nvec) {
+          const int v = sub + 16 * j;
+          if constexpr (VEC == 4) {
+            acc = fma((double)x[j].x, ts[4 * v + 0], acc);
+            acc = fma((double)x[j].y, ts[4 * v + 1], acc);
+            acc = fma((double)x[j].z, ts[4 * v + 2], acc);
+            acc = fma((double)x[j].w, ts[4 * v + 3], acc);
+          } else {
+            acc = fma(x[j].x, ts[2 * v + 0], acc);
+            acc = fma(x[j].y, ts[2 * v + 1], acc);
+          }
+        }
+      }
+    }
+    acc += __shfl_xor(acc, 1, 64);
+    acc += __shfl_xor(acc, 2, 64);
+    acc += __shfl_xor(acc, 4, 64);
+    acc += __shfl_xor(acc, 8, 64);
+    if (sub == 0 && i < n) {
+      const double ri = r[i];
+      const double th = fma(dinv != nullptr ? dinv[i] : c0p[0], ri, acc);
+      theta[i] = th;
+      rz += ri * th;
+    }
+  }
+  rz = block_sum(rz, sh);
+  if (threadIdx.x == 0 && rzp != nullptr) rzp[blk] = rz;
+}
+
 // ||y - w||^2 and ||y||^2 (float64), for the true residual; r = y - w if r is set.
 __device__ __forceinline__ void resid_body(int blk, int nblk, const double* __restrict__ y, const double* __restrict__ w,
                                                          double* __restrict__ r, int64_t n,
