@@ -146,10 +146,11 @@ __global__ void axpy_kernel(double* __restrict__ x, const double* __restrict__ d
   axpy_body(blockIdx.x, gridDim.x, x, d, n);
 }
 
-// theta = P r for the low-rank preconditioner (three passes); with rrp set the
-// middle pass first takes the stopping decision of iteration k, and the first
-// pass is skipped when `skip_partial` says the fused update already wrote the
-// t partials.
+// theta = P r for the low-rank preconditioner (t partials, t, theta: three
+// passes, or two when the apply finishes t itself, lr_fused_t); with rrp set
+// the pass that finishes t first takes the stopping decision of iteration k,
+// and the first pass is skipped when `skip_partial` says the fused update
+// already wrote the t partials.
 template <typename MT>
 laker_status enqueue_lowrank(const PrecondView& P, const double* r, double* theta, int64_t n, PcgScalars* S,
                              const double* rrp, int grr, double* rzp, double* tpart, double* t, bool skip_partial,
