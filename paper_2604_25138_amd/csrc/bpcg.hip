@@ -89,7 +89,12 @@ __global__ __launch_bounds__(kThreads) void b_lr_t_partial_kernel(const BDesc* _
 __global__ __launch_bounds__(kThreads) void b_lr_t_finish_kernel(const BDesc* __restrict__ D, const int* __restrict__ R, int decide, int masked) {
   const BDesc& d = D[R[blockIdx.y]];
   const int nb = (d.nrp + 15) / 16;
-  if ((masked && !d.active) || (int)blockIdx.x >= nb || lr_fused_t(d.n, d.nrp)) return;
+  if ((masked && !d.active) || (int)blockIdx.x >= nb) return;
+  if (lr_fused_t(d.n, d.nrp)) {
+    // t in the single solver's fused order, by one block (see lr_t_finish_fused_order_body)
+    if (blockIdx.x == 0) lr_t_finish_fused_order_body(d.tpart, d.nbt, d.nrp, d.t, d.S, decide ? d.rrp : nullptr, d.nbt);
+    return;
+  }
   lr_t_finish_body(blockIdx.x, nb, d.tpart, d.nbt, d.nrp, d.t, d.S, decide ? d.rrp : nullptr, d.nbt);
 }
 
@@ -98,10 +103,11 @@ __global__ __launch_bounds__(kThreads) void b_lr_apply_kernel(const BDesc* __res
                                                               int decide) {
   const BDesc& d = D[R[blockIdx.y]];
   if ((masked && !d.active) || (int)blockIdx.x >= d.ga) return;
-  // (as the single solver: t finished inside the apply for N_r <= 64 on up to 16384 sites)
+  // (rows and r^T theta partials as the single solver's fused apply, t from the
+  // preceding pass in the same order: the iterates stay bitwise equal)
   if (lr_fused_t(d.n, d.nrp))
     lr_apply_t_body<MT>(blockIdx.x, d.tpart, d.nbt, (const MT*)d.Bt, d.r, d.th, d.n, d.nrp, d.c0p, d.dinv, d.S,
-                        decide ? d.rrp : nullptr, d.nbt, d.rzp);
+                        nullptr, 0, d.rzp, d.t);
   else
     lr_apply_body<MT>(blockIdx.x, d.ga, (const MT*)d.Bt, d.t, d.r, d.th, d.n, d.nrp, d.c0p, d.dinv, d.S, d.rzp);
 }

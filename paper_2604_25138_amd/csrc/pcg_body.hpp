@@ -558,20 +558,15 @@ __device__ __forceinline__ void lr_apply_body(int blk, int nblk, const MT* __res
 constexpr int kFuseRows = 256;
 __host__ __device__ inline bool lr_fused_t(int64_t n, int nrp) { return nrp <= 64 && (n + kTRows - 1) / kTRows <= kFuseRows; }
 
-template <typename MT>
-__device__ __forceinline__ void lr_apply_t_body(int blk, const double* __restrict__ tpart, int nb,
-                                                const MT* __restrict__ Bt, const double* __restrict__ r,
-                                                double* __restrict__ theta, int64_t n, int nrp,
-                                                const double* __restrict__ c0p, const double* __restrict__ dinv,
-                                                PcgScalars* S, const double* __restrict__ rrp, int grr,
-                                                double* __restrict__ rzp) {
-  if (S != nullptr && S->done) return;
-  constexpr int VEC = 16 / (int)sizeof(MT);
+// t = B^T r from the t partials in the fused apply's order (thread (q, c):
+// column c of rows q, q + 4, ...; then the four sums in q order), into
+// ts[0 .. nrp);
+// with rrp set, the stopping decision of iteration k first.  Returns false
+// when the iteration has stopped.  One whole block of kThreads.
+__device__ __forceinline__ bool t_fused_order(int blk, const double* __restrict__ tpart, int nb, int nrp,
+                                              PcgScalars* S, const double* __restrict__ rrp, int grr, double* ts,
+                                              double* sh) {
   constexpr int MAXR = kFuseRows / 4;
-  constexpr int MAXV = 64 / VEC / 16;
-  using VT = typename std::conditional<VEC == 4, float4, double2>::type;
-  __shared__ double sh[16];
-  __shared__ double ts[64];
   __shared__ double red[4][64];
   const int tid = threadIdx.x;
   const int q = tid >> 6, c = tid & 63;
@@ -594,7 +589,7 @@ __device__ __forceinline__ void lr_apply_t_body(int blk, const double* __restric
 #pragma unroll
     for (int u = 0; u < 4; ++u)
       if (u < per && tid * per + u < grr) v += rv[u];
-    if (!pcg_decide_rr(blk, S->kcur - 1, S, block_sum(v, sh))) return;
+    if (!pcg_decide_rr(blk, S->kcur - 1, S, block_sum(v, sh))) return false;
   }
   double s = 0.0;
 #pragma unroll
@@ -604,6 +599,43 @@ __device__ __forceinline__ void lr_apply_t_body(int blk, const double* __restric
   __syncthreads();
   if (tid < nrp) ts[tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
   __syncthreads();
+  return true;
+}
+
+// The same t as a separate pass (one block), for the batched solver, whose
+// maps share one launch: there every block of every map adding all partial
+// rows would multiply the L2 reads.  t_in of lr_apply_t_body then takes it.
+__device__ __forceinline__ void lr_t_finish_fused_order_body(const double* __restrict__ tpart, int nb, int nrp,
+                                                             double* __restrict__ t, PcgScalars* S,
+                                                             const double* __restrict__ rrp, int grr) {
+  if (S != nullptr && S->done) return;
+  __shared__ double sh[16];
+  __shared__ double ts[64];
+  if (!t_fused_order(0, tpart, nb, nrp, S, rrp, grr, ts, sh)) return;
+  if (threadIdx.x < nrp) t[threadIdx.x] = ts[threadIdx.x];
+}
+
+template <typename MT>
+__device__ __forceinline__ void lr_apply_t_body(int blk, const double* __restrict__ tpart, int nb,
+                                                const MT* __restrict__ Bt, const double* __restrict__ r,
+                                                double* __restrict__ theta, int64_t n, int nrp,
+                                                const double* __restrict__ c0p, const double* __restrict__ dinv,
+                                                PcgScalars* S, const double* __restrict__ rrp, int grr,
+                                                double* __restrict__ rzp, const double* __restrict__ t_in = nullptr) {
+  if (S != nullptr && S->done) return;
+  constexpr int VEC = 16 / (int)sizeof(MT);
+  constexpr int MAXV = 64 / VEC / 16;
+  using VT = typename std::conditional<VEC == 4, float4, double2>::type;
+  __shared__ double sh[16];
+  __shared__ double ts[64];
+  const int tid = threadIdx.x;
+  if (t_in != nullptr) {
+    // t already finished (in the fused order) by a separate pass
+    if (tid < nrp) ts[tid] = t_in[tid];
+    __syncthreads();
+  } else if (!t_fused_order(blk, tpart, nb, nrp, S, rrp, grr, ts, sh)) {
+    return;
+  }
   const int sub = tid & 15, rl = tid >> 4;
   const int nvec = nrp / VEC;
   double rz = 0.0;
