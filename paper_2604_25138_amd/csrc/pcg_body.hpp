@@ -629,6 +629,28 @@ __device__ __forceinline__ void lr_apply_t_body(int blk, const double* __restric
   __shared__ double sh[16];
   __shared__ double ts[64];
   const int tid = threadIdx.x;
+  const int sub = tid & 15, rl = tid >> 4;
+  const int nvec = nrp / VEC;
+  // the block's rows of Bt, r and the diagonal for all four passes are loaded
+  // first: none depends on t, so their latency overlaps the t reduction
+  VT x[4][MAXV];
+  double rv4[4], cv4[4];
+#pragma unroll
+  for (int pass = 0; pass < 4; ++pass) {
+    const int64_t i = (int64_t)blk * 64 + pass * 16 + rl;
+    rv4[pass] = 0.0;
+    cv4[pass] = 0.0;
+    if (i < n) {
+      const MT* row = Bt + i * nrp;
+#pragma unroll
+      for (int j = 0; j < MAXV; ++j)
+        if (sub + 16 * j < nvec) x[pass][j] = *reinterpret_cast<const VT*>(row + VEC * (sub + 16 * j));
+      if (sub == 0) {
+        rv4[pass] = r[i];
+        cv4[pass] = dinv != nullptr ? dinv[i] : c0p[0];
+      }
+    }
+  }
   if (t_in != nullptr) {
     // t already finished (in the fused order) by a separate pass
     if (tid < nrp) ts[tid] = t_in[tid];
@@ -636,30 +658,24 @@ __device__ __forceinline__ void lr_apply_t_body(int blk, const double* __restric
   } else if (!t_fused_order(blk, tpart, nb, nrp, S, rrp, grr, ts, sh)) {
     return;
   }
-  const int sub = tid & 15, rl = tid >> 4;
-  const int nvec = nrp / VEC;
   double rz = 0.0;
+#pragma unroll
   for (int pass = 0; pass < 4; ++pass) {
     const int64_t i = (int64_t)blk * 64 + pass * 16 + rl;
     double acc = 0.0;
     if (i < n) {
-      const MT* row = Bt + i * nrp;
-      VT x[MAXV];
-#pragma unroll
-      for (int j = 0; j < MAXV; ++j)
-        if (sub + 16 * j < nvec) x[j] = *reinterpret_cast<const VT*>(row + VEC * (sub + 16 * j));
 #pragma unroll
       for (int j = 0; j < MAXV; ++j) {
         if (sub + 16 * j < nvec) {
           const int v = sub + 16 * j;
           if constexpr (VEC == 4) {
-            acc = fma((double)x[j].x, ts[4 * v + 0], acc);
-            acc = fma((double)x[j].y, ts[4 * v + 1], acc);
-            acc = fma((double)x[j].z, ts[4 * v + 2], acc);
-            acc = fma((double)x[j].w, ts[4 * v + 3], acc);
+            acc = fma((double)x[pass][j].x, ts[4 * v + 0], acc);
+            acc = fma((double)x[pass][j].y, ts[4 * v + 1], acc);
+            acc = fma((double)x[pass][j].z, ts[4 * v + 2], acc);
+            acc = fma((double)x[pass][j].w, ts[4 * v + 3], acc);
           } else {
-            acc = fma(x[j].x, ts[2 * v + 0], acc);
-            acc = fma(x[j].y, ts[2 * v + 1], acc);
+            acc = fma(x[pass][j].x, ts[2 * v + 0], acc);
+            acc = fma(x[pass][j].y, ts[2 * v + 1], acc);
           }
         }
       }
@@ -669,8 +685,8 @@ __device__ __forceinline__ void lr_apply_t_body(int blk, const double* __restric
     acc += __shfl_xor(acc, 4, 64);
     acc += __shfl_xor(acc, 8, 64);
     if (sub == 0 && i < n) {
-      const double ri = r[i];
-      const double th = fma(dinv != nullptr ? dinv[i] : c0p[0], ri, acc);
+      const double ri = rv4[pass];
+      const double th = fma(cv4[pass], ri, acc);
       theta[i] = th;
       rz += ri * th;
     }
