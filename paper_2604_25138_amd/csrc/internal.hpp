@@ -134,6 +134,34 @@ struct PartSum {
     for (; k < cnt; k += Q) s += part[(k < nr ? k : c0 + k) * m + i];
     return s;
   }
+  // row_strided with all (at most MAXC) of the thread's loads issued at once;
+  // the same sum, in the same order; longer lists take row_strided
+  template <int MAXC>
+  __device__ __forceinline__ double row_strided_all(const double* __restrict__ part, int64_t m, int64_t i, int q,
+                                                    int Q) const {
+    int64_t nr = nsplit, cnt = nsplit, c0 = 0;
+    if (sym) {
+      const int64_t I = i / kSymRows;
+      const int64_t t = sym_pos_of(I, sp.nrb);
+      const int64_t b0 = sym_block_of(sym_pos_start(t, sp.nrb, sp.ncs), sp.grid, sp.T);
+      const int64_t b1 = sym_block_of(sym_pos_start(t + 1, sp.nrb, sp.ncs) - 1, sp.grid, sp.T);
+      nr = b1 - b0 + 1;
+      cnt = nr + I;
+      c0 = sp.rs - nr;
+    }
+    if (cnt > q + (int64_t)MAXC * Q) return row_strided(part, m, i, q, Q);
+    double v[MAXC];
+#pragma unroll
+    for (int u = 0; u < MAXC; ++u) {
+      const int64_t kk = q + (int64_t)u * Q;
+      v[u] = kk < cnt ? part[(kk < nr ? kk : c0 + kk) * m + i] : 0.0;
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int u = 0; u < MAXC; ++u)
+      if (q + (int64_t)u * Q < cnt) s += v[u];
+    return s;
+  }
 };
 inline PartSum part_sum(const KmvPlan& pl) {
   PartSum ps;

@@ -339,7 +339,8 @@ __device__ __forceinline__ void pcg_update_t_body(int blk, int nblk, double* __r
   }
   if (Ap == nullptr) {
     const int64_t i = i0 + (tid % kTRows);
-    apq[tid / kTRows][tid % kTRows] = i < n ? ps.row_strided(part, n, i, tid / kTRows, kThreads / kTRows) : 0.0;
+    apq[tid / kTRows][tid % kTRows] =
+        i < n ? ps.row_strided_all<24>(part, n, i, tid / kTRows, kThreads / kTRows) : 0.0;
   }
   double v = 0.0;
 #pragma unroll
