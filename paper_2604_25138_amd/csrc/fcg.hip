@@ -141,11 +141,16 @@ laker_status fcg_run(const Problem& pb, const SolveWs& W, const PrecondView& P, 
     int cap = o.max_iter - used;
     if (cap > inner_cap) cap = inner_cap;
     const double itol = fmax(o.inner_tol, 0.5 * o.tol / rel);
-    laker_status ri =
-        pcg_run(pb, W, P, r, z, false, itol, cap, check, o.precision, o.graph != 0, o.profile != 0, &inner, st);
+    // (a single chunk is only enqueued; its iteration count is read with the
+    // step's scalars below, saving a host round trip per outer step)
+    const bool defer = check >= cap && !o.graph && !o.profile;
+    laker_status ri = pcg_run(pb, W, P, r, z, false, itol, cap, check, o.precision, o.graph != 0, o.profile != 0,
+                              &inner, st, defer);
     if (ri == LAKER_EHIP || ri == LAKER_EINVAL) return ri;
-    used += inner.iters;
-    sp->iters = used;
+    if (!defer) {
+      used += inner.iters;
+      sp->iters = used;
+    }
     if (inner.kmv_count > 0) {
       const double prev = sp->kmv_ms * sp->kmv_count;
       sp->kmv_count += inner.kmv_count;
@@ -169,7 +174,16 @@ laker_status fcg_run(const Problem& pb, const SolveWs& W, const PrecondView& P, 
     LK_TRY(dots_dev(p, q, p, r));
     step_kernel<<<g, kT, 0, st>>>(alpha, r, p, q, s, n);
     LK_CHECK_LAUNCH();
-    LK_TRY(dots(r, r, r, r, h));
+    // ||r||^2, the scalars and (deferred inner solve) its iteration count in one host read
+    int inner_iters = 0;
+    LK_TRY(dots_dev(r, r, r, r));
+    if (defer) LK_TRY(hipMemcpyAsync(&inner_iters, &W.S->iters, sizeof(int), hipMemcpyDeviceToHost, st));
+    LK_TRY(hipMemcpyAsync(h, s, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+    LK_TRY(hipStreamSynchronize(st));
+    if (defer) {
+      used += inner_iters;
+      sp->iters = used;
+    }
     if (h[3] != 0.0) return LAKER_EBREAKDOWN;
     rel = ynorm > 0.0 ? sqrt(h[0]) / ynorm : 0.0;
     if (k + 1 < 64) sp->ir_relres[k + 1] = rel;

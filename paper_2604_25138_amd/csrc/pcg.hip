@@ -267,7 +267,7 @@ laker_status true_residual(const Problem& pb, const SolveWs& ws, const double* y
 
 laker_status pcg_run(const Problem& pb, const SolveWs& ws, const PrecondView& P, const double* rhs, double* alpha,
                      bool warm, double tol, int max_iter, int check_every, int prec, bool use_graph, bool profile,
-                     laker_stats* stats, hipStream_t st) {
+                     laker_stats* stats, hipStream_t st, bool defer) {
   const int64_t n = pb.n;
   const int g = red_blocks(n);
   const bool lowrank0 = P.kind == LAKER_PRECOND_CCCP || P.kind == LAKER_PRECOND_LEARNED;
@@ -411,6 +411,15 @@ laker_status pcg_run(const Problem& pb, const SolveWs& ws, const PrecondView& P,
       if (gexec != nullptr) (void)hipGraphExecDestroy(gexec);
       return LAKER_EHIP;
     }
+  }
+  if (defer && gexec == nullptr && !prof && check_every >= max_iter) {
+    // one chunk holds every iteration the cap allows (the cap ends the loop
+    // on the device; later launches return at entry)
+    for (int c = 0; c < check_every; ++c) {
+      const laker_status e = enqueue_iteration(st);
+      if (e != LAKER_OK) return e;
+    }
+    return LAKER_OK;
   }
   PcgScalars hs;
   int k = 0;

@@ -82,9 +82,12 @@ struct PrecondLayout {
 PrecondLayout precond_layout(void* base, int64_t n, int nr);
 inline int pad_nr(int nr) { return (nr + 3) & ~3; }
 
+// defer: when one chunk covers max_iter (eager launches, no profiling), the
+// iterations are only enqueued: the call returns LAKER_OK at once and the
+// caller reads ws.S (iters, done) after its own next synchronisation.
 laker_status pcg_run(const Problem& pb, const SolveWs& ws, const PrecondView& P, const double* rhs, double* alpha,
                      bool warm, double tol, int max_iter, int check_every, int prec, bool use_graph,
-                     bool profile, laker_stats* stats, hipStream_t st);
+                     bool profile, laker_stats* stats, hipStream_t st, bool defer = false);
 laker_status true_residual(const Problem& pb, const SolveWs& ws, const double* y, const double* alpha,
                            double* r_out, double* relres, bool have_alpha, hipStream_t st);
 laker_status axpy_inplace(double* x, const double* d, int64_t n, hipStream_t st);
