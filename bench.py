@@ -58,6 +58,7 @@ PEAK_VALU_TOPS = 256 * 128 * 2.4e9 / 1e12
 EXP2_SLOTS = 4.0
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_BF16_MFMA_TFLOPS = 2500.0
+PEAK_HBM_GBS = 8000.0
 
 
 def parse():
@@ -270,7 +271,14 @@ def main():
             "relres_true": s32.relres_true, "us_per_product": s32p.kmv_ms * 1e3}
     sb32 = L.load().laker_kmat_bytes(pr.n, pr.d, L.F32)
     f32c["stored"]["gb_per_s"] = sb32 / (f32c["stored"]["us_per_product"] * 1e-6) / 1e9
+    f32c["stored"]["frac_of_hbm_peak"] = f32c["stored"]["gb_per_s"] / PEAK_HBM_GBS
     f32c["stored_bytes"] = sb32
+    # the recomputed float32 product against its two bounds: the ALU slots of
+    # the symmetric schedule (as the headline roofline) and the fp32 MFMA flops
+    us32 = f32c["recomputed"]["us_per_product"] * 1e-6
+    dist = pr.n * (pr.n + 1) / 2.0
+    f32c["recomputed"]["frac_of_alu_peak"] = (EXP2_SLOTS * dist + float(pr.n) * pr.n) / us32 / 1e12 / PEAK_VALU_TOPS
+    f32c["recomputed"]["frac_of_fp32_mfma_peak"] = 2.0 * pr.d * dist / us32 / 1e12 / PEAK_FP32_MFMA_TFLOPS
     extra["f32_stored_vs_recomputed"] = f32c
 
     # roofline of the dominant kernel: the fused product exp2(<e_i, e_j>) p of
