@@ -525,3 +525,19 @@ def test_stored_kernel_matrix_below_threshold_is_ignored():
     a1, s1 = L().pcg_solve(prob, pr.y, None, tol=1e-11, max_iter=5000, materialized=True)
     a2, s2 = L().pcg_solve(prob, pr.y, None, tol=1e-11, max_iter=5000)
     assert s1.iters == s2.iters and torch.equal(a1, a2)
+
+
+def test_flexible_cg_deferred_inner_solves_match():
+    """An inner solve that fits one chunk is enqueued without a host round trip
+    (its iteration count read with the outer step's scalars); the iterate and
+    the counts equal those of the waiting form (profiling waits) bit for bit."""
+    pr, A, ref, Z = _sym_case(6000)
+    prob = _gp(pr)
+    pc = _sym_precond("cccp", prob, Z)
+    kw = dict(tol=1e-10, max_iter=50000, precision="bf16", refine=2, inner_tol=1e-1, ir_max=1000, check_every=30,
+              inner_max_iter=30)
+    a1, s1 = L().pcg_solve(prob, pr.y, pc, **kw)
+    a2, s2 = L().pcg_solve(prob, pr.y, pc, profile=True, **kw)
+    assert s1.status == 0 and s2.status == 0
+    assert s1.iters == s2.iters and s1.ir_steps == s2.ir_steps and torch.equal(a1, a2)
+    assert s2.kmv_count == s2.iters
