@@ -1,6 +1,6 @@
 """GPU parity of the HIP path against the FP64 oracle, through the C ABI.
 
-Sizes span several tiles and a ragged tail; the BASELINE-size checks use
+Sizes span several tiles and a ragged tail; the full-size checks (n = 16384, d = 64) use
 sampled rows the oracle computes one by one.  Tolerances:
   * float64 products: 1e-13 relative to sum_j |G_ij p_j| + lam |p_i| (FP64
     rounding of d-term dot products, exp and n-term sums);
