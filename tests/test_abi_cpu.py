@@ -115,3 +115,39 @@ def test_stored_kernel_matrix_options_validated_on_the_host():
     r = lib.laker_pcg_solve(C.byref(prob), None, C.c_void_p(8), C.c_void_p(8), C.byref(opts), C.c_void_p(8),
                             ws + lib.laker_kmat_bytes(n, d, laker.F64) // 2, C.byref(st), None)
     assert r == laker.LAKER_ENOMEM
+
+
+def test_empty_inputs_rejected_on_the_host():
+    """Degenerate sizes have no device work to do and are invalid calls: a
+    problem with no sites, a prediction with no query points, a batch with no
+    maps, and a batch holding one empty map all return LAKER_EINVAL (and the
+    size queries 0) before any launch."""
+    laker, lib = _lib()
+    st = laker.laker_stats()
+    empty = laker.laker_problem(0, 4, 0, 8, 1e-2, 0.5)
+    r = lib.laker_kernel_matvec(C.byref(empty), C.c_void_p(8), C.c_void_p(8), 0, C.c_void_p(8), 1 << 30, None)
+    assert r == laker.LAKER_EINVAL
+    opts = laker.laker_pcg_opts(1e-8, 10, 0, 0, 1, 1e-2, 0, 16)
+    r = lib.laker_pcg_solve(C.byref(empty), None, C.c_void_p(8), C.c_void_p(8), C.byref(opts), C.c_void_p(8),
+                            1 << 30, C.byref(st), None)
+    assert r == laker.LAKER_EINVAL
+    r = lib.laker_predict(C.byref(empty), C.c_void_p(8), 4, C.c_void_p(8), C.c_void_p(8), 0, C.c_void_p(8), 1 << 30,
+                          None)
+    assert r == laker.LAKER_EINVAL
+    prob = laker.laker_problem(16, 4, 0, 8, 1e-2, 0.5)
+    r = lib.laker_predict(C.byref(prob), C.c_void_p(8), 0, C.c_void_p(8), C.c_void_p(8), 0, C.c_void_p(8), 1 << 30,
+                          None)                                         # m = 0 query points
+    assert r == laker.LAKER_EINVAL
+    assert lib.laker_solve_workspace_bytes(0, 4, 0) == 0
+    assert lib.laker_kmat_bytes(0, 4, 0) == 0
+
+    probs = (laker.laker_problem * 2)(prob, empty)
+    ptrs = (C.c_void_p * 2)(8, 8)
+    sts = (laker.laker_stats * 2)()
+    bo = laker.laker_batch_opts(0, 0, 0, 0)
+    for count in (0, 2):                                                # no maps; an empty map
+        r = lib.laker_pcg_solve_batched(count, probs, None, ptrs, ptrs, C.byref(opts), C.byref(bo), C.c_void_p(8),
+                                        1 << 30, sts, None)
+        assert r == laker.LAKER_EINVAL, count
+    ns = (C.c_int64 * 2)(16, 0)
+    assert lib.laker_batch_workspace_bytes(2, ns, 4) == 0
