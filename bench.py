@@ -111,6 +111,11 @@ def train_model(L, LR, d, dev, n_maps, epochs):
     return model, info
 
 
+def _note(msg):
+    """Progress of the legs on stderr (stdout carries only the JSON line)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def batched_leg(L, LR, dev, count, train_maps, train_epochs):
     """Maps of uneven size (n ~ U[1024, 16384], d = 32, lambda log-uniform in
     [1e-5, 1e-2], 1..8 transmitters) solved together to float64 relative
@@ -136,6 +141,7 @@ def batched_leg(L, LR, dev, count, train_maps, train_epochs):
     _, st, used = L.pcg_solve_batched(probs, ys, precs, cols_per_split=-1, xcd_order=False, allow_noconv=True, **kw)
     torch.cuda.synchronize()
     b = time.perf_counter()
+    _note(f"batched leg: {count} maps together in {b - a:.2f} s; now one after the other")
     its_serial = []
     for p, y in zip(probs, ys):
         pc = L.learned_precond(p, model)
@@ -194,6 +200,7 @@ def main():
         return
 
     model, train_info = train_model(L, LR, pr.d, dev, args.train_maps, args.train_epochs)
+    _note("preconditioner network trained")
 
     def step():
         res = LR.solve_with_fallback(prob, y, model, Zd, tol=tol, budget=budget, precision="bf16", refine=2,
@@ -345,10 +352,12 @@ def main():
         "extra": extra,
     }
 
+    _note("timed step and comparison legs done")
     if args.batch_maps > 0:
         extra["batched"] = batched_leg(L, LR, dev, args.batch_maps, args.train_maps, args.train_epochs)
 
     if not args.no_cpu:
+        _note("CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline(pr, Z, tol, extra.get("f64_cccp_pcg", {}).get("pcg_iters"),
                                            args.cpu_budget)
     print(json.dumps(out))
