@@ -77,6 +77,9 @@ def parse():
     ap.add_argument("--train-epochs", type=int, default=TRAIN_EPOCHS)
     ap.add_argument("--batch-maps", type=int, default=32,
                     help="maps in the batched leg (n ~ U[1024, 16384], d = 32); 0 skips it")
+    ap.add_argument("--learned-eval", type=int, default=0,
+                    help="held-out maps of 32768 sites (d = 32) on which the learned preconditioner is compared "
+                         "with a CCCP fit; 0 (default) skips the leg")
     return ap.parse_args()
 
 
@@ -154,6 +157,54 @@ def batched_leg(L, LR, dev, count, train_maps, train_epochs):
             "speedup_vs_serial": (c - b) / (b - a), "converged": sum(1 for x in st if x.status == 0),
             "worst_relres_true": max(x.relres_true for x in st), "escalations": sum(x.escalations for x in st),
             "max_iters": max(x.iters for x in st), "cols_per_split_largest": used}
+
+
+def learned_eval_leg(L, LR, dev, count, train_maps, train_epochs):
+    """Held-out maps of 32768 sites (d = 32, lambda log-uniform in [1e-5, 1e-2],
+    1..8 transmitters, seeds outside the training set): time to float64
+    relative residual 1e-6 and inner iterations with the learned preconditioner
+    (built per map; CCCP fallback on a stall) against a CCCP fit and solve,
+    both by the flexible float64 outer CG around bf16 inner PCG."""
+    import numpy as np
+    import torch
+
+    from synth import default_n_r, make_directions, make_problem
+    model, _ = train_model(L, LR, 32, dev, train_maps, train_epochs)
+    rng = np.random.default_rng(777)
+    n = 32768
+    kw = dict(tol=1e-6, precision="bf16", refine=2, inner_tol=0.1, check_every=INNER_CAP, inner_max_iter=INNER_CAP,
+              materialized=True)
+    rows = []
+    for k in range(count):
+        lam = float(10 ** rng.uniform(-5, -2))
+        ntx = int(rng.integers(1, 9))
+        pr = make_problem(n, 32, lam, n_tx=ntx, seed=50000 + k)
+        prob = L.Problem(torch.tensor(pr.E, device=dev), pr.lam, pr.scale)
+        y = torch.tensor(pr.y, device=dev)
+        Zd = torch.tensor(make_directions(n, default_n_r(n), 50000 + k), device=dev)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        res = LR.solve_with_fallback(prob, y, model, Zd, budget=20000, gamma=0.1, **kw)
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        pc = L.fit_precond(prob, Zd, gamma=0.1, rho=0.0, precision="bf16")
+        _, st = L.pcg_solve(prob, y, pc, max_iter=100000, ir_max=1000, allow_noconv=True, **kw)
+        torch.cuda.synchronize()
+        c = time.perf_counter()
+        its = res.stats.iters + (res.learned_iters if res.fell_back else 0)
+        rows.append((its, b - a, res.fell_back, res.stats.status == 0, st.iters, c - b, st.status == 0))
+        if (k + 1) % 8 == 0:
+            _note(f"learned evaluation: {k + 1} of {count} maps")
+    it_l = np.array([r[0] for r in rows], dtype=float)
+    it_c = np.array([r[4] for r in rows], dtype=float)
+    t_l = sum(r[1] for r in rows)
+    t_c = sum(r[5] for r in rows)
+    return {"maps": count, "n": n, "d": 32, "train_maps": train_maps,
+            "learned_iters_mean": float(it_l.mean()), "cccp_iters_mean": float(it_c.mean()),
+            "learned_fewer_iters_maps": int((it_l < it_c).sum()),
+            "learned_s": t_l, "cccp_s": t_c, "learned_speedup": t_c / t_l,
+            "fallbacks": sum(1 for r in rows if r[2]),
+            "converged_learned": sum(1 for r in rows if r[3]), "converged_cccp": sum(1 for r in rows if r[6])}
 
 
 def main():
@@ -353,6 +404,8 @@ def main():
     }
 
     _note("timed step and comparison legs done")
+    if args.learned_eval > 0:
+        extra["learned_eval"] = learned_eval_leg(L, LR, dev, args.learned_eval, args.train_maps, args.train_epochs)
     if args.batch_maps > 0:
         extra["batched"] = batched_leg(L, LR, dev, args.batch_maps, args.train_maps, args.train_epochs)
 
