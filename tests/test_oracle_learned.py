@@ -4,8 +4,11 @@ The network, its loss and their gradients have no printed values to match;
 they are pinned by mathematics: central finite differences of the loss (a
 dropped term, a wrong sign or a transposed weight anywhere in the backward
 pass fails these), the Woodbury solve and the loss against dense solves, the
-closed-form first Adam step, SPD-ness of S for arbitrary weights, and
-Sigma^{1/2} Z against a dense eigendecomposition of the fitted Sigma.
+closed-form first Adam step, SPD-ness of S for arbitrary weights,
+Sigma^{1/2} Z against a dense eigendecomposition of the fitted Sigma, and the
+forward pass itself through closed forms of the logistic function (SiLU at 0,
+1 and ln 3; a width-1 network whose output is exactly 4) and hand-written
+feature rows.
 """
 import math
 
@@ -114,3 +117,48 @@ def test_sigma_half_apply_matches_dense_square_root():
     assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
     # and P really is its inverse: Sigma^{1/2} P z = z
     assert np.abs(root @ np.column_stack([P.apply(probes[:, k]) for k in range(5)]) - probes).max() <= tol
+
+
+def test_silu_closed_forms():
+    """SiLU z * logistic(z): logistic(0) = 1/2, logistic(1) = e / (e + 1),
+    logistic(ln 3) = 3/4; silu(z) - silu(-z) = z (logistic(z) + logistic(-z) = 1);
+    the derivative is 1/2 at 0 and tends to 1 and 0 far out."""
+    z = np.array([0.0, 1.0, math.log(3.0), -math.log(3.0), 40.0, -40.0])
+    s = LO.silu(z)
+    assert s[0] == 0.0
+    assert s[1] == pytest.approx(math.e / (math.e + 1.0), rel=1e-15)
+    assert s[2] == pytest.approx(0.75 * math.log(3.0), rel=1e-15)
+    assert s[3] == pytest.approx(-0.25 * math.log(3.0), rel=1e-15)
+    assert s[4] == pytest.approx(40.0, rel=1e-15) and abs(s[5]) < 1e-15
+    w = np.linspace(-6.0, 6.0, 25)
+    assert np.allclose(LO.silu(w) - LO.silu(-w), w, rtol=0, atol=1e-15)
+    g = LO.silu_grad(np.array([0.0, 40.0, -40.0]))
+    assert g[0] == 0.5 and g[1] == pytest.approx(1.0, abs=1e-14) and abs(g[2]) < 1e-14
+
+
+def test_features_hand_computed_rows():
+    """x_i = [e_i, log lambda, log(n)/10, column means of e, column means of e^2]
+    for a 2 x 2 embedding written out by hand."""
+    E = np.array([[1.0, 2.0], [3.0, 4.0]])
+    X = LO.features(E, math.exp(-2.0))
+    g = [-2.0, math.log(2.0) / 10.0, 2.0, 3.0, 5.0, 10.0]
+    assert X.shape == (2, LO.input_dim(2))
+    assert np.allclose(X[0], [1.0, 2.0] + g, rtol=1e-15, atol=1e-15)
+    assert np.allclose(X[1], [3.0, 4.0] + g, rtol=1e-15, atol=1e-15)
+
+
+def test_network_forward_exact_through_logistic_of_ln3():
+    """A width-1 network whose pre-activations are both ln 3, where the
+    logistic function is exactly 3/4: o = (4 / ln 3) * (3/4) ln 3 + 1 = 4, for
+    two inputs that reach ln 3 through different input weights; the second
+    output column reads the hidden unit with weight 0 and bias -7."""
+    L3 = math.log(3.0)
+    # biases enter before each activation: (L3 + 1) - 1 = L3 and 2 (3/4 L3) / (3/4) - L3 = L3
+    params = {"W1": np.array([[L3 + 1.0], [5.0]]), "b1": np.array([-1.0]),
+              "W2": np.array([[2.0 / 0.75]]), "b2": np.array([-L3]),
+              "W3": np.array([[4.0 / L3, 0.0]]), "b3": np.array([1.0, -7.0])}
+    X = np.array([[1.0, 0.0], [0.0, (L3 + 1.0) / 5.0]])
+    out, _ = LO.mlp_forward(params, X)
+    assert out.shape == (2, 2)
+    assert out[0, 0] == pytest.approx(4.0, rel=1e-14) and out[0, 1] == -7.0
+    assert out[1, 0] == pytest.approx(4.0, rel=1e-14) and out[1, 1] == -7.0
