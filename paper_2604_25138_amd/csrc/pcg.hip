@@ -421,7 +421,7 @@ laker_status pcg_run(const Problem& pb, const SolveWs& ws, const PrecondView& P,
     }
     return LAKER_OK;
   }
-  PcgScalars hs;
+  PcgScalars hs{};   // (zero until the first read-back: error paths see no iterations)
   int k = 0;
   laker_status loop_status = LAKER_OK;
   // Eager chunks shrink near convergence: the next chunk is the number of
