@@ -151,3 +151,19 @@ def test_empty_inputs_rejected_on_the_host():
         assert r == laker.LAKER_EINVAL, count
     ns = (C.c_int64 * 2)(16, 0)
     assert lib.laker_batch_workspace_bytes(2, ns, 4) == 0
+
+
+def test_missing_library_fails_loudly_and_product_never_imports_the_oracle():
+    """Without the built library the binding raises (there is no CPU fallback),
+    and no module of the package imports the oracle."""
+    import subprocess
+    import sys
+    code = ("from paper_2604_25138_amd import laker\n"
+            "try:\n    laker.load('/nonexistent/liblaker.so')\nexcept ImportError as e:\n    print('raised', e)\n")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT, timeout=120)
+    assert r.returncode == 0 and r.stdout.startswith("raised"), (r.stdout, r.stderr[-2000:])
+    pkg = os.path.join(ROOT, "paper_2604_25138_amd")
+    for f in sorted(os.listdir(pkg)):
+        if f.endswith(".py"):
+            src = open(os.path.join(pkg, f)).read()
+            assert not re.search(r"^\s*(from|import)\s+oracle\b", src, flags=re.M), f
