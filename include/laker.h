@@ -15,8 +15,11 @@
  *  - Pointers documented as "device" point to HIP device memory owned by the
  *    caller; the library never allocates or frees device memory.  Scratch space
  *    is passed in as a caller-owned workspace whose size comes from the
- *    matching *_workspace_bytes query.  Pointers documented as "host" are
- *    ordinary host memory.
+ *    matching *_workspace_bytes query; workspaces and preconditioner buffers
+ *    start on a 256-byte boundary (as hipMalloc returns them), since the
+ *    library carves them into 256-byte-aligned pieces that its kernels read
+ *    with 16-byte vector loads.  Pointers documented as "host" are ordinary
+ *    host memory.
  *  - Matrices are row-major and densely packed: E is n x d (row i = e_i), the
  *    random directions Z are n x n_r (column k = z_k).
  *  - y, alpha and r_hat are float64 at the boundary in every precision mode.
