@@ -162,3 +162,47 @@ def test_network_forward_exact_through_logistic_of_ln3():
     assert out.shape == (2, 2)
     assert out[0, 0] == pytest.approx(4.0, rel=1e-14) and out[0, 1] == -7.0
     assert out[1, 0] == pytest.approx(4.0, rel=1e-14) and out[1, 1] == -7.0
+
+
+def test_adam_constant_gradient_every_step_closed_form():
+    """With a constant gradient g, m_t = (1 - beta1^t) g and v_t = (1 - beta2^t) g^2,
+    so the bias-corrected moments are exactly g and g^2 at every t (Kingma & Ba):
+    each of three steps moves the weights by lr g / (|g| + eps).  A missing or
+    wrong bias correction (e.g. beta^1 instead of beta^t) fails at t >= 2."""
+    rng = np.random.default_rng(31)
+    g = {"W": rng.normal(size=(3, 4)), "b": np.array([2.0, -0.5, 1e-3])}
+    p = {k: rng.normal(size=v.shape) for k, v in g.items()}
+    st = {}
+    lr, eps = 1e-2, 1e-8
+    for t in (1, 2, 3):
+        before = {k: v.copy() for k, v in p.items()}
+        LO.adam_step(p, g, st, lr=lr, t=t, eps=eps)
+        for k in p:
+            assert np.allclose(p[k] - before[k], -lr * g[k] / (np.abs(g[k]) + eps), rtol=1e-12, atol=1e-17)
+
+
+def test_adam_sign_flip_two_steps_hand_computed():
+    """g at t = 1, then -g at t = 2 (beta1 = 0.9, beta2 = 0.999), worked with exact
+    fractions: m_2 = 0.9 * 0.1 g - 0.1 g = -0.01 g, v_2 = 0.999 * 0.001 g^2 + 0.001 g^2
+    = 0.001999 g^2; m_hat = -0.01 g / 0.19, v_hat = 0.001999 g^2 / (1 - 0.999^2) = g^2.
+    The second step is therefore +lr (1/19) g / (|g| + eps) (eps = 0 here)."""
+    from fractions import Fraction as Fr
+    g = 3.0
+    p = {"x": np.array([1.0])}
+    st = {}
+    lr = 0.1
+    LO.adam_step(p, {"x": np.array([g])}, st, lr=lr, t=1, eps=0.0)
+    x1 = 1.0 - lr                      # first step: lr g / |g|
+    assert p["x"][0] == pytest.approx(x1, rel=1e-15)
+    LO.adam_step(p, {"x": np.array([-g])}, st, lr=lr, t=2, eps=0.0)
+    b1, b2 = Fr(9, 10), Fr(999, 1000)
+    G = Fr(3)
+    m2 = b1 * (1 - b1) * G - (1 - b1) * G
+    v2 = b2 * (1 - b2) * G * G + (1 - b2) * G * G
+    mh = m2 / (1 - b1 ** 2)
+    vh = v2 / (1 - b2 ** 2)
+    assert mh == Fr(-3, 19) and vh == 9
+    x2 = Fr(x1) - Fr(1, 10) * mh / 3    # sqrt(v_hat) = 3 exactly
+    assert p["x"][0] == pytest.approx(float(x2), rel=1e-14)
+    assert st["m_x"][0] == pytest.approx(float(m2), rel=1e-14)
+    assert st["v_x"][0] == pytest.approx(float(v2), rel=1e-14)

@@ -384,3 +384,145 @@ def test_laker_pcg_solves_and_preconditions():
     _, it_cg, _ = O.pcg(lambda v: A @ v, lambda v: v, pr.y, 1e-11, 5000)
     assert O.condition_number(P.dense() @ A) < O.condition_number(A)
     assert it < it_cg
+
+
+# --- metrics with hand-computed values ------------------------------------------------
+
+def test_prediction_discrepancy_hand_computed():
+    """||Gq a - Gq a_ref|| / ||Gq a_ref|| (Sec. V-A, prediction discrepancy) on a
+    2 x 2 case worked by hand: Gq a = (3, 7), Gq a_ref = (1, 3), difference
+    (2, 4): sqrt(20) / sqrt(10) = sqrt(2).  Normalising by ||Gq a|| instead
+    would give sqrt(20/58); dropping Gq, ||a - a_ref|| / ||a_ref|| = 1."""
+    Gq = np.array([[1.0, 2.0], [3.0, 4.0]])
+    a, a_ref = np.array([1.0, 1.0]), np.array([1.0, 0.0])
+    assert O.prediction_discrepancy(Gq, a, a_ref) == pytest.approx(math.sqrt(2.0), rel=1e-15)
+    # a transposed Gq gives (4, 6) and (1, 2), difference (3, 4): 5 / sqrt(5) -- not sqrt(2)
+    assert O.prediction_discrepancy(Gq.T, a, a_ref) == pytest.approx(math.sqrt(5.0), rel=1e-15)
+    assert O.prediction_discrepancy(Gq, a_ref, a_ref) == 0.0
+
+
+def test_objective_gap_hand_computed():
+    """R(a) = ||G a - y||^2 + lam a^T G a (Sec. V-A) and the relative gap on a
+    diagonal 2 x 2 case: G = diag(2, 1), lam = 1, y = (2, 1), a_ref = (1, 0):
+    R(a_ref) = 1 + 2 = 3; a = (0, 1): G a - y = (-2, 0), R = 4 + 1 = 5; gap 2/3."""
+    G = np.diag([2.0, 1.0])
+    y = np.array([2.0, 1.0])
+    assert O.objective(G, 1.0, np.array([1.0, 0.0]), y) == pytest.approx(3.0, rel=1e-15)
+    assert O.objective(G, 1.0, np.array([0.0, 1.0]), y) == pytest.approx(5.0, rel=1e-15)
+    assert O.objective_gap(G, 1.0, np.array([0.0, 1.0]), np.array([1.0, 0.0]), y) == pytest.approx(2.0 / 3.0,
+                                                                                                    rel=1e-15)
+
+
+def test_condition_number_known_spectra():
+    """kappa = lambda_max / lambda_min of the (real, positive) eigenvalues.
+    * a diagonal matrix: the ratio of its extreme entries;
+    * a non-normal triangular matrix: its diagonal entries are its eigenvalues
+      (ratio 4), while its singular values have ratio ~ 1e4 -- a singular-value
+      definition fails here;
+    * P A with P = A^{-1/2} for the clustered system, whose spectrum is known
+      in closed form: eigenvalues lam, lam + (e^{c^2}-1) q and
+      lam + (e^{c^2}-1) q + n, so kappa(A) = (lam + (e^{c^2}-1) q + n) / lam and
+      kappa(A^{-1/2} A) = sqrt(kappa(A)); P = A^{-1} gives 1."""
+    assert O.condition_number(np.diag([2.0, 5.0, 10.0])) == pytest.approx(5.0, rel=1e-14)
+    M = np.array([[1.0, 100.0], [0.0, 4.0]])
+    assert O.condition_number(M) == pytest.approx(4.0, rel=1e-13)
+    sv = np.linalg.svd(M, compute_uv=False)
+    assert sv[0] / sv[-1] > 1000.0
+    nq, q, cc, lam = 6, 5, 0.8, 0.5
+    n = nq * q
+    E = np.zeros((n, nq))
+    for i in range(n):
+        E[i, i // q] = cc
+    A = O.system_matrix(E, 1.0, lam)
+    kA = (lam + (math.exp(cc * cc) - 1.0) * q + n) / lam
+    assert O.condition_number(A) == pytest.approx(kA, rel=1e-12)
+    ev, V = np.linalg.eigh(A)
+    Ph = (V * ev ** -0.5) @ V.T
+    assert O.condition_number(Ph @ A) == pytest.approx(math.sqrt(kA), rel=1e-12)
+    assert O.condition_number(np.linalg.inv(A) @ A) == pytest.approx(1.0, rel=1e-12)
+
+
+# --- CCCP with orthonormal directions: scalar closed form -------------------------------
+
+def _orthonormal(n, nr, seed):
+    Q, _ = np.linalg.qr(np.random.default_rng(seed).normal(size=(n, nr)))
+    return Q
+
+
+def _two_level(n, nr, gamma, rho, eps, s1):
+    """One step of eqs. kernel_shrinkage_cccp_F/Sigma/normalization worked by hand for
+    Sigma = s1 on span(U_bar), s0 elsewhere, with U_bar orthonormal (C = I):
+    every q_k = 1/s1, so F = c((n/N_r) s1/(1 + eps s1) U U^T + gamma I) and
+    Sigma_tilde has eigenvalue (1-rho) c ((n/N_r) h + gamma) + rho on span(U)
+    (h = s1/(1 + eps s1)) and (1-rho) c gamma + rho elsewhere; the trace
+    normalisation divides both by tau = (1-rho) c (h + gamma) + rho."""
+    c = 1.0 / (1.0 + gamma / n)
+    h = s1 / (1.0 + eps * s1)
+    tau = (1 - rho) * c * (h + gamma) + rho
+    return ((1 - rho) * c * ((n / nr) * h + gamma) + rho) / tau, ((1 - rho) * c * gamma + rho) / tau
+
+
+def test_cccp_step_orthonormal_directions_closed_form():
+    """From Sigma_0 = I (s1 = 1), three steps of the oracle's map T equal the
+    hand-worked two-level recursion: N_r eigenvalues s1 on span(U_bar) and
+    n - N_r eigenvalues s0.  gamma = 5 with n = 40 makes c = 1/(1 + gamma/n) = 0.889
+    and rho = 0.2 keeps it from cancelling in the normalisation; eps = 1e-3
+    enters through h = s1/(1 + eps s1)."""
+    n, nr, gamma, rho, eps = 40, 6, 5.0, 0.2, 1e-3
+    U = _orthonormal(n, nr, 1)
+    S = np.eye(n)
+    s1 = 1.0
+    for _ in range(3):
+        S = O.cccp_T(S, U, gamma, rho, eps)
+        s1, s0 = _two_level(n, nr, gamma, rho, eps, s1)
+        ref = s0 * np.eye(n) + (s1 - s0) * U @ U.T
+        assert np.abs(S - ref).max() <= 1e-12 * s1
+        assert nr * s1 + (n - nr) * s0 == pytest.approx(n, rel=1e-13)
+
+
+def test_cccp_fixed_point_orthonormal_directions_closed_form():
+    """With eps = 0 the fixed point s1 of the two-level recursion solves
+    k s1^2 + (K - k n/N_r) s1 - K = 0 with k = (1-rho) c and K = (1-rho) c gamma + rho
+    (clear the denominator tau = k (s1 + gamma) + rho); s0 = K / (k s1 + K).
+    The dense iteration must converge to s1 I on span(U_bar) and s0 elsewhere,
+    and its low-rank form to the same matrix.  The second case has rho = 0,
+    where c cancels: the same roots with k = 1, K = gamma."""
+    n, nr = 48, 8
+    for gamma, rho in ((6.0, 0.3), (2.0, 0.0)):
+        c = 1.0 / (1.0 + gamma / n)
+        k = (1 - rho) * c
+        K = (1 - rho) * c * gamma + rho
+        bq = K - k * n / nr
+        s1 = (-bq + math.sqrt(bq * bq + 4.0 * k * K)) / (2.0 * k)
+        s0 = K / (k * s1 + K)
+        U = _orthonormal(n, nr, 2)
+        Sig, it, _ = O.cccp_dense(U, gamma, rho, 0.0, 1e-14, 2000)
+        assert it < 2000
+        ev = np.sort(np.linalg.eigvalsh(Sig))
+        assert np.allclose(ev[:n - nr], s0, rtol=1e-11, atol=0)
+        assert np.allclose(ev[n - nr:], s1, rtol=1e-11, atol=0)
+        a, b, w, _ = O.cccp_lowrank(U, gamma, rho, 0.0, 1e-14, 2000)
+        assert np.abs(O.lowrank_sigma(U, a, b, w) - Sig).max() <= 1e-10 * s1
+
+
+def test_cccp_smallest_eigenvalue_bound():
+    """Every iterate satisfies lambda_min(Sigma_{t+1}) >= ((1-rho) c gamma + rho) / tau_t
+    with tau_t = tr(Sigma_tilde_t) / n (the shrinkage and gamma terms add that
+    multiple of I to a PSD sum before normalising); tau_t is evaluated here
+    directly from the definition of Sigma_tilde, direction by direction."""
+    n, nr, gamma, rho, eps = 90, 30, 0.1, 0.05, 1e-10
+    _, Ub = _directions(n, nr, 19)
+    _, _, hist = O.cccp_dense(Ub, gamma, rho, eps, 1e-12, 60, record=True)
+    c = 1.0 / (1.0 + gamma / n)
+    for S0, S1 in zip(hist, hist[1:]):
+        Sinv = np.linalg.inv(S0)
+        tr_sum = 0.0
+        for kk in range(nr):
+            u = Ub[:, kk]
+            tr_sum += (u @ u) / (u @ Sinv @ u + eps)
+        tau = ((1 - rho) * c * ((n / nr) * tr_sum + gamma * n) + rho * n) / n
+        bound = ((1 - rho) * c * gamma + rho) / tau
+        lmin = np.linalg.eigvalsh(S1).min()
+        assert lmin >= bound * (1.0 - 1e-10)
+        # the bound is attained on the complement of span(U_bar) (N_r < n)
+        assert lmin <= bound * (1.0 + 1e-8)
