@@ -130,28 +130,38 @@ def cccp_T(Sigma: np.ndarray, Ubar: np.ndarray, gamma: float, rho: float, eps: f
     return St
 
 
+def _fixed_point(T, X0: np.ndarray, tol: float, max_iter: int, record: bool):
+    """Repeat X <- T(X) from X0 until the relative Frobenius change of one
+    application is at most tol, or max_iter applications.  Returns
+    (X, applications, iterates or None)."""
+    X = X0
+    seen = [X0] if record else None
+    count = 0
+    while count < max_iter:
+        X_next = T(X)
+        count += 1
+        moved = np.linalg.norm(X_next - X) / np.linalg.norm(X)
+        X = X_next
+        if record:
+            seen.append(X)
+        if moved <= tol:
+            break
+    return X, count, seen
+
+
 def cccp_dense(Ubar: np.ndarray, gamma: float = 0.1, rho: float = 0.0, eps: float = 1e-10,
                tol: float = 1e-8, max_iter: int = 300, normalize: bool = True,
                record: bool = False):
-    """Literal dense shrinkage-CCCP: Sigma_0 = I, Sigma_{t+1} = T(Sigma_t) until
-    ||Sigma_{t+1} - Sigma_t||_F / ||Sigma_t||_F <= tol or max_iter steps (Alg. 1).
+    """Sigma_star as the fixed point of the shrinkage-CCCP map T of Theorem 1
+    (eqs. kernel_shrinkage_cccp_F/Sigma/normalization), reached by applying T to
+    dense n x n matrices from Sigma = I until one application changes Sigma by
+    at most tol in relative Frobenius norm, or max_iter applications (the
+    preconditioner-learning part of Algorithm 1).
 
-    Returns (Sigma_star, iterations, history) where history holds the iterates
-    when ``record`` is set.
+    Returns (Sigma_star, applications of T, iterates when ``record`` is set).
     """
     n = Ubar.shape[0]
-    Sigma = np.eye(n)
-    hist = [Sigma] if record else None
-    it = 0
-    for it in range(1, max_iter + 1):
-        Snew = cccp_T(Sigma, Ubar, gamma, rho, eps, normalize)
-        change = np.linalg.norm(Snew - Sigma) / np.linalg.norm(Sigma)
-        Sigma = Snew
-        if record:
-            hist.append(Sigma)
-        if change <= tol:
-            break
-    return Sigma, it, hist
+    return _fixed_point(lambda S: cccp_T(S, Ubar, gamma, rho, eps, normalize), np.eye(n), tol, max_iter, record)
 
 
 def mle_objective(Theta: np.ndarray, Ubar: np.ndarray, gamma: float, eps: float = 0.0) -> float:
@@ -280,42 +290,48 @@ def fit_precond(E: np.ndarray, scale: float, lam: float, Z: np.ndarray, gamma: f
 
 def pcg(apply_A, apply_P, y: np.ndarray, tol: float, max_iter: int,
         alpha0: np.ndarray | None = None):
-    """PCG in the paper's notation: alpha^0 = 0 (or a given start),
-    r^0 = y - A alpha^0, theta^0 = P r^0, p^0 = theta^0; each step
-        delta = r^T theta / p^T A p,  alpha += delta p,  r -= delta A p,
-        stop if ||r||/||y|| <= tol (recursive r),
-        theta = P r,  beta = r_new^T theta_new / r^T theta,  p = theta + beta p.
+    """Preconditioned conjugate gradients for (lambda I + G) alpha = y with an
+    SPD preconditioner P (Sec. IV-E; Algorithm 1), written from the two
+    conditions that define CG:
+
+    * the step t along the search direction d minimises the A-norm of the
+      error on the line alpha + t d; with the residual r = y - A alpha this is
+      t = <r, P r> / <d, A d>;
+    * the next direction is P r (for the updated r) made A-conjugate to d,
+      which in CG takes only the multiple <r, P r>_new / <r, P r>_old of d.
+
+    The residual is carried recursively (r <- r - t A d), and the method stops
+    as soon as ||r|| / ||y|| <= tol on that recursive residual, before P is
+    applied again.  Starts from alpha = 0 (r = y) or from alpha0.
 
     Returns (alpha, iterations, residual_history); iterations counts the
     products with A made inside the loop.
     """
-    n = y.shape[0]
-    if alpha0 is None:
-        alpha = np.zeros(n)
-        r = y.copy()
-    else:
-        alpha = alpha0.copy()
-        r = y - apply_A(alpha)
-    theta = apply_P(r)
-    p = theta.copy()
-    rt = float(r @ theta)
     ynorm = float(np.linalg.norm(y))
-    hist = []
-    for k in range(max_iter):
-        Ap = apply_A(p)
-        delta = rt / float(p @ Ap)
-        alpha = alpha + delta * p
-        r = r - delta * Ap
-        res = float(np.linalg.norm(r)) / ynorm
-        hist.append(res)
-        if res <= tol:
-            return alpha, k + 1, hist
-        theta = apply_P(r)
-        rt_new = float(r @ theta)
-        beta = rt_new / rt
-        p = theta + beta * p
-        rt = rt_new
-    return alpha, max_iter, hist
+    if alpha0 is None:
+        x = np.zeros(y.shape[0])
+        res = y.copy()
+    else:
+        x = alpha0.copy()
+        res = y - apply_A(alpha0)
+    z = apply_P(res)
+    d = z.copy()
+    rz = float(res @ z)
+    history = []
+    steps = 0
+    while steps < max_iter:
+        Ad = apply_A(d)
+        steps += 1
+        t = rz / float(d @ Ad)
+        x = x + t * d
+        res = res - t * Ad
+        history.append(float(np.linalg.norm(res)) / ynorm)
+        if history[-1] <= tol:
+            break
+        z = apply_P(res)
+        rz_prev, rz = rz, float(res @ z)
+        d = z + (rz / rz_prev) * d
+    return x, steps, history
 
 
 # ---------------------------------------------------------------------------
