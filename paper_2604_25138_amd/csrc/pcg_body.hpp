@@ -143,6 +143,22 @@ __device__ __forceinline__ void pcg_update_body(int blk, int nblk, double* __res
   }
 }
 
+// Sum of thread tid's stripe of `count` grid-reduction partials, in the order
+// ordered_sum takes them (a contiguous stripe of per = ceil(count / kThreads)
+// entries), of which the first four were loaded ahead into v4; the rest of a
+// longer stripe (count > 4 kThreads, e.g. the ||r||^2 partials of more than
+// 65536 rows) are read here, after them.
+__device__ __forceinline__ double stripe_sum(const double (&v4)[4], const double* __restrict__ part, int count,
+                                             int tid, int per) {
+  double v = 0.0;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+    if (u < per && tid * per + u < count) v += v4[u];
+  for (int u = 4; u < per; ++u)
+    if (tid * per + u < count) v += part[tid * per + u];
+  return v;
+}
+
 // Stopping test of iteration k on the recursive residual (Alg. 1), evaluated
 // identically by every block; block 0 records it.  Returns true to continue.
 __device__ __forceinline__ bool pcg_decide_rr(int blk, int k, PcgScalars* S, double rr) {
@@ -299,10 +315,9 @@ __device__ __forceinline__ void pcg_update_t_body(int blk, int nblk, double* __r
   const int64_t i0 = (int64_t)blk * kTRows;
   // Loads that do not depend on this iteration's scalars go first, so that
   // their latencies overlap: this thread's stripe of the p^T A p partials (as
-  // ordered_sum takes them; gp <= 4 kThreads), the block's rows of p, theta,
+  // ordered_sum takes them, the first four), the block's rows of p, theta,
   // alpha, r (or Ap), then the row sums of the product's partials.
-  static_assert(kMaxBlocks <= 4 * kThreads, "four partials per thread");
-  const int per = (gp + kThreads - 1) / kThreads;
+    const int per = (gp + kThreads - 1) / kThreads;
   double pv[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
@@ -342,11 +357,7 @@ __device__ __forceinline__ void pcg_update_t_body(int blk, int nblk, double* __r
     apq[tid / kTRows][tid % kTRows] =
         i < n ? ps.row_strided_all<24>(part, n, i, tid / kTRows, kThreads / kTRows) : 0.0;
   }
-  double v = 0.0;
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
-    if (u < per && tid * per + u < gp) v += pv[u];
-  const double pap = block_sum(v, sh);   // (its barriers also publish apq)
+  const double pap = block_sum(stripe_sum(pv, pap_p, gp, tid, per), sh);   // (its barriers also publish apq)
   const int k = S->kcur - 1;
   const double dl = S->rzbuf[k & 1] / pap;
   if (!(pap > 0.0) || !isfinite(dl)) {
@@ -425,10 +436,9 @@ __device__ __forceinline__ void lr_t_finish_body(int blk, int nblk, const double
   const int col = blk * 16 + cl;
   // Inside the loop this pass first takes the stopping decision of the
   // current iteration.  Its ||r||^2 partials (this thread's stripe, as
-  // ordered_sum takes them; grr <= 4 kThreads) and, for up to 256 partial
+  // ordered_sum takes them, the first four) and, for up to 256 partial
   // rows, the t partials are loaded before it, so that the latencies overlap.
-  static_assert(kMaxBlocks <= 4 * kThreads, "four partials per thread");
-  const int per = rrp != nullptr ? (grr + kThreads - 1) / kThreads : 0;
+    const int per = rrp != nullptr ? (grr + kThreads - 1) / kThreads : 0;
   double rv[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
@@ -444,11 +454,7 @@ __device__ __forceinline__ void lr_t_finish_body(int blk, int nblk, const double
     tv[u] = pre && col < nrp && b < nb ? tpart[(int64_t)b * nrp + col] : 0.0;
   }
   if (rrp != nullptr) {
-    double v = 0.0;
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (u < per && tid * per + u < grr) v += rv[u];
-    if (!pcg_decide_rr(blk, S->kcur - 1, S, block_sum(v, shd))) return;
+    if (!pcg_decide_rr(blk, S->kcur - 1, S, block_sum(stripe_sum(rv, rrp, grr, tid, per), shd))) return;
   }
   double s = 0.0;
   if (pre) {
@@ -571,8 +577,7 @@ __device__ __forceinline__ bool t_fused_order(int blk, const double* __restrict_
   __shared__ double red[4][64];
   const int tid = threadIdx.x;
   const int q = tid >> 6, c = tid & 63;
-  static_assert(kMaxBlocks <= 4 * kThreads, "four partials per thread");
-  const int per = rrp != nullptr ? (grr + kThreads - 1) / kThreads : 0;
+    const int per = rrp != nullptr ? (grr + kThreads - 1) / kThreads : 0;
   double rv[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
@@ -586,11 +591,7 @@ __device__ __forceinline__ bool t_fused_order(int blk, const double* __restrict_
     tv[u] = c < nrp && row < nb ? tpart[(int64_t)row * nrp + c] : 0.0;
   }
   if (rrp != nullptr) {
-    double v = 0.0;
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (u < per && tid * per + u < grr) v += rv[u];
-    if (!pcg_decide_rr(blk, S->kcur - 1, S, block_sum(v, sh))) return false;
+    if (!pcg_decide_rr(blk, S->kcur - 1, S, block_sum(stripe_sum(rv, rrp, grr, tid, per), sh))) return false;
   }
   double s = 0.0;
 #pragma unroll

@@ -61,3 +61,24 @@ def test_flexible_outer_cg_at_65536_sites_lambda_1e5_stored():
     rows = np.random.default_rng(5).choice(n, size=32, replace=False)
     r = pr.y[rows] - O.matvec_rows(pr.E, pr.scale, pr.lam, alpha.cpu().numpy(), rows)
     assert np.abs(r).max() <= 5e-9 * np.linalg.norm(pr.y)
+
+
+def test_stopping_sum_covers_every_partial_beyond_65536_rows():
+    """The stopping test of PCG adds one ||r||^2 partial per 64 rows; above
+    65536 rows a thread's stripe holds more than the four partials it loads
+    ahead, and every one of them must enter the sum.  After five float32 PCG
+    iterations with a CCCP preconditioner (the separate t pass, as for any map
+    above 16384 sites) the reported recursive residual must equal the float64
+    true residual of the same iterate up to the float32 product's rounding;
+    a sum that dropped partials would report about 0.7 of it at 131072 rows."""
+    from paper_2604_25138_amd import laker as L
+    L.load()
+    n, d = 131072, 16
+    pr = make_problem(n, d, 1e-2, n_tx=2, seed=17)
+    prob = L.Problem(torch.tensor(pr.E, device=DEV), pr.lam, pr.scale)
+    pc = L.fit_precond(prob, torch.tensor(make_directions(n, 64, 17), device=DEV), gamma=0.1, precision="f32")
+    alpha, st = L.pcg_solve(prob, pr.y, pc, tol=1e-12, max_iter=5, precision="f32", check_every=5,
+                            allow_noconv=True)
+    print(f"n={n}: {st.iters} iterations, recursive {st.relres:.6e}, true {st.relres_true:.6e}")
+    assert st.status == L.LAKER_ENOCONV and st.iters == 5
+    assert abs(st.relres / st.relres_true - 1.0) <= 1e-3
