@@ -1,21 +1,25 @@
 """Benchmark of the LAKER solve path on one MI355X.
 
-A step is one full pass of the production path over one synthetic map:
-the learned rank-64-plus-diagonal preconditioner (network inference and the
-Woodbury factors), PCG to a float64 true relative residual of 1e-6 with
-bfloat16 score tiles inside float64 iterative refinement (falling back to a
-CCCP fit if PCG stalls), and reconstruction on the 45 x 45 grid.  Inputs are
-resident in HBM before the timed region.  The network is trained beforehand
-(outside the timed region, reported) on CCCP fits of smaller maps drawn from the
-same generator with random lambda and transmitter counts.
+A step is one full pass of the production path over one synthetic map (by
+default the largest single-map configuration: 65536 sites, d = 64, 4
+transmitters, lambda = 1e-5): the learned rank-64-plus-diagonal preconditioner
+(network inference and the Woodbury factors), the solve to a float64 true
+relative residual of 1e-6 by a flexible float64 outer CG around bfloat16 inner
+PCG solves (falling back to a CCCP fit if PCG stalls), and reconstruction on the
+45 x 45 grid.  Inputs are resident in HBM before the timed region.  The network
+is trained beforehand (outside the timed region, reported) on CCCP fits of
+smaller maps drawn from the same generator with random lambda and transmitter
+counts.
 
 Beside the timed path the run reports: the same map solved entirely in float64
 with the paper's CCCP preconditioner (FP64 CCCP-PCG, the metric's comparison),
-the CCCP + mixed-precision step, the roofline position of the dominant kernel
-(the fused kernel product, timed with HIP events around every product of the
-solve on the library's stream), a batched leg (maps of uneven size solved
-together vs one after the other), and the FP64 CPU oracle timed on a bounded
-sample of the same workload.
+CCCP with the timed step's mixed-precision solver at gamma = 0.1 and 1e-3, the
+roofline position of the dominant kernel (the fused kernel product, timed with
+HIP events around every product of the solve on the library's stream), the
+16384-site map (learned step; float32 products with G stored against
+recomputed), a batched leg (maps of uneven size solved together vs one after
+the other), and the FP64 CPU oracle timed on a bounded sample of the same
+workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -33,7 +37,11 @@ sys.path.insert(0, ROOT)
 METRIC = "solves/s to rel-res 1e-6 (learned+mixed vs FP64 CCCP-PCG); matvec % roofline"
 
 WORKLOADS = {
-    # the at-scale single-map configuration: 16384 sites, 64-d RFF embeddings,
+    # the largest single-map configuration: 65536 sites, 64-d RFF embeddings,
+    # 4 transmitters, lambda = 1e-5 (lambda / ||G|| ~ 1.5e-10), solved to a
+    # float64 relative residual of 1e-6
+    "n65536_d64": dict(n=65536, d=64, n_tx=4, lam=1e-5, tol=1e-6, seed=0),
+    # the at-scale float32 configuration: 16384 sites, 64-d RFF embeddings,
     # 4 transmitters, lambda = 1e-4, PCG to relative residual 1e-6
     "n16384_d64": dict(n=16384, d=64, n_tx=4, lam=1e-4, tol=1e-6, seed=0),
     # small float64 configuration: 512 sites, 16-d embeddings, lambda = 1e-3
@@ -46,6 +54,9 @@ WORKLOADS = {
 # with inner tolerance 0.1: 100 ms); the inner solves check for convergence
 # every INNER_CAP iterations, so no launches are enqueued past the cap
 INNER_CAP = 30
+# the learned solve falls back to CCCP when its residual falls by less than 2x
+# over this many inner iterations (the bench maps fall by ~1.3 decades in it)
+STALL_WINDOW = 2000
 
 # training set of the learned preconditioner: maps of TRAIN_N sites with
 # lambda log-uniform in [1e-5, 1e-2] and 1..8 transmitters
@@ -66,7 +77,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="n16384_d64", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="n65536_d64", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-c2", action="store_true", help="skip the 16384-site leg")
+    ap.add_argument("--no-paper", action="store_true", help="skip the sweep of the paper's own regime")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--counters", action="store_true",
                     help="only 20 bfloat16 products of the workload, a 20-iteration float64 PCG streaming the "
@@ -184,14 +197,14 @@ def learned_eval_leg(L, LR, dev, count, train_maps, train_epochs):
         Zd = torch.tensor(make_directions(n, default_n_r(n), 50000 + k), device=dev)
         torch.cuda.synchronize()
         a = time.perf_counter()
-        res = LR.solve_with_fallback(prob, y, model, Zd, budget=20000, gamma=0.1, **kw)
+        res = LR.solve_with_fallback(prob, y, model, Zd, budget=100000, gamma=0.1, stall_window=STALL_WINDOW, **kw)
         torch.cuda.synchronize()
         b = time.perf_counter()
         pc = L.fit_precond(prob, Zd, gamma=0.1, rho=0.0, precision="bf16")
         _, st = L.pcg_solve(prob, y, pc, max_iter=100000, ir_max=1000, allow_noconv=True, **kw)
         torch.cuda.synchronize()
         c = time.perf_counter()
-        its = res.stats.iters + (res.learned_iters if res.fell_back else 0)
+        its = res.stats.iters
         rows.append((its, b - a, res.fell_back, res.stats.status == 0, st.iters, c - b, st.status == 0))
         if (k + 1) % 8 == 0:
             _note(f"learned evaluation: {k + 1} of {count} maps")
@@ -205,6 +218,166 @@ def learned_eval_leg(L, LR, dev, count, train_maps, train_epochs):
             "learned_s": t_l, "cccp_s": t_c, "learned_speedup": t_c / t_l,
             "fallbacks": sum(1 for r in rows if r[2]),
             "converged_learned": sum(1 for r in rows if r[3]), "converged_cccp": sum(1 for r in rows if r[6])}
+
+
+def solve_cost(L, prob, y, pc, kw):
+    """Time of one solve with the given preconditioner (seconds) and its stats."""
+    import torch
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    _, st = L.pcg_solve(prob, y, pc, allow_noconv=True, **kw)
+    torch.cuda.synchronize()
+    return time.perf_counter() - a, st
+
+
+def cccp_mixed_leg(L, prob, y, Zd, Eq, tol, gamma):
+    """CCCP fit (bfloat16 directions) + the same solver as the timed step
+    (flexible float64 outer CG around capped bf16 inner PCG, stored G for the
+    outer products) + predict: the learned preconditioner's comparison with
+    identical solver options."""
+    import torch
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    pc = L.fit_precond(prob, Zd, gamma=gamma, rho=0.0, precision="bf16")
+    torch.cuda.synchronize()
+    b = time.perf_counter()
+    alc, stc = L.pcg_solve(prob, y, pc, tol=tol, max_iter=400000, precision="bf16", refine=2, inner_tol=0.1,
+                           ir_max=20000, check_every=INNER_CAP, inner_max_iter=INNER_CAP, materialized=True,
+                           allow_noconv=True)
+    torch.cuda.synchronize()
+    c = time.perf_counter()
+    L.predict(prob, alc, Eq, precision="f64")
+    torch.cuda.synchronize()
+    d_ = time.perf_counter()
+    return {"gamma": gamma, "fit_ms": (b - a) * 1e3, "solve_ms": (c - b) * 1e3, "predict_ms": (d_ - c) * 1e3,
+            "solves_per_s": 1.0 / (d_ - a), "pcg_iters": stc.iters, "outer_steps": stc.ir_steps,
+            "relres_true": stc.relres_true, "converged": stc.status == 0, "cccp_iters": pc.stats.cccp_iters}, pc
+
+
+# the paper's Table II (Sec. V-B), for direction and order of magnitude only
+# (its embedding map is unspecified; hardware not stated)
+PAPER_TABLE2 = {50: (5.05e3, 1.33e2, 16, 21), 200: (2.02e4, 1.95e2, 21, 32), 500: (5.04e4, 2.07e2, 25, 42),
+                1000: (1.01e5, 1.79e2, 28, 47), 2000: (2.02e5, 2.09e2, 30, 59)}
+
+
+def paper_regime_leg(L, dev):
+    """The paper's numerical layer (Sec. V-A): G = exp(E E^T), d_e = 10,
+    lambda = 1e-2, gamma = 0.1, rho by the undersampling rule, N_r by the
+    schedule, n in {50, 200, 500, 1000, 2000}.  Per n: kappa(lambda I + G),
+    kappa(P (lambda I + G)) and kappa(P_J (lambda I + G)) estimated from the
+    PCG coefficients (Lanczos), iterations to an objective gap of 1e-3 for
+    LAKER, Jacobi PCG and CG, LAKER's time (fit + PCG to 1e-10), final
+    residual, objective gap and map RMSE, beside the paper's Table II."""
+    import torch
+
+    from synth import default_n_r, make_directions, make_paper_problem, paper_rho
+    rows = {}
+    for n in (50, 200, 500, 1000, 2000):
+        pr = make_paper_problem(n, seed=n)
+        prob = L.Problem(torch.tensor(pr.E, device=dev), pr.lam, pr.scale)
+        y = torch.tensor(pr.y, device=dev)
+        nr = default_n_r(n)
+        rho = paper_rho(n, nr, 0.1)
+        Zd = torch.tensor(make_directions(n, nr, n), device=dev)
+        # warm-up of the kernels at this size, then LAKER timed: fit + PCG to 1e-10
+        pc = L.fit_precond(prob, Zd, gamma=0.1, rho=rho)
+        L.pcg_solve(prob, y, pc, tol=1e-10, max_iter=20000, precision="f64", allow_noconv=True)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        pc = L.fit_precond(prob, Zd, gamma=0.1, rho=rho)
+        al, st = L.pcg_solve(prob, y, pc, tol=1e-10, max_iter=20000, precision="f64", lanczos=True)
+        torch.cuda.synchronize()
+        t_laker = time.perf_counter() - a
+        jac = L.jacobi_precond(prob)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        _, sj = L.pcg_solve(prob, y, jac, tol=1e-10, max_iter=20000, precision="f64", lanczos=True,
+                            allow_noconv=True)
+        torch.cuda.synchronize()
+        t_jac = time.perf_counter() - a
+        _, sc = L.pcg_solve(prob, y, None, tol=1e-10, max_iter=20000, precision="f64", lanczos=True,
+                            allow_noconv=True)
+        a_star, _ = L.pcg_solve(prob, y, pc, tol=1e-13, max_iter=20000, precision="f64", allow_noconv=True)
+
+        def R(v):
+            g = L.kernel_matvec(prob, v, "f64") - pr.lam * v
+            return float(torch.sum((g - y) ** 2) + pr.lam * torch.dot(v, g))
+        rs = R(a_star)
+
+        def iters_to_gap(q):
+            for k in range(1, 600):
+                v, _ = L.pcg_solve(prob, y, q, tol=1e-30, max_iter=k, precision="f64", check_every=k,
+                                   allow_noconv=True)
+                if abs(R(v) - rs) <= 1e-3 * abs(rs):
+                    return k
+            return None
+        rhat = L.predict(prob, al, torch.tensor(pr.Eq, device=dev), precision="f64").cpu()
+        ref = PAPER_TABLE2[n]
+        rows[str(n)] = {
+            "n_r": nr, "rho": rho, "cccp_iters": pc.stats.cccp_iters,
+            "kappa_A": sc.cond_est, "kappa_PA": st.cond_est, "kappa_PJA": sj.cond_est,
+            "iters_to_gap_1e-3": {"laker": iters_to_gap(pc), "jacobi": iters_to_gap(jac), "cg": iters_to_gap(None)},
+            "pcg_iters_to_1e-10": {"laker": st.iters, "jacobi": sj.iters, "cg": sc.iters},
+            "laker_ms": t_laker * 1e3, "jacobi_pcg_ms": t_jac * 1e3, "relres_true": st.relres_true,
+            "obj_gap": abs(R(al) - rs) / abs(rs),
+            "rmse_db": float(torch.sqrt(torch.mean((rhat - torch.tensor(pr.r_true)) ** 2))),
+            "paper": {"kappa_A": ref[0], "kappa_PA": ref[1], "iters_laker": ref[2], "iters_jacobi": ref[3]}}
+    return rows
+
+
+def c2_leg(L, LR, model, dev):
+    """The 16384-site map (d = 64, 4 transmitters, lambda = 1e-4): the learned
+    step as timed above, and float32 CCCP-PCG with G stored once (float32
+    tiles streamed from HBM) against G recomputed in every product."""
+    import torch
+
+    from synth import default_n_r, make_directions, make_problem
+    wl = WORKLOADS["n16384_d64"]
+    pr = make_problem(wl["n"], wl["d"], wl["lam"], n_tx=wl["n_tx"], seed=wl["seed"])
+    prob = L.Problem(torch.tensor(pr.E, device=dev), pr.lam, pr.scale)
+    y = torch.tensor(pr.y, device=dev)
+    Zd = torch.tensor(make_directions(pr.n, default_n_r(pr.n), wl["seed"]), device=dev)
+    Eq = torch.tensor(pr.Eq, device=dev)
+    tol = wl["tol"]
+
+    def step():
+        res = LR.solve_with_fallback(prob, y, model, Zd, tol=tol, budget=200000, precision="bf16", refine=2,
+                                     inner_tol=0.1, gamma=0.1, check_every=INNER_CAP, inner_max_iter=INNER_CAP,
+                                     materialized=True, stall_window=STALL_WINDOW)
+        L.predict(prob, res.alpha, Eq, precision="f64")
+        return res
+
+    step()
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    reps = 5
+    for _ in range(reps):
+        res = step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - a) * 1e3 / reps
+    out = {"workload": "n=16384 d=64 n_tx=4 lambda=1e-4 tol=1e-6", "learned_step_ms": ms,
+           "learned_solves_per_s": 1e3 / ms, "learned_pcg_iters": res.stats.iters,
+           "learned_relres_true": res.stats.relres_true}
+    pc = L.fit_precond(prob, Zd, gamma=0.1, rho=0.0, precision="bf16")
+    f32c = {}
+    for mat in (False, True):
+        kw32 = dict(tol=tol, max_iter=100000, precision="f32", refine=True, inner_tol=0.1, ir_max=64,
+                    check_every=32, materialized=mat)
+        dt, s32 = solve_cost(L, prob, y, pc, kw32)
+        _, s32p = L.pcg_solve(prob, y, pc, profile=True, **kw32)
+        f32c["stored" if mat else "recomputed"] = {
+            "ms_per_solve": dt * 1e3, "pcg_iters": s32.iters, "ir_steps": s32.ir_steps,
+            "relres_true": s32.relres_true, "us_per_product": s32p.kmv_ms * 1e3}
+    sb32 = L.load().laker_kmat_bytes(pr.n, pr.d, L.F32)
+    f32c["stored"]["gb_per_s"] = sb32 / (f32c["stored"]["us_per_product"] * 1e-6) / 1e9
+    f32c["stored"]["frac_of_hbm_peak"] = f32c["stored"]["gb_per_s"] / PEAK_HBM_GBS
+    f32c["stored_bytes"] = sb32
+    us32 = f32c["recomputed"]["us_per_product"] * 1e-6
+    dist = pr.n * (pr.n + 1) / 2.0
+    f32c["recomputed"]["frac_of_alu_peak"] = (EXP2_SLOTS * dist + float(pr.n) * pr.n) / us32 / 1e12 / PEAK_VALU_TOPS
+    f32c["recomputed"]["frac_of_fp32_mfma_peak"] = 2.0 * pr.d * dist / us32 / 1e12 / PEAK_FP32_MFMA_TFLOPS
+    out["f32_stored_vs_recomputed"] = f32c
+    return out
 
 
 def main():
@@ -230,8 +403,7 @@ def main():
     Zd = torch.tensor(Z, device=dev)
     Eq = torch.tensor(pr.Eq, device=dev)
     tol = wl["tol"]
-    inner = 0.1
-    budget = 20000
+    budget = 400000
 
     if args.counters:
         # the product kernel alone, then a plain copy of known size whose
@@ -255,8 +427,8 @@ def main():
 
     def step():
         res = LR.solve_with_fallback(prob, y, model, Zd, tol=tol, budget=budget, precision="bf16", refine=2,
-                                     inner_tol=inner, gamma=0.1, check_every=INNER_CAP, inner_max_iter=INNER_CAP,
-                                     materialized=True)
+                                     inner_tol=0.1, gamma=0.1, check_every=INNER_CAP, inner_max_iter=INNER_CAP,
+                                     materialized=True, stall_window=STALL_WINDOW)
         rhat = L.predict(prob, res.alpha, Eq, precision="f64")
         return res, rhat
 
@@ -265,9 +437,12 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     runs = []
-    for _ in range(args.steps):
+    for k in range(args.steps):
         res, rhat = step()
         runs.append(res)
+        if pr.n >= 32768:
+            torch.cuda.synchronize()
+            _note(f"timed step {k + 1} of {args.steps}")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
@@ -275,76 +450,53 @@ def main():
     rmse = float(torch.sqrt(torch.mean((rhat.cpu() - torch.tensor(pr.r_true)) ** 2)))
     last = runs[-1]
     extra = {
-        "pcg_iters": last.stats.iters, "ir_steps": last.stats.ir_steps, "relres_true": last.stats.relres_true,
-        "fell_back": any(r.fell_back for r in runs), "learned_precond_ms": last.precond_ms,
+        "pcg_iters": last.stats.iters, "outer_steps": last.stats.ir_steps, "relres_true": last.stats.relres_true,
+        "fell_back": max(r.fell_back for r in runs), "learned_iters": last.learned_iters,
         "map_rmse_db": rmse, "training": train_info,
     }
-
-    # CCCP + mixed precision on the same map (the paper's preconditioner, fitted)
     torch.cuda.synchronize()
     a = time.perf_counter()
-    pc = L.fit_precond(prob, Zd, gamma=0.1, rho=0.0, precision="bf16")
+    L.learned_precond(prob, model)
     torch.cuda.synchronize()
-    b = time.perf_counter()
-    alc, stc = L.pcg_solve(prob, y, pc, tol=tol, max_iter=100000, precision="bf16", refine=True, inner_tol=inner,
-                           ir_max=64, check_every=32, materialized=True)
-    torch.cuda.synchronize()
-    c = time.perf_counter()
-    L.predict(prob, alc, Eq, precision="f64")
-    torch.cuda.synchronize()
-    d_ = time.perf_counter()
-    extra["cccp_mixed"] = {"fit_ms": (b - a) * 1e3, "solve_ms": (c - b) * 1e3, "predict_ms": (d_ - c) * 1e3,
-                           "solves_per_s": 1.0 / (d_ - a), "pcg_iters": stc.iters,
-                           "ir_steps": stc.ir_steps, "cccp_iters": pc.stats.cccp_iters, "n_r": nr}
+    extra["learned_precond_ms"] = (time.perf_counter() - a) * 1e3
+    _note("timed step done")
+
+    # CCCP + mixed precision on the same map with the same solver, at the
+    # paper's gamma = 0.1 and at the gamma of the network's training targets
+    extra["cccp_mixed"] = {}
+    pc = None
+    for g in (0.1, 1e-3):
+        leg, pcg_ = cccp_mixed_leg(L, prob, y, Zd, Eq, tol, g)
+        extra["cccp_mixed"][f"gamma_{g:g}"] = leg
+        if pc is None:
+            pc = pcg_
+    extra["cccp_mixed"]["n_r"] = nr
+    _note("CCCP + mixed precision legs done")
 
     # float64 CCCP-PCG on the same map (the method with every product in float64)
     if not args.no_f64:
         torch.cuda.synchronize()
         a = time.perf_counter()
         pc64 = L.fit_precond(prob, Zd, gamma=0.1, rho=0.0)
+        torch.cuda.synchronize()
+        fa = time.perf_counter()
         al64, st64 = L.pcg_solve(prob, y, pc64, tol=tol, max_iter=100000, precision="f64", check_every=32,
                                  materialized=True)
         L.predict(prob, al64, Eq, precision="f64")
         torch.cuda.synchronize()
         b = time.perf_counter()
         extra["f64_cccp_pcg"] = {"solves_per_s": 1.0 / (b - a), "ms_per_solve": (b - a) * 1e3,
+                                 "fit_ms": (fa - a) * 1e3, "cccp_iters": pc64.stats.cccp_iters,
                                  "pcg_iters": st64.iters, "relres_true": st64.relres_true}
         extra["speedup_vs_f64_cccp_pcg"] = (b - a) * 1e3 / ms_per_step
-
-    # float32 products on the same map, G recomputed in every product against
-    # G stored once per solve (float32 tiles streamed from HBM); CCCP, PCG to
-    # tol with float64 refinement
-    f32c = {}
-    for mat in (False, True):
-        kw32 = dict(tol=tol, max_iter=100000, precision="f32", refine=True, inner_tol=inner, ir_max=64,
-                    check_every=32, materialized=mat)
-        torch.cuda.synchronize()
-        a = time.perf_counter()
-        _, s32 = L.pcg_solve(prob, y, pc, **kw32)
-        torch.cuda.synchronize()
-        b = time.perf_counter()
-        _, s32p = L.pcg_solve(prob, y, pc, profile=True, **kw32)
-        f32c["stored" if mat else "recomputed"] = {
-            "ms_per_solve": (b - a) * 1e3, "pcg_iters": s32.iters, "ir_steps": s32.ir_steps,
-            "relres_true": s32.relres_true, "us_per_product": s32p.kmv_ms * 1e3}
-    sb32 = L.load().laker_kmat_bytes(pr.n, pr.d, L.F32)
-    f32c["stored"]["gb_per_s"] = sb32 / (f32c["stored"]["us_per_product"] * 1e-6) / 1e9
-    f32c["stored"]["frac_of_hbm_peak"] = f32c["stored"]["gb_per_s"] / PEAK_HBM_GBS
-    f32c["stored_bytes"] = sb32
-    # the recomputed float32 product against its two bounds: the ALU slots of
-    # the symmetric schedule (as the headline roofline) and the fp32 MFMA flops
-    us32 = f32c["recomputed"]["us_per_product"] * 1e-6
-    dist = pr.n * (pr.n + 1) / 2.0
-    f32c["recomputed"]["frac_of_alu_peak"] = (EXP2_SLOTS * dist + float(pr.n) * pr.n) / us32 / 1e12 / PEAK_VALU_TOPS
-    f32c["recomputed"]["frac_of_fp32_mfma_peak"] = 2.0 * pr.d * dist / us32 / 1e12 / PEAK_FP32_MFMA_TFLOPS
-    extra["f32_stored_vs_recomputed"] = f32c
+        _note("float64 CCCP-PCG leg done")
 
     # roofline of the dominant kernel: the fused product exp2(<e_i, e_j>) p of
     # the solve, timed by the library with HIP events on the stream it launches
     # on (one pair of events around every product of the loop)
     pcl = L.learned_precond(prob, model)
-    _, stp = L.pcg_solve(prob, y, pcl, tol=tol, max_iter=100000, precision="bf16", refine=2, inner_tol=inner,
-                         ir_max=1000, check_every=INNER_CAP, inner_max_iter=INNER_CAP, profile=True,
+    _, stp = L.pcg_solve(prob, y, pcl, tol=tol, max_iter=budget, precision="bf16", refine=2, inner_tol=0.1,
+                         ir_max=20000, check_every=INNER_CAP, inner_max_iter=INNER_CAP, profile=True,
                          materialized=True)
     kms = stp.kmv_ms
     pairs = float(pr.n) * pr.n
@@ -355,7 +507,7 @@ def main():
     slots = EXP2_SLOTS * distinct + pairs
     achieved = slots / (kms * 1e-3) / 1e12
     mfma_flops = 2.0 * pr.d * distinct
-    traffic = measured_traffic()
+    traffic = measured_traffic(args.workload)
     roofline = {"kernel": "kmvsym_kernel<BF16,64> (fused exp2(<e_i,e_j>) p product over the symmetric tile "
                           "schedule, bf16 score tiles on MFMA)",
                 "bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TOPS, "unit": "TOP/s",
@@ -371,8 +523,8 @@ def main():
     # reduction per call), for reference
     p = torch.randn(pr.n, dtype=torch.float64, device=dev)
 
-    def time_kmv(pname, reps=20):
-        for _ in range(3):
+    def time_kmv(pname, reps=10):
+        for _ in range(2):
             L.kernel_matvec(prob, p, pname)
         s = torch.cuda.current_stream()
         e0 = torch.cuda.Event(enable_timing=True)
@@ -387,6 +539,15 @@ def main():
     standalone = {q: time_kmv(q) for q in ("bf16", "f32", "f64")}
     extra["kmv_standalone_ms"] = standalone
     extra["kmv_standalone_gpairs_per_s"] = {q: pairs / (v * 1e-3) / 1e9 for q, v in standalone.items()}
+    _note("roofline and stand-alone products done")
+
+    if not args.no_paper:
+        extra["paper_regime"] = paper_regime_leg(L, dev)
+        _note("paper regime sweep done")
+
+    if args.workload != "n16384_d64" and not args.no_c2:
+        extra["n16384_d64"] = c2_leg(L, LR, model, dev)
+        _note("16384-site leg done")
 
     out = {
         "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
@@ -396,18 +557,19 @@ def main():
                                f"scale=1/sqrt(d) tol={tol}",
                    "path": "learned rank-64+diag preconditioner (BF16 MLP) + flexible f64 outer CG (its float64 "
                            "products stream G stored once per solve) around bf16 "
-                           f"inner PCG (<= {INNER_CAP} iterations each; CCCP fallback on stall) + predict 45x45",
+                           f"inner PCG (<= {INNER_CAP} iterations each; CCCP fallback in the library when the "
+                           f"residual falls less than 2x over {STALL_WINDOW} iterations) + predict 45x45",
                    "training": f"{args.train_maps} maps n={TRAIN_N} lambda~logU[1e-5,1e-2] n_tx~U{{1..8}}, "
                                f"{args.train_epochs} epochs, CCCP targets gamma=1e-3"},
         "roofline": roofline,
         "extra": extra,
     }
 
-    _note("timed step and comparison legs done")
     if args.learned_eval > 0:
         extra["learned_eval"] = learned_eval_leg(L, LR, dev, args.learned_eval, args.train_maps, args.train_epochs)
     if args.batch_maps > 0:
         extra["batched"] = batched_leg(L, LR, dev, args.batch_maps, args.train_maps, args.train_epochs)
+        _note("batched leg done")
 
     if not args.no_cpu:
         _note("CPU oracle sample")
@@ -416,18 +578,18 @@ def main():
     print(json.dumps(out))
 
 
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "kmvsym_bf16_n16384_d64_pmc.json")
 KMV_SOURCE = os.path.join(ROOT, "paper_2604_25138_amd", "csrc", "kmv.hip")
 
 
-def measured_traffic():
+def measured_traffic(workload):
     """HBM bytes per launch of the product kernel from the committed counter
     runs (FETCH_SIZE and WRITE_SIZE, scaled by the same counters' reading for a
     plain copy), or None when the kernel source has changed since they were
     taken (the summary records the source's SHA-256)."""
     import hashlib
+    summary = os.path.join(ROOT, "profiles", f"kmvsym_bf16_{workload}_pmc.json")
     try:
-        with open(PMC_SUMMARY) as f:
+        with open(summary) as f:
             m = json.load(f)
         with open(KMV_SOURCE, "rb") as f:
             sha = hashlib.sha256(f.read()).hexdigest()
@@ -438,38 +600,104 @@ def measured_traffic():
     return m.get("traffic_bytes_per_launch")
 
 
-def cpu_baseline(pr, Z, tol, iters_hint, budget):
-    """The FP64 oracle on the host cores: kernel construction, the CCCP fit, and
-    as many PCG iterations as fit the budget; the solve time is scaled to the
-    iteration count the float64 GPU solve needed on the same map."""
-    from oracle import laker_oracle as O
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _threads():
     threads = os.cpu_count()
     try:
         from threadpoolctl import threadpool_info
         threads = max((i.get("num_threads", 0) for i in threadpool_info()), default=threads) or threads
     except Exception:
         pass
+    return threads
+
+
+def cpu_baseline(pr, Z, tol, iters_hint, budget):
+    """The FP64 oracle on the host cores.  Up to 16384 sites: the kernel
+    matrix and the CCCP fit measured in full, PCG iterations measured on a
+    bounded sample and scaled to the iteration count of the float64 GPU solve.
+    Above, where the dense float64 matrix alone is n^2 8 bytes (34 GB at 65536
+    sites): every stage timed on a block of rows and extrapolated (the oracle's
+    cost is linear in the rows it forms): kernel matrix rows, the product of
+    those rows with a vector (one PCG iteration's product), the random
+    directions U = A Z on those rows, and the low-rank CCCP iteration on the
+    full N_r x N_r system; the solve scaled to the float64 GPU solve's
+    iteration count."""
+    import numpy as np
+
+    from oracle import laker_oracle as O
+    threads = _threads()
+    cpu = _cpu_model()
+    iters_default = iters_hint if iters_hint else 1000
+    if pr.n <= 16384:
+        t0 = time.perf_counter()
+        A = O.system_matrix(pr.E, pr.scale, pr.lam)
+        t1 = time.perf_counter()
+        P, _ = O.fit_precond(pr.E, pr.scale, pr.lam, Z, gamma=0.1, rho=0.0)
+        t2 = time.perf_counter()
+        remaining = max(1.0, budget - (t2 - t0))
+        tm = time.perf_counter()
+        _ = A @ P.apply(pr.y)
+        per_it = time.perf_counter() - tm
+        k = int(max(3, min(200, remaining / max(per_it, 1e-6))))
+        _, it_done, _ = O.pcg(lambda v: A @ v, P.apply, pr.y, tol, k)
+        t3 = time.perf_counter()
+        per_iter = (t3 - t2) / max(it_done, 1)
+        iters = iters_hint if iters_hint else it_done
+        solve_s = (t1 - t0) + (t2 - t1) + per_iter * iters
+        return {"value": 1.0 / solve_s, "unit": "solves/s", "cores": threads, "cpu": cpu, "kind": "oracle",
+                "sample": f"oracle FP64 CCCP-PCG on n={pr.n}: kernel matrix {t1 - t0:.1f}s + CCCP fit "
+                          f"{t2 - t1:.1f}s (measured) + {it_done} PCG iterations measured at "
+                          f"{per_iter * 1e3:.1f} ms each, scaled to {iters} iterations",
+                "seconds_measured": t3 - t0}
+    n, nr = pr.n, Z.shape[1]
+    rows = np.arange(min(n, 2048))
+    frac = n / len(rows)
     t0 = time.perf_counter()
-    A = O.system_matrix(pr.E, pr.scale, pr.lam)
+    Gb = O.kernel_matrix(pr.E, pr.scale, Eq=pr.E[rows])
     t1 = time.perf_counter()
-    P, _ = O.fit_precond(pr.E, pr.scale, pr.lam, Z, gamma=0.1, rho=0.0)
+    v = np.random.default_rng(0).normal(size=n)
+    reps = 5
+    for _ in range(reps):
+        _ = Gb @ v + pr.lam * v[rows]
     t2 = time.perf_counter()
-    # PCG iterations for the remaining budget
-    remaining = max(1.0, budget - (t2 - t0))
-    tm = time.perf_counter()
-    _ = A @ P.apply(pr.y)
-    per_it = time.perf_counter() - tm
-    k = int(max(3, min(200, remaining / max(per_it, 1e-6))))
-    _, it_done, _ = O.pcg(lambda v: A @ v, P.apply, pr.y, tol, k)
+    _ = Gb @ Z
     t3 = time.perf_counter()
-    per_iter = (t3 - t2) / max(it_done, 1)
-    iters = iters_hint if iters_hint else it_done
-    solve_s = (t1 - t0) + (t2 - t1) + per_iter * iters
-    return {"value": 1.0 / solve_s, "unit": "solves/s", "cores": threads, "kind": "oracle",
-            "sample": f"oracle FP64 CCCP-PCG on n={pr.n}: kernel matrix {t1 - t0:.1f}s + CCCP fit {t2 - t1:.1f}s "
-                      f"(measured) + {it_done} PCG iterations measured at {per_iter * 1e3:.1f} ms each, "
-                      f"scaled to {iters} iterations",
-            "seconds_measured": t3 - t0}
+    # the CCCP iteration on the full-size low-rank system: its cost does not
+    # depend on the values of the directions, so normalised Gaussian columns
+    # stand in for them
+    Ub = Z / np.linalg.norm(Z, axis=0)[None, :]
+    _, _, _, cit = O.cccp_lowrank(Ub, 0.1, 0.0, 1e-10, 1e-8, 40)
+    t4 = time.perf_counter()
+    P = O.LowRankPrecond(Ub, 0.5, 0.5, np.ones(nr))
+    t5 = time.perf_counter()
+    for _ in range(reps):
+        _ = P.apply(v)
+    t6 = time.perf_counter()
+    form_s = (t1 - t0) * frac
+    matvec_s = (t2 - t1) / reps * frac
+    dirs_s = (t3 - t2) * frac
+    cccp_s = (t4 - t3) / max(cit, 1) * 300 + (t5 - t4)
+    apply_s = (t6 - t5) / reps
+    iters = iters_default
+    solve_s = form_s + dirs_s + cccp_s + iters * (matvec_s + apply_s)
+    return {"value": 1.0 / solve_s, "unit": "solves/s", "cores": threads, "cpu": cpu, "kind": "oracle",
+            "extrapolated": True,
+            "sample": f"oracle FP64 CCCP-PCG on n={n}, extrapolated from a block of {len(rows)} rows "
+                      f"(x{frac:.0f}): kernel matrix {form_s:.1f}s, directions U = A Z {dirs_s:.1f}s, "
+                      f"CCCP (300 iterations, {cit} timed) {cccp_s:.1f}s, then {iters} PCG iterations at "
+                      f"{(matvec_s + apply_s) * 1e3:.0f} ms each (product {matvec_s * 1e3:.0f} ms, apply "
+                      f"{apply_s * 1e3:.1f} ms)",
+            "seconds_measured": t6 - t0}
 
 
 if __name__ == "__main__":

@@ -51,7 +51,10 @@ typedef enum {
   LAKER_ENOMEM = -2,      /* workspace or preconditioner buffer too small             */
   LAKER_EHIP = -3,        /* HIP runtime error                                         */
   LAKER_EBREAKDOWN = -4,  /* p^T A p <= 0, non-positive pivot, or a NaN/Inf             */
-  LAKER_ENOCONV = -5      /* max_iter reached before the tolerance                      */
+  LAKER_ENOCONV = -5,     /* max_iter reached before the tolerance                      */
+  LAKER_ESTALL = -6       /* the residual fell by less than 2x over the last
+                             laker_pcg_opts.stall_window iterations; alpha holds
+                             the last iterate                                       */
 } laker_status;
 
 /* Arithmetic of the kernel products.
@@ -136,6 +139,17 @@ typedef struct {
                          of the maps it applies to; workspace
                          laker_batch_workspace_bytes + the sum over those maps
                          of (256 + laker_kmat_bytes(n_b, d, F64)) bytes        */
+  int32_t stall_window; /* > 0: stop with LAKER_ESTALL when the residual (the
+                         recursive one of PCG, the float64 outer one with
+                         refinement) fell by less than a factor 2 over the last
+                         stall_window PCG iterations; checked where the host
+                         reads the residual (every check_every iterations, every
+                         outer step).  0: no stall test                         */
+  int32_t lanczos;      /* 1 (refine 0 only): record PCG's step sizes and
+                         conjugation coefficients and estimate the extreme
+                         eigenvalues of P A from the Lanczos tridiagonal they
+                         define (stats->eig_min, eig_max, cond_est), over the
+                         first 8192 iterations                                  */
 } laker_pcg_opts;
 
 typedef struct {
@@ -158,7 +172,17 @@ typedef struct {
                            breaks down in reduced precision ends with the
                            correction it has; only a float64 breakdown is an
                            error)                                               */
+  int32_t fell_back;    /* laker_learned_solve: 0 the learned preconditioner
+                           solved the system; 1 its solve stalled, 2 it broke
+                           down (its build or its solve), and the solve went on
+                           from the last iterate with a CCCP fit                 */
+  int32_t learned_iters;/* laker_learned_solve: PCG iterations with the learned
+                           preconditioner (all of them when fell_back is 0)      */
+  int32_t lanczos_steps;/* opts->lanczos: PCG iterations in the estimate         */
   int32_t reserved;
+  double eig_min;       /* opts->lanczos: smallest and largest eigenvalue of the  */
+  double eig_max;       /*   Lanczos tridiagonal of the PCG coefficients (Ritz   */
+  double cond_est;      /*   values of P A) and their ratio, kappa(P A)           */
 } laker_stats;
 
 /* ---- sizes ---------------------------------------------------------------- */
@@ -187,6 +211,21 @@ size_t laker_kmat_bytes(int64_t n, int32_t d, int32_t precision);
 laker_status laker_kernel_matvec(const laker_problem* prob, const double* p, double* w,
                                  int32_t precision, void* workspace, size_t workspace_bytes,
                                  void* stream);
+
+/* theta = P r: the preconditioner step of every PCG iteration (Alg. 1; for
+ * CCCP P = Sigma_star^{-1/2}, eq. preconditioner-Sigmma), computed once with
+ * the same kernels the solver runs in its loop.  For a low-rank precond
+ * (CCCP or learned) theta = c r + Bt (B^T r), with c the scalar b^{-1/2}
+ * (CCCP) or the diagonal D^{-1} (learned); Jacobi: theta_i = r_i / A_ii;
+ * kind LAKER_PRECOND_NONE: theta = r.  precision selects the factors the
+ * solver would read (LAKER_F64: float64 B, Bt; otherwise the float32 copies
+ * of a CCCP fit; the learned factors are float64 in every precision).
+ * r, theta: device float64 vectors of length precond->n (not aliased).
+ * workspace: laker_precond_apply_workspace_bytes(n, n_r) bytes (unused for
+ * LAKER_PRECOND_NONE). */
+size_t laker_precond_apply_workspace_bytes(int64_t n, int32_t n_r);
+laker_status laker_precond_apply(const laker_precond* precond, const double* r, double* theta, int32_t precision,
+                                 void* workspace, size_t workspace_bytes, void* stream);
 
 /* Fit P = Sigma_star^{-1/2} (Alg. 1, preconditioner learning):
  * u_k = (lambda I + G) z_k, u_bar_k = u_k/||u_k|| (eq. random_directions);
@@ -276,6 +315,30 @@ laker_status laker_learned_train_step(const laker_problem* prob, void* model, in
  * B = D^{-1} V, Bt = -B (I + V^T D^{-1} V)^{-1}. */
 laker_status laker_learned_precond(const laker_problem* prob, const void* model, laker_precond* out,
                                    void* workspace, size_t workspace_bytes, void* stream);
+
+/* Workspace bytes of laker_learned_solve (precision and materialized as in
+ * the laker_pcg_opts it will get). */
+size_t laker_learned_solve_workspace_bytes(int64_t n, int32_t d, int32_t n_r, int32_t precision,
+                                           int32_t materialized);
+
+/* Solve (lambda I + G) alpha = y with the learned preconditioner, falling back
+ * to the paper's CCCP preconditioner (Alg. 1) when that solve does not get
+ * there: the network builds P = S^{-1} (laker_learned_precond) and
+ * laker_pcg_solve runs with `opts` (opts->stall_window > 0 turns on the stall
+ * test).  If the learned build breaks down, or its solve stalls (LAKER_ESTALL),
+ * breaks down or reaches opts->max_iter, CCCP is fitted with the directions Z
+ * and options `cccp` (laker_fit_precond) into the same buffer and the solve
+ * continues from the last iterate with the same opts (a fresh max_iter, no
+ * stall test).  precond: caller-owned buffer of laker_precond_bytes(n,
+ * max(64, cccp->n_r)) bytes; on return it holds the preconditioner used last
+ * (kind LAKER_PRECOND_LEARNED or LAKER_PRECOND_CCCP).  stats: iters counts
+ * both solves; fell_back (0, 1 stall or cap, 2 breakdown) and learned_iters
+ * say what happened; cccp_iters is the fit's.  opts->warm_start and
+ * opts->lanczos must be 0.  Returns the status of the last solve. */
+laker_status laker_learned_solve(const laker_problem* prob, const void* model, const double* Z,
+                                 const laker_cccp_opts* cccp, const double* y, double* alpha,
+                                 const laker_pcg_opts* opts, laker_precond* precond, void* workspace,
+                                 size_t workspace_bytes, laker_stats* stats, void* stream);
 
 /* Workspace bytes of laker_precond_sigma_half. */
 size_t laker_sigma_half_workspace_bytes(int64_t n, int32_t n_r, int32_t m);

@@ -101,6 +101,7 @@ const char* laker_status_str(int32_t s) {
     case LAKER_EHIP: return "HIP runtime error";
     case LAKER_EBREAKDOWN: return "numerical breakdown";
     case LAKER_ENOCONV: return "iteration cap reached before the tolerance";
+    case LAKER_ESTALL: return "the residual stalled";
     default: return "unknown status";
   }
 }
@@ -145,6 +146,57 @@ laker_status laker_kernel_matvec(const laker_problem* prob, const double* p, dou
   A.out = w;
   LK_TRY(kmv_run(precision, pb.dp, pl, A, st));
   return LAKER_OK;
+}
+
+// ---- preconditioner apply ------------------------------------------------------
+}  // extern "C"
+
+namespace {
+
+struct ApplyWs {
+  double* tpart;
+  double* t;
+  PcgScalars* S;
+  double* rzp;
+  size_t total;
+};
+ApplyWs plan_apply_ws(void* base, int64_t n, int nr) {
+  WsCarver c(base);
+  ApplyWs a;
+  a.tpart = c.take<double>((size_t)((n + 63) / 64) * (size_t)pad_nr(nr > 0 ? nr : 1));
+  a.t = c.take<double>(kMaxNr);
+  a.S = c.take<PcgScalars>(1);
+  a.rzp = c.take<double>(kMaxBlocks);
+  a.total = c.bytes();
+  return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t laker_precond_apply_workspace_bytes(int64_t n, int32_t n_r) {
+  if (n < 1 || n_r < 0 || n_r > kMaxNr) return 0;
+  return plan_apply_ws(nullptr, n, n_r).total;
+}
+
+laker_status laker_precond_apply(const laker_precond* precond, const double* r, double* theta, int32_t precision,
+                                 void* workspace, size_t workspace_bytes, void* stream) {
+  if (precond == nullptr || r == nullptr || theta == nullptr || precond->n < 1) return LAKER_EINVAL;
+  if (!valid_precision(precision)) return LAKER_EINVAL;
+  const int64_t n = precond->n;
+  hipStream_t st = (hipStream_t)stream;
+  if (precond->kind == LAKER_PRECOND_NONE) {
+    LK_TRY(hipMemcpyAsync(theta, r, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    return LAKER_OK;
+  }
+  if (workspace == nullptr) return LAKER_EINVAL;
+  PrecondView view{};
+  laker_status e = make_view(precond, n, precision, &view);
+  if (e != LAKER_OK) return e;
+  ApplyWs W = plan_apply_ws(workspace, n, view.nr);
+  if (workspace_bytes < W.total) return LAKER_ENOMEM;
+  return precond_apply_once(view, r, theta, n, W.tpart, W.t, W.S, W.rzp, st);
 }
 
 laker_status laker_fit_precond(const laker_problem* prob, const double* Z, const laker_cccp_opts* opts,
@@ -199,6 +251,8 @@ laker_status laker_pcg_solve(const laker_problem* prob, const laker_precond* pre
   if (opts->refine < 0 || opts->refine > 2 || opts->inner_max_iter < 0) return LAKER_EINVAL;
   if (opts->refine && (opts->ir_max < 1 || !(opts->inner_tol > 0.0))) return LAKER_EINVAL;
   if (opts->refine == 1 && opts->ir_max > 64) return LAKER_EINVAL;
+  if (opts->stall_window < 0 || opts->lanczos < 0 || opts->lanczos > 1) return LAKER_EINVAL;
+  if (opts->lanczos && opts->refine) return LAKER_EINVAL;
   PrecondView view{};
   e = make_view(precond, prob->n, opts->precision, &view);
   if (e != LAKER_OK) return e;
@@ -235,6 +289,8 @@ laker_status laker_pcg_solve(const laker_problem* prob, const laker_precond* pre
   sp->kmv_launches = 0;
   sp->kmv_launch_ms = 0.0;
   sp->escalations = 0;
+  sp->lanczos_steps = 0;
+  sp->eig_min = sp->eig_max = sp->cond_est = 0.0;
   const int check = opts->check_every > 0 ? opts->check_every : 16;
   LK_TRY(hipMemsetAsync(W.S, 0, sizeof(PcgScalars), st));
   LK_TRY(hipMemsetAsync(W.cnt, 0, 16 * sizeof(unsigned), st));
@@ -248,8 +304,8 @@ laker_status laker_pcg_solve(const laker_problem* prob, const laker_precond* pre
   laker_status r;
   if (!opts->refine) {
     r = pcg_run(pb, W, view, y, alpha, opts->warm_start != 0, opts->tol, opts->max_iter, check, opts->precision,
-                opts->graph != 0, opts->profile != 0, sp, st);
-    if (r == LAKER_OK || r == LAKER_ENOCONV) {
+                opts->graph != 0, opts->profile != 0, sp, st, false, opts->stall_window, opts->lanczos != 0);
+    if (r == LAKER_OK || r == LAKER_ENOCONV || r == LAKER_ESTALL) {
       double rt = 0.0;
       laker_status r2 = true_residual(pb, W, y, alpha, nullptr, &rt, true, st);
       if (r2 != LAKER_OK) return r2;
@@ -263,6 +319,8 @@ laker_status laker_pcg_solve(const laker_problem* prob, const laker_precond* pre
     r = LAKER_ENOCONV;
     int used = 0;
     int prec_now = opts->precision;
+    StallTest stall;
+    stall.window = opts->stall_window;
     for (int s = 0; s <= opts->ir_max; ++s) {
       double rel = 0.0;
       laker_status r2 = true_residual(pb, W, y, alpha, W.rout, &rel, s > 0 || opts->warm_start, st);
@@ -276,6 +334,10 @@ laker_status laker_pcg_solve(const laker_problem* prob, const laker_precond* pre
         break;
       }
       if (s == opts->ir_max || used >= opts->max_iter) break;
+      if (stall.stalled(used, rel)) {
+        r = LAKER_ESTALL;
+        break;
+      }
       // no progress over two refinement steps: the inner products are too
       // coarse for this system (the correction they give does not contract the
       // float64 residual); continue with the next finer arithmetic
@@ -451,6 +513,81 @@ laker_status laker_learned_precond(const laker_problem* prob, const void* model,
   return learned_flag(W, st);
 }
 
+size_t laker_learned_solve_workspace_bytes(int64_t n, int32_t d, int32_t n_r, int32_t precision,
+                                           int32_t materialized) {
+  if (n < 1 || d < 1 || d > kMaxD || n_r < 1 || n_r > kMaxNr || !valid_precision(precision)) return 0;
+  size_t need = laker_solve_workspace_bytes(n, d, 0);
+  if (materialized) {
+    const size_t b64 = laker_kmat_bytes(n, d, LAKER_F64);
+    if (b64 > 0) {
+      need = ((need + 255) & ~size_t(255)) + b64;
+      if (precision == LAKER_F32) need = ((need + 255) & ~size_t(255)) + laker_kmat_bytes(n, d, LAKER_F32);
+    }
+  }
+  const size_t a = laker_learned_workspace_bytes(n, d, 0);
+  const size_t b = laker_fit_workspace_bytes(n, d, n_r);
+  if (a > need) need = a;
+  if (b > need) need = b;
+  return need;
+}
+
+laker_status laker_learned_solve(const laker_problem* prob, const void* model, const double* Z,
+                                 const laker_cccp_opts* cccp, const double* y, double* alpha,
+                                 const laker_pcg_opts* opts, laker_precond* precond, void* workspace,
+                                 size_t workspace_bytes, laker_stats* stats, void* stream) {
+  laker_status e = check_problem(prob);
+  if (e != LAKER_OK) return e;
+  if (model == nullptr || Z == nullptr || cccp == nullptr || y == nullptr || alpha == nullptr || opts == nullptr ||
+      precond == nullptr || precond->data == nullptr || workspace == nullptr)
+    return LAKER_EINVAL;
+  if (prob->n < kRank || cccp->n_r < 1 || cccp->n_r > kMaxNr || cccp->n_r > prob->n) return LAKER_EINVAL;
+  if (opts->warm_start || opts->lanczos) return LAKER_EINVAL;
+  const int nr_buf = cccp->n_r > kRank ? cccp->n_r : kRank;
+  if (precond->bytes < laker_precond_bytes(prob->n, nr_buf)) return LAKER_ENOMEM;
+  const size_t need = laker_learned_solve_workspace_bytes(prob->n, prob->d, cccp->n_r, opts->precision,
+                                                          opts->materialized);
+  if (need == 0) return LAKER_EINVAL;
+  if (workspace_bytes < need) return LAKER_ENOMEM;
+  laker_stats local{};
+  laker_stats* sp = stats != nullptr ? stats : &local;
+  *sp = laker_stats{};
+  // 1. the learned preconditioner, and the solve with it under the stall test
+  e = laker_learned_precond(prob, model, precond, workspace, workspace_bytes, stream);
+  int reason = 0;
+  int learned_iters = 0;
+  if (e == LAKER_EBREAKDOWN) {
+    reason = 2;
+  } else if (e != LAKER_OK) {
+    return e;
+  } else {
+    e = laker_pcg_solve(prob, precond, y, alpha, opts, workspace, workspace_bytes, sp, stream);
+    learned_iters = sp->iters;
+    if (e == LAKER_OK) {
+      sp->learned_iters = learned_iters;
+      return LAKER_OK;
+    }
+    if (e == LAKER_ESTALL || e == LAKER_ENOCONV) reason = 1;
+    else if (e == LAKER_EBREAKDOWN) reason = 2;
+    else return e;
+  }
+  // 2. fallback: the CCCP fit of Alg. 1 into the same buffer, and the solve
+  // from the learned solve's iterate (from zero after a breakdown of the build)
+  laker_stats fit{};
+  e = laker_fit_precond(prob, Z, cccp, precond, workspace, workspace_bytes, &fit, stream);
+  if (e != LAKER_OK) return e;
+  laker_pcg_opts o2 = *opts;
+  o2.stall_window = 0;
+  o2.warm_start = (reason == 1 || (reason == 2 && learned_iters > 0)) ? 1 : 0;
+  laker_stats s2{};
+  e = laker_pcg_solve(prob, precond, y, alpha, &o2, workspace, workspace_bytes, &s2, stream);
+  s2.iters += learned_iters;
+  s2.fell_back = reason;
+  s2.learned_iters = learned_iters;
+  s2.cccp_iters = fit.cccp_iters;
+  *sp = s2;
+  return e;
+}
+
 size_t laker_sigma_half_workspace_bytes(int64_t n, int32_t n_r, int32_t m) {
   if (n < 1 || n_r < 1 || n_r > kMaxNr || m < 1) return 0;
   return plan_sigma_half_ws(nullptr, n, n_r, m).total;
@@ -491,7 +628,7 @@ laker_status laker_pcg_solve_batched(int32_t count, const laker_problem* probs, 
   if (!valid_precision(opts->precision) || !(opts->tol >= 0.0) || opts->max_iter < 1) return LAKER_EINVAL;
   if (opts->refine < 0 || opts->refine > 1) return LAKER_EINVAL;
   if (opts->refine && (opts->ir_max < 1 || opts->ir_max > 64 || !(opts->inner_tol > 0.0))) return LAKER_EINVAL;
-  if (opts->warm_start) return LAKER_EINVAL;
+  if (opts->warm_start || opts->lanczos || opts->stall_window) return LAKER_EINVAL;
   if (opts->materialized < 0 || opts->materialized > 1) return LAKER_EINVAL;
   std::vector<int64_t> ns(count);
   std::vector<Problem> pbs(count);

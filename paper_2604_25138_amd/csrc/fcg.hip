@@ -133,6 +133,9 @@ laker_status fcg_run(const Problem& pb, const SolveWs& W, const PrecondView& P, 
   if (rel <= o.tol) return LAKER_OK;
   int used = 0;
   const int inner_cap = o.inner_max_iter > 0 ? o.inner_max_iter : o.max_iter;
+  StallTest stall;
+  stall.window = o.stall_window;
+  (void)stall.stalled(0, rel);
   for (int k = 0; k < o.ir_max; ++k) {
     if (used >= o.max_iter) break;
     // z = inner solve of A z = r; a reduced-precision breakdown or cap keeps
@@ -199,6 +202,7 @@ laker_status fcg_run(const Problem& pb, const SolveWs& W, const PrecondView& P, 
       if (rt <= o.tol) return LAKER_OK;
     }
     sp->relres_true = rel;
+    if (stall.stalled(used, rel)) return LAKER_ESTALL;
   }
   double rt = 0.0;
   e = true_residual(pb, W, y, alpha, nullptr, &rt, true, st);

@@ -146,6 +146,83 @@ __global__ void axpy_kernel(double* __restrict__ x, const double* __restrict__ d
   axpy_body(blockIdx.x, gridDim.x, x, d, n);
 }
 
+// After iteration k (k = kcur - 1): its step size and the conjugation
+// coefficient the run state holds.  Launches after the run has stopped see the
+// same k and rewrite the same values.
+__global__ void lanczos_record_kernel(const PcgScalars* S, double* __restrict__ coef, int cap) {
+  if (threadIdx.x != 0) return;
+  const int k = S->kcur - 1;
+  if (k < 0 || k >= cap || S->done == 2) return;
+  coef[2 * k] = S->delta;
+  coef[2 * k + 1] = S->beta;
+}
+
+// Lanczos tridiagonal of m CG steps with step sizes a_k and conjugation
+// coefficients b_k (p_{k+1} = z_{k+1} + b_k p_k):
+//   T_00 = 1 / a_0,  T_kk = 1 / a_k + b_{k-1} / a_{k-1},  T_{k-1,k} = sqrt(b_{k-1}) / a_{k-1}.
+// Its eigenvalues are the Ritz values of P A on the Krylov space.  With the
+// conjugation done inside the next product (shifted = 1) the coefficient
+// recorded after iteration k is b_{k-1}; otherwise it is b_k.
+__device__ __forceinline__ void tri_entry(const double* coef, int k, int shifted, double& diag, double& off2) {
+  const double ak = coef[2 * k];
+  diag = 1.0 / ak;
+  off2 = 0.0;
+  if (k > 0) {
+    const double am = coef[2 * (k - 1)];
+    const double bm = shifted ? coef[2 * k + 1] : coef[2 * (k - 1) + 1];
+    diag += bm / am;
+    off2 = bm / (am * am);
+  }
+}
+
+// Number of eigenvalues of T below x (Sturm sequence of the LDL^T pivots).
+__device__ int tri_count_below(const double* coef, int m, int shifted, double x) {
+  int c = 0;
+  double dprev = 1.0;
+  for (int k = 0; k < m; ++k) {
+    double dk, e2;
+    tri_entry(coef, k, shifted, dk, e2);
+    double d = dk - x - (k > 0 ? e2 / dprev : 0.0);
+    if (d == 0.0) d = -1e-300;
+    if (d < 0.0) ++c;
+    dprev = d;
+  }
+  return c;
+}
+
+// out[0] = smallest, out[1] = largest eigenvalue of T, by bisection inside the
+// Gershgorin interval (thread 0: the smallest, thread 1: the largest).
+__global__ void tridiag_extremes_kernel(const double* __restrict__ coef, int m, int shifted,
+                                        double* __restrict__ out) {
+  const int t = threadIdx.x;
+  if (t > 1) return;
+  double lo = 0.0, hi = 0.0;
+  for (int k = 0; k < m; ++k) {
+    double dk, e2;
+    tri_entry(coef, k, shifted, dk, e2);
+    const double el = k > 0 ? sqrt(e2) : 0.0;
+    double er = 0.0;
+    if (k + 1 < m) {
+      double dn, en2;
+      tri_entry(coef, k + 1, shifted, dn, en2);
+      er = sqrt(en2);
+    }
+    const double a = dk - el - er, b = dk + el + er;
+    if (k == 0 || a < lo) lo = a;
+    if (k == 0 || b > hi) hi = b;
+  }
+  if (lo < 0.0) lo = 0.0;
+  // smallest: the least x with count(x) >= 1; largest: the least x with count(x) >= m
+  const int target = t == 0 ? 1 : m;
+  double a = lo, b = hi * (1.0 + 1e-12) + 1e-300;
+  for (int it = 0; it < 200 && b - a > 1e-15 * fabs(b); ++it) {
+    const double mid = 0.5 * (a + b);
+    if (tri_count_below(coef, m, shifted, mid) >= target) b = mid;
+    else a = mid;
+  }
+  out[t] = 0.5 * (a + b);
+}
+
 // theta = P r for the low-rank preconditioner (t partials, t, theta: three
 // passes, or two when the apply finishes t itself, lr_fused_t); with rrp set
 // the pass that finishes t first takes the stopping decision of iteration k,
@@ -218,6 +295,8 @@ SolveWs plan_solve_ws(void* base, int64_t n, int d, int64_t m) {
   w.t = c.take<double>(kMaxNr);
   w.misc = c.take<double>(16);
   w.cnt = c.take<unsigned>(16);
+  w.lcoef = c.take<double>(2 * (size_t)kLanczosCap);
+  w.lout = c.take<double>(4);
   w.total = c.bytes();
   return w;
 }
@@ -267,7 +346,7 @@ laker_status true_residual(const Problem& pb, const SolveWs& ws, const double* y
 
 laker_status pcg_run(const Problem& pb, const SolveWs& ws, const PrecondView& P, const double* rhs, double* alpha,
                      bool warm, double tol, int max_iter, int check_every, int prec, bool use_graph, bool profile,
-                     laker_stats* stats, hipStream_t st, bool defer) {
+                     laker_stats* stats, hipStream_t st, bool defer, int stall_window, bool lanczos) {
   const int64_t n = pb.n;
   const int g = red_blocks(n);
   const bool lowrank0 = P.kind == LAKER_PRECOND_CCCP || P.kind == LAKER_PRECOND_LEARNED;
@@ -387,6 +466,10 @@ laker_status pcg_run(const Problem& pb, const SolveWs& ws, const PrecondView& P,
       if (!fused) pcg_pupdate_kernel<LAKER_PRECOND_CCCP><<<g, kThreads, 0, s2>>>(0, th, p, n, S, ws.rrp, g, ws.rzp, ga);
     }
     LK_CHECK_LAUNCH();
+    if (lanczos) {
+      lanczos_record_kernel<<<1, 64, 0, s2>>>(S, ws.lcoef, kLanczosCap);
+      LK_CHECK_LAUNCH();
+    }
     return LAKER_OK;
   };
 
@@ -430,6 +513,8 @@ laker_status pcg_run(const Problem& pb, const SolveWs& ws, const PrecondView& P,
   int chunk = check_every;
   double last_rr = -1.0;
   int last_it = 0;
+  StallTest stall;
+  stall.window = stall_window;
   for (;;) {
     if (gexec != nullptr) {
       if (hipGraphLaunch(gexec, st) != hipSuccess) {
@@ -451,6 +536,10 @@ laker_status pcg_run(const Problem& pb, const SolveWs& ws, const PrecondView& P,
       break;
     }
     if (hs.done || k >= max_iter + check_every) break;
+    if (stall.stalled(hs.iters, sqrt(hs.rr))) {
+      loop_status = LAKER_ESTALL;
+      break;
+    }
     chunk = check_every;
     if (last_rr > 0.0 && hs.rr > 0.0 && hs.rr < last_rr && hs.iters > last_it && hs.tol2 > 0.0) {
       const double per_it = log(hs.rr / last_rr) / (double)(hs.iters - last_it);
@@ -492,11 +581,24 @@ laker_status pcg_run(const Problem& pb, const SolveWs& ws, const PrecondView& P,
       }
     }
   }
-  if (loop_status != LAKER_OK) return loop_status;
+  if (loop_status != LAKER_OK && loop_status != LAKER_ESTALL) return loop_status;
   if (stats) {
     stats->iters += hs.iters;
     stats->relres = hs.yy > 0 ? sqrt(hs.rr / hs.yy) : 0.0;
   }
+  if (lanczos && stats != nullptr && hs.iters > 0) {
+    const int m = hs.iters < kLanczosCap ? hs.iters : kLanczosCap;
+    tridiag_extremes_kernel<<<1, 64, 0, st>>>(ws.lcoef, m, fused ? 1 : 0, ws.lout);
+    LK_CHECK_LAUNCH();
+    double h2[2] = {0.0, 0.0};
+    LK_TRY(hipMemcpyAsync(h2, ws.lout, sizeof(h2), hipMemcpyDeviceToHost, st));
+    LK_TRY(hipStreamSynchronize(st));
+    stats->lanczos_steps = m;
+    stats->eig_min = h2[0];
+    stats->eig_max = h2[1];
+    stats->cond_est = h2[0] > 0.0 ? h2[1] / h2[0] : 0.0;
+  }
+  if (loop_status == LAKER_ESTALL) return LAKER_ESTALL;
   if (hs.done == 2) return LAKER_EBREAKDOWN;
   if (hs.done == 1) return LAKER_OK;
   return LAKER_ENOCONV;
@@ -513,6 +615,26 @@ laker_status axpy_inplace(double* x, const double* d, int64_t n, hipStream_t st)
 laker_status apply_lowrank_once(const PrecondView& P, const double* r, double* theta, int64_t n, const SolveWs& ws,
                                 hipStream_t st) {
   return enqueue_lowrank_any(P, r, theta, n, nullptr, nullptr, 0, nullptr, ws.tpart, ws.t, false, st);
+}
+
+namespace {
+__global__ void clear_scalars_kernel(PcgScalars* S) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *S = PcgScalars{};
+}
+}  // namespace
+
+laker_status precond_apply_once(const PrecondView& P, const double* r, double* theta, int64_t n, double* tpart,
+                                double* t, PcgScalars* S, double* rzp, hipStream_t st) {
+  if (P.kind == LAKER_PRECOND_JACOBI) {
+    // the Jacobi pass reads the run state first: a cleared one (not done)
+    clear_scalars_kernel<<<1, 64, 0, st>>>(S);
+    LK_CHECK_LAUNCH();
+    jacobi_apply_kernel<<<red_blocks(n), kThreads, 0, st>>>(r, (const double*)P.dinv, theta, n, S, rzp);
+    LK_CHECK_LAUNCH();
+    return LAKER_OK;
+  }
+  if (P.kind != LAKER_PRECOND_CCCP && P.kind != LAKER_PRECOND_LEARNED) return LAKER_EINVAL;
+  return enqueue_lowrank_any(P, r, theta, n, nullptr, nullptr, 0, nullptr, tpart, t, false, st);
 }
 
 }  // namespace lk

@@ -42,6 +42,8 @@ struct SolveWs {
   double* t;
   double* misc;
   unsigned* cnt;
+  double* lcoef;    // Lanczos estimate: (step size, conjugation coefficient) per iteration
+  double* lout;     // its extreme Ritz values
   size_t total;
   // stored G (float64 / float32 tiles, kmat_build) placed after the carved
   // workspace when the solve asks for it; null otherwise
@@ -85,9 +87,47 @@ inline int pad_nr(int nr) { return (nr + 3) & ~3; }
 // defer: when one chunk covers max_iter (eager launches, no profiling), the
 // iterations are only enqueued: the call returns LAKER_OK at once and the
 // caller reads ws.S (iters, done) after its own next synchronisation.
+// stall_window > 0: LAKER_ESTALL when ||r|| fell by less than 2x over the last
+// stall_window iterations (checked at each read-back).  lanczos: record the
+// step sizes and conjugation coefficients and fill stats->eig_min, eig_max,
+// cond_est, lanczos_steps from the Lanczos tridiagonal they define.
+constexpr int kLanczosCap = 8192;
 laker_status pcg_run(const Problem& pb, const SolveWs& ws, const PrecondView& P, const double* rhs, double* alpha,
                      bool warm, double tol, int max_iter, int check_every, int prec, bool use_graph,
-                     bool profile, laker_stats* stats, hipStream_t st, bool defer = false);
+                     bool profile, laker_stats* stats, hipStream_t st, bool defer = false, int stall_window = 0,
+                     bool lanczos = false);
+
+// Residual history of a solve for the stall test: stalled() is true when the
+// newest residual is above half the residual of the latest record at least
+// `window` iterations older.
+struct StallTest {
+  int window = 0;
+  int n = 0;
+  int it[4096];
+  double res[4096];
+  bool stalled(int iters, double resid) {
+    if (window <= 0) return false;
+    bool s = false;
+    for (int k = n - 1; k >= 0; --k) {
+      if (it[k] <= iters - window) {
+        s = resid > 0.5 * res[k];
+        break;
+      }
+    }
+    if (n == 4096) {
+      // keep every second record (the test reads the latest old-enough one)
+      for (int k = 0; k < 2048; ++k) {
+        it[k] = it[2 * k + 1];
+        res[k] = res[2 * k + 1];
+      }
+      n = 2048;
+    }
+    it[n] = iters;
+    res[n] = resid;
+    ++n;
+    return s;
+  }
+};
 laker_status true_residual(const Problem& pb, const SolveWs& ws, const double* y, const double* alpha,
                            double* r_out, double* relres, bool have_alpha, hipStream_t st);
 laker_status axpy_inplace(double* x, const double* d, int64_t n, hipStream_t st);
@@ -101,5 +141,10 @@ laker_status fcg_run(const Problem& pb, const SolveWs& ws, const PrecondView& P,
 hipStream_t pcg_capture_stream();
 laker_status apply_lowrank_once(const PrecondView& P, const double* r, double* theta, int64_t n,
                                 const SolveWs& ws, hipStream_t st);
+// theta = P r once, with the kernels of the PCG loop (low-rank: the t partials,
+// t and the apply, or the apply that finishes t itself; Jacobi: the diagonal
+// pass, which takes its run state from S and writes r^T theta partials to rzp)
+laker_status precond_apply_once(const PrecondView& P, const double* r, double* theta, int64_t n, double* tpart,
+                                double* t, PcgScalars* S, double* rzp, hipStream_t st);
 
 }  // namespace lk

@@ -16,7 +16,7 @@ import torch
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "liblaker.so")
 
-LAKER_OK, LAKER_EINVAL, LAKER_ENOMEM, LAKER_EHIP, LAKER_EBREAKDOWN, LAKER_ENOCONV = 0, -1, -2, -3, -4, -5
+LAKER_OK, LAKER_EINVAL, LAKER_ENOMEM, LAKER_EHIP, LAKER_EBREAKDOWN, LAKER_ENOCONV, LAKER_ESTALL = 0, -1, -2, -3, -4, -5, -6
 F64, F32, BF16 = 0, 1, 2
 PRECOND_NONE, PRECOND_JACOBI, PRECOND_CCCP, PRECOND_LEARNED = 0, 1, 2, 3
 _PREC = {"f64": F64, "f32": F32, "bf16": BF16, F64: F64, F32: F32, BF16: BF16}
@@ -28,7 +28,8 @@ EXPORTS = (
     "laker_predict", "laker_status_str", "laker_mlp_layout_query", "laker_learned_workspace_bytes",
     "laker_learned_forward", "laker_learned_train_step", "laker_learned_precond",
     "laker_sigma_half_workspace_bytes", "laker_precond_sigma_half", "laker_batch_workspace_bytes",
-    "laker_pcg_solve_batched", "laker_kmat_bytes",
+    "laker_pcg_solve_batched", "laker_kmat_bytes", "laker_precond_apply_workspace_bytes", "laker_precond_apply",
+    "laker_learned_solve_workspace_bytes", "laker_learned_solve",
 )
 MLP_KEYS = ("W1", "b1", "W2", "b2", "W3", "b3")
 MLP_HIDDEN, MLP_RANK = 256, 64
@@ -53,14 +54,17 @@ class laker_pcg_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("precision", C.c_int32), ("refine", C.c_int32),
                 ("ir_max", C.c_int32), ("inner_tol", C.c_double), ("warm_start", C.c_int32),
                 ("check_every", C.c_int32), ("graph", C.c_int32), ("profile", C.c_int32),
-                ("inner_max_iter", C.c_int32), ("materialized", C.c_int32)]
+                ("inner_max_iter", C.c_int32), ("materialized", C.c_int32), ("stall_window", C.c_int32),
+                ("lanczos", C.c_int32)]
 
 
 class laker_stats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("ir_steps", C.c_int32), ("cccp_iters", C.c_int32), ("status", C.c_int32),
                 ("relres", C.c_double), ("relres_true", C.c_double), ("ir_relres", C.c_double * 64),
                 ("kmv_ms", C.c_double), ("kmv_count", C.c_int32), ("kmv_launches", C.c_int32),
-                ("kmv_launch_ms", C.c_double), ("escalations", C.c_int32), ("reserved", C.c_int32)]
+                ("kmv_launch_ms", C.c_double), ("escalations", C.c_int32), ("fell_back", C.c_int32),
+                ("learned_iters", C.c_int32), ("lanczos_steps", C.c_int32), ("reserved", C.c_int32),
+                ("eig_min", C.c_double), ("eig_max", C.c_double), ("cond_est", C.c_double)]
 
 
 class laker_mlp_layout(C.Structure):
@@ -110,6 +114,10 @@ def load(path: str = LIB_PATH):
     lib.laker_fit_precond.argtypes = [P(laker_problem), vp, P(laker_cccp_opts), P(laker_precond), vp, sz,
                                       P(laker_stats), vp]
     lib.laker_fit_precond.restype = i32
+    lib.laker_precond_apply_workspace_bytes.argtypes = [i64, i32]
+    lib.laker_precond_apply_workspace_bytes.restype = sz
+    lib.laker_precond_apply.argtypes = [P(laker_precond), vp, vp, i32, vp, sz, vp]
+    lib.laker_precond_apply.restype = i32
     lib.laker_jacobi_precond.argtypes = [P(laker_problem), P(laker_precond), vp]
     lib.laker_jacobi_precond.restype = i32
     lib.laker_pcg_solve.argtypes = [P(laker_problem), P(laker_precond), vp, vp, P(laker_pcg_opts), vp, sz,
@@ -130,6 +138,11 @@ def load(path: str = LIB_PATH):
     lib.laker_learned_train_step.restype = i32
     lib.laker_learned_precond.argtypes = [P(laker_problem), vp, P(laker_precond), vp, sz, vp]
     lib.laker_learned_precond.restype = i32
+    lib.laker_learned_solve_workspace_bytes.argtypes = [i64, i32, i32, i32, i32]
+    lib.laker_learned_solve_workspace_bytes.restype = sz
+    lib.laker_learned_solve.argtypes = [P(laker_problem), vp, vp, P(laker_cccp_opts), vp, vp, P(laker_pcg_opts),
+                                        P(laker_precond), vp, sz, P(laker_stats), vp]
+    lib.laker_learned_solve.restype = i32
     lib.laker_sigma_half_workspace_bytes.argtypes = [i64, i32, i32]
     lib.laker_sigma_half_workspace_bytes.restype = sz
     lib.laker_precond_sigma_half.argtypes = [P(laker_precond), i32, vp, vp, vp, sz, vp]
@@ -263,12 +276,29 @@ def jacobi_precond(prob: Problem) -> Precond:
     return Precond(pc.kind, prob.n, 0, data, pc)
 
 
+def precond_apply(pc: Precond, r, precision="f64") -> torch.Tensor:
+    """theta = P r with the solver's preconditioner kernels."""
+    lib = load()
+    dev = pc.data.device if pc.data is not None else torch.device("cuda")
+    r = _dev_f64(r, dev)
+    theta = torch.empty_like(r)
+    nb = lib.laker_precond_apply_workspace_bytes(pc.n, pc.n_r)
+    ws = _workspace("apply", nb, dev)
+    s = lib.laker_precond_apply(C.byref(pc.c), _ptr(r), _ptr(theta), _PREC[precision], _ptr(ws), ws.numel(),
+                                _stream())
+    _check(s, "laker_precond_apply")
+    return theta
+
+
 def pcg_solve(prob: Problem, y, precond: Precond | None = None, tol: float = 1e-10, max_iter: int = 10000,
               precision="f64", refine: bool = False, inner_tol: float = 1e-2, ir_max: int = 64,
               alpha0: torch.Tensor | None = None, check_every: int = 16, allow_noconv: bool = False,
-              graph: bool = False, profile: bool = False, inner_max_iter: int = 0, materialized: bool = False):
+              graph: bool = False, profile: bool = False, inner_max_iter: int = 0, materialized: bool = False,
+              stall_window: int = 0, lanczos: bool = False):
     """Returns (alpha, stats).  materialized: store G once per call and stream it
-    in the float64 (and float32) products."""
+    in the float64 (and float32) products; stall_window: LAKER_ESTALL when the
+    residual falls by less than 2x over that many iterations; lanczos: estimate
+    kappa(P A) from the PCG coefficients (stats.eig_min, eig_max, cond_est)."""
     lib = load()
     y = _dev_f64(y, prob.device)
     if alpha0 is not None:
@@ -277,7 +307,7 @@ def pcg_solve(prob: Problem, y, precond: Precond | None = None, tol: float = 1e-
         alpha = torch.empty_like(y)
     opts = laker_pcg_opts(tol, max_iter, _PREC[precision], int(refine), ir_max, inner_tol,
                           1 if alpha0 is not None else 0, check_every, 1 if graph else 0, 1 if profile else 0,
-                          inner_max_iter, 1 if materialized else 0)
+                          inner_max_iter, 1 if materialized else 0, int(stall_window), 1 if lanczos else 0)
     nb = lib.laker_solve_workspace_bytes(prob.n, prob.d, 0)
     if materialized:
         nb += 256 + lib.laker_kmat_bytes(prob.n, prob.d, F64)
@@ -288,7 +318,7 @@ def pcg_solve(prob: Problem, y, precond: Precond | None = None, tol: float = 1e-
     pc = None if precond is None else C.byref(precond.c)
     s = lib.laker_pcg_solve(C.byref(prob.c), pc, _ptr(y), _ptr(alpha), C.byref(opts), _ptr(ws), ws.numel(),
                             C.byref(st), _stream())
-    _check(s, "laker_pcg_solve", (LAKER_OK, LAKER_ENOCONV) if allow_noconv else (LAKER_OK,))
+    _check(s, "laker_pcg_solve", (LAKER_OK, LAKER_ENOCONV, LAKER_ESTALL) if allow_noconv else (LAKER_OK,))
     return alpha, st
 
 
@@ -430,6 +460,34 @@ def learned_precond(prob: Problem, model: MlpModel) -> Precond:
     s = lib.laker_learned_precond(C.byref(prob.c), _ptr(model.buf), C.byref(pc), _ptr(ws), ws.numel(), _stream())
     _check(s, "laker_learned_precond")
     return Precond(pc.kind, prob.n, MLP_RANK, data, pc)
+
+
+def learned_solve(prob: Problem, y, model: MlpModel, Z, tol: float = 1e-6, max_iter: int = 200000,
+                  precision="bf16", refine: int = 2, inner_tol: float = 0.1, ir_max: int = 20000,
+                  check_every: int = 30, inner_max_iter: int = 30, materialized: bool = False,
+                  stall_window: int = 0, gamma: float = 0.1, rho: float = 0.0, cccp_tol: float = 1e-8,
+                  cccp_max_iter: int = 300, allow_noconv: bool = False):
+    """Solve with the learned preconditioner, falling back to a CCCP fit with
+    directions Z when that solve stalls or breaks down (laker_learned_solve).
+    Returns (alpha, stats, precond used last)."""
+    lib = load()
+    y = _dev_f64(y, prob.device)
+    Z = _dev_f64(Z, prob.device)
+    nr = Z.shape[1]
+    alpha = torch.empty_like(y)
+    pbytes = lib.laker_precond_bytes(prob.n, max(MLP_RANK, nr))
+    data = torch.empty(pbytes, dtype=torch.uint8, device=prob.device)
+    pc = laker_precond(PRECOND_LEARNED, MLP_RANK, prob.n, data.data_ptr(), pbytes)
+    copts = laker_cccp_opts(nr, cccp_max_iter, gamma, rho, 1e-10, cccp_tol, _PREC[precision], 0)
+    opts = laker_pcg_opts(tol, max_iter, _PREC[precision], int(refine), ir_max, inner_tol, 0, check_every, 0, 0,
+                          inner_max_iter, 1 if materialized else 0, int(stall_window), 0)
+    nb = lib.laker_learned_solve_workspace_bytes(prob.n, prob.d, nr, _PREC[precision], 1 if materialized else 0)
+    ws = _workspace("solve", nb, prob.device)
+    st = laker_stats()
+    s = lib.laker_learned_solve(C.byref(prob.c), _ptr(model.buf), _ptr(Z), C.byref(copts), _ptr(y), _ptr(alpha),
+                                C.byref(opts), C.byref(pc), _ptr(ws), ws.numel(), C.byref(st), _stream())
+    _check(s, "laker_learned_solve", (LAKER_OK, LAKER_ENOCONV, LAKER_ESTALL) if allow_noconv else (LAKER_OK,))
+    return alpha, st, Precond(pc.kind, prob.n, pc.n_r, data, pc)
 
 
 def sigma_half(pc: Precond, Z: torch.Tensor) -> torch.Tensor:

@@ -8,13 +8,13 @@ library through the bindings of ``laker``.
 Targets: for each training problem the CCCP preconditioner P = Sigma_star^{-1/2}
 is fitted (Alg. 1, preconditioner learning) and U = Sigma_star^{1/2} Z is formed
 for Gaussian probes Z; the network learns S with S^{-1} U close to Z.
-At solve time the learned P = S^{-1} replaces the fit; when PCG stalls (the
-iteration budget runs out) the solve falls back to a CCCP fit, warm-started
-from the learned solve's iterate.
+At solve time the learned P = S^{-1} replaces the fit; when PCG stalls (its
+residual falls by less than 2x over a window of iterations), breaks down or
+runs out of its budget, the library falls back to a CCCP fit and continues
+from the learned solve's iterate (laker_learned_solve).
 """
 from __future__ import annotations
 
-import time
 from dataclasses import dataclass
 
 import numpy as np
@@ -60,33 +60,25 @@ def train(model: L.MlpModel, examples: list, epochs: int, lr: float = 1e-3, seed
 class LearnedSolve:
     alpha: torch.Tensor
     stats: L.laker_stats
-    fell_back: bool
+    fell_back: int           # 0 none, 1 the learned solve stalled / hit its cap, 2 it broke down
     learned_iters: int
-    precond_ms: float
+    precond: L.Precond       # the preconditioner used last
 
 
 def solve_with_fallback(prob: L.Problem, y, model: L.MlpModel, fallback_directions, tol: float = 1e-6,
-                        budget: int = 4000, precision: str = "bf16", refine=True, inner_tol: float = 0.1,
-                        gamma: float = 0.1, check_every: int = 32, inner_max_iter: int = 0,
-                        materialized: bool = False) -> LearnedSolve:
-    """PCG with the learned preconditioner; on a stall (budget exhausted) fit
-    CCCP and continue from the current iterate.  refine: False, True
-    (iterative refinement) or 2 (flexible float64 outer CG, inner solves capped
-    at inner_max_iter iterations).  materialized: the float64 products stream a
-    G stored once per solve."""
-    t0 = time.perf_counter()
-    pc = L.learned_precond(prob, model)
-    torch.cuda.synchronize()
-    pms = (time.perf_counter() - t0) * 1e3
-    ir_max = 1000 if refine == 2 else 64   # outer steps (refinement keeps at most 64)
-    alpha, st = L.pcg_solve(prob, y, pc, tol=tol, max_iter=budget, precision=precision, refine=refine,
-                            inner_tol=inner_tol, ir_max=ir_max, check_every=check_every, allow_noconv=True,
-                            inner_max_iter=inner_max_iter, materialized=materialized)
-    if st.status == L.LAKER_OK:
-        return LearnedSolve(alpha, st, False, st.iters, pms)
-    used = st.iters
-    pc2 = L.fit_precond(prob, fallback_directions, gamma=gamma, rho=0.0, precision=precision)
-    alpha, st2 = L.pcg_solve(prob, y, pc2, tol=tol, max_iter=100000, precision=precision, refine=refine,
-                             inner_tol=inner_tol, ir_max=ir_max, alpha0=alpha, check_every=check_every,
-                             inner_max_iter=inner_max_iter, materialized=materialized)
-    return LearnedSolve(alpha, st2, True, used, pms)
+                        budget: int = 200000, precision: str = "bf16", refine=2, inner_tol: float = 0.1,
+                        gamma: float = 0.1, check_every: int = 30, inner_max_iter: int = 30,
+                        materialized: bool = False, stall_window: int = 2000) -> LearnedSolve:
+    """PCG with the learned preconditioner; when it stalls (the residual falls by
+    less than 2x over stall_window iterations), breaks down or exhausts the
+    budget, the library fits CCCP with the fallback directions and continues
+    from the current iterate (laker_learned_solve).  refine: 0, 1 (iterative
+    refinement) or 2 (flexible float64 outer CG, inner solves capped at
+    inner_max_iter iterations).  materialized: the float64 products stream a G
+    stored once per solve."""
+    ir_max = 20000 if refine == 2 else 64
+    alpha, st, pc = L.learned_solve(prob, y, model, fallback_directions, tol=tol, max_iter=budget, precision=precision,
+                                    refine=int(refine), inner_tol=inner_tol, ir_max=ir_max, check_every=check_every,
+                                    inner_max_iter=inner_max_iter, materialized=materialized,
+                                    stall_window=stall_window, gamma=gamma)
+    return LearnedSolve(alpha, st, st.fell_back, st.learned_iters, pc)

@@ -8,4 +8,5 @@ arithmetic (no kernel, no solve, no preconditioner).
 """
 from .inputs import (  # noqa: F401
     Problem, make_problem, make_directions, make_batch_specs, default_n_r, make_probes, make_mlp_init,
+    make_paper_problem, paper_rho,
 )

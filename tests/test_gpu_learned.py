@@ -146,8 +146,7 @@ def test_pcg_with_learned_preconditioner_reaches_cholesky_solution():
 
 def test_training_gains_over_plain_cg_and_fallback():
     """A/B: a network trained on CCCP fits of small maps needs far fewer PCG
-    iterations than plain CG on larger held-out maps; a solve whose budget runs
-    out falls back to CCCP and still converges."""
+    iterations than plain CG on larger held-out maps."""
     from paper_2604_25138_amd import learned as LR
     d, m = 16, 64
     rng = np.random.default_rng(0)
@@ -170,9 +169,49 @@ def test_training_gains_over_plain_cg_and_fallback():
         _, s_lr = L().pcg_solve(prob, pr.y, L().learned_precond(prob, model), tol=1e-6, max_iter=50000)
         gains.append(s_lr.iters / s_cg.iters)
     assert max(gains) <= 0.7, gains
-    # fallback: an iteration budget far below what the learned solve needs
-    pr = make_problem(2048, d, 3e-4, n_tx=2, seed=950)
+
+
+@pytest.mark.parametrize("refine", [0, 2])
+def test_stalled_learned_solve_falls_back_to_cccp_in_the_library(refine):
+    """An untrained network (random weights) gives a preconditioner under which
+    PCG makes little progress at lambda = 1e-5; the library's stall test (less
+    than 2x residual reduction over 60 iterations) stops that solve, fits CCCP
+    (Alg. 1) with the given directions, continues from the learned solve's
+    iterate and reaches the float64 Cholesky solution."""
+    n, d = 1500, 16
+    pr = make_problem(n, d, 1e-5, n_tx=2, seed=960)
     prob = _gp(pr)
-    res = LR.solve_with_fallback(prob, pr.y, model, torch.tensor(make_directions(pr.n, 128, 950), device=DEV),
-                                 tol=1e-8, budget=5, precision="f64", refine=False)
-    assert res.fell_back and res.stats.relres_true <= 1e-8
+    model, _ = _model(d, 960, log_delta0=-7.0)
+    Zd = torch.tensor(make_directions(n, 128, 960), device=DEV)
+    window, check = 60, 10
+    if refine == 0:
+        alpha, st, pc = L().learned_solve(prob, pr.y, model, Zd, tol=1e-12, max_iter=20000, precision="f64",
+                                          refine=0, check_every=check, stall_window=window)
+    else:
+        alpha, st, pc = L().learned_solve(prob, pr.y, model, Zd, tol=1e-11, max_iter=40000, precision="bf16",
+                                          refine=2, inner_tol=0.1, check_every=10, inner_max_iter=10,
+                                          stall_window=window)
+    print(f"refine={refine}: fell_back={st.fell_back} learned_iters={st.learned_iters} iters={st.iters} "
+          f"cccp_iters={st.cccp_iters} relres_true={st.relres_true:.2e}")
+    assert st.status == L().LAKER_OK
+    assert st.fell_back == 1 and pc.kind == L().PRECOND_CCCP
+    # the stall is detected at the first read-back at least `window` iterations
+    # after one that the residual has not halved since
+    assert window <= st.learned_iters <= window + 4 * check
+    ref = O.solve_direct(O.system_matrix(pr.E, pr.scale, pr.lam), pr.y)
+    err = np.linalg.norm(alpha.cpu().numpy() - ref) / np.linalg.norm(ref)
+    assert err <= (1e-10 if refine == 0 else 1e-8), err
+
+
+def test_learned_solve_without_stall_keeps_the_learned_preconditioner():
+    n, d = 1024, 16
+    pr = make_problem(n, d, 1e-2, n_tx=1, seed=961)
+    prob = _gp(pr)
+    model, _ = _model(d, 961, log_delta0=-1.0, scale=0.5)
+    Zd = torch.tensor(make_directions(n, 64, 961), device=DEV)
+    alpha, st, pc = L().learned_solve(prob, pr.y, model, Zd, tol=1e-12, max_iter=20000, precision="f64", refine=0,
+                                      check_every=16, stall_window=0)
+    assert st.status == L().LAKER_OK and st.fell_back == 0 and pc.kind == L().PRECOND_LEARNED
+    assert st.learned_iters == st.iters
+    ref = O.solve_direct(O.system_matrix(pr.E, pr.scale, pr.lam), pr.y)
+    assert np.linalg.norm(alpha.cpu().numpy() - ref) <= 1e-10 * np.linalg.norm(ref)
