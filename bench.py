@@ -80,6 +80,7 @@ def parse():
     ap.add_argument("--workload", default="n65536_d64", choices=sorted(WORKLOADS))
     ap.add_argument("--no-c2", action="store_true", help="skip the 16384-site leg")
     ap.add_argument("--no-paper", action="store_true", help="skip the sweep of the paper's own regime")
+    ap.add_argument("--no-multi", action="store_true", help="skip the multi-right-hand-side and online legs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--counters", action="store_true",
                     help="only 20 bfloat16 products of the workload, a 20-iteration float64 PCG streaming the "
@@ -325,6 +326,94 @@ def paper_regime_leg(L, dev):
     return rows
 
 
+def multi_rhs_leg(L, dev, k=8):
+    """Several right-hand sides on one map (k bands or snapshots measured at the
+    same 16384 sites, d = 64, lambda = 1e-3): the k columns solved together
+    (one product launch per iteration for all columns, float64) against the
+    same k solves one after the other (float64 products recomputed, and with G
+    stored once per solve), CCCP preconditioner, PCG to 1e-6."""
+    import numpy as np
+    import torch
+
+    from synth import default_n_r, make_directions, make_problem
+    n, d, lam = 16384, 64, 1e-3
+    pr = make_problem(n, d, lam, n_tx=4, seed=11)
+    prob = L.Problem(torch.tensor(pr.E, device=dev), pr.lam, pr.scale)
+    rng = np.random.default_rng(11)
+    # band-to-band variation of the measured field
+    Y = pr.y[:, None] + rng.normal(0.0, 3.0, size=(n, k))
+    Yd = torch.tensor(Y, device=dev)
+    pc = L.fit_precond(prob, torch.tensor(make_directions(n, default_n_r(n), 11), device=dev), gamma=0.1)
+    kw = dict(tol=1e-6, max_iter=20000, precision="f64", check_every=32)
+    L.pcg_solve_multi(prob, Yd[:, :2], pc, **kw)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    _, st = L.pcg_solve_multi(prob, Yd, pc, **kw)
+    torch.cuda.synchronize()
+    t_multi = time.perf_counter() - a
+    out = {"n": n, "d": d, "lambda": lam, "k": k, "multi_s": t_multi,
+           "multi_iters": [s.iters for s in st], "multi_worst_relres_true": max(s.relres_true for s in st)}
+    for mat in (False, True):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        its = []
+        for q in range(k):
+            _, s1 = L.pcg_solve(prob, Yd[:, q], pc, materialized=mat, **kw)
+            its.append(s1.iters)
+        torch.cuda.synchronize()
+        key = "serial_stored_g" if mat else "serial_recomputed"
+        out[key + "_s"] = time.perf_counter() - a
+        out[key + "_iters"] = its
+    out["speedup_vs_serial_recomputed"] = out["serial_recomputed_s"] / t_multi
+    out["speedup_vs_serial_stored_g"] = out["serial_stored_g_s"] / t_multi
+    return out
+
+
+def online_leg(L, dev):
+    """Sites appended to a fitted map (16384 sites, 1024 of them arriving after
+    the first 15360 were fitted and solved; d = 64, lambda = 1e-3): the
+    extended fit (products with the new rows only, CCCP from the previous
+    weights) and PCG from the previous solution, against a fresh fit and a
+    solve from zero; float64, PCG to 1e-6."""
+    import torch
+
+    from synth import default_n_r, make_directions, make_problem
+    n, m, d, lam = 16384, 1024, 64, 1e-3
+    n0 = n - m
+    pr = make_problem(n, d, lam, n_tx=4, seed=12)
+    nr = default_n_r(n)
+    Z = torch.tensor(make_directions(n, nr, 12), device=dev)
+    E = torch.tensor(pr.E, device=dev)
+    prob0 = L.Problem(E[:n0].contiguous(), pr.lam, pr.scale)
+    prob = L.Problem(E, pr.lam, pr.scale)
+    y = torch.tensor(pr.y, device=dev)
+    kw = dict(tol=1e-6, max_iter=20000, precision="f64", check_every=32, materialized=True)
+    state = L.OnlineFitState(n, nr, dev)
+    pc0 = state.fit(prob0, Z[:n0].contiguous(), gamma=0.1)
+    a0, _ = L.pcg_solve(prob0, y[:n0], pc0, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pc1 = state.fit(prob, Z, gamma=0.1)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    start = torch.cat([a0, torch.zeros(m, dtype=torch.float64, device=dev)])
+    _, s1 = L.pcg_solve(prob, y, pc1, alpha0=start, **kw)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    pcf = L.fit_precond(prob, Z, gamma=0.1)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    _, s2 = L.pcg_solve(prob, y, pcf, **kw)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    return {"n_prev": n0, "appended": m, "n_r": nr,
+            "online_fit_ms": (t1 - t0) * 1e3, "online_cccp_iters": pc1.stats.cccp_iters,
+            "warm_pcg_ms": (t2 - t1) * 1e3, "warm_pcg_iters": s1.iters,
+            "fresh_fit_ms": (t3 - t2) * 1e3, "fresh_cccp_iters": pcf.stats.cccp_iters,
+            "cold_pcg_ms": (t4 - t3) * 1e3, "cold_pcg_iters": s2.iters,
+            "speedup": (t4 - t2) / (t2 - t0)}
+
+
 def c2_leg(L, LR, model, dev):
     """The 16384-site map (d = 64, 4 transmitters, lambda = 1e-4): the learned
     step as timed above, and float32 CCCP-PCG with G stored once (float32
@@ -544,6 +633,10 @@ def main():
     if not args.no_paper:
         extra["paper_regime"] = paper_regime_leg(L, dev)
         _note("paper regime sweep done")
+    if not args.no_multi:
+        extra["multi_rhs"] = multi_rhs_leg(L, dev)
+        extra["online"] = online_leg(L, dev)
+        _note("multi-right-hand-side and online legs done")
 
     if args.workload != "n16384_d64" and not args.no_c2:
         extra["n16384_d64"] = c2_leg(L, LR, model, dev)

@@ -145,6 +145,12 @@ typedef struct {
                          stall_window PCG iterations; checked where the host
                          reads the residual (every check_every iterations, every
                          outer step).  0: no stall test                         */
+  int32_t outer_history;/* refine 2: directions the flexible outer CG keeps and
+                         makes each new direction A-conjugate to (1..8; 0: 1) */
+  int32_t escalate;     /* refine 2: 1 makes the inner products finer (bfloat16 ->
+                         float32 -> float64) when the outer residual has not
+                         halved over 40 outer steps (for tolerances near the
+                         float64 floor); counted in stats->escalations          */
   int32_t lanczos;      /* 1 (refine 0 only): record PCG's step sizes and
                          conjugation coefficients and estimate the extreme
                          eigenvalues of P A from the Lanczos tridiagonal they
@@ -240,6 +246,36 @@ laker_status laker_precond_apply(const laker_precond* precond, const double* r, 
 laker_status laker_fit_precond(const laker_problem* prob, const double* Z, const laker_cccp_opts* opts,
                                laker_precond* out, void* workspace, size_t workspace_bytes,
                                laker_stats* stats, void* stream);
+
+/* ---- measurements that arrive over time -----------------------------------
+ *
+ * The paper leaves online spectrum cartography, where measurements arrive
+ * sequentially, to future work (Sec. VI).  When sites are appended to a map,
+ * the fit of Alg. 1 is extended instead of redone: the random directions keep
+ * their previous entries and gain new ones (z_k of the enlarged problem), so
+ * only the products with the new rows are formed,
+ *     U[old] += G[old, new] Z[new],   U[new] = G[new, :] Z + lambda Z[new],
+ * and the CCCP iteration starts from the previous fit's (a, b, w) instead of
+ * Sigma_0 = I.  The same solution as a fresh fit (the fixed point depends on
+ * the directions only); a PCG warm-started from [alpha_prev; 0]
+ * (laker_pcg_opts.warm_start) then finishes the enlarged solve. */
+
+/* Bytes of the state buffer for up to n_cap sites and n_r directions. */
+size_t laker_online_state_bytes(int64_t n_cap, int32_t n_r);
+
+/* Fit P = Sigma_star^{-1/2} for the n sites of prob, the first n_prev of which
+ * were fitted by the previous call on the same state (n_prev = 0: a full fit
+ * that starts the state).  Rows of E and Z keep their order: E rows
+ * [0, n_prev) and Z rows [0, n_prev) (n x n_r row-major, device) must equal
+ * the previous call's.  state: device, caller-owned, laker_online_state_bytes
+ * (n_cap, n_r) bytes with n_cap >= n; it holds the float64 directions and the
+ * CCCP weights between calls.  opts->precision must be LAKER_F64.  out,
+ * workspace (laker_fit_workspace_bytes(n, d, n_r)) and stats as for
+ * laker_fit_precond. */
+laker_status laker_fit_precond_online(const laker_problem* prob, int64_t n_prev, const double* Z,
+                                      const laker_cccp_opts* opts, void* state, size_t state_bytes,
+                                      laker_precond* out, void* workspace, size_t workspace_bytes,
+                                      laker_stats* stats, void* stream);
 
 /* Jacobi preconditioner P_J = diag(lambda I + G)^{-1} (Sec. V-A numerical-layer
  * baseline); out->data must hold laker_precond_bytes(n, 0) bytes. */
@@ -348,6 +384,34 @@ size_t laker_sigma_half_workspace_bytes(int64_t n, int32_t n_r, int32_t m);
  * Sigma_star = b I + B B^T.  Z, U: device float64 n x m row-major. */
 laker_status laker_precond_sigma_half(const laker_precond* precond, int32_t m, const double* Z, double* U,
                                       void* workspace, size_t workspace_bytes, void* stream);
+
+/* ---- several right-hand sides on one map ----------------------------------
+ *
+ * Bands or snapshots measured at the same sites share E, G and the
+ * preconditioner: k <= 8 right-hand sides y_1 .. y_k are solved together.
+ * Each column runs the PCG iteration of laker_pcg_solve (Alg. 1) with its own
+ * scalars, stopping test and retirement; the kernel product of an iteration
+ * is one launch for all columns, whose score tiles and exponentials are formed
+ * once and multiplied by the k directions.  Matrices of k columns are stored
+ * column after column: column q of Y at Y + q n. */
+
+/* Workspace bytes of laker_kernel_matvec_multi and laker_pcg_solve_multi. */
+size_t laker_multi_workspace_bytes(int64_t n, int32_t d, int32_t k);
+
+/* W = (lambda I + G) P for k <= 8 columns (P, W: device, n x k, column-major as
+ * above); precision as for laker_kernel_matvec. */
+laker_status laker_kernel_matvec_multi(const laker_problem* prob, int32_t k, const double* P, double* W,
+                                       int32_t precision, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Solve (lambda I + G) alpha_q = y_q for q < k (Y, Alpha: device, n x k,
+ * column-major).  opts: tol, max_iter (per column), precision, check_every
+ * as for laker_pcg_solve; refine, warm_start, graph, stall_window and lanczos
+ * must be 0.  precond: NULL or one preconditioner for all columns.  stats:
+ * host array of k entries (iters, relres, relres_true, status per column).
+ * Returns LAKER_OK when every column converged, else the worst status. */
+laker_status laker_pcg_solve_multi(const laker_problem* prob, const laker_precond* precond, int32_t k,
+                                   const double* Y, double* Alpha, const laker_pcg_opts* opts, void* workspace,
+                                   size_t workspace_bytes, laker_stats* stats, void* stream);
 
 /* ---- batched solve --------------------------------------------------------
  *

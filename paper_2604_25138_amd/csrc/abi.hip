@@ -228,6 +228,70 @@ laker_status laker_fit_precond(const laker_problem* prob, const double* Z, const
   return r;
 }
 
+// State buffer of the online fit: (a, b), w, then the directions U (rows up to
+// the buffer's end), so that the first two sit at fixed offsets.
+namespace {
+struct OnlineLayout {
+  double* ab;
+  double* w;
+  double* U;
+  size_t u_off;
+};
+OnlineLayout online_layout(void* base, int nr) {
+  WsCarver c(base);
+  OnlineLayout L;
+  L.ab = c.take<double>(2);
+  L.w = c.take<double>(nr);
+  L.u_off = (c.bytes());
+  L.U = base != nullptr ? reinterpret_cast<double*>(static_cast<char*>(base) + L.u_off) : nullptr;
+  return L;
+}
+}  // namespace
+
+size_t laker_online_state_bytes(int64_t n_cap, int32_t n_r) {
+  if (n_cap < 1 || n_r < 1 || n_r > kMaxNr) return 0;
+  return online_layout(nullptr, n_r).u_off + sizeof(double) * (size_t)n_cap * (size_t)n_r;
+}
+
+laker_status laker_fit_precond_online(const laker_problem* prob, int64_t n_prev, const double* Z,
+                                      const laker_cccp_opts* opts, void* state, size_t state_bytes,
+                                      laker_precond* out, void* workspace, size_t workspace_bytes,
+                                      laker_stats* stats, void* stream) {
+  laker_status e = check_problem(prob);
+  if (e != LAKER_OK) return e;
+  if (Z == nullptr || opts == nullptr || state == nullptr || out == nullptr || out->data == nullptr ||
+      workspace == nullptr)
+    return LAKER_EINVAL;
+  const int nr = opts->n_r;
+  if (nr < 1 || nr > kMaxNr || nr > prob->n || n_prev < 0 || n_prev > prob->n) return LAKER_EINVAL;
+  if (n_prev > 0 && nr > n_prev) return LAKER_EINVAL;
+  if (!(opts->gamma >= 0.0) || !isfinite(opts->gamma)) return LAKER_EINVAL;
+  if (!(opts->rho >= 0.0 && opts->rho <= 1.0)) return LAKER_EINVAL;
+  if (!finite_pos(opts->eps) || !(opts->tol >= 0.0) || opts->max_iter < 1) return LAKER_EINVAL;
+  // the state keeps float64 directions: the products are float64
+  if (opts->precision != LAKER_F64) return LAKER_EINVAL;
+  if (state_bytes < laker_online_state_bytes(prob->n, nr)) return LAKER_ENOMEM;
+  FitWs W = plan_fit_ws(workspace, prob->n, prob->d, nr);
+  if (workspace_bytes < W.total) return LAKER_ENOMEM;
+  PrecondLayout L = precond_layout(out->data, prob->n, nr);
+  if (out->bytes < L.total) return LAKER_ENOMEM;
+  const OnlineLayout SL = online_layout(state, nr);
+  OnlineFit on;
+  on.U = SL.U;
+  on.w = SL.w;
+  on.ab = SL.ab;
+  on.n_prev = n_prev;
+  out->kind = LAKER_PRECOND_CCCP;
+  out->n = prob->n;
+  out->n_r = nr;
+  laker_stats local{};
+  laker_stats* sp = stats != nullptr ? stats : &local;
+  sp->cccp_iters = 0;
+  laker_status r = fit_cccp(to_problem(prob), Z, *opts, W, L, sp, (hipStream_t)stream, &on);
+  sp->status = r;
+  return r;
+}
+
 laker_status laker_jacobi_precond(const laker_problem* prob, laker_precond* out, void* stream) {
   laker_status e = check_problem(prob);
   if (e != LAKER_OK) return e;
@@ -252,6 +316,8 @@ laker_status laker_pcg_solve(const laker_problem* prob, const laker_precond* pre
   if (opts->refine && (opts->ir_max < 1 || !(opts->inner_tol > 0.0))) return LAKER_EINVAL;
   if (opts->refine == 1 && opts->ir_max > 64) return LAKER_EINVAL;
   if (opts->stall_window < 0 || opts->lanczos < 0 || opts->lanczos > 1) return LAKER_EINVAL;
+  if (opts->outer_history < 0 || opts->outer_history > 8 || opts->escalate < 0 || opts->escalate > 1)
+    return LAKER_EINVAL;
   if (opts->lanczos && opts->refine) return LAKER_EINVAL;
   PrecondView view{};
   e = make_view(precond, prob->n, opts->precision, &view);

@@ -61,6 +61,65 @@ __global__ __launch_bounds__(kT) void dot2_kernel(const double* __restrict__ a1,
 // dot2 results, s[2] = p_prev^T q_prev, s[3] = 1 after a breakdown.  The host
 // reads them once per outer step, with ||r||^2.
 
+// Truncated flexible CG keeps the last m directions: the new direction is z
+// made A-conjugate to each of them,
+//   p = z - sum_i (z^T q_i) / (p_i^T q_i) p_i,
+// with the pairs (p_i, q_i = A p_i) in a ring of kFcgHist slots and
+// p_i^T q_i in pq[slot].  dz[i] = z^T q_(slot i) for the c slots listed.
+struct FcgSlots {
+  int c;
+  int slot[kFcgHist];
+};
+
+__global__ __launch_bounds__(kT) void mdot_kernel(const double* __restrict__ z, const double* __restrict__ Qr,
+                                                  FcgSlots sl, int64_t n, double* __restrict__ part, unsigned* cnt,
+                                                  double* __restrict__ dz) {
+  __shared__ double sh[16];
+  double acc[kFcgHist];
+#pragma unroll
+  for (int i = 0; i < kFcgHist; ++i) acc[i] = 0.0;
+  for (int64_t j = (int64_t)blockIdx.x * kT + threadIdx.x; j < n; j += (int64_t)gridDim.x * kT) {
+    const double zj = z[j];
+#pragma unroll
+    for (int i = 0; i < kFcgHist; ++i)
+      if (i < sl.c) acc[i] = fma(zj, Qr[(int64_t)sl.slot[i] * n + j], acc[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < kFcgHist; ++i) {
+    if (i < sl.c) {
+      const double v = block_sum(acc[i], sh);
+      if (threadIdx.x == 0) part[(int64_t)i * kMaxBlocks + blockIdx.x] = v;
+    }
+  }
+  if (last_block_arrived(cnt)) {
+    for (int i = 0; i < sl.c; ++i) {
+      const double t = ordered_sum(part + (int64_t)i * kMaxBlocks, gridDim.x, sh);
+      if (threadIdx.x == 0) dz[i] = t;
+    }
+    if (threadIdx.x == 0) *cnt = 0;
+  }
+}
+
+// p = z - sum_i dz[i] / pq[slot i] p_(slot i)
+__global__ void pdir_m_kernel(const double* __restrict__ z, const double* __restrict__ Pr, FcgSlots sl,
+                              const double* __restrict__ dz, const double* __restrict__ pq, double* __restrict__ p,
+                              int64_t n) {
+  double cf[kFcgHist];
+#pragma unroll
+  for (int i = 0; i < kFcgHist; ++i) cf[i] = i < sl.c ? dz[i] / pq[sl.slot[i]] : 0.0;
+  for (int64_t j = (int64_t)blockIdx.x * kT + threadIdx.x; j < n; j += (int64_t)gridDim.x * kT) {
+    double v = z[j];
+#pragma unroll
+    for (int i = 0; i < kFcgHist; ++i)
+      if (i < sl.c) v = fma(-cf[i], Pr[(int64_t)sl.slot[i] * n + j], v);
+    p[j] = v;
+  }
+}
+
+__global__ void store_pq_kernel(const double* __restrict__ s, double* __restrict__ pq, int slot) {
+  if (threadIdx.x == 0 && blockIdx.x == 0 && s[3] == 0.0) pq[slot] = s[2];
+}
+
 // p = z + beta p, beta = -(z^T q_prev) / (p_prev^T q_prev) = -s[0] / s[2]
 __global__ void pdir_kernel(const double* __restrict__ z, double* __restrict__ p, const double* __restrict__ s,
                             int64_t n) {
@@ -118,6 +177,9 @@ laker_status fcg_run(const Problem& pb, const SolveWs& W, const PrecondView& P, 
     return kmv_run(LAKER_F64, pb.dp, pl, A, st);
   };
 
+  // directions kept by the truncated flexible CG (1: the previous one only)
+  int hist = o.outer_history > 0 ? o.outer_history : 1;
+  if (hist > kFcgHist) hist = kFcgHist;
   if (!o.warm_start) LK_TRY(hipMemsetAsync(alpha, 0, sizeof(double) * n, st));
   double rel = 0.0;
   laker_status e = true_residual(pb, W, y, alpha, r, &rel, o.warm_start != 0, st);
@@ -136,6 +198,16 @@ laker_status fcg_run(const Problem& pb, const SolveWs& W, const PrecondView& P, 
   StallTest stall;
   stall.window = o.stall_window;
   (void)stall.stalled(0, rel);
+  // Inner arithmetic: the requested precision; with o.escalate made finer
+  // (bfloat16 -> float32 -> float64) when the outer residual has not halved
+  // over the last kEscalateSteps outer steps.  Near the float64 floor of the reduced
+  // product, the inner solves no longer resolve the directions where its
+  // rounding exceeds lambda, and only finer inner products make progress.
+  constexpr int kEscalateSteps = 40;
+  int prec_now = o.precision;
+  StallTest slow;
+  slow.window = kEscalateSteps;
+  (void)slow.stalled(0, rel);
   for (int k = 0; k < o.ir_max; ++k) {
     if (used >= o.max_iter) break;
     // z = inner solve of A z = r; a reduced-precision breakdown or cap keeps
@@ -147,7 +219,7 @@ laker_status fcg_run(const Problem& pb, const SolveWs& W, const PrecondView& P, 
     // (a single chunk is only enqueued; its iteration count is read with the
     // step's scalars below, saving a host round trip per outer step)
     const bool defer = check >= cap && !o.graph && !o.profile;
-    laker_status ri = pcg_run(pb, W, P, r, z, false, itol, cap, check, o.precision, o.graph != 0, o.profile != 0,
+    laker_status ri = pcg_run(pb, W, P, r, z, false, itol, cap, check, prec_now, o.graph != 0, o.profile != 0,
                               &inner, st, defer);
     if (ri == LAKER_EHIP || ri == LAKER_EINVAL) return ri;
     if (!defer) {
@@ -166,17 +238,41 @@ laker_status fcg_run(const Problem& pb, const SolveWs& W, const PrecondView& P, 
     }
     // p = z + beta p_prev, beta = -(z^T q_prev) / (p_prev^T q_prev)
     // (beta, gamma and the breakdown test on the device: one host read per step)
-    if (k == 0) {
-      LK_TRY(hipMemcpyAsync(p, z, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    double* pk = p;
+    double* qk = q;
+    if (hist == 1) {
+      if (k == 0) {
+        LK_TRY(hipMemcpyAsync(p, z, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+      } else {
+        LK_TRY(dots_dev(z, q, z, q));
+        pdir_kernel<<<g, kT, 0, st>>>(z, p, s, n);
+        LK_CHECK_LAUNCH();
+      }
     } else {
-      LK_TRY(dots_dev(z, q, z, q));
-      pdir_kernel<<<g, kT, 0, st>>>(z, p, s, n);
+      // the last min(k, hist) directions, oldest first, from the ring
+      const int slot = k % hist;
+      pk = W.fring + (int64_t)slot * n;
+      qk = W.fring + (int64_t)(kFcgHist + slot) * n;
+      FcgSlots sl{};
+      sl.c = k < hist ? k : hist;
+      for (int i = 0; i < sl.c; ++i) sl.slot[i] = (k - sl.c + i) % hist;
+      if (sl.c == 0) {
+        LK_TRY(hipMemcpyAsync(pk, z, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+      } else {
+        mdot_kernel<<<g, kT, 0, st>>>(z, W.fring + (int64_t)kFcgHist * n, sl, n, W.fpart, W.cnt, W.fdz);
+        LK_CHECK_LAUNCH();
+        pdir_m_kernel<<<g, kT, 0, st>>>(z, W.fring, sl, W.fdz, W.fpq, pk, n);
+        LK_CHECK_LAUNCH();
+      }
+    }
+    LK_TRY(product(pk, qk));
+    LK_TRY(dots_dev(pk, qk, pk, r));
+    step_kernel<<<g, kT, 0, st>>>(alpha, r, pk, qk, s, n);
+    LK_CHECK_LAUNCH();
+    if (hist > 1) {
+      store_pq_kernel<<<1, 64, 0, st>>>(s, W.fpq, k % hist);
       LK_CHECK_LAUNCH();
     }
-    LK_TRY(product(p, q));
-    LK_TRY(dots_dev(p, q, p, r));
-    step_kernel<<<g, kT, 0, st>>>(alpha, r, p, q, s, n);
-    LK_CHECK_LAUNCH();
     // ||r||^2, the scalars and (deferred inner solve) its iteration count in one host read
     int inner_iters = 0;
     LK_TRY(dots_dev(r, r, r, r));
@@ -203,6 +299,13 @@ laker_status fcg_run(const Problem& pb, const SolveWs& W, const PrecondView& P, 
     }
     sp->relres_true = rel;
     if (stall.stalled(used, rel)) return LAKER_ESTALL;
+    if (o.escalate && slow.stalled(k + 1, rel) && prec_now != LAKER_F64) {
+      prec_now = prec_now == LAKER_BF16 ? LAKER_F32 : LAKER_F64;
+      sp->escalations += 1;
+      if (prec_now == LAKER_F32) LK_TRY(prep_embed(pb.E, pb.n, pb.d, pb.dp, pb.scale, LAKER_F32, W.e32, st));
+      slow.n = 0;
+      (void)slow.stalled(k + 1, rel);
+    }
   }
   double rt = 0.0;
   e = true_residual(pb, W, y, alpha, nullptr, &rt, true, st);

@@ -173,6 +173,25 @@ __global__ __launch_bounds__(256) void cccp_q_kernel(const double* __restrict__ 
   if (lane == 0) q[k] = s / (S->a * w[k]);
 }
 
+// q_k from the refined solve X = M^{-1} C:  q_k = (X_kk + (Minv R)_kk) / (a w_k)
+// with R = C - M X the residual of the last refinement step; one wave per k.
+__global__ __launch_bounds__(256) void cccp_q_refined_kernel(const double* __restrict__ Minv,
+                                                             const double* __restrict__ X,
+                                                             const double* __restrict__ R,
+                                                             const double* __restrict__ w,
+                                                             const CccpState* __restrict__ S,
+                                                             double* __restrict__ q, int nr) {
+  if (S->done) return;
+  const int lane = threadIdx.x & 63;
+  const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (k >= nr) return;
+  double s = 0.0;
+  const double* mr = Minv + (int64_t)k * nr;
+  for (int j = lane; j < nr; j += 64) s = fma(mr[j], R[(int64_t)j * nr + k], s);
+  s = wave_sum(s);
+  if (lane == 0) q[k] = (X[(int64_t)k * nr + k] + s) / (S->a * w[k]);
+}
+
 // w <- 1/(q + eps); tau, a, b; exact Frobenius change of Sigma; stopping test.
 // One block of 1024 threads, fixed-order sums.
 __global__ __launch_bounds__(1024) void cccp_update_kernel(const double* __restrict__ C, const double* __restrict__ q,
@@ -369,6 +388,116 @@ inline int ew_grid(int64_t total) {
   return (int)(g < 1 ? 1 : g);
 }
 
+// Rectangular form for appended sites: part[s][i][k] = sum over the keys j of
+// range s of exp(<q_i, e_j>) Z[j][k], queries Eq (mq rows), keys Ek (nk rows,
+// Z row-aligned with them); same tiles and order as mrhs_f64_kernel.
+template <int DP>
+__global__ __launch_bounds__(256) void mrhs_rect_f64_kernel(const double* __restrict__ Eq, int64_t mq,
+                                                            const double* __restrict__ Ek, int64_t nk,
+                                                            const double* __restrict__ Z, int nr,
+                                                            double* __restrict__ part, int64_t cps) {
+  constexpr int BM = 64, BN = 32, NC = 64;
+  __shared__ double Ei[BM][DP + 1];
+  __shared__ double Ej[BN][DP + 1];
+  __shared__ double X[BM][BN + 1];
+  __shared__ double Zs[BN][NC + 1];
+  const int tid = threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.x * BM;
+  const int c0 = blockIdx.y * NC;
+  const int64_t j0 = (int64_t)blockIdx.z * cps;
+  const int64_t j1 = j0 + cps < nk ? j0 + cps : nk;
+  for (int idx = tid; idx < BM * DP; idx += 256) {
+    int ii = idx / DP, c = idx % DP;
+    Ei[ii][c] = (i0 + ii < mq) ? Eq[(i0 + ii) * DP + c] : 0.0;
+  }
+  const int ty = tid >> 4, tx = tid & 15;
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+  for (int64_t jt = j0; jt < j1; jt += BN) {
+    __syncthreads();
+    for (int idx = tid; idx < BN * DP; idx += 256) {
+      int jj = idx / DP, c = idx % DP;
+      Ej[jj][c] = (jt + jj < j1) ? Ek[(jt + jj) * DP + c] : 0.0;
+    }
+    for (int idx = tid; idx < BN * NC; idx += 256) {
+      int jj = idx / NC, c = idx % NC;
+      Zs[jj][c] = (jt + jj < j1 && c0 + c < nr) ? Z[(jt + jj) * nr + c0 + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < (BM * BN) / 256; ++q) {
+      int e = tid + 256 * q;
+      int ii = e / BN, jj = e % BN;
+      double s = 0.0;
+#pragma unroll
+      for (int c = 0; c < DP; ++c) s = fma(Ei[ii][c], Ej[jj][c], s);
+      X[ii][jj] = (jt + jj < j1) ? exp(s) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int jj = 0; jj < BN; ++jj) {
+      double xv[4], zv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) xv[a] = X[ty * 4 + a][jj];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) zv[b] = Zs[jj][tx * 4 + b];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = fma(xv[a], zv[b], acc[a][b]);
+    }
+  }
+  double* out = part + (int64_t)blockIdx.z * mq * nr;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    int64_t i = i0 + ty * 4 + a;
+    if (i >= mq) continue;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      int k = c0 + tx * 4 + b;
+      if (k < nr) out[i * nr + k] = acc[a][b];
+    }
+  }
+}
+
+// U[i] = base[i] + sum_s part[s][i] over mq x nr entries, where base is
+// lambda Zs (Zs set: the rows' own directions) or the previous U (in place)
+__global__ void mrhs_rect_finish_kernel(const double* __restrict__ part, int nsplit, const double* __restrict__ Zs,
+                                        double lam, int64_t total, double* __restrict__ U) {
+  for (int64_t idx = (int64_t)blockIdx.x * kT + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * kT) {
+    double s = 0.0;
+    for (int k = 0; k < nsplit; ++k) s += part[(int64_t)k * total + idx];
+    U[idx] = Zs != nullptr ? fma(lam, Zs[idx], s) : U[idx] + s;
+  }
+}
+
+// Warm start of the CCCP iteration from a previous fit's (a, b, w).
+__global__ void cccp_init_warm_kernel(CccpState* S, double* w, const double* w0, const double* ab, int nr) {
+  for (int k = threadIdx.x; k < nr; k += blockDim.x) w[k] = w0[k];
+  if (threadIdx.x == 0) {
+    S->a = ab[0];
+    S->b = ab[1];
+    S->tau = 1.0;
+    S->change = 0.0;
+    S->iters = 0;
+    S->done = 0;
+    S->gjflag = 0;
+    S->db_iters = 0;
+    S->db_change = 0.0;
+  }
+}
+
+__global__ void cccp_save_kernel(const CccpState* S, const double* w, double* w0, double* ab, int nr) {
+  for (int k = threadIdx.x; k < nr; k += blockDim.x) w0[k] = w[k];
+  if (threadIdx.x == 0) {
+    ab[0] = S->a;
+    ab[1] = S->b;
+  }
+}
+
 inline int64_t mrhs_partial_cap(int64_t n, int nr) {
   int64_t a = 4 * n * (int64_t)nr;
   int64_t b = 16 * (int64_t)nr * nr;
@@ -387,6 +516,36 @@ hipError_t launch_mrhs(int dp, const double* Eh, int64_t n, const double* Z, int
     case 128: mrhs_f64_kernel<128><<<grid, 256, 0, st>>>(Eh, n, Z, nr, part, cps); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+// part[s] = G(Eq, Ek) Z over nsplit key ranges of cps keys, then
+// U = base + sum_s part[s] (mq x nr); the split keeps mq nr nsplit within cap
+hipError_t rect_directions(int dp, const double* Eq, int64_t mq, const double* Ek, int64_t nk, const double* Z,
+                           int nr, const double* Zs, double lam, double* U, double* part, int64_t cap,
+                           hipStream_t st) {
+  if (mq < 1 || nk < 1) return hipSuccess;
+  const int64_t rowtiles = (mq + 63) / 64, coltiles = (nr + 63) / 64;
+  int64_t ns = (1024 + rowtiles * coltiles - 1) / (rowtiles * coltiles);
+  const int64_t jt = (nk + 31) / 32;
+  if (ns > jt) ns = jt;
+  if (ns > 64) ns = 64;
+  while (ns > 1 && ns * mq * nr > cap) --ns;
+  if (ns < 1) ns = 1;
+  if (mq * nr > cap) return hipErrorInvalidValue;
+  const int64_t cps = (((nk + ns - 1) / ns) + 31) / 32 * 32;
+  ns = (nk + cps - 1) / cps;
+  dim3 grid((unsigned)rowtiles, (unsigned)coltiles, (unsigned)ns);
+  switch (dp) {
+    case 16: mrhs_rect_f64_kernel<16><<<grid, 256, 0, st>>>(Eq, mq, Ek, nk, Z, nr, part, cps); break;
+    case 32: mrhs_rect_f64_kernel<32><<<grid, 256, 0, st>>>(Eq, mq, Ek, nk, Z, nr, part, cps); break;
+    case 64: mrhs_rect_f64_kernel<64><<<grid, 256, 0, st>>>(Eq, mq, Ek, nk, Z, nr, part, cps); break;
+    case 128: mrhs_rect_f64_kernel<128><<<grid, 256, 0, st>>>(Eq, mq, Ek, nk, Z, nr, part, cps); break;
+    default: return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  mrhs_rect_finish_kernel<<<ew_grid(mq * nr), kT, 0, st>>>(part, (int)ns, Zs, lam, mq * nr, U);
   return hipGetLastError();
 }
 
@@ -424,11 +583,24 @@ FitWs plan_fit_ws(void* base, int64_t n, int d, int nr) {
 }
 
 laker_status fit_cccp(const Problem& pb, const double* Z, const laker_cccp_opts& o, const FitWs& ws,
-                      const PrecondLayout& L, laker_stats* stats, hipStream_t st) {
+                      const PrecondLayout& L, laker_stats* stats, hipStream_t st, const OnlineFit* on) {
   const int64_t n = pb.n;
   const int nr = o.n_r;
-  // 1-2. U = (lambda I + G) Z: float64 tiles, or float32 / bfloat16 MFMA tiles
-  if (o.precision == LAKER_F64) {
+  const bool warm = on != nullptr && on->n_prev > 0;
+  // 1-2. U = (lambda I + G) Z: float64 tiles, or float32 / bfloat16 MFMA tiles.
+  // Sites appended to a previous fit (rows n_prev ..): only the products with
+  // the new rows are formed, in float64:
+  //   U[old] += G[old, new] Z[new],   U[new] = G[new, all] Z + lambda Z[new]
+  if (warm) {
+    const int64_t n0 = on->n_prev, m = n - n0;
+    LK_TRY(prep_embed(pb.E, n, pb.d, pb.dp, pb.scale, LAKER_F64, ws.e64, st));
+    const double* e_new = ws.e64 + n0 * pb.dp;
+    LK_TRY(rect_directions(pb.dp, ws.e64, n0, e_new, m, Z + n0 * nr, nr, nullptr, 0.0, on->U, ws.part, ws.part_cap,
+                           st));
+    LK_TRY(rect_directions(pb.dp, e_new, m, ws.e64, n, Z, nr, Z + n0 * nr, pb.lambda, on->U + n0 * nr, ws.part,
+                           ws.part_cap, st));
+    LK_TRY(hipMemcpyAsync(ws.U, on->U, sizeof(double) * n * nr, hipMemcpyDeviceToDevice, st));
+  } else if (o.precision == LAKER_F64) {
     LK_TRY(prep_embed(pb.E, n, pb.d, pb.dp, pb.scale, LAKER_F64, ws.e64, st));
     const int64_t rowtiles = (n + 63) / 64, coltiles = (nr + 63) / 64;
     int64_t ns = (1024 + rowtiles * coltiles - 1) / (rowtiles * coltiles);
@@ -446,6 +618,7 @@ laker_status fit_cccp(const Problem& pb, const double* Z, const laker_cccp_opts&
     LK_TRY(prep_embed(pb.E, n, pb.d, pb.dp, pb.scale, o.precision, ws.elow, st));
     LK_TRY(mrhs_mfma(o.precision, pb.dp, ws.elow, n, Z, ws.zlow, nr, pb.lambda, ws.U, st));
   }
+  if (on != nullptr && !warm) LK_TRY(hipMemcpyAsync(on->U, ws.U, sizeof(double) * n * nr, hipMemcpyDeviceToDevice, st));
   // 3. U_bar = U / ||U||  (column-wise)
   {
     int64_t rpb = (n + 255) / 256;
@@ -463,7 +636,8 @@ laker_status fit_cccp(const Problem& pb, const double* Z, const laker_cccp_opts&
     LK_TRY(gemm_f64(nr, nr, n, ws.U, 1, nr, ws.U, nr, 1, ws.C, nr, 1.0, nullptr, 0.0, ws.part, ns, st));
   }
   // 5. CCCP iterations
-  cccp_init_kernel<<<1, 256, 0, st>>>(ws.S, ws.w, nr);
+  if (warm) cccp_init_warm_kernel<<<1, 256, 0, st>>>(ws.S, ws.w, on->w, on->ab, nr);
+  else cccp_init_kernel<<<1, 256, 0, st>>>(ws.S, ws.w, nr);
   LK_CHECK_LAUNCH();
   // grid-barrier counter of the inverse sweeps: zero here, then advanced by a
   // known amount per sweep
@@ -480,13 +654,31 @@ laker_status fit_cccp(const Problem& pb, const double* Z, const laker_cccp_opts&
   LK_TRY(hipMemsetAsync(ws.S->cnt, 0, sizeof(ws.S->cnt), st));
   CccpState hs;
   const int qgrid = (nr + 3) / 4;
+  const size_t mbq = (size_t)nr * nr * sizeof(double);
+  int nsq = gemm_pick_split(nr, nr, nr, ws.part_cap);
+  if (nsq > 4) nsq = 4;
   for (int t = 0; t < o.max_iter; ++t) {
-    if (t > 0) {
+    if (t > 0 || warm) {
+      // q_k = (M^{-1} C)_kk / (a w_k) from the solve M X = C: the blocked
+      // Gauss-Jordan inverse Minv of M is accurate in norm, but the diagonal of
+      // Minv C cancels (it is 1 - (b/a) Minv_kk / w_k), so the solve is refined
+      // twice with Minv as the approximate inverse (X <- X + Minv (C - M X)),
+      // which brings q to the accuracy of a direct solve of M X = C
       cccp_build_m_kernel<<<ew_grid((int64_t)nr * nr), kT, 0, st>>>(ws.C, ws.w, ws.S, ws.M, nr);
       LK_CHECK_LAUNCH();
+      LK_TRY(hipMemcpyAsync(ws.Yi, ws.M, mbq, hipMemcpyDeviceToDevice, st));
       LK_TRY(inverse(1, ws.M, nullptr, &ws.S->ld_y, nullptr));
+      LK_TRY(gemm_f64(nr, nr, nr, ws.M, nr, 1, ws.C, nr, 1, ws.Zi, nr, 1.0, nullptr, 0.0, ws.part, nsq, st));
+      for (int rs = 0; rs < 2; ++rs) {
+        LK_TRY(hipMemcpyAsync(ws.Gs, ws.C, mbq, hipMemcpyDeviceToDevice, st));
+        LK_TRY(gemm_f64(nr, nr, nr, ws.Yi, nr, 1, ws.Zi, nr, 1, ws.Gs, nr, -1.0, nullptr, 1.0, ws.part, nsq, st));
+        if (rs == 1) break;
+        LK_TRY(gemm_f64(nr, nr, nr, ws.M, nr, 1, ws.Gs, nr, 1, ws.Zi, nr, 1.0, nullptr, 1.0, ws.part, nsq, st));
+      }
+      cccp_q_refined_kernel<<<qgrid, 256, 0, st>>>(ws.M, ws.Zi, ws.Gs, ws.w, ws.S, ws.q, nr);
+    } else {
+      cccp_q_kernel<<<qgrid, 256, 0, st>>>(ws.M, ws.C, ws.w, ws.S, ws.q, nr, 1);
     }
-    cccp_q_kernel<<<qgrid, 256, 0, st>>>(ws.M, ws.C, ws.w, ws.S, ws.q, nr, t == 0 ? 1 : 0);
     LK_CHECK_LAUNCH();
     cccp_update_kernel<<<1, 1024, 0, st>>>(ws.C, ws.q, ws.w, ws.wnew, ws.S, nr, (double)n, o.gamma, o.rho, o.eps,
                                            o.tol, o.max_iter);
@@ -498,6 +690,10 @@ laker_status fit_cccp(const Problem& pb, const double* Z, const laker_cccp_opts&
   }
   if (hs.done == 2) return LAKER_EBREAKDOWN;
   if (stats) stats->cccp_iters = hs.iters;
+  if (on != nullptr) {
+    cccp_save_kernel<<<1, 256, 0, st>>>(ws.S, ws.w, on->w, on->ab, nr);
+    LK_CHECK_LAUNCH();
+  }
   // 6. B and R = b I + B^T B; coupled Newton-Schulz iteration on R / c
   //    (c = ||R||_F, so the spectrum lies in (0, 1]):
   //      P = Z Y,  T = (3 I - P) / 2,  Y <- Y T,  Z <- T Z,

@@ -42,8 +42,18 @@ struct FitWs {
 };
 FitWs plan_fit_ws(void* base, int64_t n, int d, int nr);
 
+// State of a fit that later fits extend with appended sites: the unscaled
+// directions U = (lambda I + G) Z of the sites so far (float64, rows in site
+// order) and the CCCP weights (w, a, b) it ended with.
+struct OnlineFit {
+  double* U;        // n_cap x n_r
+  double* w;        // n_r
+  double* ab;       // a, b
+  int64_t n_prev;   // sites of the previous fit (0: this fit starts the state)
+};
+
 laker_status fit_cccp(const Problem& pb, const double* Z, const laker_cccp_opts& o, const FitWs& ws,
-                      const PrecondLayout& L, laker_stats* stats, hipStream_t st);
+                      const PrecondLayout& L, laker_stats* stats, hipStream_t st, const OnlineFit* on = nullptr);
 laker_status fit_jacobi(const Problem& pb, const PrecondLayout& L, hipStream_t st);
 
 }  // namespace lk

@@ -295,6 +295,10 @@ SolveWs plan_solve_ws(void* base, int64_t n, int d, int64_t m) {
   w.t = c.take<double>(kMaxNr);
   w.misc = c.take<double>(16);
   w.cnt = c.take<unsigned>(16);
+  w.fring = c.take<double>(2 * (size_t)kFcgHist * (size_t)n);
+  w.fpq = c.take<double>(kFcgHist);
+  w.fdz = c.take<double>(kFcgHist);
+  w.fpart = c.take<double>((size_t)kFcgHist * kMaxBlocks);
   w.lcoef = c.take<double>(2 * (size_t)kLanczosCap);
   w.lout = c.take<double>(4);
   w.total = c.bytes();

@@ -14,6 +14,8 @@ struct Problem {
   const double* E;
 };
 
+constexpr int kFcgHist = 8;   // directions the truncated flexible CG can keep
+
 // Carved solve workspace.
 struct SolveWs {
   double* e64;
@@ -42,6 +44,10 @@ struct SolveWs {
   double* t;
   double* misc;
   unsigned* cnt;
+  double* fring;    // truncated flexible CG: kFcgHist directions, then their products (n each)
+  double* fpq;      //   p_i^T q_i per slot
+  double* fdz;      //   z^T q_i of the current step
+  double* fpart;    //   block partials of those (kFcgHist x kMaxBlocks)
   double* lcoef;    // Lanczos estimate: (step size, conjugation coefficient) per iteration
   double* lout;     // its extreme Ritz values
   size_t total;

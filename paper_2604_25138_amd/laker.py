@@ -30,6 +30,8 @@ EXPORTS = (
     "laker_sigma_half_workspace_bytes", "laker_precond_sigma_half", "laker_batch_workspace_bytes",
     "laker_pcg_solve_batched", "laker_kmat_bytes", "laker_precond_apply_workspace_bytes", "laker_precond_apply",
     "laker_learned_solve_workspace_bytes", "laker_learned_solve",
+    "laker_multi_workspace_bytes", "laker_kernel_matvec_multi", "laker_pcg_solve_multi",
+    "laker_online_state_bytes", "laker_fit_precond_online",
 )
 MLP_KEYS = ("W1", "b1", "W2", "b2", "W3", "b3")
 MLP_HIDDEN, MLP_RANK = 256, 64
@@ -55,7 +57,7 @@ class laker_pcg_opts(C.Structure):
                 ("ir_max", C.c_int32), ("inner_tol", C.c_double), ("warm_start", C.c_int32),
                 ("check_every", C.c_int32), ("graph", C.c_int32), ("profile", C.c_int32),
                 ("inner_max_iter", C.c_int32), ("materialized", C.c_int32), ("stall_window", C.c_int32),
-                ("lanczos", C.c_int32)]
+                ("outer_history", C.c_int32), ("escalate", C.c_int32), ("lanczos", C.c_int32)]
 
 
 class laker_stats(C.Structure):
@@ -118,6 +120,11 @@ def load(path: str = LIB_PATH):
     lib.laker_precond_apply_workspace_bytes.restype = sz
     lib.laker_precond_apply.argtypes = [P(laker_precond), vp, vp, i32, vp, sz, vp]
     lib.laker_precond_apply.restype = i32
+    lib.laker_online_state_bytes.argtypes = [i64, i32]
+    lib.laker_online_state_bytes.restype = sz
+    lib.laker_fit_precond_online.argtypes = [P(laker_problem), i64, vp, P(laker_cccp_opts), vp, sz, P(laker_precond),
+                                             vp, sz, P(laker_stats), vp]
+    lib.laker_fit_precond_online.restype = i32
     lib.laker_jacobi_precond.argtypes = [P(laker_problem), P(laker_precond), vp]
     lib.laker_jacobi_precond.restype = i32
     lib.laker_pcg_solve.argtypes = [P(laker_problem), P(laker_precond), vp, vp, P(laker_pcg_opts), vp, sz,
@@ -143,6 +150,13 @@ def load(path: str = LIB_PATH):
     lib.laker_learned_solve.argtypes = [P(laker_problem), vp, vp, P(laker_cccp_opts), vp, vp, P(laker_pcg_opts),
                                         P(laker_precond), vp, sz, P(laker_stats), vp]
     lib.laker_learned_solve.restype = i32
+    lib.laker_multi_workspace_bytes.argtypes = [i64, i32, i32]
+    lib.laker_multi_workspace_bytes.restype = sz
+    lib.laker_kernel_matvec_multi.argtypes = [P(laker_problem), i32, vp, vp, i32, vp, sz, vp]
+    lib.laker_kernel_matvec_multi.restype = i32
+    lib.laker_pcg_solve_multi.argtypes = [P(laker_problem), P(laker_precond), i32, vp, vp, P(laker_pcg_opts), vp, sz,
+                                          P(laker_stats), vp]
+    lib.laker_pcg_solve_multi.restype = i32
     lib.laker_sigma_half_workspace_bytes.argtypes = [i64, i32, i32]
     lib.laker_sigma_half_workspace_bytes.restype = sz
     lib.laker_precond_sigma_half.argtypes = [P(laker_precond), i32, vp, vp, vp, sz, vp]
@@ -267,6 +281,43 @@ def fit_precond(prob: Problem, Z: torch.Tensor, n_r: int | None = None, gamma: f
     return Precond(pc.kind, prob.n, nr, data, pc, st)
 
 
+class OnlineFitState:
+    """Device state of a fit that later fits extend with appended sites
+    (laker_fit_precond_online): directions of the sites so far and the CCCP
+    weights, for up to n_cap sites and n_r directions."""
+
+    def __init__(self, n_cap: int, n_r: int, device="cuda"):
+        lib = load()
+        self.n_cap, self.n_r = int(n_cap), int(n_r)
+        self.buf = torch.zeros(lib.laker_online_state_bytes(self.n_cap, self.n_r), dtype=torch.uint8, device=device)
+        self.n = 0     # sites fitted so far
+
+    def fit(self, prob: Problem, Z, gamma: float = 0.1, rho: float = 0.0, eps: float = 1e-10, tol: float = 1e-8,
+            max_iter: int = 300) -> Precond:
+        """Fit the preconditioner of prob (its first self.n sites are those of
+        the previous fit, in the same order; Z has the previous rows first)."""
+        lib = load()
+        Z = _dev_f64(Z, prob.device)
+        nr = self.n_r
+        pbytes = lib.laker_precond_bytes(prob.n, nr)
+        data = torch.empty(pbytes, dtype=torch.uint8, device=prob.device)
+        pc = laker_precond(PRECOND_CCCP, nr, prob.n, data.data_ptr(), pbytes)
+        opts = laker_cccp_opts(nr, max_iter, gamma, rho, eps, tol, F64, 0)
+        nb = lib.laker_fit_workspace_bytes(prob.n, prob.d, nr)
+        ws = _workspace("fit", nb, prob.device)
+        st = laker_stats()
+        s = lib.laker_fit_precond_online(C.byref(prob.c), self.n, _ptr(Z), C.byref(opts), _ptr(self.buf),
+                                         self.buf.numel(), C.byref(pc), _ptr(ws), ws.numel(), C.byref(st), _stream())
+        _check(s, "laker_fit_precond_online")
+        self.n = prob.n
+        return Precond(pc.kind, prob.n, nr, data, pc, st)
+
+    def directions(self) -> torch.Tensor:
+        """The stored unscaled directions U = (lambda I + G) Z (n x n_r view)."""
+        off = load().laker_online_state_bytes(1, self.n_r) - 8 * self.n_r
+        return self.buf[off:off + 8 * self.n * self.n_r].view(torch.float64).view(self.n, self.n_r)
+
+
 def jacobi_precond(prob: Problem) -> Precond:
     lib = load()
     pbytes = lib.laker_precond_bytes(prob.n, 0)
@@ -294,11 +345,13 @@ def pcg_solve(prob: Problem, y, precond: Precond | None = None, tol: float = 1e-
               precision="f64", refine: bool = False, inner_tol: float = 1e-2, ir_max: int = 64,
               alpha0: torch.Tensor | None = None, check_every: int = 16, allow_noconv: bool = False,
               graph: bool = False, profile: bool = False, inner_max_iter: int = 0, materialized: bool = False,
-              stall_window: int = 0, lanczos: bool = False):
+              stall_window: int = 0, lanczos: bool = False, outer_history: int = 0, escalate: bool = False):
     """Returns (alpha, stats).  materialized: store G once per call and stream it
     in the float64 (and float32) products; stall_window: LAKER_ESTALL when the
     residual falls by less than 2x over that many iterations; lanczos: estimate
-    kappa(P A) from the PCG coefficients (stats.eig_min, eig_max, cond_est)."""
+    kappa(P A) from the PCG coefficients (stats.eig_min, eig_max, cond_est);
+    outer_history: directions the flexible outer CG (refine=2) keeps; escalate:
+    finer inner products when its outer residual stalls."""
     lib = load()
     y = _dev_f64(y, prob.device)
     if alpha0 is not None:
@@ -307,7 +360,8 @@ def pcg_solve(prob: Problem, y, precond: Precond | None = None, tol: float = 1e-
         alpha = torch.empty_like(y)
     opts = laker_pcg_opts(tol, max_iter, _PREC[precision], int(refine), ir_max, inner_tol,
                           1 if alpha0 is not None else 0, check_every, 1 if graph else 0, 1 if profile else 0,
-                          inner_max_iter, 1 if materialized else 0, int(stall_window), 1 if lanczos else 0)
+                          inner_max_iter, 1 if materialized else 0, int(stall_window), int(outer_history),
+                          1 if escalate else 0, 1 if lanczos else 0)
     nb = lib.laker_solve_workspace_bytes(prob.n, prob.d, 0)
     if materialized:
         nb += 256 + lib.laker_kmat_bytes(prob.n, prob.d, F64)
@@ -466,7 +520,7 @@ def learned_solve(prob: Problem, y, model: MlpModel, Z, tol: float = 1e-6, max_i
                   precision="bf16", refine: int = 2, inner_tol: float = 0.1, ir_max: int = 20000,
                   check_every: int = 30, inner_max_iter: int = 30, materialized: bool = False,
                   stall_window: int = 0, gamma: float = 0.1, rho: float = 0.0, cccp_tol: float = 1e-8,
-                  cccp_max_iter: int = 300, allow_noconv: bool = False):
+                  cccp_max_iter: int = 300, allow_noconv: bool = False, outer_history: int = 0):
     """Solve with the learned preconditioner, falling back to a CCCP fit with
     directions Z when that solve stalls or breaks down (laker_learned_solve).
     Returns (alpha, stats, precond used last)."""
@@ -480,7 +534,7 @@ def learned_solve(prob: Problem, y, model: MlpModel, Z, tol: float = 1e-6, max_i
     pc = laker_precond(PRECOND_LEARNED, MLP_RANK, prob.n, data.data_ptr(), pbytes)
     copts = laker_cccp_opts(nr, cccp_max_iter, gamma, rho, 1e-10, cccp_tol, _PREC[precision], 0)
     opts = laker_pcg_opts(tol, max_iter, _PREC[precision], int(refine), ir_max, inner_tol, 0, check_every, 0, 0,
-                          inner_max_iter, 1 if materialized else 0, int(stall_window), 0)
+                          inner_max_iter, 1 if materialized else 0, int(stall_window), int(outer_history), 0, 0)
     nb = lib.laker_learned_solve_workspace_bytes(prob.n, prob.d, nr, _PREC[precision], 1 if materialized else 0)
     ws = _workspace("solve", nb, prob.device)
     st = laker_stats()
@@ -501,6 +555,50 @@ def sigma_half(pc: Precond, Z: torch.Tensor) -> torch.Tensor:
     s = lib.laker_precond_sigma_half(C.byref(pc.c), m, _ptr(Z), _ptr(U), _ptr(ws), ws.numel(), _stream())
     _check(s, "laker_precond_sigma_half")
     return U
+
+
+# ---------------------------------------------------------------------------
+# several right-hand sides on one map
+# ---------------------------------------------------------------------------
+
+def _columns(Y, device) -> torch.Tensor:
+    """(n, k) input as k contiguous columns (the library's column-major layout)."""
+    Y = torch.as_tensor(Y, dtype=torch.float64)
+    if Y.dim() == 1:
+        Y = Y[:, None]
+    return Y.t().contiguous().to(device)
+
+
+def kernel_matvec_multi(prob: Problem, P, precision="f64") -> torch.Tensor:
+    """W = (lambda I + G) P for an (n, k) block P (k <= 8); returns (n, k)."""
+    lib = load()
+    Pc = _columns(P, prob.device)
+    k = Pc.shape[0]
+    W = torch.empty_like(Pc)
+    nb = lib.laker_multi_workspace_bytes(prob.n, prob.d, k)
+    ws = _workspace("multi", nb, prob.device)
+    s = lib.laker_kernel_matvec_multi(C.byref(prob.c), k, _ptr(Pc), _ptr(W), _PREC[precision], _ptr(ws), ws.numel(),
+                                      _stream())
+    _check(s, "laker_kernel_matvec_multi")
+    return W.t()
+
+
+def pcg_solve_multi(prob: Problem, Y, precond: Precond | None = None, tol: float = 1e-10, max_iter: int = 10000,
+                    precision="f64", check_every: int = 16, allow_noconv: bool = False):
+    """Solve for the k <= 8 columns of Y (n, k) together; returns (alpha (n, k), stats list)."""
+    lib = load()
+    Yc = _columns(Y, prob.device)
+    k = Yc.shape[0]
+    A = torch.empty_like(Yc)
+    opts = laker_pcg_opts(tol, max_iter, _PREC[precision], 0, 1, 1e-2, 0, check_every, 0, 0, 0, 0, 0, 0, 0, 0)
+    nb = lib.laker_multi_workspace_bytes(prob.n, prob.d, k)
+    ws = _workspace("multi", nb, prob.device)
+    st = (laker_stats * k)()
+    pc = None if precond is None else C.byref(precond.c)
+    s = lib.laker_pcg_solve_multi(C.byref(prob.c), pc, k, _ptr(Yc), _ptr(A), C.byref(opts), _ptr(ws), ws.numel(), st,
+                                  _stream())
+    _check(s, "laker_pcg_solve_multi", (LAKER_OK, LAKER_ENOCONV) if allow_noconv else (LAKER_OK,))
+    return A.t(), list(st)
 
 
 # ---------------------------------------------------------------------------

@@ -68,7 +68,8 @@ class LearnedSolve:
 def solve_with_fallback(prob: L.Problem, y, model: L.MlpModel, fallback_directions, tol: float = 1e-6,
                         budget: int = 200000, precision: str = "bf16", refine=2, inner_tol: float = 0.1,
                         gamma: float = 0.1, check_every: int = 30, inner_max_iter: int = 30,
-                        materialized: bool = False, stall_window: int = 2000) -> LearnedSolve:
+                        materialized: bool = False, stall_window: int = 2000,
+                        outer_history: int = 0) -> LearnedSolve:
     """PCG with the learned preconditioner; when it stalls (the residual falls by
     less than 2x over stall_window iterations), breaks down or exhausts the
     budget, the library fits CCCP with the fallback directions and continues
@@ -80,5 +81,5 @@ def solve_with_fallback(prob: L.Problem, y, model: L.MlpModel, fallback_directio
     alpha, st, pc = L.learned_solve(prob, y, model, fallback_directions, tol=tol, max_iter=budget, precision=precision,
                                     refine=int(refine), inner_tol=inner_tol, ir_max=ir_max, check_every=check_every,
                                     inner_max_iter=inner_max_iter, materialized=materialized,
-                                    stall_window=stall_window, gamma=gamma)
+                                    stall_window=stall_window, gamma=gamma, outer_history=outer_history)
     return LearnedSolve(alpha, st, st.fell_back, st.learned_iters, pc)

