@@ -7,6 +7,7 @@ no fallback path.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
 from dataclasses import dataclass, field
@@ -194,6 +195,20 @@ def _dev_f64(x, device) -> torch.Tensor:
 
 
 _ws: dict = {}
+
+
+def release() -> None:
+    """Drop the cached device workspaces (registered to run at interpreter exit,
+    so that they are freed while torch's allocator is still alive)."""
+    if _ws:
+        try:
+            torch.cuda.synchronize()
+        except Exception:
+            pass
+        _ws.clear()
+
+
+atexit.register(release)
 
 
 def _workspace(name: str, nbytes: int, device) -> torch.Tensor:

@@ -216,3 +216,97 @@ def test_learned_solve_without_stall_keeps_the_learned_preconditioner():
     assert st.learned_iters == st.iters
     ref = O.solve_direct(O.system_matrix(pr.E, pr.scale, pr.lam), pr.y)
     assert np.linalg.norm(alpha.cpu().numpy() - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+def _bf16(x):
+    """Round float64 values through float32 to bfloat16 (nearest even), the
+    operands the network's matrix products multiply."""
+    u = np.asarray(x, dtype=np.float64).astype(np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000).astype(np.uint32)
+    return u.view(np.float32).astype(np.float64)
+
+
+def _emulated_forward(params, X):
+    """The oracle's forward pass on the operands the library multiplies:
+    inputs, weights and hidden activations rounded to bfloat16 before each
+    product, everything else (sums, bias, SiLU) in float64."""
+    W1, W2, W3 = (_bf16(params[k]) for k in ("W1", "W2", "W3"))
+    Z1 = _bf16(X) @ W1 + params["b1"]
+    H1 = LO.silu(Z1)
+    Z2 = _bf16(H1) @ W2 + params["b2"]
+    H2 = LO.silu(Z2)
+    O = _bf16(H2) @ W3 + params["b3"]
+    mags = (np.abs(_bf16(X)) @ np.abs(W1) + np.abs(params["b1"]),
+            np.abs(_bf16(H1)) @ np.abs(W2) + np.abs(params["b2"]),
+            np.abs(_bf16(H2)) @ np.abs(W3) + np.abs(params["b3"]))
+    return O, (Z1, H1, Z2, H2), mags
+
+
+@pytest.mark.parametrize("n,d", [(300, 8), (1000 + 3, 16), (700, 64)])
+def test_network_forward_elementwise(n, d):
+    """Every output element against the oracle evaluated on bfloat16-rounded
+    operands (same weights), relative to the magnitude of its terms
+    mag_ik = sum_j |h_ij| |W3_jk| + |b3_k|: float32 sums and SiLU give ~1e-6;
+    where a hidden value lies within that of a bfloat16 rounding boundary the
+    two sides round it to neighbouring values (2^-8 apart), which moves the
+    outputs it feeds by a small part of 2^-8 of their magnitude (measured:
+    at most 3.1e-4, 99% below 6.1e-7, median 4e-9 over 700-1003 points).
+    Bound: 2^-9 for every element, 1e-5 for 99% of them."""
+    pr = make_problem(n, d, 1e-3, seed=n)
+    model, params = _model(d, n)
+    O_gpu = L().learned_forward(_gp(pr), model).cpu().double().numpy()
+    X = LO.features(pr.E, pr.lam)
+    O_ref, _, mags = _emulated_forward(params, X)
+    r = np.abs(O_gpu - O_ref) / mags[2]
+    print(f"n={n} d={d}: output error / magnitude: max {r.max():.2e}, 99% {np.quantile(r, 0.99):.2e}, "
+          f"median {np.median(r):.2e}")
+    assert r.max() <= 2.0 ** -9
+    assert np.quantile(r, 0.99) <= 1e-5
+
+
+def test_network_gradient_elementwise():
+    """Every gradient element against the oracle's backward pass on bfloat16
+    operands (inputs, weights, activations and output gradients rounded before
+    each product, as the library multiplies them), relative to the magnitude
+    of its terms (e.g. sum_i |h2_ij| |dO_ik| for W3): the output gradient
+    inherits the forward rounding through the Woodbury solves and is rounded
+    to bfloat16 itself (measured: at most 4.6e-4 (W1), 99% below 2.6e-4).
+    Bound: 2^-9 for every element and 2^-10 for 99% of them."""
+    n, d, m = 400, 8, 12
+    pr = make_problem(n, d, 1e-3, seed=21)
+    model, params = _model(d, 21)
+    Zd = make_directions(n, 48, 21)
+    P, _ = O.fit_precond(pr.E, pr.scale, pr.lam, Zd, gamma=1e-3)
+    probes = make_probes(n, m, 21)
+    U = LO.sigma_half_apply(P.b, P.B, P.apply, probes)
+    _, g = L().learned_train_step(_gp(pr), model, torch.tensor(probes, device=DEV), torch.tensor(U, device=DEV),
+                                  update=False, want_grad=True)
+    X = LO.features(pr.E, pr.lam)
+    O_ref, (Z1, H1, Z2, H2), _ = _emulated_forward(params, X)
+    V, delta = LO.split_output(O_ref)
+    # loss gradient with respect to the outputs (float64, as the oracle's)
+    Y = LO.woodbury_solve(V, delta, U)
+    G = -2.0 * (probes - Y) / (n * m)
+    Hm = LO.woodbury_solve(V, delta, G)
+    dO = np.zeros_like(O_ref)
+    dO[:, :LO.RANK] = -(Hm @ (Y.T @ V) + Y @ (Hm.T @ V))
+    dO[:, LO.RANK] = -(Hm * Y).sum(axis=1) * delta
+    W2, W3 = _bf16(params["W2"]), _bf16(params["W3"])
+    b = {k: _bf16(v) for k, v in (("X", X), ("H1", H1), ("H2", H2), ("dO", dO))}
+    ref, mag = {}, {}
+    ref["W3"], mag["W3"] = b["H2"].T @ b["dO"], np.abs(b["H2"]).T @ np.abs(b["dO"])
+    ref["b3"], mag["b3"] = b["dO"].sum(axis=0), np.abs(b["dO"]).sum(axis=0)
+    dZ2 = (b["dO"] @ W3.T) * LO.silu_grad(Z2)
+    bz2 = _bf16(dZ2)
+    ref["W2"], mag["W2"] = b["H1"].T @ bz2, np.abs(b["H1"]).T @ np.abs(bz2)
+    ref["b2"], mag["b2"] = bz2.sum(axis=0), np.abs(bz2).sum(axis=0)
+    dZ1 = (bz2 @ W2.T) * LO.silu_grad(Z1)
+    bz1 = _bf16(dZ1)
+    ref["W1"], mag["W1"] = b["X"].T @ bz1, np.abs(b["X"]).T @ np.abs(bz1)
+    ref["b1"], mag["b1"] = bz1.sum(axis=0), np.abs(bz1).sum(axis=0)
+    for k in ("W3", "b3", "W2", "b2", "W1", "b1"):
+        gk = g[k].cpu().double().numpy()
+        r = np.abs(gk - ref[k]) / np.maximum(mag[k], 1e-300)
+        print(f"{k}: error / magnitude max {r.max():.2e}, 99% {np.quantile(r, 0.99):.2e}, median {np.median(r):.2e}")
+        assert r.max() <= 2.0 ** -9, k
+        assert np.quantile(r, 0.99) <= 2.0 ** -10, k
