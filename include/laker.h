@@ -218,6 +218,20 @@ laker_status laker_kernel_matvec(const laker_problem* prob, const double* p, dou
                                  int32_t precision, void* workspace, size_t workspace_bytes,
                                  void* stream);
 
+/* w = (lambda I + G) p as laker_kernel_matvec computes it (the same kernels,
+ * bitwise the same result), for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  It takes no workspace and allocates nothing: its scratch (the
+ * prepared embedding copy and the product's partial sums) is a file-scope
+ * device array of 64 MiB, one per GPU, held until the process ends.  Problems
+ * whose scratch exceeds it return LAKER_ENOMEM before any launch (it holds
+ * every precision at n <= 32768 with d <= 64).  All calls on one GPU share
+ * that GPU's array, so calls that overlap on one GPU (on different streams or
+ * host threads) race; calls ordered on one stream do not.  p, w: device
+ * float64 vectors of length n. */
+laker_status laker_kernel_matvec_noalloc(const laker_problem* prob, const double* p, double* w, int32_t precision,
+                                         void* stream);
+
 /* theta = P r: the preconditioner step of every PCG iteration (Alg. 1; for
  * CCCP P = Sigma_star^{-1/2}, eq. preconditioner-Sigmma), computed once with
  * the same kernels the solver runs in its loop.  For a low-rank precond

@@ -30,7 +30,7 @@ EXPORTS = (
     "laker_learned_forward", "laker_learned_train_step", "laker_learned_precond",
     "laker_sigma_half_workspace_bytes", "laker_precond_sigma_half", "laker_batch_workspace_bytes",
     "laker_pcg_solve_batched", "laker_kmat_bytes", "laker_precond_apply_workspace_bytes", "laker_precond_apply",
-    "laker_learned_solve_workspace_bytes", "laker_learned_solve",
+    "laker_learned_solve_workspace_bytes", "laker_learned_solve", "laker_kernel_matvec_noalloc",
     "laker_multi_workspace_bytes", "laker_kernel_matvec_multi", "laker_pcg_solve_multi",
     "laker_online_state_bytes", "laker_fit_precond_online",
 )
