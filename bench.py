@@ -40,12 +40,12 @@ WORKLOADS = {
     # the largest single-map configuration: 65536 sites, 64-d RFF embeddings,
     # 4 transmitters, lambda = 1e-5 (lambda / ||G|| ~ 1.5e-10), solved to a
     # float64 relative residual of 1e-6
-    "n65536_d64": dict(n=65536, d=64, n_tx=4, lam=1e-5, tol=1e-6, seed=0),
+    "n65536_d64": dict(n=65536, d=64, n_tx=4, lam=1e-5, tol=1e-6, seed=0, history=8),
     # the at-scale float32 configuration: 16384 sites, 64-d RFF embeddings,
     # 4 transmitters, lambda = 1e-4, PCG to relative residual 1e-6
-    "n16384_d64": dict(n=16384, d=64, n_tx=4, lam=1e-4, tol=1e-6, seed=0),
+    "n16384_d64": dict(n=16384, d=64, n_tx=4, lam=1e-4, tol=1e-6, seed=0, history=1),
     # small float64 configuration: 512 sites, 16-d embeddings, lambda = 1e-3
-    "n512_d16": dict(n=512, d=16, n_tx=1, lam=1e-3, tol=1e-6, seed=0),
+    "n512_d16": dict(n=512, d=16, n_tx=1, lam=1e-3, tol=1e-6, seed=0, history=1),
 }
 
 # the solve: flexible float64 outer CG around bf16 inner PCG solves of at most
@@ -54,6 +54,10 @@ WORKLOADS = {
 # with inner tolerance 0.1: 100 ms); the inner solves check for convergence
 # every INNER_CAP iterations, so no launches are enqueued past the cap
 INNER_CAP = 30
+# directions the flexible outer CG keeps (per workload, `history`): at 65536
+# sites keeping 8 took 2.74 / 2.80 s per solve on two maps against 3.51 / 3.27 s
+# with 1 (cap 30; cap 20: 2.85 / 2.70 against 3.31 / 3.14); at 16384 sites it
+# makes no difference (0.061-0.064 s)
 # the learned solve falls back to CCCP when its residual falls by less than 2x
 # over this many inner iterations (the bench maps fall by ~1.3 decades in it)
 STALL_WINDOW = 2000
@@ -89,7 +93,7 @@ def parse():
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work in the CPU sample")
     ap.add_argument("--train-maps", type=int, default=TRAIN_MAPS)
     ap.add_argument("--train-epochs", type=int, default=TRAIN_EPOCHS)
-    ap.add_argument("--batch-maps", type=int, default=32,
+    ap.add_argument("--batch-maps", type=int, default=256,
                     help="maps in the batched leg (n ~ U[1024, 16384], d = 32); 0 skips it")
     ap.add_argument("--learned-eval", type=int, default=0,
                     help="held-out maps of 32768 sites (d = 32) on which the learned preconditioner is compared "
@@ -149,16 +153,25 @@ def batched_leg(L, LR, dev, count, train_maps, train_epochs):
         ys.append(torch.tensor(pr.y, device=dev))
     kw = dict(tol=1e-6, max_iter=200000, precision="bf16", refine=True, inner_tol=0.1, ir_max=64, check_every=32,
               materialized=True)
-    # autotune once (cached per size class), then time
+    # autotune once (cached per size class), then time without and with the
+    # iteration chunks captured into HIP graphs
     precs = [L.learned_precond(p, model) for p in probs]
     L.pcg_solve_batched(probs, ys, precs, cols_per_split=-1, xcd_order=False, allow_noconv=True, **kw)
     torch.cuda.synchronize()
-    a = time.perf_counter()
-    precs = [L.learned_precond(p, model) for p in probs]
-    _, st, used = L.pcg_solve_batched(probs, ys, precs, cols_per_split=-1, xcd_order=False, allow_noconv=True, **kw)
-    torch.cuda.synchronize()
+    timed = {}
+    for graph in (False, True):
+        a = time.perf_counter()
+        precs = [L.learned_precond(p, model) for p in probs]
+        _, st_g, used = L.pcg_solve_batched(probs, ys, precs, cols_per_split=-1, xcd_order=False, allow_noconv=True,
+                                            graph=graph, **kw)
+        torch.cuda.synchronize()
+        timed[graph] = (time.perf_counter() - a, st_g)
+    use_graph = timed[True][0] < timed[False][0]
+    b_s, st = timed[use_graph]
+    _note(f"batched leg: {count} maps together in {b_s:.2f} s (graphs {'on' if use_graph else 'off'}); "
+          "now one after the other")
     b = time.perf_counter()
-    _note(f"batched leg: {count} maps together in {b - a:.2f} s; now one after the other")
+    a = b - b_s
     its_serial = []
     for p, y in zip(probs, ys):
         pc = L.learned_precond(p, model)
@@ -168,6 +181,7 @@ def batched_leg(L, LR, dev, count, train_maps, train_epochs):
     c = time.perf_counter()
     return {"maps": count, "pairs_per_sweep": float(sum(p.n * p.n for p in probs)),
             "batched_s": b - a, "maps_per_s": count / (b - a), "serial_s": c - b, "serial_maps_per_s": count / (c - b),
+            "batched_s_graphs_off": timed[False][0], "batched_s_graphs_on": timed[True][0], "graphs": use_graph,
             "speedup_vs_serial": (c - b) / (b - a), "converged": sum(1 for x in st if x.status == 0),
             "worst_relres_true": max(x.relres_true for x in st), "escalations": sum(x.escalations for x in st),
             "max_iters": max(x.iters for x in st), "cols_per_split_largest": used}
@@ -231,7 +245,7 @@ def solve_cost(L, prob, y, pc, kw):
     return time.perf_counter() - a, st
 
 
-def cccp_mixed_leg(L, prob, y, Zd, Eq, tol, gamma):
+def cccp_mixed_leg(L, prob, y, Zd, Eq, tol, gamma, hist):
     """CCCP fit (bfloat16 directions) + the same solver as the timed step
     (flexible float64 outer CG around capped bf16 inner PCG, stored G for the
     outer products) + predict: the learned preconditioner's comparison with
@@ -244,7 +258,7 @@ def cccp_mixed_leg(L, prob, y, Zd, Eq, tol, gamma):
     b = time.perf_counter()
     alc, stc = L.pcg_solve(prob, y, pc, tol=tol, max_iter=400000, precision="bf16", refine=2, inner_tol=0.1,
                            ir_max=20000, check_every=INNER_CAP, inner_max_iter=INNER_CAP, materialized=True,
-                           allow_noconv=True)
+                           allow_noconv=True, outer_history=hist)
     torch.cuda.synchronize()
     c = time.perf_counter()
     L.predict(prob, alc, Eq, precision="f64")
@@ -492,6 +506,7 @@ def main():
     Zd = torch.tensor(Z, device=dev)
     Eq = torch.tensor(pr.Eq, device=dev)
     tol = wl["tol"]
+    hist = wl["history"]
     budget = 400000
 
     if args.counters:
@@ -517,7 +532,7 @@ def main():
     def step():
         res = LR.solve_with_fallback(prob, y, model, Zd, tol=tol, budget=budget, precision="bf16", refine=2,
                                      inner_tol=0.1, gamma=0.1, check_every=INNER_CAP, inner_max_iter=INNER_CAP,
-                                     materialized=True, stall_window=STALL_WINDOW)
+                                     materialized=True, stall_window=STALL_WINDOW, outer_history=hist)
         rhat = L.predict(prob, res.alpha, Eq, precision="f64")
         return res, rhat
 
@@ -555,7 +570,7 @@ def main():
     extra["cccp_mixed"] = {}
     pc = None
     for g in (0.1, 1e-3):
-        leg, pcg_ = cccp_mixed_leg(L, prob, y, Zd, Eq, tol, g)
+        leg, pcg_ = cccp_mixed_leg(L, prob, y, Zd, Eq, tol, g, hist)
         extra["cccp_mixed"][f"gamma_{g:g}"] = leg
         if pc is None:
             pc = pcg_
@@ -586,7 +601,7 @@ def main():
     pcl = L.learned_precond(prob, model)
     _, stp = L.pcg_solve(prob, y, pcl, tol=tol, max_iter=budget, precision="bf16", refine=2, inner_tol=0.1,
                          ir_max=20000, check_every=INNER_CAP, inner_max_iter=INNER_CAP, profile=True,
-                         materialized=True)
+                         materialized=True, outer_history=hist)
     kms = stp.kmv_ms
     pairs = float(pr.n) * pr.n
     # the symmetric product forms each of the n (n + 1) / 2 distinct kernel
@@ -650,7 +665,8 @@ def main():
                                f"scale=1/sqrt(d) tol={tol}",
                    "path": "learned rank-64+diag preconditioner (BF16 MLP) + flexible f64 outer CG (its float64 "
                            "products stream G stored once per solve) around bf16 "
-                           f"inner PCG (<= {INNER_CAP} iterations each; CCCP fallback in the library when the "
+                           f"inner PCG (<= {INNER_CAP} iterations each; {hist} outer directions kept; CCCP "
+                           f"fallback in the library when the "
                            f"residual falls less than 2x over {STALL_WINDOW} iterations) + predict 45x45",
                    "training": f"{args.train_maps} maps n={TRAIN_N} lambda~logU[1e-5,1e-2] n_tx~U{{1..8}}, "
                                f"{args.train_epochs} epochs, CCCP targets gamma=1e-3"},

@@ -479,6 +479,29 @@ class MlpModel:
     def params(self) -> dict:
         return {k: v.detach().cpu().double().numpy() for k, v in self.tensor_views(0).items()}
 
+    def save(self, path: str) -> None:
+        """Write the float32 weights, the Adam moments and the step count to an
+        .npz file (plain arrays, no pickled objects)."""
+        import numpy as np
+        arrays = {"d": np.array([self.d]), "step": np.array([self.step])}
+        for blk, tag in ((0, "w"), (1, "m"), (2, "v")):
+            for k, t in self.tensor_views(blk).items():
+                arrays[f"{tag}_{k}"] = t.detach().cpu().numpy()
+        np.savez(path, **arrays)
+
+    @classmethod
+    def load(cls, path: str, device="cuda") -> "MlpModel":
+        """Read a model written by save (the layout is rebuilt for its d)."""
+        import numpy as np
+        with np.load(path, allow_pickle=False) as z:
+            model = cls(int(z["d"][0]), device)
+            for blk, tag in ((0, "w"), (1, "m"), (2, "v")):
+                views = model.tensor_views(blk)
+                for k in MLP_KEYS:
+                    views[k].copy_(torch.as_tensor(z[f"{tag}_{k}"], dtype=torch.float32))
+            model.step = int(z["step"][0])
+        return model
+
     def grad_views(self, flat: torch.Tensor) -> dict:
         out = {}
         for t, (k, shp) in enumerate(self._shapes().items()):

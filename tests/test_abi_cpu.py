@@ -167,3 +167,30 @@ def test_missing_library_fails_loudly_and_product_never_imports_the_oracle():
         if f.endswith(".py"):
             src = open(os.path.join(pkg, f)).read()
             assert not re.search(r"^\s*(from|import)\s+oracle\b", src, flags=re.M), f
+
+
+def test_model_save_load_round_trip(tmp_path):
+    """The network's weights, Adam moments and step count survive a save/load
+    (host memory; the layout comes from the library's size query)."""
+    import numpy as np
+    laker, _ = _lib()
+    from synth import make_mlp_init
+    d = 8
+    m = laker.MlpModel(d, "cpu")
+    lay = laker.mlp_layout(d)
+    m.set_params(make_mlp_init(lay.in_dim, laker.MLP_HIDDEN, laker.MLP_RANK + 1, 3))
+    for blk in (1, 2):
+        for k, t in m.tensor_views(blk).items():
+            t.copy_(torch_rand_like(t, blk))
+    m.step = 17
+    f = tmp_path / "model.npz"
+    m.save(str(f))
+    m2 = laker.MlpModel.load(str(f), "cpu")
+    assert m2.d == d and m2.step == 17
+    assert np.array_equal(m.buf.numpy(), m2.buf.numpy())
+
+
+def torch_rand_like(t, seed):
+    import torch
+    g = torch.Generator().manual_seed(seed)
+    return torch.rand(t.shape, generator=g, dtype=t.dtype)
