@@ -95,9 +95,9 @@ def parse():
     ap.add_argument("--train-epochs", type=int, default=TRAIN_EPOCHS)
     ap.add_argument("--batch-maps", type=int, default=256,
                     help="maps in the batched leg (n ~ U[1024, 16384], d = 32); 0 skips it")
-    ap.add_argument("--learned-eval", type=int, default=0,
+    ap.add_argument("--learned-eval", type=int, default=8,
                     help="held-out maps of 32768 sites (d = 32) on which the learned preconditioner is compared "
-                         "with a CCCP fit; 0 (default) skips the leg")
+                         "with a CCCP fit under the same solver options; 0 skips the leg")
     return ap.parse_args()
 
 
