@@ -66,11 +66,16 @@ STALL_WINDOW = 2000
 # lambda log-uniform in [1e-5, 1e-2] and 1..8 transmitters
 TRAIN_N, TRAIN_MAPS, TRAIN_EPOCHS, TRAIN_PROBES = 4096, 96, 30, 128
 
-# fp32 vector rate: 256 CUs x 128 lanes x 2.4 GHz single-issue multiply-adds
-# (the 157.3 TFLOP/s fp32 vector peak counts 2 flops each); exp2 issues at a
-# quarter of that rate, so it takes 4 of these slots
-PEAK_VALU_TOPS = 256 * 128 * 2.4e9 / 1e12
-EXP2_SLOTS = 4.0
+# vector ALU issue rate: 256 CUs x 64 lanes x 2.4 GHz unpacked float32
+# multiply-adds, one slot each.  The library is built without packed float32
+# instructions, and the 157.3 TFLOP/s fp32 vector figure counts them (128
+# lanes' worth); 64 lanes is the issue width of the 78.6 TFLOP/s fp64 vector
+# figure.  exp2 (v_exp_f32) issues at half that rate and takes 2 slots.  Both
+# were measured by calib/valu_rates.hip: 57.6 lane-FMA and 29.0 lane-exp2 per CU
+# per clock at 8 waves per SIMD, exp2 + 2 FMA at 15.5 per CU per clock (the two
+# do not overlap).
+PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
+EXP2_SLOTS = 2.0
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
@@ -612,8 +617,8 @@ def main():
     achieved = slots / (kms * 1e-3) / 1e12
     mfma_flops = 2.0 * pr.d * distinct
     traffic = measured_traffic(args.workload)
-    roofline = {"kernel": "kmvsym_kernel<BF16,64> (fused exp2(<e_i,e_j>) p product over the symmetric tile "
-                          "schedule, bf16 score tiles on MFMA)",
+    roofline = {"kernel": "kmvsym16_kernel<64> (fused exp2(<e_i,e_j>) p product over the symmetric tile "
+                          "schedule, bf16 16x16x32 score tiles on MFMA, 64 rows per wave)",
                 "bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TOPS, "unit": "TOP/s",
                 "frac": achieved / PEAK_VALU_TOPS, "traffic": traffic,
                 "per_launch": {"pairs": pairs, "distinct_entries": distinct, "valu_slot_ops": slots,

@@ -15,6 +15,9 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "liblaker.so")
+# issue-rate calibration program behind the ALU roofline's peak (not part of the library)
+CALIB_SRC = os.path.join(PKG, "calib", "valu_rates.hip")
+CALIB = os.path.join(PKG, "calib", "valu_rates")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
@@ -52,9 +55,19 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    build_calib()
     if verbose:
-        print(f"built {LIB}")
+        print(f"built {LIB} and {CALIB}")
     return LIB
+
+
+def build_calib() -> str:
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
+           "-packed-fp32-ops", CALIB_SRC, "-o", CALIB]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed on {CALIB_SRC}:\n{r.stdout}\n{r.stderr}")
+    return CALIB
 
 
 if __name__ == "__main__":

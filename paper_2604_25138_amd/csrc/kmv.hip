@@ -9,13 +9,14 @@
 // float32 / bfloat16 copies are pre-scaled by sqrt(s log2 e) so that the MFMA
 // output is directly the exp2 argument; float64 copies by sqrt(s) (exp).
 //
-// Work split: a wave owns 32 rows (16 for float64) and sweeps the key tiles of
-// one column range; a block holds four waves.  The score tile S = Q K^T comes
-// from MFMA (32x32x2 f32, 32x32x16 bf16, 16x16x4 f64); each lane then applies
-// exp to its S entries and accumulates exp(S) p_j into per-row partial sums
-// (float64 across stages, float32 within a stage), which are combined across
-// lanes once at the end.  Column ranges write
-// partial sums; a following pass adds them in a fixed order and applies
+// Work split (rectangular kernels): a wave owns 32 rows (16 for float64) and
+// sweeps the key tiles of one column range; a block holds four waves.  The
+// symmetric kernels below split a 256-row block differently.  The score tile
+// S = Q K^T comes from MFMA (32x32x2 f32, 32x32x16 or 16x16x32 bf16, 16x16x4
+// f64); each lane then applies exp to its S entries and accumulates
+// exp(S) p_j into per-row partial sums (float64 across stages, float32 within
+// a stage), which are combined across lanes once at the end.  Column ranges
+// write partial sums; a following pass adds them in a fixed order and applies
 // lambda p.  Inside PCG the symmetric kernels also form p^T A p from the
 // partials they write (one float64 per block), and the step-update pass adds
 // the partials of each row itself.
@@ -31,6 +32,7 @@ constexpr double kLog2e = 1.4426950408889634074;
 
 typedef float v16f __attribute__((ext_vector_type(16)));
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
@@ -355,15 +357,16 @@ __global__ __launch_bounds__(256) void kmv32_batch_kernel(const KmvArgs* __restr
 // wave-halves go through LDS and are added in a fixed order by the first 128
 // threads while the next stage runs.
 // ---------------------------------------------------------------------------
-// Block total of the per-thread p^T A p sums of a symmetric launch (512
-// threads), in a fixed order: wave 0 adds the eight waves' values lane by
-// lane, then the lanes by a shuffle tree.
+// Block total of the per-thread p^T A p sums of a symmetric launch (NT
+// threads), in a fixed order: wave 0 adds the waves' values lane by lane, then
+// the lanes by a shuffle tree.
+template <int NT = 512>
 __device__ __forceinline__ void sym_pap_store(double* papl, double* out) {
   __syncthreads();
   if (threadIdx.x < 64) {
     double s = papl[threadIdx.x];
 #pragma unroll
-    for (int w = 1; w < 8; ++w) s += papl[w * 64 + threadIdx.x];
+    for (int w = 1; w < NT / 64; ++w) s += papl[w * 64 + threadIdx.x];
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
     if (threadIdx.x == 0) *out = s;
@@ -371,32 +374,39 @@ __device__ __forceinline__ void sym_pap_store(double* papl, double* out) {
 }
 
 // Inputs of the on-the-fly conjugation (A.theta set), loaded at kernel entry
-// so that their latency overlaps the first key-row fetches: this thread's two
-// r^T theta partials (entries tid and tid + 512 of at most 1024; the index is
-// clamped and the value masked when summed) and S->first / S->rzold.
+// so that their latency overlaps the first key-row fetches: this thread's
+// r^T theta partials (entries tid + k NT of at most 1024; the index is clamped
+// and the value masked when summed) and S->first / S->rzold.
+template <int NT = 512>
 struct ConjIn {
-  double a, c, rzold;
+  double v[1024 / NT];
+  double rzold;
   int first;
 };
-__device__ __forceinline__ ConjIn sym_conj_issue(const KmvArgs& A) {
-  ConjIn r{0.0, 0.0, 0.0, 1};
+template <int NT = 512>
+__device__ __forceinline__ ConjIn<NT> sym_conj_issue(const KmvArgs& A) {
+  ConjIn<NT> r{};
+  r.first = 1;
   if (A.theta == nullptr) return r;
   const int t = threadIdx.x, g = A.grz;
-  r.a = A.rzp[t < g ? t : g - 1];
-  r.c = A.rzp[t + 512 < g ? t + 512 : g - 1];
+#pragma unroll
+  for (int k = 0; k < 1024 / NT; ++k) r.v[k] = A.rzp[t + k * NT < g ? t + k * NT : g - 1];
   r.rzold = A.S->rzold;
   r.first = A.S->first;
   return r;
 }
 // beta = r^T theta / S->rzold (0 while S->first), the same in every block
-// (fixed-order sum over the 512-thread block); block 0 records beta and the
-// new r^T theta (slot kcur & 1, read by the step update).  Called before kcur
-// advances.
-__device__ __forceinline__ double sym_conj_finish(const KmvArgs& A, const ConjIn& in, int64_t b) {
+// (fixed-order sum over the block); block 0 records beta and the new r^T theta
+// (slot kcur & 1, read by the step update).  Called before kcur advances.
+template <int NT = 512>
+__device__ __forceinline__ double sym_conj_finish(const KmvArgs& A, const ConjIn<NT>& in, int64_t b) {
   if (A.theta == nullptr) return 0.0;
   __shared__ double sh[16];
   const int t = threadIdx.x, g = A.grz;
-  const double rz = block_sum((t < g ? in.a : 0.0) + (t + 512 < g ? in.c : 0.0), sh);
+  double mine = 0.0;
+#pragma unroll
+  for (int k = 0; k < 1024 / NT; ++k) mine += t + k * NT < g ? in.v[k] : 0.0;
+  const double rz = block_sum(mine, sh);
   const double beta = in.first ? 0.0 : rz / in.rzold;
   if (b == 0 && t == 0) {
     A.S->rzbuf[A.S->kcur & 1] = rz;
@@ -432,7 +442,7 @@ __global__ __launch_bounds__(512) void kmvsym_kernel(KmvArgs A, SymPlan P) {
   __shared__ double pdl[3][KT];
   __shared__ double prl[512];
   __shared__ double papl[512];
-  const ConjIn cin = sym_conj_issue(A);
+  const ConjIn<512> cin = sym_conj_issue<512>(A);
   if (A.S != nullptr && A.S->done) return;
   const int64_t b = blockIdx.x;
   // direction entry j: p_j, or theta_j + beta p_j when conjugating (beta is
@@ -741,6 +751,330 @@ __global__ __launch_bounds__(512) void kmvsym_kernel(KmvArgs A, SymPlan P) {
 }
 
 // ---------------------------------------------------------------------------
+// Symmetric square product in bfloat16 on 16x16x32 MFMA tiles (dp = 32, 64).
+// The schedule of kmvsym_kernel (row blocks of 256 against column stages of
+// 128 on or right of the block diagonal, interleaved row-block order), on a
+// grid of 2 kSymGrid blocks of four waves, two blocks per CU.  Each wave owns
+// 64 rows as four 16-row tiles, so every key fragment it reads from LDS feeds
+// four score tiles (half the fragment reads per kernel entry of the eight-wave
+// kernel), and a lane (column q = lane % 16, row group g = lane / 16) holds
+// rows 4 g + 0..3 of each row tile: 16 float64 row sums, where 32x32 tiles
+// would need 32 for 64 rows.  A block synchronizes four waves per stage
+// instead of eight.  The kernel is bound by vector issue: per kernel entry one
+// exp2 (two issue slots) and two multiply-adds, plus the MFMA issue.
+//
+// Fragments: for MFMA step s a lane supplies elements
+// g (dp / 4) + 8 s + 0..7 of its row (query rows: A operand, key rows: B);
+// the score tile's lane holds S[4 g + i][q], i = 0..3.
+// ---------------------------------------------------------------------------
+template <int DP>
+struct FragB16x {
+  static constexpr int S = DP / 32;   // MFMA steps
+  v8bf v[S];
+  __device__ __forceinline__ void load(const uint16_t* __restrict__ base, int64_t row, int g) {
+    const u32x4* src = reinterpret_cast<const u32x4*>(base + row * DP + g * (DP / 4));
+#pragma unroll
+    for (int q = 0; q < S; ++q) v[q] = __builtin_bit_cast(v8bf, src[q]);
+  }
+};
+
+template <int DP>
+__device__ __forceinline__ v4f tile16_bf16(const FragB16x<DP>& a, const FragB16x<DP>& b) {
+  v4f c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int s = 0; s < FragB16x<DP>::S; ++s) c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v[s], b.v[s], c, 0, 0, 0);
+  return c;
+}
+
+template <int DP>
+__global__ __launch_bounds__(256, 2) void kmvsym16_kernel(KmvArgs A, SymPlan P) {
+  using St = SymStage<LAKER_BF16, DP>;
+  using Frag = FragB16x<DP>;
+  constexpr int KT = St::KT;
+  constexpr int NT = 256;
+  constexpr int RT = 4;                 // 16-row tiles per wave
+  constexpr int CROWS = 16;             // column-sum rows: four row groups of four waves
+  constexpr int CPITCH = KT + 32;       // (consecutive rows start 32 banks apart)
+  static_assert(St::STAGERS == NT, "every thread stages key rows");
+  __shared__ __attribute__((aligned(16))) unsigned char lds[2][St::BYTES];
+  __shared__ float colbuf[2][CROWS * CPITCH];
+  // p^T A p partials (A.pap set): p of the staged columns of three stages in
+  // flight, p of the row each lane writes, and one running sum per thread
+  __shared__ double pdl[3][KT];
+  __shared__ double prl[NT];
+  __shared__ double papl[NT];
+  const ConjIn<NT> cin = sym_conj_issue<NT>(A);
+  if (A.S != nullptr && A.S->done) return;
+  const int64_t b = blockIdx.x;
+  const double* __restrict__ th = A.theta;
+  const double* __restrict__ p = A.p;
+  double beta = 0.0;
+  auto pval = [&](int64_t j) { return th != nullptr ? fma(beta, p[j], th[j]) : p[j]; };
+  const int64_t s0 = P.T * b / P.grid, s1 = P.T * (b + 1) / P.grid;
+  const bool wp = A.pap != nullptr;
+  const int64_t L = s1 - s0;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int q = lane & 15, g = lane >> 4;
+  const int64_t n = A.n;
+  const int64_t ncs = P.ncs;
+  const uint16_t* __restrict__ Q = reinterpret_cast<const uint16_t*>(A.K);
+  const unsigned char* __restrict__ Kb = reinterpret_cast<const unsigned char*>(A.K);
+  double* __restrict__ part = A.part;
+
+  const int64_t nrb = P.nrb;
+  int64_t t0 = 0;
+  while (sym_pos_start(t0 + 1, nrb, ncs) <= s0) ++t0;
+  const int64_t I0 = sym_rowblock_at(t0, nrb);
+  const int64_t J0 = 2 * I0 + (s0 - sym_pos_start(t0, nrb, ncs));
+
+  // ---- LDS staging of the key rows of column stage J (every thread)
+  u32x4 stg[St::PER_T];
+  double stp = 0.0;
+  bool stv = false;
+  auto fetch_keys = [&](int64_t J) {
+    const int64_t js = J * KT;
+    const unsigned char* sb = Kb + js * St::ROWB;
+    if (js + KT <= n) {
+#pragma unroll
+      for (int u = 0; u < St::PER_T; ++u) {
+        const int ch = tid + NT * u;
+        if (St::CHUNKS % NT == 0 || ch < St::CHUNKS) stg[u] = *reinterpret_cast<const u32x4*>(sb + ch * 16);
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < St::PER_T; ++u) {
+        const int ch = tid + NT * u;
+        if (St::CHUNKS % NT == 0 || ch < St::CHUNKS) {
+          const int rr = ch / (St::ROWB / 16);
+          const int cc = ch - rr * (St::ROWB / 16);
+          int64_t kr = js + rr;
+          if (kr > n - 1) kr = n - 1;
+          stg[u] = *reinterpret_cast<const u32x4*>(Kb + kr * St::ROWB + cc * 16);
+        }
+      }
+    }
+  };
+  auto fetch_w = [&](int64_t J) {
+    if (tid < KT) {
+      const int64_t kj = J * KT + tid;
+      stv = kj < n;
+      stp = pval(kj < n ? kj : n - 1);
+    }
+  };
+  auto fetch = [&](int64_t J) {
+    fetch_keys(J);
+    fetch_w(J);
+  };
+  auto store = [&](int buf, int ring) {
+#pragma unroll
+    for (int u = 0; u < St::PER_T; ++u) {
+      const int ch = tid + NT * u;
+      if (St::CHUNKS % NT == 0 || ch < St::CHUNKS) {
+        const int rr = ch / (St::ROWB / 16);
+        const int cc = ch - rr * (St::ROWB / 16);
+        *reinterpret_cast<u32x4*>(&lds[buf][rr * St::PITCH + cc * 16]) = stg[u];
+      }
+    }
+    if (tid < KT) {
+      reinterpret_cast<float*>(&lds[buf][KT * St::PITCH])[tid] = stv ? (float)stp : 0.f;
+      if (wp) pdl[ring][tid] = stv ? stp : 0.0;
+    }
+  };
+  auto advance = [&](int64_t& t, int64_t& I, int64_t& J) {
+    if (++J == ncs) {
+      ++t;
+      I = sym_rowblock_at(t, nrb);
+      J = 2 * I;
+    }
+  };
+
+  // ---- per row block state.  Row tile k of the wave: rows
+  // I kSymRows + 64 wv + 16 k + 0..15; the lane's rows in it: 4 g + 0..3.
+  Frag a[RT];
+  float rw[RT][4];
+  double acc[RT][4];
+  double prn = 0.0;   // p of the row this lane writes, for the next row block
+  int64_t Icur = -1;
+  // the row this lane writes after the row-sum exchange: value j = q of its
+  // row group, i.e. row tile q / 4, row 4 g + q % 4 of it
+  const int wrow = 16 * (q >> 2) + 4 * g + (q & 3);
+  auto load_rows = [&](int64_t I) {
+    const int64_t row0 = I * kSymRows + wv * 64;
+#pragma unroll
+    for (int k = 0; k < RT; ++k) {
+      int64_t qi = row0 + 16 * k + q;
+      if (qi > n - 1) qi = n - 1;
+      a[k].load(Q, qi, g);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t row = row0 + 16 * k + 4 * g + i;
+        rw[k][i] = row < n ? (float)pval(row) : 0.f;
+      }
+    }
+    if (wp) prn = row0 + wrow < n ? pval(row0 + wrow) : 0.0;
+  };
+  auto open_rows = [&](int64_t I) {
+#pragma unroll
+    for (int k = 0; k < RT; ++k)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc[k][i] = 0.0;
+    if (wp) prl[tid] = prn;
+    Icur = I;
+  };
+  // row sums over the 16 lanes of a row group: a halving exchange over the 16
+  // values v_j = acc[j / 4][j % 4] (lanes with bit 3 set keep j = 8..15, ...)
+  // leaves lane q with value j = q summed over its 16 lanes
+  auto flush_rows = [&]() {
+    double v8[8], v4[4], v2[2];
+    const bool s3 = (q & 8) != 0, s2 = (q & 4) != 0, s1 = (q & 2) != 0, s0b = (q & 1) != 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const double lo = acc[j >> 2][j & 3], hi = acc[(j + 8) >> 2][(j + 8) & 3];
+      v8[j] = (s3 ? hi : lo) + __shfl_xor(s3 ? lo : hi, 8, 64);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v4[j] = (s2 ? v8[j + 4] : v8[j]) + __shfl_xor(s2 ? v8[j] : v8[j + 4], 4, 64);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) v2[j] = (s1 ? v4[j + 2] : v4[j]) + __shfl_xor(s1 ? v4[j] : v4[j + 2], 2, 64);
+    const double v = (s0b ? v2[1] : v2[0]) + __shfl_xor(s0b ? v2[0] : v2[1], 1, 64);
+    const int64_t slot = b - sym_block_of(sym_pos_start(sym_pos_of(Icur, nrb), nrb, ncs), P.grid, P.T);
+    const int64_t row = Icur * kSymRows + wv * 64 + wrow;
+    if (row < n) {
+      part[slot * n + row] = v;
+      if (wp) {
+        // the block holding the row block's diagonal stage adds lam p_i^2
+        const double pr = prl[tid];
+        double s = fma(pr, v, papl[tid]);
+        if (slot == 0) s = fma(A.lam * pr, pr, s);
+        papl[tid] = s;
+      }
+    }
+  };
+  // column sums of the stage held in colbuf[buf] (16 rows, fixed order): two
+  // adjacent lanes per column, each adding eight rows, then each other's
+  auto flush_cols = [&](int buf, int ring, int64_t I, int64_t J) {
+    const int ct = tid >> 1, hf = tid & 1;
+    double v = 0.0;
+#pragma unroll
+    for (int k = 0; k < CROWS / 2; ++k) v += (double)colbuf[buf][(hf * (CROWS / 2) + k) * CPITCH + ct];
+    v += __shfl_xor(v, 1, 64);
+    const int64_t col = J * KT + ct;
+    if (hf == 0 && col < n) {
+      part[(P.rs + I) * n + col] = v;
+      if (wp) papl[tid] = fma(pdl[ring][ct], v, papl[tid]);
+    }
+  };
+
+  auto load_b = [&](Frag& bf, const unsigned char* base, int v) {
+    const unsigned char* rowp = base + (v * 16 + q) * St::PITCH + g * (St::ROWB / 4);
+#pragma unroll
+    for (int s = 0; s < Frag::S; ++s) bf.v[s] = __builtin_bit_cast(v8bf, *reinterpret_cast<const u32x4*>(rowp + 16 * s));
+  };
+  // one stage: the wave's four row tiles against the eight 16-column tiles of
+  // the staged key rows
+  auto stage = [&](int buf, auto mirror) {
+    constexpr bool MIR = decltype(mirror)::value;
+    constexpr int NV = KT / 16;
+    const unsigned char* base = lds[buf];
+    const float* pw = reinterpret_cast<const float*>(base + KT * St::PITCH);
+    float accf[RT][4];
+    float pv[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) pv[v] = pw[v * 16 + q];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      // (one column tile at a time: the other block on the CU covers the
+      // fragment reads' latency -- reading the next tile's fragments ahead, in
+      // a loop over tile pairs that fits the registers, measured no faster,
+      // and unrolled it overflows them)
+      __builtin_amdgcn_sched_barrier(0);
+      Frag bv;
+      load_b(bv, base, v);
+      const float pvf = pv[v];
+      // (first terms are products, not multiply-adds onto zero)
+      auto madd = [&](float x, float y, float acc0, bool first) { return first ? x * y : fmaf(x, y, acc0); };
+      float gk[RT];
+#pragma unroll
+      for (int k = 0; k < RT; ++k) {
+        const v4f sc = tile16_bf16<DP>(a[k], bv);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float t = kexp2(sc[i]);
+          accf[k][i] = madd(t, pvf, accf[k][i], v == 0);
+          if constexpr (MIR) gk[k] = madd(t, rw[k][i], gk[k], i == 0);
+        }
+      }
+      if constexpr (MIR) colbuf[buf][(wv * 4 + g) * CPITCH + v * 16 + q] = (gk[0] + gk[1]) + (gk[2] + gk[3]);
+    }
+#pragma unroll
+    for (int k = 0; k < RT; ++k)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc[k][i] += (double)accf[k][i];
+  };
+
+  // ---- pipeline (as the rectangular kernel): registers hold stage k + 1 at
+  // the top of iteration k; one barrier per stage
+  int64_t tc = t0, Ic = I0, Jc = J0;   // stage k
+  int64_t tf = t0, If = I0, Jf = J0;   // next stage to fetch
+  // stage s keeps the float64 p of its columns in pdl[s % 3]: written when the
+  // stage is stored (iteration s - 1), read when its columns are flushed
+  // (iteration s + 1), overwritten by stage s + 3 (iteration s + 2)
+  auto ring_next = [](int q) { return q == 2 ? 0 : q + 1; };
+  int rcur = 0;
+  fetch_keys(Jf);
+  beta = sym_conj_finish<NT>(A, cin, b);
+  if (A.pcg_step && b == 0 && tid == 0) A.S->kcur += 1;
+  if (s0 >= s1) {
+    if (wp && tid == 0) A.pap[b] = 0.0;
+    return;
+  }
+  if (wp) papl[tid] = 0.0;
+  fetch_w(Jf);
+  advance(tf, If, Jf);
+  store(0, 0);
+  if (L > 1) {
+    fetch(Jf);
+    advance(tf, If, Jf);
+  }
+  load_rows(I0);
+  __syncthreads();
+  int64_t Ip = -1, Jp = -1;   // previous off-diagonal stage whose columns are pending
+  int rp = 0;
+  for (int64_t k = 0; k < L; ++k) {
+    const int buf = (int)(k & 1);
+    if (k + 1 < L) store(buf ^ 1, ring_next(rcur));
+    if (k + 2 < L) {
+      fetch(Jf);
+      advance(tf, If, Jf);
+    }
+    if (Ip >= 0) {
+      flush_cols(buf ^ 1, rp, Ip, Jp);
+      Ip = -1;
+    }
+    if (Ic != Icur) {
+      if (Icur >= 0) flush_rows();
+      open_rows(Ic);
+    }
+    if (Jc >= 2 * Ic + 2) {
+      stage(buf, std::true_type{});
+      Ip = Ic;
+      Jp = Jc;
+      rp = rcur;
+    } else {
+      stage(buf, std::false_type{});
+    }
+    advance(tc, Ic, Jc);
+    rcur = ring_next(rcur);
+    if (k + 1 < L && Ic != Icur) load_rows(Ic);
+    __syncthreads();
+  }
+  if (Ip >= 0) flush_cols((int)((L - 1) & 1), rp, Ip, Jp);
+  flush_rows();
+  if (wp) sym_pap_store<NT>(papl, A.pap + b);
+}
+
+// ---------------------------------------------------------------------------
 // Symmetric square product in float64 (dp <= 64): the schedule of the
 // float32 / bfloat16 kernel (256-row blocks against 128-column stages on or
 // right of the block diagonal, interleaved row-block order, fixed 256-block
@@ -759,7 +1093,7 @@ __global__ __launch_bounds__(512) void kmvsym64_kernel(KmvArgs A, SymPlan P) {
   // one running sum per thread
   __shared__ double pdl[2][kSymCols];
   __shared__ double papl[512];
-  const ConjIn cin = sym_conj_issue(A);
+  const ConjIn<512> cin = sym_conj_issue<512>(A);
   if (A.S != nullptr && A.S->done) return;
   const int64_t b = blockIdx.x;
   const double beta = sym_conj_finish(A, cin, b);
@@ -1371,12 +1705,12 @@ KmvPlan kmv_plan(int64_t m, int64_t n, int prec) {
 // Symmetric schedule for the square product of n rows, or sym = 0 when the
 // rectangular one applies: dp > 64, fewer stages than blocks, or more row
 // blocks than the column slots are sized for.
-static SymPlan sym_plan(int64_t n) {
+static SymPlan sym_plan(int64_t n, int grid = kSymGrid) {
   SymPlan sp{};
   sp.nrb = (int)((n + kSymRows - 1) / kSymRows);
   sp.ncs = (int)((n + kSymCols - 1) / kSymCols);
   sp.T = (int64_t)sp.nrb * sp.ncs - (int64_t)sp.nrb * (sp.nrb - 1);
-  sp.grid = kSymGrid;
+  sp.grid = grid;
   sp.rs = 0;
   for (int64_t t = 0; t < sp.nrb; ++t) {
     const int64_t b0 = sym_block_of(sym_pos_start(t, sp.nrb, sp.ncs), sp.grid, sp.T);
@@ -1405,11 +1739,16 @@ static bool sym_applies(int64_t n, int dp, int prec) {
   return nrb * ncs - nrb * (nrb - 1) >= sym_min_stages(prec) * kSymGrid;
 }
 
+// bfloat16 products of dp = 32 and 64 run the four-wave 16x16 kernel on twice
+// as many blocks (two per CU); the others kSymGrid blocks of eight waves
+static bool sym16_applies(int dp, int prec) { return prec == LAKER_BF16 && (dp == 32 || dp == 64); }
+static int sym_grid(int dp, int prec) { return sym16_applies(dp, prec) ? 2 * kSymGrid : kSymGrid; }
+
 KmvPlan kmv_plan_square(int64_t n, int dp, int prec) {
   KmvPlan pl = kmv_plan(n, n, prec);
   if (sym_applies(n, dp, prec)) {
     pl.sym = 1;
-    pl.sp = sym_plan(n);
+    pl.sp = sym_plan(n, sym_grid(dp, prec));
   }
   return pl;
 }
@@ -1418,9 +1757,11 @@ size_t kmv_part_elems(int64_t m, int64_t n) {
   const int64_t rows = n > m ? n : m;
   size_t e = (size_t)kMaxSplit * rows;
   if (sym_applies(n, 64, LAKER_F64)) {   // the loosest threshold
-    const SymPlan sp = sym_plan(n);
-    const size_t es = (size_t)(sp.rs + sp.nrb) * n;
-    if (es > e) e = es;
+    for (int grid : {kSymGrid, 2 * kSymGrid}) {
+      const SymPlan sp = sym_plan(n, grid);
+      const size_t es = (size_t)(sp.rs + sp.nrb) * n;
+      if (es > e) e = es;
+    }
   }
   return e;
 }
@@ -1437,6 +1778,13 @@ hipError_t launch_sym64(int dp, const KmvArgs& A, const SymPlan& sp, hipStream_t
 
 template <int PREC>
 hipError_t launch_sym(int dp, const KmvArgs& A, const SymPlan& sp, hipStream_t st) {
+  // the plan's grid belongs to the kernel's block shape
+  if (sp.grid != sym_grid(dp, PREC)) return hipErrorInvalidValue;
+  if (sym16_applies(dp, PREC)) {
+    if (dp == 32) kmvsym16_kernel<32><<<sp.grid, 256, 0, st>>>(A, sp);
+    else kmvsym16_kernel<64><<<sp.grid, 256, 0, st>>>(A, sp);
+    return hipGetLastError();
+  }
   switch (dp) {
     case 16: kmvsym_kernel<PREC, 16><<<sp.grid, 512, 0, st>>>(A, sp); break;
     case 32: kmvsym_kernel<PREC, 32><<<sp.grid, 512, 0, st>>>(A, sp); break;
