@@ -33,6 +33,9 @@ constexpr int kMaxSplit = 64;   // largest number of column ranges of one produc
 // then one column slot per row block:
 //   part[k n + i]          k < slots(block of i):   row sums of i
 //   part[(rs + I) n + i]   I < row block of i:       transposed sums of i
+// With f32 (the bfloat16 kernel) the slots are float32, same positions in
+// (float*)part: each is a float64 sum rounded once, far inside the bfloat16
+// product's accuracy, and the partials' traffic halves.
 constexpr int kSymRows = 256;
 constexpr int kSymCols = 128;
 constexpr int kSymGrid = 256;
@@ -42,6 +45,7 @@ struct SymPlan {
   int ncs;      // column stages
   int grid;     // blocks of the launch
   int rs;       // row slots (largest count over the row blocks)
+  int f32;      // slots stored as float32
   int64_t T;    // stages
 };
 // row block at position t of the order, and the position of row block I
@@ -72,44 +76,33 @@ int kmv_rows_per_block(int prec);
 // doubles of the partial buffer the products of an (m x n) problem may use
 size_t kmv_part_elems(int64_t m, int64_t n);
 
-// Layout of the partial sums of one product, and their fixed-order sum.
+// Layout of the partial sums of one product, and their fixed-order sum.  The
+// readers take the slot type once per call (float32 slots: sp.f32) and then
+// issue their loads in batches, as for float64 slots.
 struct PartSum {
   int nsplit;
   int sym;
   SymPlan sp;
   // s += part[(first + k) m + i] for k < count, in order; the loads are
   // issued eight at a time so that their latencies overlap
-  __device__ __forceinline__ static void add_run(double& s, const double* __restrict__ part, int64_t m, int64_t i,
+  template <typename PT>
+  __device__ __forceinline__ static void add_run(double& s, const PT* __restrict__ part, int64_t m, int64_t i,
                                                  int64_t first, int64_t count) {
     int64_t k = 0;
     for (; k + 8 <= count; k += 8) {
-      double v[8];
+      PT v[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q) v[q] = part[(first + k + q) * m + i];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) s += v[q];
+      for (int q = 0; q < 8; ++q) s += (double)v[q];
     }
-    for (; k < count; ++k) s += part[(first + k) * m + i];
+    for (; k < count; ++k) s += (double)part[(first + k) * m + i];
   }
-  __device__ __forceinline__ double row(const double* __restrict__ part, int64_t m, int64_t i) const {
-    double s = 0.0;
-    if (!sym) {
-      add_run(s, part, m, i, 0, nsplit);
-      return s;
-    }
-    const int64_t I = i / kSymRows;
-    const int64_t t = sym_pos_of(I, sp.nrb);
-    const int64_t b0 = sym_block_of(sym_pos_start(t, sp.nrb, sp.ncs), sp.grid, sp.T);
-    const int64_t b1 = sym_block_of(sym_pos_start(t + 1, sp.nrb, sp.ncs) - 1, sp.grid, sp.T);
-    add_run(s, part, m, i, 0, b1 - b0 + 1);
-    add_run(s, part, m, i, sp.rs, I);
-    return s;
-  }
-  // the same list of partials of row i (row slots, then column slots), but
-  // only positions q, q + Q, q + 2 Q, ... of it, added in that order
-  __device__ __forceinline__ double row_strided(const double* __restrict__ part, int64_t m, int64_t i, int q,
-                                                int Q) const {
-    int64_t nr = nsplit, cnt = nsplit, c0 = 0;
+  // row slots of row i (count nr) and the offset of its column slots
+  __device__ __forceinline__ void row_list(int64_t i, int64_t& nr, int64_t& cnt, int64_t& c0) const {
+    nr = nsplit;
+    cnt = nsplit;
+    c0 = 0;
     if (sym) {
       const int64_t I = i / kSymRows;
       const int64_t t = sym_pos_of(I, sp.nrb);
@@ -119,48 +112,71 @@ struct PartSum {
       cnt = nr + I;
       c0 = sp.rs - nr;
     }
+  }
+  template <typename PT>
+  __device__ __forceinline__ double row_t(const PT* __restrict__ part, int64_t m, int64_t i) const {
+    double s = 0.0;
+    int64_t nr, cnt, c0;
+    row_list(i, nr, cnt, c0);
+    add_run(s, part, m, i, 0, nr);
+    if (cnt > nr) add_run(s, part, m, i, sp.rs, cnt - nr);
+    return s;
+  }
+  __device__ __forceinline__ double row(const double* __restrict__ part, int64_t m, int64_t i) const {
+    return sym && sp.f32 ? row_t(reinterpret_cast<const float*>(part), m, i) : row_t(part, m, i);
+  }
+  // the same list of partials of row i (row slots, then column slots), but
+  // only positions q, q + Q, q + 2 Q, ... of it, added in that order
+  template <typename PT>
+  __device__ __forceinline__ double row_strided_t(const PT* __restrict__ part, int64_t m, int64_t i, int q,
+                                                  int Q) const {
+    int64_t nr, cnt, c0;
+    row_list(i, nr, cnt, c0);
     double s = 0.0;
     int64_t k = q;
     for (; k + 7 * Q < cnt; k += 8 * Q) {
-      double v[8];
+      PT v[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int64_t kk = k + u * Q;
         v[u] = part[(kk < nr ? kk : c0 + kk) * m + i];
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) s += v[u];
+      for (int u = 0; u < 8; ++u) s += (double)v[u];
     }
-    for (; k < cnt; k += Q) s += part[(k < nr ? k : c0 + k) * m + i];
+    for (; k < cnt; k += Q) s += (double)part[(k < nr ? k : c0 + k) * m + i];
     return s;
+  }
+  __device__ __forceinline__ double row_strided(const double* __restrict__ part, int64_t m, int64_t i, int q,
+                                                int Q) const {
+    return sym && sp.f32 ? row_strided_t(reinterpret_cast<const float*>(part), m, i, q, Q)
+                         : row_strided_t(part, m, i, q, Q);
   }
   // row_strided with all (at most MAXC) of the thread's loads issued at once;
   // the same sum, in the same order; longer lists take row_strided
-  template <int MAXC>
-  __device__ __forceinline__ double row_strided_all(const double* __restrict__ part, int64_t m, int64_t i, int q,
-                                                    int Q) const {
-    int64_t nr = nsplit, cnt = nsplit, c0 = 0;
-    if (sym) {
-      const int64_t I = i / kSymRows;
-      const int64_t t = sym_pos_of(I, sp.nrb);
-      const int64_t b0 = sym_block_of(sym_pos_start(t, sp.nrb, sp.ncs), sp.grid, sp.T);
-      const int64_t b1 = sym_block_of(sym_pos_start(t + 1, sp.nrb, sp.ncs) - 1, sp.grid, sp.T);
-      nr = b1 - b0 + 1;
-      cnt = nr + I;
-      c0 = sp.rs - nr;
-    }
-    if (cnt > q + (int64_t)MAXC * Q) return row_strided(part, m, i, q, Q);
-    double v[MAXC];
+  template <int MAXC, typename PT>
+  __device__ __forceinline__ double row_strided_all_t(const PT* __restrict__ part, int64_t m, int64_t i, int q,
+                                                      int Q) const {
+    int64_t nr, cnt, c0;
+    row_list(i, nr, cnt, c0);
+    if (cnt > q + (int64_t)MAXC * Q) return row_strided_t(part, m, i, q, Q);
+    PT v[MAXC];
 #pragma unroll
     for (int u = 0; u < MAXC; ++u) {
       const int64_t kk = q + (int64_t)u * Q;
-      v[u] = kk < cnt ? part[(kk < nr ? kk : c0 + kk) * m + i] : 0.0;
+      v[u] = kk < cnt ? part[(kk < nr ? kk : c0 + kk) * m + i] : (PT)0;
     }
     double s = 0.0;
 #pragma unroll
     for (int u = 0; u < MAXC; ++u)
-      if (q + (int64_t)u * Q < cnt) s += v[u];
+      if (q + (int64_t)u * Q < cnt) s += (double)v[u];
     return s;
+  }
+  template <int MAXC>
+  __device__ __forceinline__ double row_strided_all(const double* __restrict__ part, int64_t m, int64_t i, int q,
+                                                    int Q) const {
+    return sym && sp.f32 ? row_strided_all_t<MAXC>(reinterpret_cast<const float*>(part), m, i, q, Q)
+                         : row_strided_all_t<MAXC>(part, m, i, q, Q);
   }
 };
 inline PartSum part_sum(const KmvPlan& pl) {

@@ -820,7 +820,8 @@ __global__ __launch_bounds__(256, 2) void kmvsym16_kernel(KmvArgs A, SymPlan P) 
   const int64_t ncs = P.ncs;
   const uint16_t* __restrict__ Q = reinterpret_cast<const uint16_t*>(A.K);
   const unsigned char* __restrict__ Kb = reinterpret_cast<const unsigned char*>(A.K);
-  double* __restrict__ part = A.part;
+  // partial slots in float32 (the plan's f32)
+  float* __restrict__ partf = reinterpret_cast<float*>(A.part);
 
   const int64_t nrb = P.nrb;
   int64_t t0 = 0;
@@ -941,11 +942,12 @@ __global__ __launch_bounds__(256, 2) void kmvsym16_kernel(KmvArgs A, SymPlan P) 
     const int64_t slot = b - sym_block_of(sym_pos_start(sym_pos_of(Icur, nrb), nrb, ncs), P.grid, P.T);
     const int64_t row = Icur * kSymRows + wv * 64 + wrow;
     if (row < n) {
-      part[slot * n + row] = v;
+      const float vf = (float)v;
+      partf[slot * n + row] = vf;
       if (wp) {
         // the block holding the row block's diagonal stage adds lam p_i^2
         const double pr = prl[tid];
-        double s = fma(pr, v, papl[tid]);
+        double s = fma(pr, (double)vf, papl[tid]);
         if (slot == 0) s = fma(A.lam * pr, pr, s);
         papl[tid] = s;
       }
@@ -961,8 +963,10 @@ __global__ __launch_bounds__(256, 2) void kmvsym16_kernel(KmvArgs A, SymPlan P) 
     v += __shfl_xor(v, 1, 64);
     const int64_t col = J * KT + ct;
     if (hf == 0 && col < n) {
-      part[(P.rs + I) * n + col] = v;
-      if (wp) papl[tid] = fma(pdl[ring][ct], v, papl[tid]);
+      // float32 slot (the plan's f32); p^T A p takes the stored value
+      const float vf = (float)v;
+      partf[(P.rs + I) * n + col] = vf;
+      if (wp) papl[tid] = fma(pdl[ring][ct], (double)vf, papl[tid]);
     }
   };
 
@@ -1749,6 +1753,7 @@ KmvPlan kmv_plan_square(int64_t n, int dp, int prec) {
   if (sym_applies(n, dp, prec)) {
     pl.sym = 1;
     pl.sp = sym_plan(n, sym_grid(dp, prec));
+    pl.sp.f32 = sym16_applies(dp, prec) ? 1 : 0;
   }
   return pl;
 }

@@ -116,13 +116,13 @@ __global__ __launch_bounds__(kThreads) void lr_t_finish_kernel(const double* __r
   lr_t_finish_body(blockIdx.x, gridDim.x, tpart, nb, nrp, t, S, rrp, grr);
 }
 
-template <typename MT>
+template <typename MT, int MAXR>
 __global__ __launch_bounds__(kThreads) void lr_apply_kernel(const MT* __restrict__ Bt, const double* __restrict__ t,
                                                             const double* __restrict__ r, double* __restrict__ theta,
                                                             int64_t n, int nrp, const double* __restrict__ c0p,
                                                             const double* __restrict__ dinv, const PcgScalars* S,
                                                             double* __restrict__ rzp) {
-  lr_apply_body<MT>(blockIdx.x, gridDim.x, Bt, t, r, theta, n, nrp, c0p, dinv, S, rzp);
+  lr_apply_body<MT, MAXR>(blockIdx.x, gridDim.x, Bt, t, r, theta, n, nrp, c0p, dinv, S, rzp);
 }
 
 template <typename MT>
@@ -246,8 +246,14 @@ laker_status enqueue_lowrank(const PrecondView& P, const double* r, double* thet
   }
   lr_t_finish_kernel<<<(P.nrp + 15) / 16, kThreads, 0, st>>>(tpart, nb, P.nrp, t, S, rrp, grr);
   LK_CHECK_LAUNCH();
-  lr_apply_kernel<MT><<<(unsigned)apply_blocks(n), kThreads, 0, st>>>((const MT*)P.Bt, t, r, theta, n, P.nrp, P.c0p,
-                                                                      (const double*)P.dinv, S, rzp);
+  // (ranks up to 64, the learned preconditioner's, keep more rows in flight)
+  if (P.nrp <= 64)
+    lr_apply_kernel<MT, 64><<<(unsigned)apply_blocks(n), kThreads, 0, st>>>((const MT*)P.Bt, t, r, theta, n, P.nrp,
+                                                                            P.c0p, (const double*)P.dinv, S, rzp);
+  else
+    lr_apply_kernel<MT, kMaxNr><<<(unsigned)apply_blocks(n), kThreads, 0, st>>>((const MT*)P.Bt, t, r, theta, n,
+                                                                                P.nrp, P.c0p, (const double*)P.dinv,
+                                                                                S, rzp);
   LK_CHECK_LAUNCH();
   return LAKER_OK;
 }

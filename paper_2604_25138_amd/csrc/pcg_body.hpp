@@ -485,7 +485,7 @@ __device__ __forceinline__ void lr_t_finish_body(int blk, int nblk, const double
 // theta = c r + Bt t (c = c0, or dinv_i for a diagonal-plus-low-rank
 // preconditioner): 16 lanes per row (four rows per wave), 16-byte loads,
 // t in LDS; partials of r^T theta.
-template <typename MT>
+template <typename MT, int MAXR = kMaxNr>
 __device__ __forceinline__ void lr_apply_body(int blk, int nblk, const MT* __restrict__ Bt, const double* __restrict__ t,
                                                             const double* __restrict__ r, double* __restrict__ theta,
                                                             int64_t n, int nrp, const double* __restrict__ c0p,
@@ -501,53 +501,57 @@ __device__ __forceinline__ void lr_apply_body(int blk, int nblk, const MT* __res
   const int sub = threadIdx.x & 15;
   const int rl = threadIdx.x >> 4;                  // row slot within the block (16 per pass)
   const int nvec = nrp / VEC;
+  // (ranks up to MAXR; a pass issues MAXV loads per thread)
+  constexpr int MAXV = (MAXR + VEC * 16 - 1) / (VEC * 16);
+  using VT = typename std::conditional<VEC == 4, float4, double2>::type;
+  // UNR passes at a time, so that about four row loads per thread are in
+  // flight (at rank 64 one pass issues a single load, too few to stream Bt);
+  // all of them are issued before the first use, and the passes are then
+  // finished in order, as one at a time would
+  constexpr int UNR = MAXV >= 4 ? 1 : 4 / MAXV;
+  const int64_t stride = (int64_t)nblk * 16;
   double rz = 0.0;
-  for (int64_t i0 = (int64_t)blk * 16; i0 < n; i0 += (int64_t)nblk * 16) {
-    const int64_t i = i0 + rl;
-    double acc = 0.0;
-    if (i < n) {
-      // all of the lane's loads are issued before the first use
-      constexpr int MAXV = kMaxNr / VEC / 16;
+  for (int64_t i0 = (int64_t)blk * 16; i0 < n; i0 += stride * UNR) {
+    VT x[UNR][MAXV];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int64_t i = i0 + u * stride + rl;
       const MT* row = Bt + i * nrp;
-      if constexpr (VEC == 4) {
-        float4 x[MAXV];
 #pragma unroll
-        for (int j = 0; j < MAXV; ++j)
-          if (sub + 16 * j < nvec) x[j] = *reinterpret_cast<const float4*>(row + 4 * (sub + 16 * j));
+      for (int j = 0; j < MAXV; ++j)
+        if (i < n && sub + 16 * j < nvec) x[u][j] = *reinterpret_cast<const VT*>(row + VEC * (sub + 16 * j));
+    }
 #pragma unroll
-        for (int j = 0; j < MAXV; ++j) {
-          if (sub + 16 * j < nvec) {
-            const int v = sub + 16 * j;
-            acc = fma((double)x[j].x, ts[4 * v + 0], acc);
-            acc = fma((double)x[j].y, ts[4 * v + 1], acc);
-            acc = fma((double)x[j].z, ts[4 * v + 2], acc);
-            acc = fma((double)x[j].w, ts[4 * v + 3], acc);
-          }
-        }
-      } else {
-        double2 x[MAXV];
-#pragma unroll
-        for (int j = 0; j < MAXV; ++j)
-          if (sub + 16 * j < nvec) x[j] = *reinterpret_cast<const double2*>(row + 2 * (sub + 16 * j));
+    for (int u = 0; u < UNR; ++u) {
+      const int64_t i = i0 + u * stride + rl;
+      double acc = 0.0;
+      if (i < n) {
 #pragma unroll
         for (int j = 0; j < MAXV; ++j) {
           if (sub + 16 * j < nvec) {
             const int v = sub + 16 * j;
-            acc = fma(x[j].x, ts[2 * v + 0], acc);
-            acc = fma(x[j].y, ts[2 * v + 1], acc);
+            if constexpr (VEC == 4) {
+              acc = fma((double)x[u][j].x, ts[4 * v + 0], acc);
+              acc = fma((double)x[u][j].y, ts[4 * v + 1], acc);
+              acc = fma((double)x[u][j].z, ts[4 * v + 2], acc);
+              acc = fma((double)x[u][j].w, ts[4 * v + 3], acc);
+            } else {
+              acc = fma(x[u][j].x, ts[2 * v + 0], acc);
+              acc = fma(x[u][j].y, ts[2 * v + 1], acc);
+            }
           }
         }
       }
-    }
-    acc += __shfl_xor(acc, 1, 64);
-    acc += __shfl_xor(acc, 2, 64);
-    acc += __shfl_xor(acc, 4, 64);
-    acc += __shfl_xor(acc, 8, 64);
-    if (sub == 0 && i < n) {
-      const double ri = r[i];
-      const double th = fma(dinv != nullptr ? dinv[i] : c0, ri, acc);
-      theta[i] = th;
-      rz += ri * th;
+      acc += __shfl_xor(acc, 1, 64);
+      acc += __shfl_xor(acc, 2, 64);
+      acc += __shfl_xor(acc, 4, 64);
+      acc += __shfl_xor(acc, 8, 64);
+      if (sub == 0 && i < n) {
+        const double ri = r[i];
+        const double th = fma(dinv != nullptr ? dinv[i] : c0, ri, acc);
+        theta[i] = th;
+        rz += ri * th;
+      }
     }
   }
   rz = block_sum(rz, sh);
