@@ -71,9 +71,9 @@ TRAIN_N, TRAIN_MAPS, TRAIN_EPOCHS, TRAIN_PROBES = 4096, 96, 30, 128
 # instructions, and the 157.3 TFLOP/s fp32 vector figure counts them (128
 # lanes' worth); 64 lanes is the issue width of the 78.6 TFLOP/s fp64 vector
 # figure.  exp2 (v_exp_f32) issues at half that rate and takes 2 slots.  Both
-# were measured by calib/valu_rates.hip: 57.6 lane-FMA and 29.0 lane-exp2 per CU
-# per clock at 8 waves per SIMD, exp2 + 2 FMA at 15.5 per CU per clock (the two
-# do not overlap).
+# were measured by calib/valu_rates.hip: 57-58 lane-FMA and 28-30 lane-exp2 per
+# CU per nominal clock at 8 waves per SIMD, exp2 + 2 FMA at 15.3-15.5 (the two
+# do not overlap); all ~11% under 64 / 32, the clock the busy chip holds.
 PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
 EXP2_SLOTS = 2.0
 PEAK_FP32_MFMA_TFLOPS = 157.3
