@@ -12,7 +12,9 @@ sampled rows the oracle computes one by one.  Tolerances:
   * bfloat16 products: compared with the oracle evaluated on the same
     bfloat16-rounded pre-scaled rows (G_ij = 2^{<e^_i, e^_j>}), 2e-6 relative
     (bfloat16 products are exact in float32; float32 MFMA accumulation over d
-    terms and exp2 as above);
+    terms and exp2 as above; the square products of dp = 32, 64 store their
+    partial sums in float32, one rounding of each, 2^-24 of the magnitude at
+    most in all);
   * float64 solves: alpha within 1e-10 (relative) of the Cholesky solution when
     PCG is run to 1e-12.
 """
@@ -122,6 +124,24 @@ def test_matvec_symmetric_schedule_bf16_sampled_rows(n, d):
     p = np.random.default_rng(n).normal(size=n)
     w = L().kernel_matvec(_gp(pr), torch.tensor(p, device=DEV), "bf16").cpu().numpy()
     rng = np.random.default_rng(n + 1)
+    rows = np.unique(np.r_[np.arange(0, n, 256), np.minimum(np.arange(255, n + 255, 256), n - 1),
+                           rng.choice(n, 64, replace=False)])
+    Eb = _bf16_rows(pr.E, pr.scale)
+    refb = O.matvec_rows(Eb, np.log(2.0), pr.lam, p, rows)
+    magb = np.array([np.exp2(Eb @ Eb[i]) @ np.abs(p) + pr.lam * abs(p[i]) for i in rows])
+    assert (np.abs(w[rows] - refb) / magb).max() <= 2e-6
+
+
+def test_matvec_symmetric_schedule_bf16_full_size():
+    """The bench's map size (65536 sites, d = 64, lambda = 1e-5) plus a ragged
+    row block: the four-wave bfloat16 kernel with float32 partials, first and
+    last row of every row block and 64 random rows against the oracle's
+    one-row evaluation on the same bfloat16-rounded rows."""
+    n, d = 65536 + 77, 64
+    pr = make_problem(n, d, 1e-5, n_tx=4, seed=5)
+    p = np.random.default_rng(7).normal(size=n)
+    w = L().kernel_matvec(_gp(pr), torch.tensor(p, device=DEV), "bf16").cpu().numpy()
+    rng = np.random.default_rng(8)
     rows = np.unique(np.r_[np.arange(0, n, 256), np.minimum(np.arange(255, n + 255, 256), n - 1),
                            rng.choice(n, 64, replace=False)])
     Eb = _bf16_rows(pr.E, pr.scale)
