@@ -242,6 +242,8 @@ size_t plan_batch_ws(int count, const int64_t* n, int d, size_t* offsets, void* 
   w.run_op = c.take<int>(count);
   w.hs = c.take<PcgScalars>(count);
   w.misc = c.take<double>((size_t)2 * count);
+  w.plans = c.take<SymPlan>(count);
+  w.sym_list = c.take<int>(count);
   w.total = c.bytes();
   if (out) *out = w;
   return w.total;
@@ -395,11 +397,14 @@ laker_status pcg_batch(int count, const Problem* pbs, const SolveWs* wss, const 
   const int kPrecOrder[3] = {LAKER_BF16, LAKER_F32, LAKER_F64};
   std::vector<int> pm(count, prec);
   int grp_off[3] = {0, 0, 0}, grp_nt[3] = {0, 0, 0};
-  // maps whose square product takes the symmetric schedule: their products are
-  // launched one map at a time with the single solver's kernel (and plan), the
-  // other maps share the tile table
+  // maps whose square product takes the symmetric schedule run the single
+  // solver's kernel and plan: the bfloat16 ones of dp = 32, 64 all in one
+  // launch (grid row = map), the others one map at a time; the other maps
+  // share the tile table
   std::vector<int> sym_in[3];
   std::vector<KmvPlan> sq_in(count);
+  std::vector<SymPlan> sym_plans(count);
+  const bool sym_batch = kmv_sym16(dp, LAKER_BF16);
   // arguments of every map; tiles only for the maps in `members`
   auto rebuild_inner = [&](const std::vector<int>& members) -> laker_status {
     std::vector<int> in_list(count, 0);
@@ -421,6 +426,11 @@ laker_status pcg_batch(int count, const Problem* pbs, const SolveWs* wss, const 
         if (sq_in[b].sym) {
           if (in_list[b]) sym_in[q].push_back(b);
           hd[b].ps = part_sum(sq_in[b]);
+          // (the fields kmv_run fills in, for the batched launch)
+          A.cps = sq_in[b].cols_per_split;
+          A.nsplit = sq_in[b].nsplit;
+          A.ps = part_sum(sq_in[b]);
+          sym_plans[b] = sq_in[b].sp;
           A.pap = wss[b].papp;
           A.lam = pbs[b].lambda;
           if (lowrank) {
@@ -444,6 +454,11 @@ laker_status pcg_batch(int count, const Problem* pbs, const SolveWs* wss, const 
       tl_all.insert(tl_all.end(), tl.begin(), tl.end());
     }
     LK_TRY(hipMemcpyAsync(bw.inner, hin.data(), sizeof(KmvArgs) * count, hipMemcpyHostToDevice, st));
+    if (sym_batch && !sym_in[0].empty()) {
+      LK_TRY(hipMemcpyAsync(bw.plans, sym_plans.data(), sizeof(SymPlan) * count, hipMemcpyHostToDevice, st));
+      LK_TRY(hipMemcpyAsync(bw.sym_list, sym_in[0].data(), sizeof(int) * sym_in[0].size(), hipMemcpyHostToDevice,
+                            st));
+    }
     if (!tl_all.empty())
       LK_TRY(hipMemcpyAsync(bw.tiles_in, tl_all.data(), sizeof(int) * tl_all.size(), hipMemcpyHostToDevice, st));
     return LAKER_OK;
@@ -500,7 +515,10 @@ laker_status pcg_batch(int count, const Problem* pbs, const SolveWs* wss, const 
       if (grp_nt[q] > 0)
         LK_TRY(kmv_run_batch(kPrecOrder[q], dp, count, bw.inner, bw.tiles_in + 3 * (int64_t)grp_off[q], grp_nt[q],
                              false, max_n, s2));
-      for (int b : sym_in[q]) LK_TRY(kmv_run(kPrecOrder[q], dp, sq_in[b], hin[b], s2));
+      if (q == 0 && sym_batch)
+        LK_TRY(kmv_run_sym16_batch(dp, (int)sym_in[0].size(), bw.inner, bw.plans, bw.sym_list, s2));
+      else
+        for (int b : sym_in[q]) LK_TRY(kmv_run(kPrecOrder[q], dp, sq_in[b], hin[b], s2));
     }
     b_ap_kernel<<<dim3(gx, nit), kThreads, 0, s2>>>(bw.desc, bw.run_it);
     LK_CHECK_LAUNCH();

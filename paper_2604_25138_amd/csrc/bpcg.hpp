@@ -56,6 +56,8 @@ struct BatchWs {
   int* run_op;           // maps of the current host-side operation
   PcgScalars* hs;        // gathered scalars of every map
   double* misc;          // gathered outer residual norms (2 per map)
+  SymPlan* plans;        // square plans of the inner products (one per map)
+  int* sym_list;         // maps whose inner products share the symmetric batched launch
   size_t total;
 };
 

@@ -245,6 +245,13 @@ hipError_t kmat_build(int dp, const double* e64, int64_t n, int prec, void* out,
 // problem whose mode is 1 (max_m: the largest row count).
 hipError_t kmv_run_batch(int prec, int dp, int count, const KmvArgs* As_dev, const int* tiles_dev, int ntiles,
                          bool finish, int64_t max_m, hipStream_t st);
+// Symmetric bfloat16 products (mode 0) of several maps in one launch: maps
+// list_dev[0 .. count) with arguments As_dev[map] and square plans Ps_dev[map]
+// (kmv_plan_square(n, dp, LAKER_BF16).sp, symmetric); kmv_sym16(dp, prec): the
+// precisions and widths whose symmetric products this launch covers.
+bool kmv_sym16(int dp, int prec);
+hipError_t kmv_run_sym16_batch(int dp, int count, const KmvArgs* As_dev, const SymPlan* Ps_dev,
+                               const int* list_dev, hipStream_t st);
 
 // ---- multi right-hand-side product and the fit (fit.hip) ----
 

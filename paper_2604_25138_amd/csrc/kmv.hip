@@ -786,8 +786,10 @@ __device__ __forceinline__ v4f tile16_bf16(const FragB16x<DP>& a, const FragB16x
   return c;
 }
 
+// (the body of the single-map and the batched launch; b: the block's index
+// in the map's grid)
 template <int DP>
-__global__ __launch_bounds__(256, 2) void kmvsym16_kernel(KmvArgs A, SymPlan P) {
+__device__ __forceinline__ void kmvsym16_body(const KmvArgs& A, const SymPlan& P, const int64_t b) {
   using St = SymStage<LAKER_BF16, DP>;
   using Frag = FragB16x<DP>;
   constexpr int KT = St::KT;
@@ -805,7 +807,6 @@ __global__ __launch_bounds__(256, 2) void kmvsym16_kernel(KmvArgs A, SymPlan P) 
   __shared__ double papl[NT];
   const ConjIn<NT> cin = sym_conj_issue<NT>(A);
   if (A.S != nullptr && A.S->done) return;
-  const int64_t b = blockIdx.x;
   const double* __restrict__ th = A.theta;
   const double* __restrict__ p = A.p;
   double beta = 0.0;
@@ -1076,6 +1077,23 @@ __global__ __launch_bounds__(256, 2) void kmvsym16_kernel(KmvArgs A, SymPlan P) 
   if (Ip >= 0) flush_cols((int)((L - 1) & 1), rp, Ip, Jp);
   flush_rows();
   if (wp) sym_pap_store<NT>(papl, A.pap + b);
+}
+
+template <int DP>
+__global__ __launch_bounds__(256, 2) void kmvsym16_kernel(KmvArgs A, SymPlan P) {
+  kmvsym16_body<DP>(A, P, blockIdx.x);
+}
+
+// Several maps' products in one launch (the batched solver): grid row y is
+// map list[y], with its arguments As[map] and plan Ps[map] (every plan of this
+// kernel has the same grid); each block does what it does in the map's own
+// launch, so the results are bitwise those of the single launches.
+template <int DP>
+__global__ __launch_bounds__(256, 2) void kmvsym16_batch_kernel(const KmvArgs* __restrict__ As,
+                                                               const SymPlan* __restrict__ Ps,
+                                                               const int* __restrict__ list) {
+  const int m = list[blockIdx.y];
+  kmvsym16_body<DP>(As[m], Ps[m], blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1747,6 +1765,18 @@ static bool sym_applies(int64_t n, int dp, int prec) {
 // as many blocks (two per CU); the others kSymGrid blocks of eight waves
 static bool sym16_applies(int dp, int prec) { return prec == LAKER_BF16 && (dp == 32 || dp == 64); }
 static int sym_grid(int dp, int prec) { return sym16_applies(dp, prec) ? 2 * kSymGrid : kSymGrid; }
+
+bool kmv_sym16(int dp, int prec) { return sym16_applies(dp, prec); }
+
+hipError_t kmv_run_sym16_batch(int dp, int count, const KmvArgs* As_dev, const SymPlan* Ps_dev,
+                               const int* list_dev, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  if (!sym16_applies(dp, LAKER_BF16) || count > 65535) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)(2 * kSymGrid), (unsigned)count);
+  if (dp == 32) kmvsym16_batch_kernel<32><<<grid, 256, 0, st>>>(As_dev, Ps_dev, list_dev);
+  else kmvsym16_batch_kernel<64><<<grid, 256, 0, st>>>(As_dev, Ps_dev, list_dev);
+  return hipGetLastError();
+}
 
 KmvPlan kmv_plan_square(int64_t n, int dp, int prec) {
   KmvPlan pl = kmv_plan(n, n, prec);
