@@ -63,8 +63,10 @@ INNER_CAP = 30
 STALL_WINDOW = 2000
 
 # training set of the learned preconditioner: maps of TRAIN_N sites with
-# lambda log-uniform in [1e-5, 1e-2] and 1..8 transmitters
-TRAIN_N, TRAIN_MAPS, TRAIN_EPOCHS, TRAIN_PROBES = 4096, 96, 30, 128
+# lambda log-uniform in [1e-5, 1e-2] and 1..8 transmitters (inner iterations
+# of the 65536-site solve: 96 maps x 30 epochs 4239, 192 x 60 4056,
+# 384 x 60 4080, 384 x 120 4122)
+TRAIN_N, TRAIN_MAPS, TRAIN_EPOCHS, TRAIN_PROBES = 4096, 192, 60, 128
 
 # vector ALU issue rate: 256 CUs x 64 lanes x 2.4 GHz unpacked float32
 # multiply-adds, one slot each.  The library is built without packed float32
