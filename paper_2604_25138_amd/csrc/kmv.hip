@@ -474,7 +474,7 @@ __global__ __launch_bounds__(512) void kmvsym_kernel(KmvArgs A, SymPlan P) {
 
   // ---- LDS staging of the key rows of column stage J (as the rectangular kernel)
   u32x4 stg[St::PER_T];
-  double stp = 0.0;
+  double stp = 0.0, stt = 0.0;
   bool stv = false;
   // Waves 0-3 move the key rows (global -> registers -> LDS) and waves 2-3 add
   // up the column sums: in a stage the second wave of each SIMD (waves 4-7)
@@ -508,7 +508,11 @@ __global__ __launch_bounds__(512) void kmvsym_kernel(KmvArgs A, SymPlan P) {
     if (tid < KT) {
       const int64_t kj = J * KT + tid;
       stv = kj < n;
-      stp = pval(kj < n ? kj : n - 1);
+      // raw entries: the conjugation waits for the store, a stage later, so
+      // that no wait on these loads (and the key rows in flight) comes here
+      const int64_t jj = kj < n ? kj : n - 1;
+      stp = p[jj];
+      if (th != nullptr) stt = th[jj];
     }
   };
   auto fetch = [&](int64_t J) {
@@ -528,8 +532,9 @@ __global__ __launch_bounds__(512) void kmvsym_kernel(KmvArgs A, SymPlan P) {
       }
     }
     if (tid < KT) {
-      reinterpret_cast<float*>(&lds[buf][KT * St::PITCH])[tid] = stv ? (float)stp : 0.f;
-      if (wp) pdl[ring][tid] = stv ? stp : 0.0;
+      const double w = th != nullptr ? fma(beta, stp, stt) : stp;
+      reinterpret_cast<float*>(&lds[buf][KT * St::PITCH])[tid] = stv ? (float)w : 0.f;
+      if (wp) pdl[ring][tid] = stv ? w : 0.0;
     }
   };
   auto advance = [&](int64_t& t, int64_t& I, int64_t& J) {
@@ -549,20 +554,29 @@ __global__ __launch_bounds__(512) void kmvsym_kernel(KmvArgs A, SymPlan P) {
   // query fragment and row weights of row block I; issued at the end of the
   // stage before the row block changes (their last readers are that stage's
   // products), so that the loads complete behind its barrier
+  // (every load is issued before the first use: rows past n read row n - 1
+  // and are masked afterwards)
   auto load_rows = [&](int64_t I) {
     const int64_t row0 = I * kSymRows + wv * 32;
     int64_t qi = row0 + c;
     if (qi > n - 1) qi = n - 1;
     a.load(Q, qi, h);
+    const int rn = c >> 1;
+    const int64_t rowp = row0 + (rn >> 2) * 8 + h * 4 + (rn & 3);
+    double pr[17], tr[17];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int64_t row = row0 + (r >> 2) * 8 + h * 4 + (r & 3);
-      rw[r] = row < n ? (float)pval(row) : 0.f;
+    for (int r = 0; r < 17; ++r) {
+      const int64_t row = r < 16 ? row0 + (r >> 2) * 8 + h * 4 + (r & 3) : rowp;
+      const int64_t rr = row < n ? row : n - 1;
+      pr[r] = p[rr];
+      tr[r] = th != nullptr ? th[rr] : 0.0;
     }
-    if (wp) {
-      const int r = c >> 1;
-      const int64_t row = row0 + (r >> 2) * 8 + h * 4 + (r & 3);
-      prn = row < n ? pval(row) : 0.0;
+#pragma unroll
+    for (int r = 0; r < 17; ++r) {
+      const int64_t row = r < 16 ? row0 + (r >> 2) * 8 + h * 4 + (r & 3) : rowp;
+      const double v = row < n ? (th != nullptr ? fma(beta, pr[r], tr[r]) : pr[r]) : 0.0;
+      if (r < 16) rw[r] = (float)v;
+      else if (wp) prn = v;
     }
   };
   auto open_rows = [&](int64_t I) {
@@ -832,7 +846,7 @@ __device__ __forceinline__ void kmvsym16_body(const KmvArgs& A, const SymPlan& P
 
   // ---- LDS staging of the key rows of column stage J (every thread)
   u32x4 stg[St::PER_T];
-  double stp = 0.0;
+  double stp = 0.0, stt = 0.0;
   bool stv = false;
   auto fetch_keys = [&](int64_t J) {
     const int64_t js = J * KT;
@@ -861,7 +875,11 @@ __device__ __forceinline__ void kmvsym16_body(const KmvArgs& A, const SymPlan& P
     if (tid < KT) {
       const int64_t kj = J * KT + tid;
       stv = kj < n;
-      stp = pval(kj < n ? kj : n - 1);
+      // raw entries: the conjugation waits for the store, a stage later, so
+      // that no wait on these loads (and the key rows in flight) comes here
+      const int64_t jj = kj < n ? kj : n - 1;
+      stp = p[jj];
+      if (th != nullptr) stt = th[jj];
     }
   };
   auto fetch = [&](int64_t J) {
@@ -879,8 +897,9 @@ __device__ __forceinline__ void kmvsym16_body(const KmvArgs& A, const SymPlan& P
       }
     }
     if (tid < KT) {
-      reinterpret_cast<float*>(&lds[buf][KT * St::PITCH])[tid] = stv ? (float)stp : 0.f;
-      if (wp) pdl[ring][tid] = stv ? stp : 0.0;
+      const double w = th != nullptr ? fma(beta, stp, stt) : stp;
+      reinterpret_cast<float*>(&lds[buf][KT * St::PITCH])[tid] = stv ? (float)w : 0.f;
+      if (wp) pdl[ring][tid] = stv ? w : 0.0;
     }
   };
   auto advance = [&](int64_t& t, int64_t& I, int64_t& J) {
@@ -901,20 +920,31 @@ __device__ __forceinline__ void kmvsym16_body(const KmvArgs& A, const SymPlan& P
   // the row this lane writes after the row-sum exchange: value j = q of its
   // row group, i.e. row tile q / 4, row 4 g + q % 4 of it
   const int wrow = 16 * (q >> 2) + 4 * g + (q & 3);
+  // (every load is issued before the first use: rows past n read row n - 1
+  // and are masked afterwards)
   auto load_rows = [&](int64_t I) {
     const int64_t row0 = I * kSymRows + wv * 64;
+    double pr[4 * RT + 1], tr[4 * RT + 1];
 #pragma unroll
     for (int k = 0; k < RT; ++k) {
       int64_t qi = row0 + 16 * k + q;
       if (qi > n - 1) qi = n - 1;
       a[k].load(Q, qi, g);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int64_t row = row0 + 16 * k + 4 * g + i;
-        rw[k][i] = row < n ? (float)pval(row) : 0.f;
-      }
     }
-    if (wp) prn = row0 + wrow < n ? pval(row0 + wrow) : 0.0;
+#pragma unroll
+    for (int j = 0; j <= 4 * RT; ++j) {
+      const int64_t row = j < 4 * RT ? row0 + 16 * (j >> 2) + 4 * g + (j & 3) : row0 + wrow;
+      const int64_t rr = row < n ? row : n - 1;
+      pr[j] = p[rr];
+      tr[j] = th != nullptr ? th[rr] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j <= 4 * RT; ++j) {
+      const int64_t row = j < 4 * RT ? row0 + 16 * (j >> 2) + 4 * g + (j & 3) : row0 + wrow;
+      const double v = row < n ? (th != nullptr ? fma(beta, pr[j], tr[j]) : pr[j]) : 0.0;
+      if (j < 4 * RT) rw[j >> 2][j & 3] = (float)v;
+      else if (wp) prn = v;
+    }
   };
   auto open_rows = [&](int64_t I) {
 #pragma unroll
