@@ -810,7 +810,9 @@ __device__ __forceinline__ void kmvsym16_body(const KmvArgs& A, const SymPlan& P
   constexpr int NT = 256;
   constexpr int RT = 4;                 // 16-row tiles per wave
   constexpr int CROWS = 16;             // column-sum rows: four row groups of four waves
-  constexpr int CPITCH = KT + 32;       // (consecutive rows start 32 banks apart)
+  // (rows 16 banks apart: the four row groups of a wave write disjoint banks,
+  // and rows two apart -- the halves of a column's flush -- 32 banks apart)
+  constexpr int CPITCH = KT + 16;
   static_assert(St::STAGERS == NT, "every thread stages key rows");
   __shared__ __attribute__((aligned(16))) unsigned char lds[2][St::BYTES];
   __shared__ float colbuf[2][CROWS * CPITCH];
@@ -985,12 +987,13 @@ __device__ __forceinline__ void kmvsym16_body(const KmvArgs& A, const SymPlan& P
     }
   };
   // column sums of the stage held in colbuf[buf] (16 rows, fixed order): two
-  // adjacent lanes per column, each adding eight rows, then each other's
+  // adjacent lanes per column, one adding rows 0, 1, 4, 5, ..., the other
+  // rows 2, 3, 6, 7, ..., then each other's
   auto flush_cols = [&](int buf, int ring, int64_t I, int64_t J) {
     const int ct = tid >> 1, hf = tid & 1;
     double v = 0.0;
 #pragma unroll
-    for (int k = 0; k < CROWS / 2; ++k) v += (double)colbuf[buf][(hf * (CROWS / 2) + k) * CPITCH + ct];
+    for (int k = 0; k < CROWS / 2; ++k) v += (double)colbuf[buf][((k >> 1) * 4 + hf * 2 + (k & 1)) * CPITCH + ct];
     v += __shfl_xor(v, 1, 64);
     const int64_t col = J * KT + ct;
     if (hf == 0 && col < n) {
@@ -1029,7 +1032,8 @@ __device__ __forceinline__ void kmvsym16_body(const KmvArgs& A, const SymPlan& P
       const float pvf = pv[v];
       // (first terms are products, not multiply-adds onto zero)
       auto madd = [&](float x, float y, float acc0, bool first) { return first ? x * y : fmaf(x, y, acc0); };
-      float gk[RT];
+      // column sums in two chains: row tiles 0, 1 and row tiles 2, 3
+      float gk[2];
 #pragma unroll
       for (int k = 0; k < RT; ++k) {
         const v4f sc = tile16_bf16<DP>(a[k], bv);
@@ -1037,10 +1041,10 @@ __device__ __forceinline__ void kmvsym16_body(const KmvArgs& A, const SymPlan& P
         for (int i = 0; i < 4; ++i) {
           const float t = kexp2(sc[i]);
           accf[k][i] = madd(t, pvf, accf[k][i], v == 0);
-          if constexpr (MIR) gk[k] = madd(t, rw[k][i], gk[k], i == 0);
+          if constexpr (MIR) gk[k >> 1] = madd(t, rw[k][i], gk[k >> 1], (k & 1) == 0 && i == 0);
         }
       }
-      if constexpr (MIR) colbuf[buf][(wv * 4 + g) * CPITCH + v * 16 + q] = (gk[0] + gk[1]) + (gk[2] + gk[3]);
+      if constexpr (MIR) colbuf[buf][(wv * 4 + g) * CPITCH + v * 16 + q] = gk[0] + gk[1];
     }
 #pragma unroll
     for (int k = 0; k < RT; ++k)
