@@ -9,7 +9,8 @@
 //   * v_exp_f32 (the hardware exp2),
 //   * exp2 followed by 1, 2 or 4 dependent multiply-adds (do they overlap?),
 //   * 32x32x16 bfloat16 MFMA alone and with 16 / 32 exp2 per 4 MFMA in the
-//     same wave (does the matrix core run beside the vector ALU?),
+//     same wave (does the matrix core run beside the vector ALU?), and the
+//     same for eight 16x16x32 MFMA (the same flops in twice the instructions),
 // at 1, 2, 4 and 8 waves per SIMD.  Each thread keeps 8 independent chains so
 // that latency does not hide the issue rate, and writes one float at the end.
 //
@@ -107,6 +108,32 @@ __global__ __launch_bounds__(kThreads) void mfma_exp_rate(float* out, int iters)
   out[blockIdx.x * blockDim.x + threadIdx.x] = s;
 }
 
+// the same flops as eight independent 16x16x32 bfloat16 MFMA (the symmetric
+// product's tile), with NE exp2 per iteration
+typedef float v4f __attribute__((ext_vector_type(4)));
+template <int NE>
+__global__ __launch_bounds__(kThreads) void mfma16_exp_rate(float* out, int iters) {
+  v8bf av, bv;
+  for (int j = 0; j < 8; ++j) {
+    av[j] = (__bf16)(threadIdx.x * 1e-3f);
+    bv[j] = (__bf16)(j * 1e-3f);
+  }
+  v4f c[8];
+  for (int k = 0; k < 8; ++k) c[k] = v4f{0.f, 0.f, 0.f, 0.f};
+  float x[16];
+  for (int j = 0; j < 16; ++j) x[j] = threadIdx.x * 1e-3f + j * 0.01f;
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) c[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c[k], 0, 0, 0);
+#pragma unroll
+    for (int e = 0; e < NE; ++e) x[e % 16] = __builtin_amdgcn_exp2f(-x[e % 16]);
+  }
+  float s = 0.f;
+  for (int k = 0; k < 8; ++k) s += c[k][0] + c[k][1] + c[k][2] + c[k][3];
+  for (int j = 0; j < 16; ++j) s += x[j];
+  out[blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
 int main() {
   int cus = 0, khz = 0;
   CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0));
@@ -149,6 +176,13 @@ int main() {
         "flop");
     run("bf16 MFMA + 32 exp2", [&] { mfma_exp_rate<32><<<blocks, kThreads>>>(out, iters); }, 4.0 * 32768 / 64,
         "flop");
+    // eight 16x16x32 MFMA: 8 * 16384 flops per wave, the same as four 32x32x16
+    run("bf16 MFMA 16x16x32", [&] { mfma16_exp_rate<0><<<blocks, kThreads>>>(out, iters); }, 8.0 * 16384 / 64,
+        "flop");
+    run("bf16 MFMA 16x16x32 + 16 exp2", [&] { mfma16_exp_rate<16><<<blocks, kThreads>>>(out, iters); },
+        8.0 * 16384 / 64, "flop");
+    run("bf16 MFMA 16x16x32 + 32 exp2", [&] { mfma16_exp_rate<32><<<blocks, kThreads>>>(out, iters); },
+        8.0 * 16384 / 64, "flop");
     CHECK(hipFree(out));
   }
   return 0;
