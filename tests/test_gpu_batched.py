@@ -128,12 +128,14 @@ def test_batch_with_symmetric_maps_is_bitwise_equal_to_single_solves():
         assert stats[b].iters == s1.iters and torch.equal(alphas[b], a1), b
 
 
-@pytest.mark.parametrize("kind", ["none", "cccp"])
-def test_batch_with_several_symmetric_maps_is_bitwise_equal_to_single_solves(kind):
+@pytest.mark.parametrize("kind,graph", [("none", False), ("cccp", False), ("cccp", True)])
+def test_batch_with_several_symmetric_maps_is_bitwise_equal_to_single_solves(kind, graph):
     """Three symmetric-size maps of different sizes (different stage lists per
     grid row) share one launch of the bf16 symmetric product in the batch; with
     a CCCP preconditioner the launch also conjugates each map's direction with
-    its own beta.  Every map reproduces its single solve bit for bit."""
+    its own beta; with graph the iterations between host checks replay a HIP
+    graph (re-captured whenever maps retire).  Every map reproduces its single
+    solve bit for bit."""
     specs = [(14500, 1e-3, 3, 81), (10300, 1e-3, 2, 82), (12288 + 5, 1e-4, 4, 83), (1500, 1e-3, 2, 84)]
     maps = []
     for n, lam, ntx, seed in specs:
@@ -141,7 +143,8 @@ def test_batch_with_several_symmetric_maps_is_bitwise_equal_to_single_solves(kin
         maps.append((pr, L().Problem(torch.tensor(pr.E, device=DEV), pr.lam, pr.scale)))
     precs = _precs(maps, kind)
     kw = dict(tol=1e-9, max_iter=100000, precision="bf16", refine=True, inner_tol=0.1, check_every=16)
-    alphas, stats, _ = L().pcg_solve_batched([p for _, p in maps], [pr.y for pr, _ in maps], precs, **kw)
+    alphas, stats, _ = L().pcg_solve_batched([p for _, p in maps], [pr.y for pr, _ in maps], precs, graph=graph,
+                                             **kw)
     for b, (pr, p) in enumerate(maps):
         a1, s1 = L().pcg_solve(p, pr.y, None if precs is None else precs[b], **kw)
         assert stats[b].status == 0 and stats[b].relres_true <= 1e-9, b
