@@ -10,7 +10,10 @@
 //   * exp2 followed by 1, 2 or 4 dependent multiply-adds (do they overlap?),
 //   * 32x32x16 bfloat16 MFMA alone and with 16 / 32 exp2 per 4 MFMA in the
 //     same wave (does the matrix core run beside the vector ALU?), and the
-//     same for eight 16x16x32 MFMA (the same flops in twice the instructions),
+//     same for eight 16x16x32 MFMA (the same flops in twice the instructions)
+//     and for the older 16x16x16 / 32x32x8 forms,
+//   * the symmetric product's work per 1024 kernel entries (16 per lane): the
+//     score MFMA of either tile shape with 16 exp2 and 32 multiply-adds,
 // at 1, 2, 4 and 8 waves per SIMD.  Each thread keeps 8 independent chains so
 // that latency does not hide the issue rate, and writes one float at the end.
 //
@@ -134,6 +137,91 @@ __global__ __launch_bounds__(kThreads) void mfma16_exp_rate(float* out, int iter
   out[blockIdx.x * blockDim.x + threadIdx.x] = s;
 }
 
+// the same flops as sixteen 16x16x16 or eight 32x32x8 bfloat16 MFMA (the
+// older instructions, half the K)
+typedef short v4s __attribute__((ext_vector_type(4)));
+template <int NE>
+__global__ __launch_bounds__(kThreads) void mfma16k16_exp_rate(float* out, int iters) {
+  v4s av, bv;
+  for (int j = 0; j < 4; ++j) {
+    av[j] = (short)(threadIdx.x + j);
+    bv[j] = (short)(j * 3 + 1);
+  }
+  v4f c[16];
+  for (int k = 0; k < 16; ++k) c[k] = v4f{0.f, 0.f, 0.f, 0.f};
+  float x[16];
+  for (int j = 0; j < 16; ++j) x[j] = threadIdx.x * 1e-3f + j * 0.01f;
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) c[k] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, c[k], 0, 0, 0);
+#pragma unroll
+    for (int e = 0; e < NE; ++e) x[e % 16] = __builtin_amdgcn_exp2f(-x[e % 16]);
+  }
+  float s = 0.f;
+  for (int k = 0; k < 16; ++k) s += c[k][0] + c[k][1] + c[k][2] + c[k][3];
+  for (int j = 0; j < 16; ++j) s += x[j];
+  out[blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+template <int NE>
+__global__ __launch_bounds__(kThreads) void mfma32k8_exp_rate(float* out, int iters) {
+  v4s av, bv;
+  for (int j = 0; j < 4; ++j) {
+    av[j] = (short)(threadIdx.x + j);
+    bv[j] = (short)(j * 3 + 1);
+  }
+  v16f c[8];
+  for (int k = 0; k < 8; ++k) c[k] = v16f{};
+  float x[16];
+  for (int j = 0; j < 16; ++j) x[j] = threadIdx.x * 1e-3f + j * 0.01f;
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) c[k] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av, bv, c[k], 0, 0, 0);
+#pragma unroll
+    for (int e = 0; e < NE; ++e) x[e % 16] = __builtin_amdgcn_exp2f(-x[e % 16]);
+  }
+  float s = 0.f;
+  for (int k = 0; k < 8; ++k)
+    for (int j = 0; j < 16; ++j) s += c[k][j];
+  for (int j = 0; j < 16; ++j) s += x[j];
+  out[blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
+// The symmetric product's work per 1024 kernel entries at d = 64, on
+// independent chains: NM32 32x32x16 MFMA (4: one score tile) or NM16 16x16x32
+// MFMA (8: four score tiles), 16 exp2 and 32 multiply-adds (row and column
+// sums) per lane.
+template <int NM32, int NM16>
+__global__ __launch_bounds__(kThreads) void tile_mix_rate(float* out, int iters, float a) {
+  v8bf av, bv;
+  for (int j = 0; j < 8; ++j) {
+    av[j] = (__bf16)(threadIdx.x * 1e-3f);
+    bv[j] = (__bf16)(j * 1e-3f);
+  }
+  v16f c[4];
+  v4f d[8];
+  for (int k = 0; k < 4; ++k) c[k] = v16f{};
+  for (int k = 0; k < 8; ++k) d[k] = v4f{0.f, 0.f, 0.f, 0.f};
+  float x[16], y[16];
+  for (int j = 0; j < 16; ++j) {
+    x[j] = threadIdx.x * 1e-3f + j * 0.01f;
+    y[j] = j;
+  }
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int k = 0; k < NM32; ++k) c[k & 3] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, c[k & 3], 0, 0, 0);
+#pragma unroll
+    for (int k = 0; k < NM16; ++k) d[k & 7] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, d[k & 7], 0, 0, 0);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) x[e] = __builtin_amdgcn_exp2f(-x[e]);
+#pragma unroll
+    for (int f = 0; f < 32; ++f) y[f & 15] = fmaf(y[f & 15], a, x[(f * 7) & 15]);
+  }
+  float s = 0.f;
+  for (int j = 0; j < 16; ++j) s += x[j] + y[j] + c[0][j] + c[1][j] + c[2][j] + c[3][j];
+  for (int k = 0; k < 8; ++k) s += d[k][0] + d[k][1] + d[k][2] + d[k][3];
+  out[blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
 int main() {
   int cus = 0, khz = 0;
   CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0));
@@ -183,6 +271,21 @@ int main() {
         8.0 * 16384 / 64, "flop");
     run("bf16 MFMA 16x16x32 + 32 exp2", [&] { mfma16_exp_rate<32><<<blocks, kThreads>>>(out, iters); },
         8.0 * 16384 / 64, "flop");
+    run("bf16 MFMA 16x16x16", [&] { mfma16k16_exp_rate<0><<<blocks, kThreads>>>(out, iters); }, 16.0 * 8192 / 64,
+        "flop");
+    run("bf16 MFMA 16x16x16 + 16 exp2", [&] { mfma16k16_exp_rate<16><<<blocks, kThreads>>>(out, iters); },
+        16.0 * 8192 / 64, "flop");
+    run("bf16 MFMA 32x32x8", [&] { mfma32k8_exp_rate<0><<<blocks, kThreads>>>(out, iters); }, 8.0 * 16384 / 64,
+        "flop");
+    run("bf16 MFMA 32x32x8 + 16 exp2", [&] { mfma32k8_exp_rate<16><<<blocks, kThreads>>>(out, iters); },
+        8.0 * 16384 / 64, "flop");
+    // per 1024 kernel entries: 16 per lane
+    run("16 exp2 + 32 FMA per lane", [&] { tile_mix_rate<0, 0><<<blocks, kThreads>>>(out, iters, 0.999f); }, 16.0,
+        "entries");
+    run("+ 4 MFMA 32x32x16", [&] { tile_mix_rate<4, 0><<<blocks, kThreads>>>(out, iters, 0.999f); }, 16.0,
+        "entries");
+    run("+ 8 MFMA 16x16x32", [&] { tile_mix_rate<0, 8><<<blocks, kThreads>>>(out, iters, 0.999f); }, 16.0,
+        "entries");
     CHECK(hipFree(out));
   }
   return 0;
