@@ -63,10 +63,12 @@ INNER_CAP = 30
 STALL_WINDOW = 2000
 
 # training set of the learned preconditioner: maps of TRAIN_N sites with
-# lambda log-uniform in [1e-5, 1e-2] and 1..8 transmitters (inner iterations
-# of the 65536-site solve: 96 maps x 30 epochs 4239, 192 x 60 4056,
-# 384 x 60 4080, 384 x 120 4122)
-TRAIN_N, TRAIN_MAPS, TRAIN_EPOCHS, TRAIN_PROBES = 4096, 192, 60, 128
+# lambda log-uniform in [1e-5, 1e-2] and 1..8 transmitters.  Chosen on the
+# held-out leg (8 maps of 32768 sites, d = 32, mean inner iterations against
+# CCCP's 1091): 192 maps x 60 epochs of 2048 sites 768, of 4096 sites 842,
+# 384 x 60 of 2048 sites 929.  The 65536-site map's inner iterations with the
+# same sets: 3801, 4166 and 3510 (of 8192 sites: 4680, of 512: fell back)
+TRAIN_N, TRAIN_MAPS, TRAIN_EPOCHS, TRAIN_PROBES = 2048, 192, 60, 128
 
 # vector ALU issue rate: 256 CUs x 64 lanes x 2.4 GHz unpacked float32
 # multiply-adds, one slot each.  The library is built without packed float32
