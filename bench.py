@@ -63,12 +63,14 @@ INNER_CAP = 30
 STALL_WINDOW = 2000
 
 # training set of the learned preconditioner: maps of TRAIN_N sites with
-# lambda log-uniform in [1e-5, 1e-2] and 1..8 transmitters.  Chosen on the
-# held-out leg (8 maps of 32768 sites, d = 32, mean inner iterations against
-# CCCP's 1091): 192 maps x 60 epochs of 2048 sites 768, of 4096 sites 842,
-# 384 x 60 of 2048 sites 929.  The 65536-site map's inner iterations with the
-# same sets: 3801, 4166 and 3510 (of 8192 sites: 4680, of 512: fell back)
-TRAIN_N, TRAIN_MAPS, TRAIN_EPOCHS, TRAIN_PROBES = 2048, 192, 60, 128
+# lambda log-uniform in [1e-5, 1e-2] and 1..8 transmitters, CCCP targets at
+# gamma = 1e-3.  Chosen on the held-out leg (8 maps of 32768 sites, d = 32,
+# mean inner iterations against CCCP's 1091): 192 maps of 2048 sites for 30 /
+# 60 / 90 / 120 / 180 epochs 775 / 768 / 740 / 836 / 1019; 60 epochs of 4096
+# sites 842, 384 maps of 2048 sites 929; targets at gamma 1e-2 / 1e-4 785 /
+# 813.  The 65536-site map's inner iterations follow (3850 / 3801 / 3662 /
+# 3981 / 3879; 4166 with 4096-site maps; of 8192 sites 4680, of 512 a fallback)
+TRAIN_N, TRAIN_MAPS, TRAIN_EPOCHS, TRAIN_PROBES = 2048, 192, 90, 128
 
 # vector ALU issue rate: 256 CUs x 64 lanes x 2.4 GHz unpacked float32
 # multiply-adds, one slot each.  The library is built without packed float32
