@@ -26,77 +26,80 @@ namespace {
 
 constexpr int kT = 256;
 
-// part[s][i][k] = sum_{j in split s} exp(<q_i, q_j>) Z[j][k]   (float64)
-template <int DP>
-__global__ __launch_bounds__(256) void mrhs_f64_kernel(const double* __restrict__ Eh, int64_t n,
-                                                       const double* __restrict__ Z, int nr,
-                                                       double* __restrict__ part, int64_t cps) {
-  constexpr int BM = 64, BN = 32, NC = 64;
-  __shared__ double Ei[BM][DP + 1];
-  __shared__ double Ej[BN][DP + 1];
-  __shared__ double X[BM][BN + 1];
-  __shared__ double Zs[BN][NC + 1];
-  const int tid = threadIdx.x;
-  const int64_t i0 = (int64_t)blockIdx.x * BM;
-  const int c0 = blockIdx.y * NC;
+// part[s][i][k] = sum_{j in split s} exp(<q_i, q_j>) Z[j][k]   (float64, on the
+// f64 MFMA).  A wave owns 16 rows (i) and NCT 16-column tiles of Z and walks
+// the split's keys (j) 16 at a time: the score tile is formed transposed,
+// S^T = (key rows) (query rows)^T by DP / 4 steps of the 16x16x4 f64 MFMA, so
+// that its output -- register r of lane l holds key 4 r + l / 16 against row
+// l % 16 -- is, after exp, the lane's A operand of step r of the product with
+// Z (row l % 16, k-slot l / 16 = key 4 r + l / 16); the B operand of that step
+// is Z[key 4 r + l / 16][column l % 16 of the tile].  Each score tile feeds
+// all NCT column tiles (the scalar kernel below recomputed it for every 64
+// columns).  Key and Z rows come straight from L2: the four waves of a block
+// read the same ones.
+typedef double v4d_ __attribute__((ext_vector_type(4)));
+template <int DP, int NCT>
+__global__ __launch_bounds__(256) void mrhs_f64m_kernel(const double* __restrict__ Eh, int64_t n,
+                                                        const double* __restrict__ Z, int nr,
+                                                        double* __restrict__ part, int64_t cps) {
+  constexpr int S = DP / 4;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int c = lane & 15, h = lane >> 4;
+  const int64_t row0 = (int64_t)blockIdx.x * 64 + wv * 16;
+  const int c0 = blockIdx.y * (16 * NCT);
   const int64_t j0 = (int64_t)blockIdx.z * cps;
   const int64_t j1 = j0 + cps < n ? j0 + cps : n;
-  for (int idx = tid; idx < BM * DP; idx += 256) {
-    int ii = idx / DP, c = idx % DP;
-    Ei[ii][c] = (i0 + ii < n) ? Eh[(i0 + ii) * DP + c] : 0.0;
+  // query fragment (B operand of the score): element h (DP / 4) + s of row row0 + c
+  double qf[S];
+  {
+    int64_t r = row0 + c;
+    if (r > n - 1) r = n - 1;
+    const double* src = Eh + r * DP + h * S;
+#pragma unroll
+    for (int s = 0; s < S; ++s) qf[s] = src[s];
   }
-  const int ty = tid >> 4, tx = tid & 15;
-  double acc[4][4];
+  // the lane's Z column in tile t, clamped to the last column (masked on store)
+  int zc[NCT];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int t = 0; t < NCT; ++t) zc[t] = c0 + 16 * t + c < nr ? c0 + 16 * t + c : nr - 1;
+  v4d_ acc[NCT];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-  for (int64_t jt = j0; jt < j1; jt += BN) {
-    __syncthreads();
-    for (int idx = tid; idx < BN * DP; idx += 256) {
-      int jj = idx / DP, c = idx % DP;
-      Ej[jj][c] = (jt + jj < j1) ? Eh[(jt + jj) * DP + c] : 0.0;
+  for (int t = 0; t < NCT; ++t) acc[t] = v4d_{0.0, 0.0, 0.0, 0.0};
+  for (int64_t k0 = j0; k0 < j1; k0 += 16) {
+    double kf[S];
+    {
+      int64_t kr = k0 + c;
+      if (kr > n - 1) kr = n - 1;
+      const double* src = Eh + kr * DP + h * S;
+#pragma unroll
+      for (int s = 0; s < S; ++s) kf[s] = src[s];
     }
-    for (int idx = tid; idx < BN * NC; idx += 256) {
-      int jj = idx / NC, c = idx % NC;
-      Zs[jj][c] = (jt + jj < j1 && c0 + c < nr) ? Z[(jt + jj) * nr + c0 + c] : 0.0;
-    }
-    __syncthreads();
+    v4d_ sc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int q = 0; q < (BM * BN) / 256; ++q) {
-      int e = tid + 256 * q;
-      int ii = e / BN, jj = e % BN;
-      double s = 0.0;
+    for (int s = 0; s < S; ++s) sc = __builtin_amdgcn_mfma_f64_16x16x4f64(kf[s], qf[s], sc, 0, 0, 0);
 #pragma unroll
-      for (int c = 0; c < DP; ++c) s = fma(Ei[ii][c], Ej[jj][c], s);
-      X[ii][jj] = (jt + jj < j1) ? exp(s) : 0.0;
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int jj = 0; jj < BN; ++jj) {
-      double xv[4], zv[4];
+    for (int r = 0; r < 4; ++r) {
+      const int64_t key = k0 + 4 * r + h;
+      const double x = key < j1 ? exp(sc[r]) : 0.0;
+      const double* zrow = Z + (key < n ? key : n - 1) * (int64_t)nr;
 #pragma unroll
-      for (int a = 0; a < 4; ++a) xv[a] = X[ty * 4 + a][jj];
-#pragma unroll
-      for (int b = 0; b < 4; ++b) zv[b] = Zs[jj][tx * 4 + b];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = fma(xv[a], zv[b], acc[a][b]);
+      for (int t = 0; t < NCT; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(x, zrow[zc[t]], acc[t], 0, 0, 0);
     }
   }
+  // register r of lane l: row row0 + 4 r + l / 16, column c0 + 16 t + l % 16
   double* out = part + (int64_t)blockIdx.z * n * nr;
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    int64_t i = i0 + ty * 4 + a;
-    if (i >= n) continue;
+  for (int t = 0; t < NCT; ++t) {
+    const int col = c0 + 16 * t + c;
+    if (col >= nr) continue;
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      int k = c0 + tx * 4 + b;
-      if (k < nr) out[i * nr + k] = acc[a][b];
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = row0 + 4 * r + h;
+      if (row < n) out[row * nr + col] = acc[t][r];
     }
   }
 }
+
 
 // U = lambda Z + sum_s part[s]
 __global__ void mrhs_finish_kernel(const double* __restrict__ part, int nsplit, const double* __restrict__ Z,
@@ -390,7 +393,8 @@ inline int ew_grid(int64_t total) {
 
 // Rectangular form for appended sites: part[s][i][k] = sum over the keys j of
 // range s of exp(<q_i, e_j>) Z[j][k], queries Eq (mq rows), keys Ek (nk rows,
-// Z row-aligned with them); same tiles and order as mrhs_f64_kernel.
+// Z row-aligned with them): blocks of 64 queries x 64 columns of Z, keys 32 at
+// a time, each score tile formed in LDS by scalar f64 multiply-adds.
 template <int DP>
 __global__ __launch_bounds__(256) void mrhs_rect_f64_kernel(const double* __restrict__ Eq, int64_t mq,
                                                             const double* __restrict__ Ek, int64_t nk,
@@ -506,14 +510,19 @@ inline int64_t mrhs_partial_cap(int64_t n, int nr) {
   return m > c ? m : c;
 }
 
+// columns of Z per block of the f64 MFMA directions product: 16 NCT, NCT = 8
+// (4 for dp = 128, whose fragments take twice the registers)
+inline int mrhs_nct(int dp) { return dp == 128 ? 4 : 8; }
+
 hipError_t launch_mrhs(int dp, const double* Eh, int64_t n, const double* Z, int nr, double* part, int nsplit,
                        int64_t cps, hipStream_t st) {
-  dim3 grid((unsigned)((n + 63) / 64), (unsigned)((nr + 63) / 64), (unsigned)nsplit);
+  const int cols = 16 * mrhs_nct(dp);
+  dim3 grid((unsigned)((n + 63) / 64), (unsigned)((nr + cols - 1) / cols), (unsigned)nsplit);
   switch (dp) {
-    case 16: mrhs_f64_kernel<16><<<grid, 256, 0, st>>>(Eh, n, Z, nr, part, cps); break;
-    case 32: mrhs_f64_kernel<32><<<grid, 256, 0, st>>>(Eh, n, Z, nr, part, cps); break;
-    case 64: mrhs_f64_kernel<64><<<grid, 256, 0, st>>>(Eh, n, Z, nr, part, cps); break;
-    case 128: mrhs_f64_kernel<128><<<grid, 256, 0, st>>>(Eh, n, Z, nr, part, cps); break;
+    case 16: mrhs_f64m_kernel<16, 8><<<grid, 256, 0, st>>>(Eh, n, Z, nr, part, cps); break;
+    case 32: mrhs_f64m_kernel<32, 8><<<grid, 256, 0, st>>>(Eh, n, Z, nr, part, cps); break;
+    case 64: mrhs_f64m_kernel<64, 8><<<grid, 256, 0, st>>>(Eh, n, Z, nr, part, cps); break;
+    case 128: mrhs_f64m_kernel<128, 4><<<grid, 256, 0, st>>>(Eh, n, Z, nr, part, cps); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -602,7 +611,7 @@ laker_status fit_cccp(const Problem& pb, const double* Z, const laker_cccp_opts&
     LK_TRY(hipMemcpyAsync(ws.U, on->U, sizeof(double) * n * nr, hipMemcpyDeviceToDevice, st));
   } else if (o.precision == LAKER_F64) {
     LK_TRY(prep_embed(pb.E, n, pb.d, pb.dp, pb.scale, LAKER_F64, ws.e64, st));
-    const int64_t rowtiles = (n + 63) / 64, coltiles = (nr + 63) / 64;
+    const int64_t rowtiles = (n + 63) / 64, coltiles = (nr + 16 * mrhs_nct(pb.dp) - 1) / (16 * mrhs_nct(pb.dp));
     int64_t ns = (1024 + rowtiles * coltiles - 1) / (rowtiles * coltiles);
     int64_t jt = (n + 31) / 32;
     if (ns > jt) ns = jt;

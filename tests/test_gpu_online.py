@@ -68,3 +68,27 @@ def test_appended_sites_extend_the_fit(n0, m, d, nr):
     ref = O.solve_direct(O.system_matrix(pr.E, pr.scale, pr.lam), pr.y)
     assert np.linalg.norm(a1.cpu().numpy() - ref) <= 1e-10 * np.linalg.norm(ref)
     assert s1.iters <= s2.iters
+
+
+@pytest.mark.parametrize("n,d,nr,seed", [(12288 + 37, 64, 200, 3), (3000 + 5, 100, 70, 4)])
+def test_float64_directions_elementwise(n, d, nr, seed):
+    """U = (lambda I + G) Z of a fresh float64 fit (eq. random_directions: the
+    product every float64 fit starts from), on sampled rows -- the first and
+    last of every 64-row block and 64 random ones -- against the oracle's
+    one-row evaluation, 1e-13 relative to sum_j |G_ij Z_jk| + lambda |Z_ik|.
+    The sizes leave ragged row blocks and column tiles, and d = 100 runs the
+    dp = 128 form."""
+    pr = make_problem(n, d, 1e-3, n_tx=3, seed=seed)
+    Z = make_directions(n, nr, seed)
+    prob = L().Problem(torch.tensor(pr.E, device=DEV), pr.lam, pr.scale)
+    state = L().OnlineFitState(n, nr, DEV)
+    state.fit(prob, torch.tensor(Z, device=DEV), gamma=0.1)
+    U = state.directions().cpu().numpy()
+    rng = np.random.default_rng(seed)
+    rows = np.unique(np.r_[np.arange(0, n, 64), np.minimum(np.arange(63, n + 63, 64), n - 1),
+                           rng.choice(n, 64, replace=False)])
+    for i in rows:
+        g = np.exp(pr.scale * (pr.E @ pr.E[i]))
+        ref = g @ Z + pr.lam * Z[i]
+        mag = g @ np.abs(Z) + pr.lam * np.abs(Z[i])
+        assert (np.abs(U[i] - ref) / mag).max() <= 1e-13, i
