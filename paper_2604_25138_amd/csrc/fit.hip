@@ -26,8 +26,9 @@ namespace {
 
 constexpr int kT = 256;
 
-// part[s][i][k] = sum_{j in split s} exp(<q_i, q_j>) Z[j][k]   (float64, on the
-// f64 MFMA).  A wave owns 16 rows (i) and NCT 16-column tiles of Z and walks
+// part[s][i][k] = sum_{j in split s} exp(<q_i, e_j>) Z[j][k]   (float64, on the
+// f64 MFMA; queries q (mq rows), keys e (nk rows, Z row-aligned with them):
+// the same rows for a fit, the old and the appended sites for the online update).  A wave owns 16 rows (i) and NCT 16-column tiles of Z and walks
 // the split's keys (j) 16 at a time: the score tile is formed transposed,
 // S^T = (key rows) (query rows)^T by DP / 4 steps of the 16x16x4 f64 MFMA, so
 // that its output -- register r of lane l holds key 4 r + l / 16 against row
@@ -39,7 +40,8 @@ constexpr int kT = 256;
 // read the same ones.
 typedef double v4d_ __attribute__((ext_vector_type(4)));
 template <int DP, int NCT>
-__global__ __launch_bounds__(256) void mrhs_f64m_kernel(const double* __restrict__ Eh, int64_t n,
+__global__ __launch_bounds__(256) void mrhs_f64m_kernel(const double* __restrict__ Eq, int64_t mq,
+                                                        const double* __restrict__ Ek, int64_t nk,
                                                         const double* __restrict__ Z, int nr,
                                                         double* __restrict__ part, int64_t cps) {
   constexpr int S = DP / 4;
@@ -48,13 +50,13 @@ __global__ __launch_bounds__(256) void mrhs_f64m_kernel(const double* __restrict
   const int64_t row0 = (int64_t)blockIdx.x * 64 + wv * 16;
   const int c0 = blockIdx.y * (16 * NCT);
   const int64_t j0 = (int64_t)blockIdx.z * cps;
-  const int64_t j1 = j0 + cps < n ? j0 + cps : n;
+  const int64_t j1 = j0 + cps < nk ? j0 + cps : nk;
   // query fragment (B operand of the score): element h (DP / 4) + s of row row0 + c
   double qf[S];
   {
     int64_t r = row0 + c;
-    if (r > n - 1) r = n - 1;
-    const double* src = Eh + r * DP + h * S;
+    if (r > mq - 1) r = mq - 1;
+    const double* src = Eq + r * DP + h * S;
 #pragma unroll
     for (int s = 0; s < S; ++s) qf[s] = src[s];
   }
@@ -69,8 +71,8 @@ __global__ __launch_bounds__(256) void mrhs_f64m_kernel(const double* __restrict
     double kf[S];
     {
       int64_t kr = k0 + c;
-      if (kr > n - 1) kr = n - 1;
-      const double* src = Eh + kr * DP + h * S;
+      if (kr > nk - 1) kr = nk - 1;
+      const double* src = Ek + kr * DP + h * S;
 #pragma unroll
       for (int s = 0; s < S; ++s) kf[s] = src[s];
     }
@@ -81,13 +83,13 @@ __global__ __launch_bounds__(256) void mrhs_f64m_kernel(const double* __restrict
     for (int r = 0; r < 4; ++r) {
       const int64_t key = k0 + 4 * r + h;
       const double x = key < j1 ? exp(sc[r]) : 0.0;
-      const double* zrow = Z + (key < n ? key : n - 1) * (int64_t)nr;
+      const double* zrow = Z + (key < nk ? key : nk - 1) * (int64_t)nr;
 #pragma unroll
       for (int t = 0; t < NCT; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(x, zrow[zc[t]], acc[t], 0, 0, 0);
     }
   }
   // register r of lane l: row row0 + 4 r + l / 16, column c0 + 16 t + l % 16
-  double* out = part + (int64_t)blockIdx.z * n * nr;
+  double* out = part + (int64_t)blockIdx.z * mq * nr;
 #pragma unroll
   for (int t = 0; t < NCT; ++t) {
     const int col = c0 + 16 * t + c;
@@ -95,7 +97,7 @@ __global__ __launch_bounds__(256) void mrhs_f64m_kernel(const double* __restrict
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int64_t row = row0 + 4 * r + h;
-      if (row < n) out[row * nr + col] = acc[t][r];
+      if (row < mq) out[row * nr + col] = acc[t][r];
     }
   }
 }
@@ -391,81 +393,6 @@ inline int ew_grid(int64_t total) {
   return (int)(g < 1 ? 1 : g);
 }
 
-// Rectangular form for appended sites: part[s][i][k] = sum over the keys j of
-// range s of exp(<q_i, e_j>) Z[j][k], queries Eq (mq rows), keys Ek (nk rows,
-// Z row-aligned with them): blocks of 64 queries x 64 columns of Z, keys 32 at
-// a time, each score tile formed in LDS by scalar f64 multiply-adds.
-template <int DP>
-__global__ __launch_bounds__(256) void mrhs_rect_f64_kernel(const double* __restrict__ Eq, int64_t mq,
-                                                            const double* __restrict__ Ek, int64_t nk,
-                                                            const double* __restrict__ Z, int nr,
-                                                            double* __restrict__ part, int64_t cps) {
-  constexpr int BM = 64, BN = 32, NC = 64;
-  __shared__ double Ei[BM][DP + 1];
-  __shared__ double Ej[BN][DP + 1];
-  __shared__ double X[BM][BN + 1];
-  __shared__ double Zs[BN][NC + 1];
-  const int tid = threadIdx.x;
-  const int64_t i0 = (int64_t)blockIdx.x * BM;
-  const int c0 = blockIdx.y * NC;
-  const int64_t j0 = (int64_t)blockIdx.z * cps;
-  const int64_t j1 = j0 + cps < nk ? j0 + cps : nk;
-  for (int idx = tid; idx < BM * DP; idx += 256) {
-    int ii = idx / DP, c = idx % DP;
-    Ei[ii][c] = (i0 + ii < mq) ? Eq[(i0 + ii) * DP + c] : 0.0;
-  }
-  const int ty = tid >> 4, tx = tid & 15;
-  double acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-  for (int64_t jt = j0; jt < j1; jt += BN) {
-    __syncthreads();
-    for (int idx = tid; idx < BN * DP; idx += 256) {
-      int jj = idx / DP, c = idx % DP;
-      Ej[jj][c] = (jt + jj < j1) ? Ek[(jt + jj) * DP + c] : 0.0;
-    }
-    for (int idx = tid; idx < BN * NC; idx += 256) {
-      int jj = idx / NC, c = idx % NC;
-      Zs[jj][c] = (jt + jj < j1 && c0 + c < nr) ? Z[(jt + jj) * nr + c0 + c] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < (BM * BN) / 256; ++q) {
-      int e = tid + 256 * q;
-      int ii = e / BN, jj = e % BN;
-      double s = 0.0;
-#pragma unroll
-      for (int c = 0; c < DP; ++c) s = fma(Ei[ii][c], Ej[jj][c], s);
-      X[ii][jj] = (jt + jj < j1) ? exp(s) : 0.0;
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int jj = 0; jj < BN; ++jj) {
-      double xv[4], zv[4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) xv[a] = X[ty * 4 + a][jj];
-#pragma unroll
-      for (int b = 0; b < 4; ++b) zv[b] = Zs[jj][tx * 4 + b];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = fma(xv[a], zv[b], acc[a][b]);
-    }
-  }
-  double* out = part + (int64_t)blockIdx.z * mq * nr;
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    int64_t i = i0 + ty * 4 + a;
-    if (i >= mq) continue;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      int k = c0 + tx * 4 + b;
-      if (k < nr) out[i * nr + k] = acc[a][b];
-    }
-  }
-}
 
 // U[i] = base[i] + sum_s part[s][i] over mq x nr entries, where base is
 // lambda Zs (Zs set: the rows' own directions) or the previous U (in place)
@@ -514,15 +441,15 @@ inline int64_t mrhs_partial_cap(int64_t n, int nr) {
 // (4 for dp = 128, whose fragments take twice the registers)
 inline int mrhs_nct(int dp) { return dp == 128 ? 4 : 8; }
 
-hipError_t launch_mrhs(int dp, const double* Eh, int64_t n, const double* Z, int nr, double* part, int nsplit,
-                       int64_t cps, hipStream_t st) {
+hipError_t launch_mrhs(int dp, const double* Eq, int64_t mq, const double* Ek, int64_t nk, const double* Z, int nr,
+                       double* part, int nsplit, int64_t cps, hipStream_t st) {
   const int cols = 16 * mrhs_nct(dp);
-  dim3 grid((unsigned)((n + 63) / 64), (unsigned)((nr + cols - 1) / cols), (unsigned)nsplit);
+  dim3 grid((unsigned)((mq + 63) / 64), (unsigned)((nr + cols - 1) / cols), (unsigned)nsplit);
   switch (dp) {
-    case 16: mrhs_f64m_kernel<16, 8><<<grid, 256, 0, st>>>(Eh, n, Z, nr, part, cps); break;
-    case 32: mrhs_f64m_kernel<32, 8><<<grid, 256, 0, st>>>(Eh, n, Z, nr, part, cps); break;
-    case 64: mrhs_f64m_kernel<64, 8><<<grid, 256, 0, st>>>(Eh, n, Z, nr, part, cps); break;
-    case 128: mrhs_f64m_kernel<128, 4><<<grid, 256, 0, st>>>(Eh, n, Z, nr, part, cps); break;
+    case 16: mrhs_f64m_kernel<16, 8><<<grid, 256, 0, st>>>(Eq, mq, Ek, nk, Z, nr, part, cps); break;
+    case 32: mrhs_f64m_kernel<32, 8><<<grid, 256, 0, st>>>(Eq, mq, Ek, nk, Z, nr, part, cps); break;
+    case 64: mrhs_f64m_kernel<64, 8><<<grid, 256, 0, st>>>(Eq, mq, Ek, nk, Z, nr, part, cps); break;
+    case 128: mrhs_f64m_kernel<128, 4><<<grid, 256, 0, st>>>(Eq, mq, Ek, nk, Z, nr, part, cps); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -534,7 +461,7 @@ hipError_t rect_directions(int dp, const double* Eq, int64_t mq, const double* E
                            int nr, const double* Zs, double lam, double* U, double* part, int64_t cap,
                            hipStream_t st) {
   if (mq < 1 || nk < 1) return hipSuccess;
-  const int64_t rowtiles = (mq + 63) / 64, coltiles = (nr + 63) / 64;
+  const int64_t rowtiles = (mq + 63) / 64, coltiles = (nr + 16 * mrhs_nct(dp) - 1) / (16 * mrhs_nct(dp));
   int64_t ns = (1024 + rowtiles * coltiles - 1) / (rowtiles * coltiles);
   const int64_t jt = (nk + 31) / 32;
   if (ns > jt) ns = jt;
@@ -544,15 +471,7 @@ hipError_t rect_directions(int dp, const double* Eq, int64_t mq, const double* E
   if (mq * nr > cap) return hipErrorInvalidValue;
   const int64_t cps = (((nk + ns - 1) / ns) + 31) / 32 * 32;
   ns = (nk + cps - 1) / cps;
-  dim3 grid((unsigned)rowtiles, (unsigned)coltiles, (unsigned)ns);
-  switch (dp) {
-    case 16: mrhs_rect_f64_kernel<16><<<grid, 256, 0, st>>>(Eq, mq, Ek, nk, Z, nr, part, cps); break;
-    case 32: mrhs_rect_f64_kernel<32><<<grid, 256, 0, st>>>(Eq, mq, Ek, nk, Z, nr, part, cps); break;
-    case 64: mrhs_rect_f64_kernel<64><<<grid, 256, 0, st>>>(Eq, mq, Ek, nk, Z, nr, part, cps); break;
-    case 128: mrhs_rect_f64_kernel<128><<<grid, 256, 0, st>>>(Eq, mq, Ek, nk, Z, nr, part, cps); break;
-    default: return hipErrorInvalidValue;
-  }
-  hipError_t e = hipGetLastError();
+  hipError_t e = launch_mrhs(dp, Eq, mq, Ek, nk, Z, nr, part, (int)ns, cps, st);
   if (e != hipSuccess) return e;
   mrhs_rect_finish_kernel<<<ew_grid(mq * nr), kT, 0, st>>>(part, (int)ns, Zs, lam, mq * nr, U);
   return hipGetLastError();
@@ -620,7 +539,7 @@ laker_status fit_cccp(const Problem& pb, const double* Z, const laker_cccp_opts&
     if (ns < 1) ns = 1;
     int64_t cps = (((n + ns - 1) / ns) + 31) / 32 * 32;
     ns = (n + cps - 1) / cps;
-    LK_TRY(launch_mrhs(pb.dp, ws.e64, n, Z, nr, ws.part, (int)ns, cps, st));
+    LK_TRY(launch_mrhs(pb.dp, ws.e64, n, ws.e64, n, Z, nr, ws.part, (int)ns, cps, st));
     mrhs_finish_kernel<<<ew_grid(n * nr), kT, 0, st>>>(ws.part, (int)ns, Z, pb.lambda, n * nr, ws.U);
     LK_CHECK_LAUNCH();
   } else {
