@@ -34,10 +34,10 @@ constexpr int kT = 256;
 // that its output -- register r of lane l holds key 4 r + l / 16 against row
 // l % 16 -- is, after exp, the lane's A operand of step r of the product with
 // Z (row l % 16, k-slot l / 16 = key 4 r + l / 16); the B operand of that step
-// is Z[key 4 r + l / 16][column l % 16 of the tile].  Each score tile feeds
-// all NCT column tiles (the scalar kernel below recomputed it for every 64
-// columns).  Key and Z rows come straight from L2: the four waves of a block
-// read the same ones.
+// is Z[key 4 r + l / 16][column l % 16 of the tile].  Each score tile and its
+// exp feed all NCT column tiles, so they are formed once per 16 NCT columns of
+// Z.  Key and Z rows come straight from L2: the four waves of a block read the
+// same ones.
 typedef double v4d_ __attribute__((ext_vector_type(4)));
 template <int DP, int NCT>
 __global__ __launch_bounds__(256) void mrhs_f64m_kernel(const double* __restrict__ Eq, int64_t mq,
