@@ -70,14 +70,16 @@ def test_appended_sites_extend_the_fit(n0, m, d, nr):
     assert s1.iters <= s2.iters
 
 
-@pytest.mark.parametrize("n,d,nr,seed", [(12288 + 37, 64, 200, 3), (3000 + 5, 100, 70, 4)])
+@pytest.mark.parametrize("n,d,nr,seed", [(12288 + 37, 64, 200, 3), (3000 + 5, 100, 70, 4), (7, 3, 3, 5),
+                                         (40, 16, 17, 6)])
 def test_float64_directions_elementwise(n, d, nr, seed):
     """U = (lambda I + G) Z of a fresh float64 fit (eq. random_directions: the
     product every float64 fit starts from), on sampled rows -- the first and
-    last of every 64-row block and 64 random ones -- against the oracle's
-    one-row evaluation, 1e-13 relative to sum_j |G_ij Z_jk| + lambda |Z_ik|.
-    The sizes leave ragged row blocks and column tiles, and d = 100 runs the
-    dp = 128 form."""
+    last of every 64-row block and up to 64 random ones -- against the
+    oracle's one-row evaluation, 1e-13 relative to sum_j |G_ij Z_jk| +
+    lambda |Z_ik|.  The sizes leave ragged row blocks and column tiles, d = 100
+    runs the dp = 128 form, and the small maps have fewer rows and columns than
+    one 16 x 16 tile."""
     pr = make_problem(n, d, 1e-3, n_tx=3, seed=seed)
     Z = make_directions(n, nr, seed)
     prob = L().Problem(torch.tensor(pr.E, device=DEV), pr.lam, pr.scale)
@@ -86,7 +88,7 @@ def test_float64_directions_elementwise(n, d, nr, seed):
     U = state.directions().cpu().numpy()
     rng = np.random.default_rng(seed)
     rows = np.unique(np.r_[np.arange(0, n, 64), np.minimum(np.arange(63, n + 63, 64), n - 1),
-                           rng.choice(n, 64, replace=False)])
+                           rng.choice(n, min(n, 64), replace=False)])
     for i in rows:
         g = np.exp(pr.scale * (pr.E @ pr.E[i]))
         ref = g @ Z + pr.lam * Z[i]
