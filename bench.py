@@ -51,8 +51,11 @@ WORKLOADS = {
 # the solve: flexible float64 outer CG around bf16 inner PCG solves of at most
 # INNER_CAP iterations each (a sweep of the cap on the n16384_d64 map:
 # 15 -> 110 ms, 20 -> 96, 25 -> 96, 30 -> 85, 40 -> 90; iterative refinement
-# with inner tolerance 0.1: 100 ms); the inner solves check for convergence
-# every INNER_CAP iterations, so no launches are enqueued past the cap
+# with inner tolerance 0.1: 100 ms; on the n65536_d64 map with the trained
+# network: 20 / 25 / 30 / 40 / 50 -> 2.30 / 2.30 / 2.18 / 2.21 / 2.24 s, and
+# the held-out leg's learned solves 1.05 / 1.12 / 1.06 / 1.17 / 1.24 s); the
+# inner solves check for convergence every INNER_CAP iterations, so no
+# launches are enqueued past the cap
 INNER_CAP = 30
 # directions the flexible outer CG keeps (per workload, `history`): at 65536
 # sites keeping 8 took 2.74 / 2.80 s per solve on two maps against 3.51 / 3.27 s
