@@ -1,5 +1,6 @@
 // Small dense float64 linear algebra on the device, used by the preconditioner
-// fit: a tiled GEMM with column/row strides and split-K partials, and an
+// fit: a tiled GEMM on the f64 MFMA with column/row strides and split-K
+// partials, and an
 // in-place blocked Gauss-Jordan inverse of an SPD matrix (no pivoting: the
 // Schur complements of an SPD matrix stay SPD) that also returns log det.
 #include "dense.hpp"
@@ -11,6 +12,13 @@ namespace {
 constexpr int TB = 64;   // output tile
 constexpr int TK = 16;   // depth slice
 
+// One split-K part of C = A B on the 16x16x4 f64 MFMA: a block forms a 64 x 64
+// output tile from 16-deep slices of A and B staged in LDS (any strides); wave w
+// owns rows 32 (w / 2) .. + 31 and columns 32 (w % 2) .. + 31 as 2 x 2 MFMA
+// tiles.  In MFMA step q of a slice a lane supplies A[row l % 16][k = 4 q + l / 16]
+// and B[k = 4 q + l / 16][column l % 16]; register r of its result holds row
+// 4 r + l / 16, column l % 16 of the tile.
+typedef double v4d_ __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(256) void gemm_f64_kernel(int64_t M, int64_t N, int64_t K, const double* __restrict__ A,
                                                        int64_t sai, int64_t sak, const double* __restrict__ B,
                                                        int64_t sbk, int64_t sbj, double* __restrict__ P,
@@ -18,15 +26,17 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(int64_t M, int64_t N, int
   __shared__ double As[TK][TB + 1];
   __shared__ double Bs[TK][TB + 1];
   const int tid = threadIdx.x;
-  const int ty = tid >> 4, tx = tid & 15;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int c = lane & 15, h = lane >> 4;
+  const int wr = (wv >> 1) * 32, wc = (wv & 1) * 32;
   const int64_t i0 = (int64_t)blockIdx.y * TB, j0 = (int64_t)blockIdx.x * TB;
   const int64_t k0 = (int64_t)blockIdx.z * kps;
   const int64_t k1 = k0 + kps < K ? k0 + kps : K;
-  double acc[4][4];
+  v4d_ acc[2][2];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+    for (int b = 0; b < 2; ++b) acc[a][b] = v4d_{0.0, 0.0, 0.0, 0.0};
   const bool a_row_contig = (sak == 1);
   const bool b_row_contig = (sbj == 1);
   for (int64_t kk = k0; kk < k1; kk += TK) {
@@ -44,30 +54,33 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(int64_t M, int64_t N, int
     }
     __syncthreads();
 #pragma unroll
-    for (int k_ = 0; k_ < TK; ++k_) {
-      double av[4], bv[4];
+    for (int q = 0; q < TK / 4; ++q) {
+      const int kr = 4 * q + h;
+      double av[2], bv[2];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) av[a] = As[k_][ty * 4 + a];
+      for (int a = 0; a < 2; ++a) av[a] = As[kr][wr + 16 * a + c];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) bv[b] = Bs[k_][tx * 4 + b];
+      for (int b = 0; b < 2; ++b) bv[b] = Bs[kr][wc + 16 * b + c];
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
+        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
     }
     __syncthreads();
   }
   double* out = P + (int64_t)blockIdx.z * M * N;
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    int64_t gi = i0 + ty * 4 + a;
-    if (gi >= M) continue;
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      int64_t gj = j0 + tx * 4 + b;
-      if (gj < N) out[gi * N + gj] = acc[a][b];
+    for (int b = 0; b < 2; ++b) {
+      const int64_t gj = j0 + wc + 16 * b + c;
+      if (gj >= N) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gi = i0 + wr + 16 * a + 4 * r + h;
+        if (gi < M) out[gi * N + gj] = acc[a][b][r];
+      }
     }
-  }
 }
 
 // C[i*ldc + j] = alpha * (*alpha_dev) * sum_s P[s] + beta * C   (alpha_dev may be null)
