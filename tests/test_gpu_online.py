@@ -12,6 +12,9 @@ the previous fit's weights.  Checks:
   from Sigma_0 = I;
 * PCG warm-started from [alpha_prev; 0] reaches the Cholesky solution of the
   enlarged system in no more iterations than from zero.
+The float64 directions product itself (the fit's first step, on the f64 MFMA)
+is also checked row by row against the oracle at several shapes, down to maps
+smaller than one 16 x 16 tile.
 """
 import numpy as np
 import pytest
